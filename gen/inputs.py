@@ -1,0 +1,148 @@
+"""Seeded synthetic inputs shared by the CPU oracle and the GPU path.
+
+This module generates inputs only: grid sizes, the node field kappa, right-hand
+sides and random choices.  It holds none of the solver's arithmetic (no edge
+weights, no stencil, no elimination), so the oracle and the HIP path can both
+draw from it without sharing any part of the method.
+
+Conventions (used by every caller):
+  * The grid has n2 rows (the interface length) and n1 columns (the slab
+    direction) of interior unknowns; the Dirichlet ring adds one node on each
+    side.  Node (c, r) of the interior, 0 <= c < n1, 0 <= r < n2, sits at
+    x = (c+1) h, y = (r+1) h with h = 1/(n2+1).
+  * The coefficient field is stored on the nodes including the ring, shape
+    (n1+2, n2+2), the row index r fastest: kappa[c+1, r+1] belongs to node
+    (c, r).
+  * Right-hand sides have shape (nrhs, n1, n2), r fastest.
+
+The coefficient field is exp(g) with g a Gaussian random field with the
+squared-exponential covariance k(d) = sigma^2 exp(-d^2 / (2 l^2)), l = 0.05,
+sigma^2 = 1.  It is sampled exactly from the separable covariance
+K = Kx (x) Ky: g = Fx Z Fy^T with F = V sqrt(max(lambda, 0)) from the
+symmetric eigendecomposition of each 1-D covariance matrix (a Cholesky
+factor does not exist: the 1-D matrices are numerically singular).
+"""
+from __future__ import annotations
+
+import functools
+from dataclasses import dataclass, field
+
+import numpy as np
+
+GRF_LENGTH = 0.05
+GRF_VARIANCE = 1.0
+
+# Seeds of the synthetic workloads.
+SEED_KAPPA = 0
+SEED_KAPPA_OBS = 1
+SEED_RHS = 100
+SEED_NOISE = 200
+SEED_FD_NODES = 300
+SEED_BATCH = 400
+
+
+def default_h(n2: int) -> float:
+    """Grid spacing: n2 interior rows between y = 0 and y = 1."""
+    return 1.0 / (n2 + 1)
+
+
+@functools.lru_cache(maxsize=32)
+def _grf_factor(npts: int, h: float, length: float) -> np.ndarray:
+    x = np.arange(npts, dtype=np.float64) * h
+    d = x[:, None] - x[None, :]
+    k = np.exp(-(d * d) / (2.0 * length * length))
+    lam, v = np.linalg.eigh(k)
+    return np.ascontiguousarray(v * np.sqrt(np.maximum(lam, 0.0))[None, :])
+
+
+def grf(n2: int, n1: int, seed: int, h: float | None = None,
+        length: float = GRF_LENGTH, variance: float = GRF_VARIANCE) -> np.ndarray:
+    """Gaussian random field on the (n1+2) x (n2+2) nodes (ring included)."""
+    if h is None:
+        h = default_h(n2)
+    fx = _grf_factor(n1 + 2, float(h), float(length))
+    fy = _grf_factor(n2 + 2, float(h), float(length))
+    z = np.random.default_rng(seed).standard_normal((n1 + 2, n2 + 2))
+    return np.sqrt(variance) * (fx @ z @ fy.T)
+
+
+def kappa_lognormal(n2: int, n1: int, seed: int, h: float | None = None) -> np.ndarray:
+    return np.exp(grf(n2, n1, seed, h))
+
+
+def kappa_const(n2: int, n1: int, value: float = 1.0) -> np.ndarray:
+    return np.full((n1 + 2, n2 + 2), float(value))
+
+
+def rhs_uniform(n2: int, n1: int, nrhs: int, seed: int = SEED_RHS) -> np.ndarray:
+    return np.random.default_rng(seed).uniform(-1.0, 1.0, (nrhs, n1, n2))
+
+
+def rhs_normal(n2: int, n1: int, nrhs: int, seed: int = SEED_RHS) -> np.ndarray:
+    return np.random.default_rng(seed).standard_normal((nrhs, n1, n2))
+
+
+@dataclass
+class Workload:
+    """One synthetic problem: grid, slab width, coefficient field and loads."""
+    name: str
+    n2: int
+    n1: int
+    b: int
+    nrhs: int
+    kappa_kind: str          # "const" or "lognormal"
+    rhs_kind: str            # "uniform" or "normal"
+    kappa_seed: int = SEED_KAPPA
+    rhs_seed: int = SEED_RHS
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def h(self) -> float:
+        return default_h(self.n2)
+
+    @property
+    def m(self) -> int:
+        return self.n1 // (self.b + 1)
+
+    @property
+    def N(self) -> int:
+        return self.n1 * self.n2
+
+    def kappa(self) -> np.ndarray:
+        if self.kappa_kind == "const":
+            return kappa_const(self.n2, self.n1)
+        return kappa_lognormal(self.n2, self.n1, self.kappa_seed, self.h)
+
+    def rhs(self, nrhs: int | None = None) -> np.ndarray:
+        k = self.nrhs if nrhs is None else nrhs
+        if self.rhs_kind == "normal":
+            return rhs_normal(self.n2, self.n1, k, self.rhs_seed)
+        return rhs_uniform(self.n2, self.n1, k, self.rhs_seed)
+
+
+# The five synthetic workloads: Poisson 64x64 (b=7, 8 slabs); lognormal
+# diffusion 1024x1024 (b=31); lognormal diffusion 2048 rows x 4096 columns
+# (b=31, 128 slabs, 16 normal RHS); the 512x512 differentiation case (b=15);
+# the batch of uneven problems is drawn by batch_problems().
+POISSON_64 = Workload("poisson_64x64_b7", 64, 64, 7, 1, "const", "uniform")
+DIFFUSION_1024 = Workload("diffusion_1024x1024_b31", 1024, 1024, 31, 1, "lognormal", "uniform")
+DIFFUSION_2048x4096 = Workload("diffusion_2048x4096_b31", 2048, 4096, 31, 16, "lognormal", "normal")
+ADJOINT_512 = Workload("adjoint_512x512_b15", 512, 512, 15, 1, "lognormal", "uniform")
+
+
+def batch_problems(count: int = 256, seed: int = SEED_BATCH) -> list[Workload]:
+    """Uneven batch: n2 in {128,...,1024}, n1 in {128,...,2048}, b in {7,15,31}, 1-16 RHS.
+
+    n1 is rounded down to a multiple of b+1 so that the slabs tile the grid.
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        n2 = int(rng.choice([128, 256, 512, 1024]))
+        n1 = int(rng.choice([128, 256, 512, 1024, 2048]))
+        b = int(rng.choice([7, 15, 31]))
+        nrhs = int(rng.integers(1, 17))
+        n1 = (n1 // (b + 1)) * (b + 1)
+        out.append(Workload(f"batch_{i}", n2, n1, b, nrhs, "lognormal", "uniform",
+                            kappa_seed=1000 + i, rhs_seed=2000 + i))
+    return out

@@ -1,0 +1,411 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle itself.
+
+Each test checks the oracle against something the paper or the mathematics
+fixes: hand-worked fixtures, dense brute force, closed forms for the constant
+coefficient case, the fast sine-transform Poisson solver, invariants of
+Schur complements of M-matrices, the rank property (Prop. 1, as corrected),
+second-order convergence to a manufactured solution, the 1-D Green's
+function, adjoint identities and finite differences of the loss.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.fft
+import scipy.sparse.linalg as spla
+
+from gen import inputs as G
+from oracle import slab_oracle as O
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, name)) as fh:
+        return json.load(fh)
+
+
+def _dense_T(fac):
+    """Assemble the oracle's blocks into the full reduced matrix."""
+    m = len(fac.s1.T_diag)
+    n = fac.s1.T_diag[0].shape[0]
+    T = np.zeros((m * n, m * n))
+    for j in range(m):
+        T[j * n:(j + 1) * n, j * n:(j + 1) * n] = fac.s1.T_diag[j]
+    for j in range(m - 1):
+        T[j * n:(j + 1) * n, (j + 1) * n:(j + 2) * n] = fac.s1.T_up[j]
+        T[(j + 1) * n:(j + 2) * n, j * n:(j + 1) * n] = fac.s1.T_lo[j]
+    return T
+
+
+# --------------------------------------------------------------------------- maps
+
+@pytest.mark.parametrize("name", ["maps_n2_2_n1_4_b1.json", "maps_n2_3_n1_6_b2.json"])
+def test_maps_golden(name):
+    g = _golden(name)
+    mp = O.index_maps(g["n2"], g["n1"], g["b"])
+    assert mp["m"] == g["m"]
+    for key in ("col_kind", "slab_of_col", "local_of_col", "perm_even", "perm_odd"):
+        assert mp[key].tolist() == g[key], key
+
+
+@pytest.mark.parametrize("n2,n1,b", [(1, 2, 1), (5, 16, 3), (7, 24, 7), (4, 32, 15)])
+def test_maps_partition_and_adjacency(n2, n1, b):
+    """I_1, I_2, ... partition the grid; slab-local neighbours are 1 or b apart."""
+    mp = O.index_maps(n2, n1, b)
+    allidx = np.concatenate([mp["perm_even"], mp["perm_odd"]])
+    assert sorted(allidx.tolist()) == list(range(n1 * n2))
+    assert mp["m"] * (b + 1) == n1
+    # local position r*b+k is node (s(b+1)+k, r): recover (c, r) independently
+    pe = mp["perm_even"].reshape(mp["m"], n2, b)
+    for s in range(mp["m"]):
+        for r in range(n2):
+            for k in range(b):
+                c, rr = divmod(int(pe[s, r, k]), n2)
+                assert (c, rr) == (s * (b + 1) + k, r)
+    assert np.all(mp["col_kind"][b::b + 1] == 1)
+    assert mp["col_kind"].sum() == mp["m"]
+
+
+def test_bad_dims_rejected():
+    for args in [(4, 10, 3), (0, 8, 3), (4, 8, 0), (4, 1, 1)]:
+        with pytest.raises(ValueError):
+            O.index_maps(*args)
+
+
+# ------------------------------------------------------------------- stencil (hand)
+
+def test_stencil_golden():
+    g = _golden("stencil_2x1.json")
+    p = O.make_problem(np.array(g["kappa"], float), g["n2"], g["n1"], g["b"], g["h"])
+    np.testing.assert_allclose(p.A.toarray(), np.array(g["A"], float), rtol=0, atol=1e-12)
+    fac = O.factor(p)
+    np.testing.assert_allclose(fac.s1.T_diag[0][0, 0], g["T00"], rtol=1e-15)
+    u = O.solve(fac, np.array(g["f"], float).reshape(1, 2, 1))
+    np.testing.assert_allclose(u.reshape(-1), g["u"], rtol=1e-14)
+
+
+def test_stencil_entries_against_loops():
+    """Edge weights and A against a pure-Python loop over nodes and neighbours."""
+    n2, n1, b = 3, 4, 1
+    h = 0.3
+    kap = G.kappa_lognormal(n2, n1, 5, h)
+    p = O.make_problem(kap, n2, n1, b, h)
+    A = np.zeros((n1 * n2, n1 * n2))
+    for c in range(n1):
+        for r in range(n2):
+            pidx = c * n2 + r
+            for dc, dr in ((-1, 0), (1, 0), (0, -1), (0, 1)):
+                cq, rq = c + dc, r + dr
+                w = (kap[c + 1, r + 1] + kap[cq + 1, rq + 1]) / (2 * h * h)
+                A[pidx, pidx] += w
+                if 0 <= cq < n1 and 0 <= rq < n2:
+                    A[pidx, cq * n2 + rq] -= w
+    np.testing.assert_allclose(p.A.toarray(), A, rtol=1e-15, atol=0)
+
+
+# ------------------------------------------------------------- P1 brute force
+
+CASES = [(1, 4, 1, 2), (2, 6, 2, 2), (3, 8, 3, 2), (5, 8, 1, 4), (8, 16, 7, 2),
+         (16, 24, 7, 3), (16, 12, 2, 4), (5, 4, 3, 1)]
+
+
+@pytest.mark.parametrize("n2,n1,b,m", [(c[0], c[1], c[2], c[3]) for c in CASES])
+def test_brute_force(n2, n1, b, m):
+    assert n1 // (b + 1) == m
+    kap = G.kappa_lognormal(n2, n1, 7)
+    p = O.make_problem(kap, n2, n1, b)
+    A = p.A.toarray()
+    nrhs = 3
+    f = G.rhs_uniform(n2, n1, nrhs, 11)
+    F = f.reshape(nrhs, -1).T
+    fac = O.factor(p)
+    # u
+    u_ref = np.linalg.solve(A, F).T.reshape(f.shape)
+    u = O.solve(fac, f)
+    assert np.abs(u - u_ref).max() <= 1e-13 * np.abs(u_ref).max()
+    # T as the dense Schur complement of all slab interiors
+    e, o = p.maps["perm_even"], p.maps["perm_odd"]
+    Aee, Aeo, Aoe, Aoo = A[np.ix_(e, e)], A[np.ix_(e, o)], A[np.ix_(o, e)], A[np.ix_(o, o)]
+    T_ref = Aoo - Aoe @ np.linalg.solve(Aee, Aeo)
+    T = _dense_T(fac)
+    assert np.abs(T - T_ref).max() <= 1e-13 * np.abs(T_ref).max()
+    # reduced right-hand side f~ = f_o - A_oe A_ee^-1 f_e  (eqs. (f1)-(f5))
+    ft_ref = (F[o] - Aoe @ np.linalg.solve(Aee, F[e])).T.reshape(nrhs, m, n2)
+    ft = O.reduced_rhs(p, fac.s1, f)
+    assert np.abs(ft - ft_ref).max() <= 1e-13 * np.abs(ft_ref).max()
+    # S_j: Schur complement of the leading j blocks of T onto block j (Alg. 1)
+    for j in range(m):
+        sl = slice(j * n2, (j + 1) * n2)
+        if j == 0:
+            S_ref = T_ref[sl, sl]
+        else:
+            lead = slice(0, j * n2)
+            S_ref = T_ref[sl, sl] - T_ref[sl, lead] @ np.linalg.solve(T_ref[lead, lead], T_ref[lead, sl])
+        assert np.abs(fac.s2.S[j] - S_ref).max() <= 1e-12 * np.abs(S_ref).max()
+
+
+# ------------------------------------------------------- P2 closed-form T, kappa = 1
+
+def _cheb_u(k, x):
+    """Chebyshev polynomial of the second kind by its three-term recurrence."""
+    u_prev, u = np.ones_like(x), 2 * x
+    if k == 0:
+        return u_prev
+    for _ in range(k - 1):
+        u_prev, u = u, 2 * x * u - u_prev
+    return u
+
+
+def _dst_q(n):
+    i = np.arange(1, n + 1)
+    return np.sqrt(2.0 / (n + 1)) * np.sin(np.pi * np.outer(i, i) / (n + 1))
+
+
+@pytest.mark.parametrize("n2,n1,b", [(64, 64, 7), (9, 12, 2), (33, 40, 3), (20, 16, 1)])
+def test_closed_form_T_poisson(n2, n1, b):
+    """kappa = 1: each sine mode of the interface decouples; the slab becomes a
+    tridiagonal Toeplitz matrix tridiag(-1, a_k, -1) of order b whose inverse's
+    corner entries are U_{b-1}(a/2)/U_b(a/2) and 1/U_b(a/2)."""
+    h = 1.0 / (n2 + 1)
+    p = O.make_problem(G.kappa_const(n2, n1), n2, n1, b, h)
+    fac = O.factor(p)
+    m = p.m
+    Q = _dst_q(n2)
+    a = 4 - 2 * np.cos(np.pi * np.arange(1, n2 + 1) / (n2 + 1))
+    ub = _cheb_u(b, a / 2)
+    ub1 = _cheb_u(b - 1, a / 2)
+    both = Q @ np.diag(a - 2 * ub1 / ub) @ Q / h ** 2
+    last = Q @ np.diag(a - ub1 / ub) @ Q / h ** 2
+    off = -Q @ np.diag(1 / ub) @ Q / h ** 2
+    scale = np.abs(both).max()
+    for j in range(m):
+        ref = both if j < m - 1 else last
+        assert np.abs(fac.s1.T_diag[j] - ref).max() <= 1e-13 * scale
+    for j in range(m - 1):
+        assert np.abs(fac.s1.T_up[j] - off).max() <= 1e-13 * scale
+        assert np.abs(fac.s1.T_lo[j] - off).max() <= 1e-13 * scale
+
+
+# ------------------------------------------------------------ P3 fast Poisson
+
+@pytest.mark.parametrize("n2,n1,b", [(64, 64, 7), (48, 96, 15), (31, 30, 4)])
+def test_fast_poisson(n2, n1, b):
+    h = 1.0 / (n2 + 1)
+    p = O.make_problem(G.kappa_const(n2, n1), n2, n1, b, h)
+    f = G.rhs_uniform(n2, n1, 2, 3)
+    k1 = np.arange(1, n1 + 1)[:, None]
+    k2 = np.arange(1, n2 + 1)[None, :]
+    lam = (4 - 2 * np.cos(np.pi * k1 / (n1 + 1)) - 2 * np.cos(np.pi * k2 / (n2 + 1))) / h ** 2
+    u_ref = np.stack([scipy.fft.idstn(scipy.fft.dstn(fi, type=1, norm="ortho") / lam,
+                                      type=1, norm="ortho") for fi in f])
+    u = O.solve(O.factor(p), f)
+    assert np.abs(u - u_ref).max() <= 1e-12 * np.abs(u_ref).max()
+
+
+# ------------------------------------------------------ P4 interface identity
+
+def test_interface_identity():
+    n2, n1, b = 40, 48, 7
+    p = O.make_problem(G.kappa_lognormal(n2, n1, 2), n2, n1, b)
+    f = G.rhs_uniform(n2, n1, 2, 9)
+    fac = O.factor(p)
+    ft = O.reduced_rhs(p, fac.s1, f)
+    uo = O.sweeping_solve(fac.s1, fac.s2, ft)
+    u_ref = O.direct_solve(p, f)
+    uo_ref = O.interface_values(u_ref, p)
+    assert np.abs(uo - uo_ref).max() <= 1e-12 * np.abs(uo_ref).max()
+
+
+# -------------------------------------------------- P5 SPD / M-matrix invariants
+
+@pytest.mark.parametrize("seed", [0, 4])
+def test_spd_m_matrix(seed):
+    n2, n1, b = 24, 40, 4
+    p = O.make_problem(G.kappa_lognormal(n2, n1, seed), n2, n1, b)
+    fac = O.factor(p)
+    T = _dense_T(fac)
+    assert np.abs(T - T.T).max() <= 1e-12 * np.abs(T).max()
+    np.linalg.cholesky(T)
+    off = T - np.diag(np.diag(T))
+    assert off.max() <= 1e-12 * np.abs(T).max()
+    assert (T.sum(axis=1) >= -1e-9 * np.abs(T).max()).all()
+    for S in fac.s2.S:
+        assert np.abs(S - S.T).max() <= 1e-11 * np.abs(S).max()
+        np.linalg.cholesky(S)
+        offS = S - np.diag(np.diag(S))
+        assert offS.max() <= 1e-11 * np.abs(S).max()
+    # no coupling beyond neighbouring interfaces
+    n = n2
+    assert np.abs(T[:n, 2 * n:]).max() == 0.0
+
+
+# ------------------------------------------------- P6 rank property (Prop. 1)
+
+def _num_rank(M, rel=1e-14):
+    s = np.linalg.svd(M, compute_uv=False)
+    return int((s > rel * s[0]).sum()) if s[0] > 0 else 0
+
+
+@pytest.mark.parametrize("b", [1, 2, 3])
+def test_rank_property(b):
+    """Sparse part removed, a contiguous row block J_B against the rest J_F of an
+    interface has rank <= 2b per adjacent slab; the coupling block T_{j,j+1}
+    (one slab) has rank <= 2b.  The bound is reached for small b."""
+    n2 = 40
+    n1 = 3 * (b + 1)
+    p = O.make_problem(G.kappa_lognormal(n2, n1, 1), n2, n1, b)
+    fac = O.factor(p)
+    B = np.arange(12, 24)
+    F = np.setdiff1d(np.arange(n2), B)
+    # interface 0 touches slabs 0 and 1, interface m-1 only slab m-1
+    for j, nslabs in ((0, 2), (p.m - 1, 1)):
+        schur = fac.s1.T_diag[j] - p.block(p.I_o(j), p.I_o(j)).toarray()
+        r = _num_rank(schur[np.ix_(F, B)])
+        assert r == 2 * b * nslabs
+    r = _num_rank(fac.s1.T_up[0][np.ix_(F, B)])
+    assert r == 2 * b
+
+
+# ------------------------------------------------ P7 manufactured solution
+
+def _manufactured():
+    """u* = sin(pi x) sin(pi y), kappa = exp(sin(2 pi x) cos(2 pi y) / 2) on the
+    unit square; f = -div(kappa grad u*) differentiated symbolically."""
+    import sympy as sy
+    x, y = sy.symbols("x y")
+    us = sy.sin(sy.pi * x) * sy.sin(sy.pi * y)
+    ks = sy.exp(sy.Rational(1, 2) * sy.sin(2 * sy.pi * x) * sy.cos(2 * sy.pi * y))
+    fs = -(sy.diff(ks * sy.diff(us, x), x) + sy.diff(ks * sy.diff(us, y), y))
+    return [sy.lambdify((x, y), e, "numpy") for e in (us, ks, fs)]
+
+
+@pytest.mark.parametrize("b", [3, 7])
+def test_second_order_convergence(b):
+    u_f, k_f, f_f = _manufactured()
+    errs = []
+    for n in (32, 64, 128):
+        assert n % (b + 1) == 0
+        h = 1.0 / (n + 1)                      # square: (n1 + 1) h = (n2 + 1) h = 1
+        xs = np.arange(n + 2) * h
+        X, Y = np.meshgrid(xs, xs, indexing="ij")
+        p = O.make_problem(k_f(X, Y), n, n, b, h)
+        Xi, Yi = X[1:-1, 1:-1], Y[1:-1, 1:-1]
+        u = O.solve(O.factor(p), f_f(Xi, Yi)[None])[0]
+        errs.append(np.abs(u - u_f(Xi, Yi)).max())
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(orders > 1.85) and np.all(orders < 2.15), (errs, orders)
+
+
+# ------------------------------------------------------------- P8 n2 = 1
+
+@pytest.mark.parametrize("n1,b", [(12, 2), (16, 3), (8, 1)])
+def test_one_dimensional(n1, b):
+    """n2 = 1, kappa = 1: A = tridiag(-1, 4, -1)/h^2 along the columns (two ring
+    edges per node vertically); compare u with the closed-form 1-D inverse and T
+    with the scalar Schur complement of a chain."""
+    h = 0.5
+    p = O.make_problem(G.kappa_const(1, n1), 1, n1, b, h)
+    fac = O.factor(p)
+    # 1-D matrix M = tridiag(-1, 4, -1)/h^2: Chebyshev form of the inverse
+    a = 4.0
+    Ua = [_cheb_u(k, np.array(a / 2)) for k in range(n1 + 1)]
+    Minv = np.zeros((n1, n1))
+    for i in range(n1):
+        for j in range(n1):
+            lo, hi = min(i, j), max(i, j)
+            Minv[i, j] = Ua[lo] * Ua[n1 - 1 - hi] / Ua[n1] * h * h
+    f = G.rhs_uniform(1, n1, 1, 4)
+    u = O.solve(fac, f)
+    np.testing.assert_allclose(u.reshape(-1), Minv @ f.reshape(-1), rtol=1e-13, atol=1e-15)
+    # T: a slab of b nodes between two interfaces is tridiag(-1, 4, -1) of order b
+    ub, ub1 = Ua[b], Ua[b - 1]
+    for j in range(p.m):
+        ref = (4 - 2 * ub1 / ub) if j < p.m - 1 else (4 - ub1 / ub)
+        np.testing.assert_allclose(fac.s1.T_diag[j][0, 0] * h * h, ref, rtol=1e-14)
+    for j in range(p.m - 1):
+        np.testing.assert_allclose(fac.s1.T_up[j][0, 0] * h * h, -1 / ub, rtol=1e-14)
+
+
+# ------------------------------------------------------------ P9 adjoint
+
+def test_adjoint_symmetric_and_duality():
+    n2, n1, b = 20, 24, 3
+    p = O.make_problem(G.kappa_lognormal(n2, n1, 3), n2, n1, b)
+    f = G.rhs_uniform(n2, n1, 2, 1)
+    g = G.rhs_normal(n2, n1, 2, 2)
+    fac = O.factor(p)
+    u = O.solve(fac, f)
+    lam = O.solve_adjoint(p, g)
+    assert np.abs(lam - O.solve(fac, g)).max() <= 1e-13 * np.abs(lam).max()
+    lhs = np.sum(u * g)
+    rhs = np.sum(f * lam)
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def test_adjoint_transposes_nonsymmetric():
+    """The transpose path really uses A^T: on a non-symmetric operator with the
+    same 5-point pattern it must agree with a sparse solve of A^T."""
+    import scipy.sparse as sp
+    n2, n1, b = 9, 12, 2
+    p = O.make_problem(G.kappa_lognormal(n2, n1, 8), n2, n1, b)
+    rng = np.random.default_rng(0)
+    A = p.A.tocoo()
+    vals = A.data * np.where(A.row != A.col, 1 + 0.3 * rng.uniform(-1, 1, A.nnz), 1.0)
+    p.A = sp.csr_matrix((vals, (A.row, A.col)), shape=A.shape)
+    g = G.rhs_normal(n2, n1, 2, 5)
+    lam = O.solve_adjoint(p, g)
+    ref = spla.spsolve(p.A.T.tocsc(), g.reshape(2, -1).T).T.reshape(g.shape)
+    assert np.abs(lam - ref).max() <= 1e-12 * np.abs(ref).max()
+    u = O.solve(O.factor(p), g)
+    ref_u = spla.spsolve(p.A.tocsc(), g.reshape(2, -1).T).T.reshape(g.shape)
+    assert np.abs(u - ref_u).max() <= 1e-12 * np.abs(ref_u).max()
+    assert np.abs(u - lam).max() > 1e-6 * np.abs(ref).max()
+
+
+# ------------------------------------------------------------ P10 gradient
+
+def test_gradient_central_fd():
+    n2, n1, b = 16, 20, 3
+    h = 1.0 / (n2 + 1)
+    theta = G.grf(n2, n1, 10, h)
+    theta_obs = G.grf(n2, n1, 1, h)
+    f = G.rhs_uniform(n2, n1, 1, 6)
+    p_obs = O.make_problem(np.exp(theta_obs), n2, n1, b, h)
+    u_obs = O.solve(O.factor(p_obs), f)
+
+    def loss(th):
+        p = O.make_problem(np.exp(th), n2, n1, b, h)
+        u = O.solve(O.factor(p), f)
+        return 0.5 * np.sum((u - u_obs) ** 2), p, u
+
+    L0, p, u = loss(theta)
+    lam = O.solve_adjoint(p, u - u_obs)
+    grad = O.kappa_grad(p, u, lam)
+    rng = np.random.default_rng(G.SEED_FD_NODES)
+    nodes = [(int(rng.integers(1, n1 + 1)), int(rng.integers(1, n2 + 1))) for _ in range(16)]
+    # plus ring nodes, which enter through the boundary edges
+    nodes += [(0, 3), (n1 + 1, 5), (4, 0), (7, n2 + 1)]
+    eps = 1e-6
+    gmax = np.abs(grad).max()
+    for (i, j) in nodes:
+        tp = theta.copy(); tp[i, j] += eps
+        tm = theta.copy(); tm[i, j] -= eps
+        fd = (loss(tp)[0] - loss(tm)[0]) / (2 * eps)
+        assert abs(fd - grad[i, j]) <= 1e-5 * gmax, (i, j, fd, grad[i, j])
+    # corner ring nodes touch no edge
+    assert grad[0, 0] == 0 and grad[n1 + 1, n2 + 1] == 0
+
+
+# ------------------------------------------------------ cross-check vs SuperLU
+
+def test_superlu_crosscheck_lognormal():
+    n2, n1, b = 96, 128, 15
+    p = O.make_problem(G.kappa_lognormal(n2, n1, 0), n2, n1, b)
+    f = G.rhs_uniform(n2, n1, 2, 100)
+    u = O.solve(O.factor(p), f)
+    u_ref = O.direct_solve(p, f)
+    for k in range(2):
+        assert np.linalg.norm(u[k] - u_ref[k]) <= 1e-12 * np.linalg.norm(u_ref[k])
+    assert O.relres(p, u, f).max() <= 1e-12
