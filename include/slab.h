@@ -1,0 +1,158 @@
+/*
+ * slab.h -- C ABI of the MI355X slab solver (SlabLU hot path, dense-T variant).
+ *
+ * Solves A u = f (paper Sec. 1.1, eq. (Au=f)) for the 5-point discretization of
+ * -div(kappa grad u) = f on a uniform grid of n2 rows x n1 columns of interior
+ * nodes with homogeneous Dirichlet data on the ring around them (Sec. 2.1, eq.
+ * (discretization), generalised to a variable coefficient with the edge weight
+ * w_e = (kappa_p + kappa_q) / (2 h^2)).  The grid is cut into slabs of b
+ * interior columns separated by one-column interfaces (Sec. 2.2, Fig. 1): in
+ * every period of b+1 columns the first b columns are a slab interior and the
+ * last is an interface, so there are m = n1/(b+1) slabs and m interfaces.
+ *
+ *   slab_factor         Alg. 3: eliminate every slab interior (stage one,
+ *                       Sec. 3.1) and factor the block-tridiagonal reduced
+ *                       matrix T of n2 x n2 dense blocks (stage two, Alg. 1).
+ *   slab_solve          Alg. 4: reduced right-hand side (eqs. (f1)-(f5)), the
+ *                       sweeping solve (Alg. 2) and the interior back
+ *                       substitution (eq. (usol_even)); in mixed precision
+ *                       wrapped in FP64 iterative refinement.
+ *   slab_solve_adjoint  A^T lambda = g from the same stored factors, applied
+ *                       transposed.
+ *   slab_free           release a handle.
+ *
+ * Conventions shared by every entry point:
+ *   Layout   Vectors are stored in natural order, row index r fastest: entry
+ *            (k, c, r) of right-hand side k at column c, row r is at offset
+ *            k*ld + c*n2 + r with ld >= n1*n2 (torch shape (nrhs, n1, n2)).
+ *            The coefficient field covers the ring too: shape (n1+2, n2+2),
+ *            node (c, r) at (c+1)*(n2+2) + (r+1).
+ *   Memory   Pointers to vectors and fields are DEVICE pointers on the current
+ *            HIP device, owned by the caller and left untouched after the call
+ *            returns.  The handle owns every factor it allocates.
+ *   Streams  Work is issued on the given hipStream_t (NULL = default stream).
+ *            Every call returns only after its work has finished, because it
+ *            reports breakdown and convergence.
+ *   Errors   Every call returns a status; nothing throws across the ABI.  On
+ *            failure outputs are unspecified, the handle (if any) stays valid,
+ *            and slab_last_error() describes the failure (thread-local).
+ *            Argument checks run on the host before any HIP call.
+ *   Threads  A handle may be used by one thread / stream at a time.
+ */
+#ifndef SLAB_H_
+#define SLAB_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct slab_handle_s* slab_handle;
+
+/* status codes */
+#define SLAB_OK 0
+#define SLAB_E_INVALID (-1)   /* bad argument: sizes, null pointer, kappa <= 0 or non-finite */
+#define SLAB_E_NOMEM (-2)     /* device allocation failed */
+#define SLAB_E_BREAKDOWN (-3) /* zero, negative or non-finite pivot (matrix not SPD) */
+#define SLAB_E_NOCONV (-4)    /* refinement did not reach tol within max_iter */
+#define SLAB_E_HIP (-5)       /* a HIP runtime call failed */
+
+/* precision of the factorization */
+#define SLAB_FP64 0          /* every phase in FP64 */
+#define SLAB_FP32_REFINE 1   /* slab factors, T blocks and the block factorization in FP32;
+                                FP64 sum forming T, FP64 residual and update */
+
+/* option flags */
+#define SLAB_KEEP_REDUCED 1  /* keep FP64 copies of T and of every S_j (Alg. 1) for export */
+#define SLAB_COEF_LOG 2      /* the field passed is theta = log(kappa), not kappa */
+
+typedef struct {
+  int32_t n1;          /* interior columns (slab direction); n1 % (b+1) == 0, n1 >= 2 */
+  int32_t n2;          /* interior rows = interface length n; 1 <= n2 */
+  int32_t b;           /* interior columns per slab; 1 <= b <= 63 */
+  double h;            /* grid spacing, > 0 */
+  const double* kappa; /* device, (n1+2)*(n2+2) FP64, r fastest; > 0 and finite
+                          (or theta = log kappa, finite, with SLAB_COEF_LOG) */
+} slab_problem;
+
+typedef struct {
+  int32_t precision;   /* SLAB_FP64 or SLAB_FP32_REFINE */
+  double tol;          /* target max-over-columns ||f - A u||_2 / ||f||_2 (e.g. 1e-10) */
+  int32_t max_iter;    /* refinement iterations allowed (>= 1; FP64 uses at most this too) */
+  int32_t flags;       /* SLAB_KEEP_REDUCED | SLAB_COEF_LOG */
+} slab_options;
+
+typedef struct {
+  int32_t iterations;  /* solve passes performed */
+  double max_relres;   /* max over columns of the final relative residual (FP64) */
+  int32_t failed_block;/* factor: block index of a breakdown, else -1 */
+} slab_solve_info;
+
+/* Host-only check of the problem description and options (no HIP call).
+   Returns SLAB_OK or SLAB_E_INVALID. */
+int slab_check_problem(const slab_problem* prob, const slab_options* opts);
+
+/* Alg. 3 (factor).  prob->kappa is read during the call only.  On success
+   *out receives a new handle.  SLAB_E_INVALID for bad sizes or a coefficient
+   that is not positive and finite; SLAB_E_BREAKDOWN if a pivot block is not
+   positive definite (its interface index is in info->failed_block when info is
+   not NULL). */
+int slab_factor(const slab_problem* prob, const slab_options* opts, void* hip_stream,
+                slab_handle* out, slab_solve_info* info);
+
+/* Alg. 4 (solve) for nrhs right-hand sides f -> u (device FP64, natural order,
+   leading dimension ld).  f and u must not overlap.  Mixed precision refines
+   until the max relative residual is <= tol (else SLAB_E_NOCONV, u holds the
+   last iterate); FP64 refines only while above tol.  info may be NULL. */
+int slab_solve(slab_handle h, const double* f, double* u, int32_t nrhs, int64_t ld,
+               void* hip_stream, slab_solve_info* info);
+
+/* A^T lambda = g with the stored factors applied transposed (transposed slab
+   sweeps, transposed block-tridiagonal sweep).  Same conventions as slab_solve. */
+int slab_solve_adjoint(slab_handle h, const double* g, double* lam, int32_t nrhs, int64_t ld,
+                       void* hip_stream, slab_solve_info* info);
+
+/* Release the handle and its device memory (NULL is a no-op). */
+int slab_free(slab_handle h);
+
+/* ---- auxiliary entry points ---------------------------------------------- */
+
+/* Index maps of the clustering (Sec. 2.2): device int32 col_kind[n1] (1 for an
+   interface column), slab_of_col[n1] = c/(b+1), local_of_col[n1] = c%(b+1),
+   int64 perm_even[m*n2*b] (slab s, local r*b+k -> natural (s(b+1)+k)*n2 + r),
+   perm_odd[m*n2] (interface j, row r -> natural (j(b+1)+b)*n2 + r).
+   Any output pointer may be NULL to skip it. */
+int slab_index_maps(int32_t n1, int32_t n2, int32_t b, int32_t* col_kind, int32_t* slab_of_col,
+                    int32_t* local_of_col, int64_t* perm_even, int64_t* perm_odd, void* hip_stream);
+
+/* Gradient of a loss L(u) with respect to the coefficient, given u = A^-1 f and
+   lam = A^-T dL/du (nrhs columns each, summed): dL/dw_e = -(lam_p - lam_q)(u_p - u_q)
+   on every edge (ring values zero), dw_e/dkappa_p = 1/(2h^2).  mode 0 writes
+   dL/dkappa, mode 1 writes dL/dtheta = kappa dL/dkappa, on the (n1+2)*(n2+2)
+   field (device FP64). */
+int slab_kappa_grad(slab_handle h, const double* u, const double* lam, int32_t nrhs, int64_t ld,
+                    int32_t mode, double* grad, void* hip_stream);
+
+/* Per-column relative residual ||f - A u||_2/||f||_2 in FP64 (relerr_res of
+   Sec. 5.1); relres is a HOST array of nrhs doubles. */
+int slab_residual(slab_handle h, const double* f, const double* u, int32_t nrhs, int64_t ld,
+                  double* relres, void* hip_stream);
+
+/* Export a reduced block as FP64 n2 x n2 row-major into device memory out:
+   which = 0: T_jj, 1: T_{j,j+1} (j < m-1), 2: S_j of Alg. 1 before its
+   factorization.  Needs SLAB_KEEP_REDUCED at factor time. */
+int slab_export_reduced(slab_handle h, int32_t which, int32_t j, double* out, void* hip_stream);
+
+/* Sizes and timings of a handle: what = 0 m, 1 n1, 2 n2, 3 b, 4 precision,
+   5 device bytes held, 10+p elapsed microseconds of factor phase p
+   (0 weights, 1 slab factor, 2 Schur formation, 3 assembly, 4 block factor). */
+int slab_query(slab_handle h, int32_t what, int64_t* value);
+
+/* Message of the last failure on this thread ("" if none). */
+const char* slab_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SLAB_H_ */

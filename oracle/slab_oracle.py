@@ -250,6 +250,41 @@ class StageOne:
     T_lo: list             # T_{j+1,j}, j = 0..m-2
 
 
+def slab_contributions(prob: Problem, s: int, factor: "SlabFactor | None" = None,
+                       transpose: bool = False) -> dict:
+    """Schur-complement pieces that slab s (I_{2s}) adds to the reduced blocks.
+
+    Returns {(jr, jc): C} with C = A_{o(jr),2s} A_{2s,2s}^-1 A_{2s,o(jc)} for the
+    interfaces jr, jc in {s-1, s} that exist (eq. (T11_detailed)).
+    """
+    A = prob.A.T.tocsr() if transpose else prob.A
+    Ie = prob.I_e(s)
+    if factor is None:
+        factor = SlabFactor(A[Ie][:, Ie], prob.b)
+    nbrs = [j for j in (s - 1, s) if 0 <= j < prob.m]
+    out = {}
+    for jc in nbrs:
+        X = factor.solve(A[Ie][:, prob.I_o(jc)].toarray())     # A_{2s,2s}^-1 A_{2s, o(jc)}
+        for jr in nbrs:
+            out[(jr, jc)] = A[prob.I_o(jr)][:, Ie] @ X
+    return out
+
+
+def interface_blocks(prob: Problem, j: int) -> tuple:
+    """T_jj and (for j < m-1) T_{j,j+1} from the two slabs touching interface j only."""
+    A = prob.A
+    Tjj = A[prob.I_o(j)][:, prob.I_o(j)].toarray()
+    Tup = None
+    for s in (j, j + 1):
+        if s >= prob.m:
+            continue
+        C = slab_contributions(prob, s)
+        Tjj -= C[(j, j)]
+        if s == j + 1:
+            Tup = A[prob.I_o(j)][:, prob.I_o(j + 1)].toarray() - C[(j, j + 1)]
+    return Tjj, Tup
+
+
 def stage_one(prob: Problem, transpose: bool = False) -> StageOne:
     """Eliminate every slab interior and form the block-tridiagonal T (eq. (dell3)).
 
@@ -263,33 +298,23 @@ def stage_one(prob: Problem, transpose: bool = False) -> StageOne:
     corresponding block of A^T, which gives the reduced system of A^T.
     """
     A = prob.A.T.tocsr() if transpose else prob.A
-    m, n2 = prob.m, prob.n2
+    m = prob.m
 
     def blk(I, J):
         return A[I][:, J]
 
-    factors = []
-    for s in range(m):
-        factors.append(SlabFactor(blk(prob.I_e(s), prob.I_e(s)), prob.b))
+    factors = [SlabFactor(blk(prob.I_e(s), prob.I_e(s)), prob.b) for s in range(m)]
     T_diag = [blk(prob.I_o(j), prob.I_o(j)).toarray() for j in range(m)]
     T_up = [blk(prob.I_o(j), prob.I_o(j + 1)).toarray() for j in range(m - 1)]
     T_lo = [blk(prob.I_o(j + 1), prob.I_o(j)).toarray() for j in range(m - 1)]
     for s in range(m):
-        Ie = prob.I_e(s)
-        fac = factors[s]
-        # interfaces touching slab s: j = s-1 (left) and j = s (right)
-        nbrs = [j for j in (s - 1, s) if 0 <= j < m]
-        for jc in nbrs:
-            Aeo = blk(Ie, prob.I_o(jc)).toarray()
-            X = fac.solve(Aeo)                     # A_{2s,2s}^-1 A_{2s, o(jc)}
-            for jr in nbrs:
-                C = blk(prob.I_o(jr), Ie) @ X      # A_{o(jr),2s} A_{2s,2s}^-1 A_{2s,o(jc)}
-                if jr == jc:
-                    T_diag[jr] -= C
-                elif jc == jr + 1:
-                    T_up[jr] -= C
-                else:
-                    T_lo[jc] -= C
+        for (jr, jc), C in slab_contributions(prob, s, factors[s], transpose).items():
+            if jr == jc:
+                T_diag[jr] -= C
+            elif jc == jr + 1:
+                T_up[jr] -= C
+            else:
+                T_lo[jc] -= C
     return StageOne(factors, T_diag, T_up, T_lo)
 
 

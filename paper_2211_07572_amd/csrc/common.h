@@ -1,0 +1,89 @@
+// Shared definitions of the slab solver's HIP sources (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include <string>
+
+// ---------------------------------------------------------------------------
+// Error reporting (thread-local message, status codes of slab.h).
+// ---------------------------------------------------------------------------
+namespace slab {
+
+void set_error(const std::string& msg);
+
+#define SLAB_HIP_CHECK(expr)                                                   \
+  do {                                                                         \
+    hipError_t e_ = (expr);                                                    \
+    if (e_ != hipSuccess) {                                                    \
+      ::slab::set_error(std::string(#expr " failed: ") + hipGetErrorString(e_)); \
+      return SLAB_E_HIP;                                                       \
+    }                                                                          \
+  } while (0)
+
+// Launch-error check after a kernel launch.
+#define SLAB_LAUNCH_CHECK()                                                    \
+  do {                                                                         \
+    hipError_t e_ = hipGetLastError();                                         \
+    if (e_ != hipSuccess) {                                                    \
+      ::slab::set_error(std::string("kernel launch failed at ") + __FILE__ +    \
+                        ":" + std::to_string(__LINE__) + ": " +                 \
+                        hipGetErrorString(e_));                                \
+      return SLAB_E_HIP;                                                       \
+    }                                                                          \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// MFMA 16x16x4 wrappers.  One wave computes D(16x16) += A(16x4) B(4x16):
+//   lane l supplies A[l%16][l/16] and B[l/16][l%16];
+//   lane l = 16 g + c holds D[acc_row(g, i)][c] in accumulator element i, with
+//   acc_row(g, i) = 4 g + i for the FP32 instruction and g + 4 i for the FP64
+//   instruction (measured on gfx950: the FP64 result rows are interleaved).
+// ---------------------------------------------------------------------------
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct acc4;
+template <> struct acc4<double> { typedef d4 type; };
+template <> struct acc4<float> { typedef f4 type; };
+
+__device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfma16(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <typename T> __host__ __device__ __forceinline__ int acc_row(int g, int i);
+template <> __host__ __device__ __forceinline__ int acc_row<float>(int g, int i) { return 4 * g + i; }
+template <> __host__ __device__ __forceinline__ int acc_row<double>(int g, int i) { return g + 4 * i; }
+// Inverse of acc_row within a 16-row tile: lane group and element holding row r16.
+template <typename T> __host__ __device__ __forceinline__ int acc_group(int r16);
+template <typename T> __host__ __device__ __forceinline__ int acc_elem(int r16);
+template <> __host__ __device__ __forceinline__ int acc_group<float>(int r16) { return r16 >> 2; }
+template <> __host__ __device__ __forceinline__ int acc_elem<float>(int r16) { return r16 & 3; }
+template <> __host__ __device__ __forceinline__ int acc_group<double>(int r16) { return r16 & 3; }
+template <> __host__ __device__ __forceinline__ int acc_elem<double>(int r16) { return r16 >> 2; }
+
+// Padded slab-block order: BP in {16, 32, 64} >= b.
+inline int padded_block(int b) { return b <= 16 ? 16 : (b <= 32 ? 32 : 64); }
+
+// Position of element (row, col) of a BP x BP propagator in the fragment-major
+// layout read by the Schur kernel.  Fragment (mt, ks) for ks = 4*mt2 + i holds,
+// in lane l = 16 g + n, the element (16 mt + n, 16 mt2 + acc_row(g, i)); the
+// k index is permuted so that an MFMA result can be fed back as the next
+// step's B operand without moving data between lanes.
+template <typename T>
+__host__ __device__ __forceinline__ int swz_index(int row, int col, int BP) {
+  const int NK = BP / 4;
+  const int mt = row >> 4, n = row & 15;
+  const int mt2 = col >> 4, g = acc_group<T>(col & 15), i = acc_elem<T>(col & 15);
+  const int ks = 4 * mt2 + i;
+  return (mt * NK + ks) * 64 + 16 * g + n;
+}
+
+inline unsigned int ceil_div(long long a, long long b) { return (unsigned int)((a + b - 1) / b); }
+
+}  // namespace slab

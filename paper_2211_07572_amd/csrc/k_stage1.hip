@@ -1,0 +1,499 @@
+// Stage one of the slab solver: edge weights, index maps, slab factorizations
+// (two-sided block recursion), the boundary columns of each slab inverse, the
+// Schur-complement propagation on MFMA, and assembly of the reduced blocks T.
+//
+// Paper: Sec. 2 (discretization, clustering), Sec. 3.1 (Schur complements,
+// eqs. (dell1)-(T35)), Alg. 3 (first loop: factor every slab interior).
+#include "launch.h"
+
+namespace slab {
+
+// ---------------------------------------------------------------------------
+// Coefficient field: copy (or exponentiate theta) and check positivity.
+// status[0] is set to 1 when some kappa is not > 0 or not finite.
+// ---------------------------------------------------------------------------
+__global__ void k_coef(const double* __restrict__ coef, long long count, int is_log,
+                       double* __restrict__ kappa, int* __restrict__ status) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count;
+       i += (long long)gridDim.x * blockDim.x) {
+    double v = coef[i];
+    double k = is_log ? exp(v) : v;
+    if (!(k > 0.0) || !isfinite(k)) status[0] = 1;
+    kappa[i] = k;
+  }
+}
+
+// Edge weights w = (kappa_p + kappa_q) / (2 h^2) of the 5-point stencil.
+// wh[c*n2 + r], c = 0..n1: edge (c-1, r)-(c, r); wv[c*(n2+1) + r], r = 0..n2:
+// edge (c, r-1)-(c, r).  Columns/rows -1 and n1/n2 are the Dirichlet ring.
+__global__ void k_weights(const double* __restrict__ kappa, int n1, int n2, double h,
+                          double* __restrict__ wh, double* __restrict__ wv) {
+  const long long nh = (long long)(n1 + 1) * n2;
+  const long long nv = (long long)n1 * (n2 + 1);
+  const long long ld = n2 + 2;
+  const double hh = h * h;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < nh + nv;
+       i += (long long)gridDim.x * blockDim.x) {
+    if (i < nh) {
+      long long c = i / n2, r = i % n2;  // edge between ring-padded columns c and c+1
+      wh[i] = 0.5 * (kappa[c * ld + r + 1] + kappa[(c + 1) * ld + r + 1]) / hh;
+    } else {
+      long long j = i - nh;
+      long long c = j / (n2 + 1), r = j % (n2 + 1);
+      wv[j] = 0.5 * (kappa[(c + 1) * ld + r] + kappa[(c + 1) * ld + r + 1]) / hh;
+    }
+  }
+}
+
+int launch_coef_weights(const double* coef, int is_log, int n1, int n2, double h, double* kappa,
+                        double* wh, double* wv, int* status, hipStream_t st) {
+  long long count = (long long)(n1 + 2) * (n2 + 2);
+  unsigned grid = (unsigned)std::min<long long>((count + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_coef, dim3(grid), dim3(256), 0, st, coef, count, is_log, kappa, status);
+  SLAB_LAUNCH_CHECK();
+  long long tot = (long long)(n1 + 1) * n2 + (long long)n1 * (n2 + 1);
+  grid = (unsigned)std::min<long long>((tot + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_weights, dim3(grid), dim3(256), 0, st, kappa, n1, n2, h, wh, wv);
+  SLAB_LAUNCH_CHECK();
+  return SLAB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Index maps of the clustering (Sec. 2.2).
+// ---------------------------------------------------------------------------
+__global__ void k_maps(int n1, int n2, int b, int32_t* col_kind, int32_t* slab_of_col,
+                       int32_t* local_of_col, int64_t* perm_even, int64_t* perm_odd) {
+  const int m = n1 / (b + 1);
+  const long long ne = (long long)m * n2 * b;
+  const long long no = (long long)m * n2;
+  const long long tot = n1 + ne + no;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < tot;
+       i += (long long)gridDim.x * blockDim.x) {
+    if (i < n1) {
+      int c = (int)i;
+      if (col_kind) col_kind[c] = (c % (b + 1) == b) ? 1 : 0;
+      if (slab_of_col) slab_of_col[c] = c / (b + 1);
+      if (local_of_col) local_of_col[c] = c % (b + 1);
+    } else if (i < n1 + ne) {
+      long long e = i - n1;
+      long long s = e / ((long long)n2 * b);
+      long long rem = e % ((long long)n2 * b);
+      long long r = rem / b, k = rem % b;
+      if (perm_even) perm_even[e] = (s * (b + 1) + k) * n2 + r;
+    } else {
+      long long o = i - n1 - ne;
+      long long j = o / n2, r = o % n2;
+      if (perm_odd) perm_odd[o] = (j * (b + 1) + b) * n2 + r;
+    }
+  }
+}
+
+int launch_maps(int n1, int n2, int b, int32_t* ck, int32_t* sc, int32_t* lc, int64_t* pe,
+                int64_t* po, hipStream_t st) {
+  const int m = n1 / (b + 1);
+  long long tot = n1 + (long long)m * n2 * b + (long long)m * n2;
+  unsigned grid = (unsigned)std::min<long long>((tot + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_maps, dim3(grid), dim3(256), 0, st, n1, n2, b, ck, sc, lc, pe, po);
+  SLAB_LAUNCH_CHECK();
+  return SLAB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Row `lane` of the slab block D_r (b x b, tridiagonal: one grid row of a slab
+// interior, b-fastest local order), padded to BP with identity rows.
+// ---------------------------------------------------------------------------
+template <typename T, int BP>
+__device__ __forceinline__ void build_D_row(T (&a)[BP], const double* __restrict__ wh,
+                                            const double* __restrict__ wv, int n2, int b, int c0,
+                                            int r, int lane) {
+  const bool act = lane < b;
+  double d = 1.0, wl = 0.0, wr = 0.0;
+  if (act) {
+    const long long c = c0 + lane;
+    d = wh[c * n2 + r] + wh[(c + 1) * n2 + r] + wv[c * (n2 + 1) + r] + wv[c * (n2 + 1) + r + 1];
+    if (lane > 0) wl = wh[c * n2 + r];
+    if (lane < b - 1) wr = wh[(c + 1) * n2 + r];
+  }
+#pragma unroll
+  for (int k = 0; k < BP; ++k) {
+    double v = (k == lane) ? d : ((k == lane - 1) ? -wl : ((k == lane + 1) ? -wr : 0.0));
+    a[k] = (T)v;
+  }
+}
+
+// Symmetric sweep operator over all pivots: on return a (row `lane`) holds
+// row `lane` of -M^{-1}.  Row-per-lane; the pivot column is exchanged through
+// LDS (by symmetry it equals the pivot row).  Returns false on a pivot that is
+// not positive and finite.
+template <typename T, int BP>
+__device__ __forceinline__ bool sweep_inverse(T (&a)[BP], T (*colbuf)[BP], int lane) {
+  bool ok = true;
+#pragma unroll
+  for (int p = 0; p < BP; ++p) {
+    if (lane < BP) colbuf[p & 1][lane] = a[p];
+    __syncthreads();
+    const T d = colbuf[p & 1][p];
+    ok = ok && (d > (T)0) && isfinite((double)d);
+    const T inv = (T)1 / d;
+    if (lane == p) {
+#pragma unroll
+      for (int k = 0; k < BP; ++k) a[k] = colbuf[p & 1][k] * inv;
+      a[p] = -inv;
+    } else {
+      const T f = a[p] * inv;
+#pragma unroll
+      for (int k = 0; k < BP; ++k) a[k] -= f * colbuf[p & 1][k];
+      a[p] = f;
+    }
+  }
+  return ok;
+}
+
+// ---------------------------------------------------------------------------
+// Slab factorization (Alg. 3 first loop), block-tridiagonal form of the banded
+// slab matrix A_{2s,2s}: diagonal blocks D_r, couplings A_{r,r-1} = -W_r with
+// W_r = diag of the vertical edge weights between grid rows r-1 and r.
+//   top-down  (dir 0):  Dl_0 = D_0,        Dl_r = D_r - W_r Gl_{r-1} W_r,    Gl_r = Dl_r^-1
+//   bottom-up (dir 1):  Dr_{n-1} = D_{n-1}, Dr_r = D_r - W_{r+1} Gr_{r+1} W_{r+1}
+// Stored: Gl_r row-major (block solves), Hr_r = Gr_r W_r in fragment-major
+// order (Schur propagation).  One wave per (slab, direction).
+// ---------------------------------------------------------------------------
+template <typename T, int BP>
+__global__ __launch_bounds__(64) void k_slab_factor(const double* __restrict__ wh,
+                                                    const double* __restrict__ wv, int n2, int b,
+                                                    T* __restrict__ Gl, T* __restrict__ Hsw,
+                                                    int* __restrict__ status) {
+  const int s = blockIdx.x >> 1, dir = blockIdx.x & 1;
+  const int lane = threadIdx.x;
+  const int c0 = s * (b + 1);
+  const long long c = c0 + (lane < b ? lane : 0);
+  __shared__ T colbuf[2][BP];
+  __shared__ T wsh[BP];
+  T g[BP];
+  T a[BP];
+#pragma unroll
+  for (int k = 0; k < BP; ++k) g[k] = (T)0;
+  bool ok = true;
+  for (int t = 0; t < n2; ++t) {
+    const int r = dir == 0 ? t : n2 - 1 - t;
+    T wc = (T)0;  // coupling to the previously processed grid row
+    if (t > 0 && lane < b) wc = (T)(dir == 0 ? wv[c * (n2 + 1) + r] : wv[c * (n2 + 1) + r + 1]);
+    if (lane < BP) wsh[lane] = wc;
+    __syncthreads();
+    build_D_row<T, BP>(a, wh, wv, n2, b, c0, r, lane);
+#pragma unroll
+    for (int k = 0; k < BP; ++k) a[k] -= wc * g[k] * wsh[k];
+    ok = sweep_inverse<T, BP>(a, colbuf, lane) && ok;
+#pragma unroll
+    for (int k = 0; k < BP; ++k) g[k] = -a[k];
+    if (dir == 0) {
+      if (lane < BP) {
+        T* dst = Gl + (((size_t)s * n2 + r) * BP + lane) * BP;
+#pragma unroll
+        for (int k = 0; k < BP; ++k) dst[k] = g[k];
+      }
+    } else {
+      // Hr_r = Gr_r W_r: scale column k by the edge between rows r-1 and r.
+      T wup = (T)0;
+      if (lane < b) wup = (T)wv[c * (n2 + 1) + r];
+      __syncthreads();
+      if (lane < BP) wsh[lane] = wup;
+      __syncthreads();
+      if (lane < BP) {
+        T* dst = Hsw + ((size_t)s * n2 + r) * BP * BP;
+#pragma unroll
+        for (int k = 0; k < BP; ++k) dst[swz_index<T>(lane, k, BP)] = g[k] * wsh[k];
+      }
+    }
+    __syncthreads();
+  }
+  if (!ok && lane == 0) { status[0] = 2; status[1] = s; }
+}
+
+// ---------------------------------------------------------------------------
+// Boundary columns of the diagonal block of each slab inverse:
+//   Sigma_rho = (D_rho - W_rho Gl_{rho-1} W_rho - W_{rho+1} Gr_{rho+1} W_{rho+1})^-1,
+// columns k = 0 (left, next to interface s-1) and k = b-1 (right, next to
+// interface s), pre-scaled by the interface edge weights:
+//   sig[s][rho][0] = wL_rho Sigma_rho[:, 0],  sig[s][rho][1] = wR_rho Sigma_rho[:, b-1].
+// These start the downward propagation (Sec. 3.1, eq. (T11_detailed)).
+// Four waves per block, one (slab, rho) per wave.
+// ---------------------------------------------------------------------------
+template <typename T, int BP>
+__global__ __launch_bounds__(256) void k_sigma(const double* __restrict__ wh,
+                                               const double* __restrict__ wv, int n2, int b, int m,
+                                               const T* __restrict__ Gl, const T* __restrict__ Hsw,
+                                               T* __restrict__ sig, int* __restrict__ status) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const long long idx = (long long)blockIdx.x * 4 + wave;
+  const bool valid = idx < (long long)m * n2;
+  const int s = valid ? (int)(idx / n2) : 0;
+  const int rho = valid ? (int)(idx % n2) : 0;
+  const int c0 = s * (b + 1);
+  const long long c = c0 + (lane < b ? lane : 0);
+  __shared__ T colbuf_all[4][2][BP];
+  __shared__ T wsh_all[4][BP];
+  T (*colbuf)[BP] = colbuf_all[wave];
+  T* wsh = wsh_all[wave];
+  T a[BP];
+  build_D_row<T, BP>(a, wh, wv, n2, b, c0, rho, lane);
+  // top coupling: W_rho Gl_{rho-1} W_rho
+  T wt = (T)0;
+  if (rho > 0 && lane < b) wt = (T)wv[c * (n2 + 1) + rho];
+  if (lane < BP) wsh[lane] = wt;
+  __syncthreads();
+  if (rho > 0 && lane < BP) {
+    const T* G = Gl + (((size_t)s * n2 + rho - 1) * BP + lane) * BP;
+#pragma unroll
+    for (int k = 0; k < BP; ++k) a[k] -= wt * G[k] * wsh[k];
+  }
+  // bottom coupling: W_{rho+1} Hr_{rho+1} (Hr already carries the column scaling)
+  if (rho < n2 - 1 && lane < BP) {
+    T wb = (T)0;
+    if (lane < b) wb = (T)wv[c * (n2 + 1) + rho + 1];
+    const T* H = Hsw + ((size_t)s * n2 + rho + 1) * BP * BP;
+#pragma unroll
+    for (int k = 0; k < BP; ++k) a[k] -= wb * H[swz_index<T>(lane, k, BP)];
+  }
+  __syncthreads();
+  bool ok = sweep_inverse<T, BP>(a, colbuf, lane);
+  if (valid && lane < BP) {
+    T left = (T)0, right = (T)0;
+#pragma unroll
+    for (int k = 0; k < BP; ++k) {
+      if (k == 0) left = -a[k];
+      if (k == b - 1) right = -a[k];
+    }
+    const double wL = wh[(long long)c0 * n2 + rho];
+    const double wR = wh[(long long)(c0 + b) * n2 + rho];
+    T* dst = sig + ((size_t)s * n2 + rho) * 2 * BP;
+    dst[lane] = (T)(wL * (double)left);
+    dst[BP + lane] = (T)(wR * (double)right);
+  }
+  if (valid && !ok && lane == 0) { status[0] = 2; status[1] = s; }
+}
+
+// ---------------------------------------------------------------------------
+// Schur propagation.  For slab s the 2n x 2n block A_oe A_ee^-1 A_eo needs the
+// entries of A_ee^-1 at the slab's first and last column only.  Column rho of
+// the inverse below its diagonal block follows
+//   (A_ee^-1)_{r,rho} = Hr_r (A_ee^-1)_{r-1,rho},  r > rho,
+// so each chain starts from sig[s][rho] and is propagated down the slab.  A
+// workgroup carries 64 consecutive rho (128 chains: left and right) as the
+// N dimension of 16x16x4 MFMA tiles whose results stay in registers between
+// steps (the fragment-major propagator order makes the output layout equal the
+// next B operand).  Row 0 of a chain sits in lane group 0, element 0 for both
+// precisions.  Outputs, lower triangles (r >= rho) only, per slab:
+//   PLL[s][r][rho] = wL_r (A_ee^-1)[(r,0),(rho,0)] wL_rho     (-> T_{s-1,s-1})
+//   PRR[s][r][rho] = wR_r (A_ee^-1)[(r,b-1),(rho,b-1)] wR_rho (-> T_{s,s})
+//   PLR[s][r][rho] = wL_r (A_ee^-1)[(r,0),(rho,b-1)] wR_rho   (-> T_{s-1,s})
+//   PRL[s][r][rho] = wR_r (A_ee^-1)[(r,b-1),(rho,0)] wL_rho   (-> T_{s,s-1})
+// ---------------------------------------------------------------------------
+template <typename T, int BP>
+__global__ __launch_bounds__(256) void k_schur(const double* __restrict__ wh, int n2, int b, int m,
+                                               const T* __restrict__ Hsw, const T* __restrict__ sig,
+                                               T* __restrict__ PRR, T* __restrict__ PLL,
+                                               T* __restrict__ PLR, T* __restrict__ PRL) {
+  typedef typename acc4<T>::type V4;
+  constexpr int NM = BP / 16, NK = BP / 4;
+  const int q = blockIdx.x / m, s = blockIdx.x % m;
+  const int rho0 = q * 64;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int g = lane >> 4, nn = lane & 15;
+  const int Y = wave >> 1;                 // 0: left chains, 1: right chains
+  const int rb = rho0 + (wave & 1) * 32;  // first rho of this wave
+  const int c0 = s * (b + 1);
+  const size_t nsq = (size_t)n2 * n2;
+  const int RB = b - 1;
+  const int mtR = RB >> 4, gR = acc_group<T>(RB & 15), iR = acc_elem<T>(RB & 15);
+  T* outL = (Y == 0) ? PLL : PLR;
+  T* outR = (Y == 0) ? PRL : PRR;
+  const bool wL_ok = s > 0;
+  const bool wR_ok = (Y == 1) || (s > 0);
+
+  V4 acc[2][NM];
+#pragma unroll
+  for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+    for (int mt = 0; mt < NM; ++mt) acc[nt][mt] = V4{0, 0, 0, 0};
+
+  for (int r = rho0; r < n2; ++r) {
+    if (r > rho0) {
+      const T* H = Hsw + ((size_t)s * n2 + r) * BP * BP;
+      T afr[NM][NK];
+#pragma unroll
+      for (int mt = 0; mt < NM; ++mt)
+#pragma unroll
+        for (int ks = 0; ks < NK; ++ks) afr[mt][ks] = H[(mt * NK + ks) * 64 + lane];
+      V4 nacc[2][NM];
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+        for (int mt = 0; mt < NM; ++mt) {
+          V4 d = V4{0, 0, 0, 0};
+#pragma unroll
+          for (int mt2 = 0; mt2 < NM; ++mt2)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) d = mfma16(afr[mt][4 * mt2 + i], acc[nt][mt2][i], d);
+          nacc[nt][mt] = d;
+        }
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+        for (int mt = 0; mt < NM; ++mt) acc[nt][mt] = nacc[nt][mt];
+    }
+    // start the chains of rho = r
+    const int jr = r - rb;
+    if (jr >= 0 && jr < 32 && nn == (jr & 15)) {
+      const T* sv = sig + (((size_t)s * n2 + r) * 2 + Y) * BP;
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt)
+        if (nt == (jr >> 4)) {
+#pragma unroll
+          for (int mt = 0; mt < NM; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc[nt][mt][i] = sv[16 * mt + acc_row<T>(g, i)];
+        }
+    }
+    // emit rows (r, left) and (r, right) of the chains started so far
+    const double wLr = wh[(size_t)c0 * n2 + r];
+    const double wRr = wh[(size_t)(c0 + b) * n2 + r];
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+      const int rho = rb + 16 * nt + nn;
+      if (rho <= r) {
+        const size_t off = (size_t)s * nsq + (size_t)r * n2 + rho;
+        if (g == 0 && wL_ok) outL[off] = (T)(wLr * (double)acc[nt][0][0]);
+        if (g == gR && wR_ok) {
+          T v = (T)0;
+#pragma unroll
+          for (int mt = 0; mt < NM; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+              if (mt == mtR && i == iR) v = acc[nt][mt][i];
+          outR[off] = (T)(wRr * (double)v);
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Assembly of the reduced blocks (eqs. (T11)-(T35)), sums in FP64:
+//   T_jj     = A_oo(j) - PRR[j] - PLL[j+1]      (symmetric; full block written)
+//   T_{j,j+1} = -PLR[j+1] (lower part), -PRL[j+1]^T (upper part)
+// A_oo(j): diagonal of the interface column, -w on the vertical edges.
+// 32x32 tiles; upper tiles read the transposed source tile through LDS.
+// Outputs in the working precision T, and in FP64 when T64 pointers are given.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ double diag_value(const double* __restrict__ wh,
+                                             const double* __restrict__ wv, int n2, int b, int m,
+                                             int j, const T* __restrict__ PRR,
+                                             const T* __restrict__ PLL, int R, int P) {
+  const long long cj = (long long)j * (b + 1) + b;
+  double a = 0.0;
+  if (R == P)
+    a = wh[cj * n2 + R] + wh[(cj + 1) * n2 + R] + wv[cj * (n2 + 1) + R] + wv[cj * (n2 + 1) + R + 1];
+  else if (R == P + 1)
+    a = -wv[cj * (n2 + 1) + R];
+  const size_t nsq = (size_t)n2 * n2;
+  const size_t off = (size_t)R * n2 + P;
+  double v = a - (double)PRR[(size_t)j * nsq + off];
+  if (j + 1 < m) v -= (double)PLL[(size_t)(j + 1) * nsq + off];
+  return v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_assemble(const double* __restrict__ wh,
+                                                  const double* __restrict__ wv, int n2, int b,
+                                                  int m, const T* __restrict__ PRR,
+                                                  const T* __restrict__ PLL,
+                                                  const T* __restrict__ PLR,
+                                                  const T* __restrict__ PRL, T* __restrict__ Tdiag,
+                                                  T* __restrict__ Toff, double* __restrict__ Tdiag64,
+                                                  double* __restrict__ Toff64) {
+  __shared__ double tile[32][33];
+  const int j = blockIdx.y;
+  const bool off = blockIdx.z == 1;
+  if (off && j >= m - 1) return;
+  const int ntl = (n2 + 31) / 32;
+  const int ti = blockIdx.x / ntl, tj = blockIdx.x % ntl;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const size_t nsq = (size_t)n2 * n2;
+  const int s = j + 1;
+  // transposed source tile (rows from tj range, cols from ti range) for r < rho
+  if (ti <= tj) {
+    for (int yy = ty; yy < 32; yy += 8) {
+      const int R = tj * 32 + yy, P = ti * 32 + tx;  // source (R, P), R >= P needed
+      double v = 0.0;
+      if (R < n2 && P < n2 && R >= P) {
+        if (!off) v = diag_value<T>(wh, wv, n2, b, m, j, PRR, PLL, R, P);
+        else v = -(double)PRL[(size_t)s * nsq + (size_t)R * n2 + P];
+      }
+      tile[yy][tx] = v;
+    }
+  }
+  __syncthreads();
+  for (int yy = ty; yy < 32; yy += 8) {
+    const int r = ti * 32 + yy, rho = tj * 32 + tx;
+    if (r >= n2 || rho >= n2) continue;
+    double v;
+    if (r >= rho) {
+      if (!off) v = diag_value<T>(wh, wv, n2, b, m, j, PRR, PLL, r, rho);
+      else v = -(double)PLR[(size_t)s * nsq + (size_t)r * n2 + rho];
+    } else {
+      v = tile[tx][yy];  // source (rho, r)
+    }
+    const size_t o = (size_t)j * nsq + (size_t)r * n2 + rho;
+    if (!off) {
+      Tdiag[o] = (T)v;
+      if (Tdiag64) Tdiag64[o] = v;
+    } else {
+      Toff[o] = (T)v;
+      if (Toff64) Toff64[o] = v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+template <typename T, int BP>
+static int stage1_bp(const Stage1Args& A, hipStream_t st) {
+  const int m = A.m, n2 = A.n2, b = A.b;
+  hipLaunchKernelGGL((k_slab_factor<T, BP>), dim3(2 * m), dim3(64), 0, st, A.wh, A.wv, n2, b,
+                     (T*)A.Gl, (T*)A.Hsw, A.status);
+  SLAB_LAUNCH_CHECK();
+  if (A.ev[0]) SLAB_HIP_CHECK(hipEventRecord((hipEvent_t)A.ev[0], st));
+  const long long waves = (long long)m * n2;
+  hipLaunchKernelGGL((k_sigma<T, BP>), dim3(ceil_div(waves, 4)), dim3(256), 0, st, A.wh, A.wv, n2,
+                     b, m, (const T*)A.Gl, (const T*)A.Hsw, (T*)A.sig, A.status);
+  SLAB_LAUNCH_CHECK();
+  const int nchunk = (n2 + 63) / 64;
+  hipLaunchKernelGGL((k_schur<T, BP>), dim3(nchunk * m), dim3(256), 0, st, A.wh, n2, b, m,
+                     (const T*)A.Hsw, (const T*)A.sig, (T*)A.PRR, (T*)A.PLL, (T*)A.PLR,
+                     (T*)A.PRL);
+  SLAB_LAUNCH_CHECK();
+  if (A.ev[1]) SLAB_HIP_CHECK(hipEventRecord((hipEvent_t)A.ev[1], st));
+  const int ntl = (n2 + 31) / 32;
+  hipLaunchKernelGGL((k_assemble<T>), dim3(ntl * ntl, m, 2), dim3(256), 0, st, A.wh, A.wv, n2, b,
+                     m, (const T*)A.PRR, (const T*)A.PLL, (const T*)A.PLR, (const T*)A.PRL,
+                     (T*)A.Tdiag, (T*)A.Toff, A.Tdiag64, A.Toff64);
+  SLAB_LAUNCH_CHECK();
+  if (A.ev[2]) SLAB_HIP_CHECK(hipEventRecord((hipEvent_t)A.ev[2], st));
+  return SLAB_OK;
+}
+
+template <typename T>
+int launch_stage1(const Stage1Args& A, hipStream_t st) {
+  switch (padded_block(A.b)) {
+    case 16: return stage1_bp<T, 16>(A, st);
+    case 32: return stage1_bp<T, 32>(A, st);
+    default: return stage1_bp<T, 64>(A, st);
+  }
+}
+template int launch_stage1<float>(const Stage1Args&, hipStream_t);
+template int launch_stage1<double>(const Stage1Args&, hipStream_t);
+
+}  // namespace slab

@@ -1,0 +1,307 @@
+"""Python binding of the slab solver's C ABI (include/slab.h).
+
+Argument marshalling only: every step of factor and solve runs in the HIP
+library libslab.so built in this package.  PyTorch supplies device memory and
+the current stream.  If the library is missing the import of this module
+still works, but every call raises: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+PKG_DIR = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG_DIR, "libslab.so")
+HEADER = os.path.join(os.path.dirname(PKG_DIR), "include", "slab.h")
+
+SLAB_OK = 0
+SLAB_E_INVALID = -1
+SLAB_E_NOMEM = -2
+SLAB_E_BREAKDOWN = -3
+SLAB_E_NOCONV = -4
+SLAB_E_HIP = -5
+
+SLAB_FP64 = 0
+SLAB_FP32_REFINE = 1
+
+SLAB_KEEP_REDUCED = 1
+SLAB_COEF_LOG = 2
+
+_STATUS_NAMES = {0: "SLAB_OK", -1: "SLAB_E_INVALID", -2: "SLAB_E_NOMEM", -3: "SLAB_E_BREAKDOWN",
+                 -4: "SLAB_E_NOCONV", -5: "SLAB_E_HIP"}
+
+
+class SlabError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class slab_problem(ctypes.Structure):
+    _fields_ = [("n1", ctypes.c_int32), ("n2", ctypes.c_int32), ("b", ctypes.c_int32),
+                ("h", ctypes.c_double), ("kappa", ctypes.c_void_p)]
+
+
+class slab_options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+class slab_solve_info(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("max_relres", ctypes.c_double),
+                ("failed_block", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def header_functions() -> list[str]:
+    """Names of the functions declared in include/slab.h."""
+    text = open(HEADER).read()
+    return re.findall(r"^\s*(?:int|const char\*)\s+(slab_\w+)\s*\(", text, flags=re.M)
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libslab.so (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} not found: build it with python -m paper_2211_07572_amd.build_lib")
+    L = ctypes.CDLL(path)
+    vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    L.slab_last_error.restype = ctypes.c_char_p
+    L.slab_last_error.argtypes = []
+    L.slab_check_problem.argtypes = [ctypes.POINTER(slab_problem), ctypes.POINTER(slab_options)]
+    L.slab_factor.argtypes = [ctypes.POINTER(slab_problem), ctypes.POINTER(slab_options), vp,
+                              ctypes.POINTER(vp), ctypes.POINTER(slab_solve_info)]
+    L.slab_solve.argtypes = [vp, vp, vp, i32, i64, vp, ctypes.POINTER(slab_solve_info)]
+    L.slab_solve_adjoint.argtypes = [vp, vp, vp, i32, i64, vp, ctypes.POINTER(slab_solve_info)]
+    L.slab_free.argtypes = [vp]
+    L.slab_index_maps.argtypes = [i32, i32, i32, vp, vp, vp, vp, vp, vp]
+    L.slab_kappa_grad.argtypes = [vp, vp, vp, i32, i64, i32, vp, vp]
+    L.slab_residual.argtypes = [vp, vp, vp, i32, i64, ctypes.POINTER(dp), vp]
+    L.slab_export_reduced.argtypes = [vp, i32, i32, vp, vp]
+    L.slab_query.argtypes = [vp, i32, ctypes.POINTER(i64)]
+    for name in header_functions():
+        if name != "slab_last_error":
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != SLAB_OK:
+        raise SlabError(rc, load_library().slab_last_error().decode(errors="replace"))
+
+
+def _stream_ptr(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_f64(t, name):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64):
+        raise TypeError(f"{name} must be a CUDA float64 tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class SlabHandle:
+    """Owns one factorization (an opaque slab_handle)."""
+
+    def __init__(self, ptr, n2, n1, b, h, precision):
+        self._ptr = ptr
+        self.n2, self.n1, self.b, self.h, self.precision = n2, n1, b, h, precision
+        self.m = n1 // (b + 1)
+        self.last_info = slab_solve_info()
+
+    @property
+    def ptr(self):
+        if not self._ptr:
+            raise ValueError("handle already freed")
+        return self._ptr
+
+    def free(self):
+        if self._ptr:
+            load_library().slab_free(self._ptr)
+            self._ptr = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def query(self, what: int) -> int:
+        v = ctypes.c_int64()
+        _check(load_library().slab_query(self.ptr, what, ctypes.byref(v)))
+        return v.value
+
+    def phase_us(self) -> dict:
+        names = ["weights+slab_factor", "slab_factor", "schur", "assemble", "block_factor"]
+        return {n: self.query(10 + i) for i, n in enumerate(names)}
+
+
+def _vec_shape(t, n2, n1):
+    if t.dim() == 2:
+        t = t.unsqueeze(0)
+    if t.dim() != 3 or t.shape[1] != n1 or t.shape[2] != n2:
+        raise ValueError(f"expected shape (nrhs, {n1}, {n2}), got {tuple(t.shape)}")
+    return t
+
+
+def slab_factor(kappa, n2: int, n1: int, b: int, h: float | None = None, precision: int = SLAB_FP64,
+                tol: float = 1e-10, max_iter: int = 10, keep_reduced: bool = False,
+                coef_log: bool = False, stream=None) -> SlabHandle:
+    """Alg. 3 on the device field kappa (or theta = log kappa), shape (n1+2, n2+2)."""
+    L = load_library()
+    if h is None:
+        h = 1.0 / (n2 + 1)
+    if tuple(kappa.shape) != (n1 + 2, n2 + 2):
+        raise ValueError(f"kappa must have shape {(n1 + 2, n2 + 2)}")
+    prob = slab_problem(n1, n2, b, float(h), _dev_f64(kappa, "kappa"))
+    flags = (SLAB_KEEP_REDUCED if keep_reduced else 0) | (SLAB_COEF_LOG if coef_log else 0)
+    opts = slab_options(precision, float(tol), int(max_iter), flags)
+    out = ctypes.c_void_p()
+    info = slab_solve_info()
+    _check(L.slab_factor(ctypes.byref(prob), ctypes.byref(opts), _stream_ptr(stream),
+                         ctypes.byref(out), ctypes.byref(info)))
+    return SlabHandle(out, n2, n1, b, h, precision)
+
+
+def _solve(fn, handle: SlabHandle, f, out=None, stream=None, check=True):
+    import torch
+    f3 = _vec_shape(f, handle.n2, handle.n1)
+    if not f3.is_contiguous():
+        f3 = f3.contiguous()
+    u = torch.empty_like(f3) if out is None else _vec_shape(out, handle.n2, handle.n1)
+    info = slab_solve_info()
+    rc = fn(handle.ptr, _dev_f64(f3, "f"), _dev_f64(u, "u"), f3.shape[0], handle.n1 * handle.n2,
+            _stream_ptr(stream), ctypes.byref(info))
+    handle.last_info = info
+    if check:
+        _check(rc)
+    return u.view(f.shape) if f.dim() == 2 else u
+
+
+def slab_solve(handle: SlabHandle, f, out=None, stream=None, check=True):
+    """Alg. 4: u = A^-1 f for f of shape (nrhs, n1, n2) (or (n1, n2)), CUDA float64."""
+    return _solve(load_library().slab_solve, handle, f, out, stream, check)
+
+
+def slab_solve_adjoint(handle: SlabHandle, g, out=None, stream=None, check=True):
+    """lambda = A^-T g with the stored factors applied transposed."""
+    return _solve(load_library().slab_solve_adjoint, handle, g, out, stream, check)
+
+
+def slab_free(handle: SlabHandle):
+    handle.free()
+
+
+def slab_index_maps(n2: int, n1: int, b: int, stream=None) -> dict:
+    import torch
+    m = n1 // (b + 1) if b + 1 > 0 else 0
+    dev = torch.device("cuda")
+    out = dict(col_kind=torch.empty(n1, dtype=torch.int32, device=dev),
+               slab_of_col=torch.empty(n1, dtype=torch.int32, device=dev),
+               local_of_col=torch.empty(n1, dtype=torch.int32, device=dev),
+               perm_even=torch.empty(max(m * n2 * b, 1), dtype=torch.int64, device=dev),
+               perm_odd=torch.empty(max(m * n2, 1), dtype=torch.int64, device=dev))
+    p = {k: ctypes.c_void_p(v.data_ptr()) for k, v in out.items()}
+    _check(load_library().slab_index_maps(n1, n2, b, p["col_kind"], p["slab_of_col"],
+                                          p["local_of_col"], p["perm_even"], p["perm_odd"],
+                                          _stream_ptr(stream)))
+    out["perm_even"] = out["perm_even"][:m * n2 * b]
+    out["perm_odd"] = out["perm_odd"][:m * n2]
+    out["m"] = m
+    return out
+
+
+def slab_kappa_grad(handle: SlabHandle, u, lam, mode: int = 1, stream=None):
+    """dL/dkappa (mode 0) or dL/dtheta (mode 1) on the (n1+2, n2+2) field."""
+    import torch
+    u3 = _vec_shape(u, handle.n2, handle.n1).contiguous()
+    l3 = _vec_shape(lam, handle.n2, handle.n1).contiguous()
+    grad = torch.empty((handle.n1 + 2, handle.n2 + 2), dtype=torch.float64, device=u3.device)
+    _check(load_library().slab_kappa_grad(handle.ptr, _dev_f64(u3, "u"), _dev_f64(l3, "lam"),
+                                          u3.shape[0], handle.n1 * handle.n2, mode,
+                                          _dev_f64(grad, "grad"), _stream_ptr(stream)))
+    return grad
+
+
+def slab_residual(handle: SlabHandle, f, u, stream=None) -> list[float]:
+    f3 = _vec_shape(f, handle.n2, handle.n1).contiguous()
+    u3 = _vec_shape(u, handle.n2, handle.n1).contiguous()
+    arr = (ctypes.c_double * f3.shape[0])()
+    _check(load_library().slab_residual(handle.ptr, _dev_f64(f3, "f"), _dev_f64(u3, "u"),
+                                        f3.shape[0], handle.n1 * handle.n2, arr,
+                                        _stream_ptr(stream)))
+    return list(arr)
+
+
+def slab_export_reduced(handle: SlabHandle, which: int, j: int, stream=None):
+    """FP64 copy of T_jj (which=0), T_{j,j+1} (1) or S_j (2); needs keep_reduced."""
+    import torch
+    out = torch.empty((handle.n2, handle.n2), dtype=torch.float64, device="cuda")
+    _check(load_library().slab_export_reduced(handle.ptr, which, j, _dev_f64(out, "out"),
+                                              _stream_ptr(stream)))
+    return out
+
+
+def slab_check_problem(n2: int, n1: int, b: int, h: float, kappa_ptr: int = 1,
+                       precision: int = SLAB_FP64, tol: float = 1e-10, max_iter: int = 10,
+                       flags: int = 0) -> int:
+    """Host-only argument check; returns the status code (no HIP call is made)."""
+    prob = slab_problem(n1, n2, b, float(h), ctypes.c_void_p(kappa_ptr))
+    opts = slab_options(precision, float(tol), int(max_iter), flags)
+    return load_library().slab_check_problem(ctypes.byref(prob), ctypes.byref(opts))
+
+
+# ---------------------------------------------------------------------------
+# Differentiable solve: u(theta) = A(exp(theta))^-1 f.
+# ---------------------------------------------------------------------------
+def _autograd():
+    import torch
+
+    class SlabSolveFunction(torch.autograd.Function):
+        """Forward: slab_factor (theta = log kappa) + slab_solve.  Backward:
+        slab_solve_adjoint for lambda = A^-T dL/du, then the edge-product
+        gradient kernel for dL/dtheta; dL/df = lambda."""
+
+        @staticmethod
+        def forward(ctx, theta, f, n2, n1, b, h, precision, tol):
+            handle = slab_factor(theta.contiguous(), n2, n1, b, h, precision=precision, tol=tol,
+                                 coef_log=True)
+            u = slab_solve(handle, f.contiguous())
+            ctx.handle = handle
+            ctx.save_for_backward(u)
+            return u
+
+        @staticmethod
+        def backward(ctx, gu):
+            (u,) = ctx.saved_tensors
+            handle = ctx.handle
+            lam = slab_solve_adjoint(handle, gu.contiguous())
+            gtheta = slab_kappa_grad(handle, u, lam, mode=1)
+            return gtheta, lam, None, None, None, None, None, None
+
+    return SlabSolveFunction
+
+
+_fn = None
+
+
+def solve_theta(theta, f, n2: int, n1: int, b: int, h: float | None = None,
+                precision: int = SLAB_FP64, tol: float = 1e-10):
+    """Differentiable u = A(exp theta)^-1 f (a torch.autograd.Function)."""
+    global _fn
+    if _fn is None:
+        _fn = _autograd()
+    if h is None:
+        h = 1.0 / (n2 + 1)
+    return _fn.apply(theta, f, n2, n1, b, h, precision, tol)

@@ -1,0 +1,239 @@
+"""GPU parity of the HIP slab solver against the FP64 CPU oracle.
+
+Every test calls the C ABI through the thin binding and compares with the
+oracle on the same seeded inputs.  Tolerances: FP64 results within 1e-12
+relative (per block / per column); mixed precision is judged by the
+relative residual 1e-10 recomputed on the host with the oracle's A.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from gen import inputs as G
+from oracle import slab_oracle as O
+from paper_2211_07572_amd import slab as S
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def _dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def _rel_fro(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _col_rel(u, ref):
+    u = u.reshape(u.shape[0], -1)
+    ref = ref.reshape(ref.shape[0], -1)
+    return np.linalg.norm(u - ref, axis=1) / np.linalg.norm(ref, axis=1)
+
+
+# (n2, n1, b): ragged interface lengths over 64-wide tiles, every padded block
+# order (16, 32) and b = 1, a single slab, and the 1-D case n2 = 1.
+CASES = [
+    (200, 80, 7),
+    (130, 128, 31),
+    (70, 96, 15),
+    (33, 24, 1),
+    (45, 40, 3),
+    (5, 4, 3),
+    (1, 8, 1),
+    (64, 64, 7),
+]
+
+
+@pytest.mark.parametrize("n2,n1,b", [(64, 64, 7), (1, 2, 1), (1024, 1024, 31), (2048, 4096, 31),
+                                     (7, 30, 4)])
+def test_index_maps_bit_exact(n2, n1, b):
+    got = S.slab_index_maps(n2, n1, b)
+    ref = O.index_maps(n2, n1, b)
+    assert got["m"] == ref["m"]
+    for key in ("col_kind", "slab_of_col", "local_of_col", "perm_even", "perm_odd"):
+        g = got[key].cpu().numpy()
+        assert g.dtype in (np.int32, np.int64)
+        assert np.array_equal(g, ref[key]), key
+
+
+@pytest.mark.parametrize("n2,n1,b", CASES)
+def test_fp64_reduced_blocks_and_solve(n2, n1, b):
+    print(f"case fp64 n2={n2} n1={n1} b={b}", flush=True)
+    kap = G.kappa_lognormal(n2, n1, 3)
+    prob = O.make_problem(kap, n2, n1, b)
+    fac = O.factor(prob)
+    h = S.slab_factor(_dev(kap), n2, n1, b, keep_reduced=True)
+    for j in range(prob.m):
+        T = S.slab_export_reduced(h, 0, j).cpu().numpy()
+        assert _rel_fro(T, fac.s1.T_diag[j]) <= 1e-12, ("T_jj", j)
+        Sj = S.slab_export_reduced(h, 2, j).cpu().numpy()
+        assert _rel_fro(Sj, fac.s2.S[j]) <= 1e-12, ("S_j", j)
+    for j in range(prob.m - 1):
+        Tu = S.slab_export_reduced(h, 1, j).cpu().numpy()
+        assert _rel_fro(Tu, fac.s1.T_up[j]) <= 1e-12, ("T_j,j+1", j)
+    f = G.rhs_uniform(n2, n1, 3, 7)
+    u = S.slab_solve(h, _dev(f)).cpu().numpy()
+    u_ref = O.solve(fac, f)
+    assert _col_rel(u, u_ref).max() <= 1e-12
+    assert O.relres(prob, u, f).max() <= 1e-12
+    assert h.last_info.iterations == 1
+    h.free()
+
+
+@pytest.mark.parametrize("n2,n1,b", CASES)
+def test_fp32_refinement(n2, n1, b):
+    print(f"case fp32 n2={n2} n1={n1} b={b}", flush=True)
+    kap = G.kappa_lognormal(n2, n1, 4)
+    prob = O.make_problem(kap, n2, n1, b)
+    h = S.slab_factor(_dev(kap), n2, n1, b, precision=S.SLAB_FP32_REFINE, tol=1e-10,
+                      keep_reduced=True)
+    f = G.rhs_normal(n2, n1, 4, 8)
+    u = S.slab_solve(h, _dev(f)).cpu().numpy()
+    rr = O.relres(prob, u, f)
+    assert rr.max() <= 1e-10, rr
+    assert h.last_info.max_relres <= 1e-10
+    assert 1 <= h.last_info.iterations <= 6
+    # T and S_j are formed from FP32 slab work with an FP64 sum: state the error
+    fac = O.factor(prob)
+    errT = max(_rel_fro(S.slab_export_reduced(h, 0, j).cpu().numpy(), fac.s1.T_diag[j])
+               for j in range(prob.m))
+    assert errT <= 1e-5, errT
+    h.free()
+
+
+@pytest.mark.parametrize("n2,n1,b", [(200, 80, 7), (70, 96, 15), (33, 24, 1)])
+def test_adjoint_matches_oracle(n2, n1, b):
+    kap = G.kappa_lognormal(n2, n1, 5)
+    prob = O.make_problem(kap, n2, n1, b)
+    h = S.slab_factor(_dev(kap), n2, n1, b)
+    g = G.rhs_normal(n2, n1, 2, 9)
+    lam = S.slab_solve_adjoint(h, _dev(g)).cpu().numpy()
+    lam_ref = O.solve_adjoint(prob, g)
+    assert _col_rel(lam, lam_ref).max() <= 1e-12
+    u = S.slab_solve(h, _dev(g)).cpu().numpy()
+    assert _col_rel(lam, u).max() <= 1e-12          # A is symmetric
+    f = G.rhs_uniform(n2, n1, 2, 10)
+    uf = S.slab_solve(h, _dev(f)).cpu().numpy()
+    assert abs(np.sum(uf * g) - np.sum(f * lam)) <= 1e-11 * abs(np.sum(uf * g))
+    h.free()
+
+
+def test_gradient_kernel_matches_oracle():
+    n2, n1, b = 40, 48, 7
+    theta = G.grf(n2, n1, 12)
+    prob = O.make_problem(np.exp(theta), n2, n1, b)
+    f = G.rhs_uniform(n2, n1, 2, 11)
+    fac = O.factor(prob)
+    u = O.solve(fac, f)
+    lam = O.solve_adjoint(prob, u - 0.5)
+    ref = O.kappa_grad(prob, u, lam)
+    h = S.slab_factor(_dev(theta), n2, n1, b, coef_log=True)
+    g1 = S.slab_kappa_grad(h, _dev(u), _dev(lam), mode=1).cpu().numpy()
+    assert np.abs(g1 - ref).max() <= 1e-12 * np.abs(ref).max()
+    g0 = S.slab_kappa_grad(h, _dev(u), _dev(lam), mode=0).cpu().numpy()
+    assert np.abs(g0 * np.exp(theta) - ref).max() <= 1e-12 * np.abs(ref).max()
+    h.free()
+
+
+def test_autograd_gradient_vs_central_fd():
+    n2, n1, b = 14, 16, 3
+    h_ = 1.0 / (n2 + 1)
+    theta0 = G.grf(n2, n1, 13, h_)
+    f = _dev(G.rhs_uniform(n2, n1, 1, 12))
+    u_obs = _dev(O.solve(O.factor(O.make_problem(np.exp(G.grf(n2, n1, 1, h_)), n2, n1, b)),
+                         G.rhs_uniform(n2, n1, 1, 12)))
+
+    def loss(th):
+        u = S.solve_theta(th, f, n2, n1, b)
+        return 0.5 * ((u - u_obs) ** 2).sum()
+
+    th = _dev(theta0).requires_grad_(True)
+    L = loss(th)
+    (grad,) = torch.autograd.grad(L, th)
+    grad = grad.cpu().numpy()
+    rng = np.random.default_rng(G.SEED_FD_NODES)
+    eps = 1e-6
+    gmax = np.abs(grad).max()
+    for _ in range(12):
+        i, j = int(rng.integers(1, n1 + 1)), int(rng.integers(1, n2 + 1))
+        tp = theta0.copy(); tp[i, j] += eps
+        tm = theta0.copy(); tm[i, j] -= eps
+        with torch.no_grad():
+            fd = (loss(_dev(tp)).item() - loss(_dev(tm)).item()) / (2 * eps)
+        assert abs(fd - grad[i, j]) <= 1e-5 * gmax, (i, j, fd, grad[i, j])
+
+
+def test_poisson_64_closed_form():
+    """kappa = 1 on 64 x 64, b = 7: T against the sine-mode closed form."""
+    n2 = n1 = 64
+    b = 7
+    h = 1.0 / 65
+    hd = S.slab_factor(_dev(G.kappa_const(n2, n1)), n2, n1, b, h, keep_reduced=True)
+    i = np.arange(1, n2 + 1)
+    Q = np.sqrt(2.0 / (n2 + 1)) * np.sin(np.pi * np.outer(i, i) / (n2 + 1))
+    a = 4 - 2 * np.cos(np.pi * i / (n2 + 1))
+    x = a / 2
+    U = [np.ones_like(x), 2 * x]
+    for _ in range(b):
+        U.append(2 * x * U[-1] - U[-2])
+    both = Q @ np.diag(a - 2 * U[b - 1] / U[b]) @ Q / h ** 2
+    last = Q @ np.diag(a - U[b - 1] / U[b]) @ Q / h ** 2
+    off = -Q @ np.diag(1 / U[b]) @ Q / h ** 2
+    for j in range(8):
+        ref = both if j < 7 else last
+        assert _rel_fro(S.slab_export_reduced(hd, 0, j).cpu().numpy(), ref) <= 1e-13
+    for j in range(7):
+        assert _rel_fro(S.slab_export_reduced(hd, 1, j).cpu().numpy(), off) <= 1e-13
+    f = G.rhs_uniform(n2, n1, 1, G.SEED_RHS)
+    u = S.slab_solve(hd, _dev(f)).cpu().numpy()
+    u_ref = O.solve(O.factor(O.make_problem(G.kappa_const(n2, n1), n2, n1, b, h)), f)
+    assert _col_rel(u, u_ref).max() <= 1e-12
+    hd.free()
+
+
+def test_error_paths():
+    n2, n1, b = 16, 16, 3
+    kap = G.kappa_lognormal(n2, n1, 0)
+    bad = kap.copy(); bad[5, 5] = 0.0
+    with pytest.raises(S.SlabError) as e:
+        S.slab_factor(_dev(bad), n2, n1, b)
+    assert e.value.status == S.SLAB_E_INVALID
+    bad = kap.copy(); bad[3, 7] = np.nan
+    with pytest.raises(S.SlabError) as e:
+        S.slab_factor(_dev(bad), n2, n1, b)
+    assert e.value.status == S.SLAB_E_INVALID
+    # one FP32 pass cannot reach 1e-14: non-convergence is reported, u is the iterate
+    h = S.slab_factor(_dev(kap), n2, n1, b, precision=S.SLAB_FP32_REFINE, tol=1e-14, max_iter=1)
+    f = _dev(G.rhs_uniform(n2, n1, 1, 1))
+    with pytest.raises(S.SlabError) as e:
+        S.slab_solve(h, f)
+    assert e.value.status == S.SLAB_E_NOCONV
+    assert h.last_info.iterations == 1 and h.last_info.max_relres > 1e-14
+    h.free()
+
+
+def test_run_to_run_determinism():
+    n2, n1, b = 130, 128, 31
+    kap = _dev(G.kappa_lognormal(n2, n1, 6))
+    f = _dev(G.rhs_normal(n2, n1, 3, 2))
+    outs = []
+    for _ in range(2):
+        h = S.slab_factor(kap, n2, n1, b, precision=S.SLAB_FP32_REFINE)
+        outs.append(S.slab_solve(h, f).cpu().numpy())
+        h.free()
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_many_rhs_column_groups():
+    """nrhs = 40 crosses the 16-column sweep groups and 32-column product groups."""
+    n2, n1, b = 70, 48, 7
+    kap = G.kappa_lognormal(n2, n1, 7)
+    prob = O.make_problem(kap, n2, n1, b)
+    h = S.slab_factor(_dev(kap), n2, n1, b)
+    f = G.rhs_uniform(n2, n1, 40, 3)
+    u = S.slab_solve(h, _dev(f)).cpu().numpy()
+    assert _col_rel(u, O.solve(O.factor(prob), f)).max() <= 1e-12
+    h.free()
