@@ -1,0 +1,223 @@
+"""Benchmark: factor+solve DOF/s of the slab solver on one MI355X.
+
+Workload: -div(kappa grad u) = f on 2048 rows x 4096 columns (8.39M unknowns),
+slab width b = 31 (128 slabs, interfaces of 2048 points), kappa = exp(GRF)
+(squared-exponential covariance, length 0.05, variance 1), 16 right-hand sides
+N(0,1).  One step = slab_factor + slab_solve of all 16 right-hand sides to a
+max relative residual of 1e-10 + slab_free.  The headline value is the
+FP32 + FP64-refinement form; the plain FP64 form is timed beside it.
+
+Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from gen import inputs as G  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="diffusion_2048x4096_b31")
+    ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--precision", choices=["mixed", "fp32"], default="mixed",
+                    help="mixed: FP64 slab work + FP32 reduced system; fp32: FP32 throughout "
+                         "(both with FP64 refinement to 1e-10)")
+    ap.add_argument("--skip-other", action="store_true")
+    ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--cpu-slabs", type=int, default=1)
+    return ap.parse_args()
+
+
+def workload(name: str) -> G.Workload:
+    table = {w.name: w for w in (G.POISSON_64, G.DIFFUSION_1024, G.DIFFUSION_2048x4096, G.ADJOINT_512)}
+    return table[name]
+
+
+def schur_flops(w: G.Workload) -> float:
+    """Algorithmic flops of the Schur propagation (one launch covers every slab):
+    per slab 2n chains (n for slab 0), chain rho propagated over n-1-rho steps of
+    a b x b matrix-vector product (2 b^2 flops)."""
+    n, b, m = w.n2, w.b, w.m
+    return 2.0 * b * b * n * (n - 1) * (m - 0.5)
+
+
+def block_factor_flops(w: G.Workload) -> float:
+    """Algorithmic flops of the block factorization: per interface block the
+    Cholesky factor (n^3/3) and its inverse (n^3/3); per coupling Z_j = L_j^-1 T_{j,j+1}
+    (n^3) and the symmetric update of S_{j+1} (n^3)."""
+    n, m = w.n2, w.m
+    return m * (2.0 / 3.0) * n ** 3 + (m - 1) * 2.0 * n ** 3
+
+
+def run_gpu(w: G.Workload, precision: int, steps: int, warmup: int, kappa, f):
+    import torch
+    from paper_2211_07572_amd import slab as S
+    torch.cuda.synchronize()
+    infos = []
+    phases = []
+
+    def one():
+        h = S.slab_factor(kappa, w.n2, w.n1, w.b, w.h, precision=precision, tol=1e-10, max_iter=10)
+        u = S.slab_solve(h, f)
+        infos.append((h.last_info.iterations, h.last_info.max_relres))
+        phases.append(h.phase_us())
+        h.free()
+        return u
+
+    for _ in range(warmup):
+        one()
+    torch.cuda.synchronize()
+    infos.clear()
+    phases.clear()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        u = one()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    return dt, u, infos, phases
+
+
+def cpu_baseline(w: G.Workload, kappa_np: np.ndarray, f_np: np.ndarray, slabs: int = 1) -> dict:
+    """The FP64 oracle timed on a bounded sample of the same workload and scaled.
+
+    Sample: stage one for `slabs` slab(s) (banded LU + all 2n boundary solves),
+    one step of Alg. 1 on n x n blocks, and the solve work of one slab and one
+    Alg. 2 block step for the 16 right-hand sides; the estimate for the whole
+    job is m times each per-slab / per-block figure.
+    """
+    import scipy.linalg as sla
+    from oracle import slab_oracle as O
+    t_setup = time.perf_counter()
+    prob = O.make_problem(kappa_np, w.n2, w.n1, w.b, w.h)
+    setup_s = time.perf_counter() - t_setup
+    m, n = prob.m, prob.n2
+    # stage one: slabs 1..slabs (each touches two interfaces)
+    t0 = time.perf_counter()
+    contrib = [O.slab_contributions(prob, s) for s in range(1, 1 + slabs)]
+    t_slab = (time.perf_counter() - t0) / slabs
+    C = contrib[0]
+    Tjj = prob.block(prob.I_o(0), prob.I_o(0)).toarray() - C[(0, 0)]
+    Tup = -C[(0, 1)]
+    Tlo = -C[(1, 0)]
+    T11 = prob.block(prob.I_o(1), prob.I_o(1)).toarray() - C[(1, 1)]
+    # one step of Alg. 1: factor S_j, form S_{j+1}
+    t0 = time.perf_counter()
+    lu = sla.lu_factor(Tjj)
+    S1 = T11 - Tlo @ sla.lu_solve(lu, Tup)
+    sla.lu_factor(S1)
+    t_step = time.perf_counter() - t0
+    # solve: one slab's reduced RHS and interior solve, one Alg. 2 block step
+    fac1 = O.SlabFactor(prob.block(prob.I_e(1), prob.I_e(1)), w.b)
+    F = f_np.reshape(f_np.shape[0], -1)
+    t0 = time.perf_counter()
+    y = fac1.solve(F[:, prob.I_e(1)].T)
+    _ = prob.block(prob.I_o(1), prob.I_e(1)) @ y
+    _ = fac1.solve(F[:, prob.I_e(1)].T)
+    t_solve_slab = time.perf_counter() - t0
+    g = F[:, prob.I_o(1)].T.copy()
+    t0 = time.perf_counter()
+    g -= Tlo @ sla.lu_solve(lu, g)
+    g = sla.lu_solve(lu, g)
+    g -= sla.lu_solve(lu, Tup @ g)
+    t_solve_blk = time.perf_counter() - t0
+    total = m * t_slab + (m - 1) * t_step + m * t_solve_slab + m * t_solve_blk
+    sampled = slabs * t_slab + t_step + t_solve_slab + t_solve_blk
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": w.N / total, "unit": "DOF/s", "cores": threads, "kind": "oracle",
+            "sample": (f"FP64 oracle (NumPy/SciPy-LAPACK, {threads} BLAS threads) timed on "
+                       f"{slabs} slab of stage one, 1 step of Alg. 1, 1 slab + 1 block of the "
+                       f"16-RHS solve ({sampled:.1f} s), scaled by m={m}: estimated "
+                       f"{total:.0f} s for the whole job"),
+            "estimated_total_s": total, "sampled_s": sampled, "setup_s": setup_s}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    from paper_2211_07572_amd import slab as S
+    S.load_library()
+    w = workload(args.workload)
+    kappa_np = w.kappa()
+    f_np = w.rhs()
+    kappa = torch.as_tensor(kappa_np, device="cuda")
+    f = torch.as_tensor(f_np, device="cuda").contiguous()
+    torch.cuda.synchronize()
+
+    prec = {"mixed": S.SLAB_MIXED, "fp32": S.SLAB_FP32_REFINE}[args.precision]
+    dt32, u32, info32, ph32 = run_gpu(w, prec, args.steps, args.warmup, kappa, f)
+    relres32 = max(r for _, r in info32)
+    iters32 = max(i for i, _ in info32)
+    ph = {k: float(np.median([p[k] for p in ph32])) for k in ph32[0]}
+    result = {
+        "metric": "factor+solve DOF/s, FP32+refine vs FP64 on GPU at rel. residual 1e-10",
+        "value": w.N / dt32,
+        "unit": "DOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt32 * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n2": w.n2, "n1": w.n1, "b": w.b, "slabs": w.m,
+                   "nrhs": w.nrhs, "N": w.N, "kappa": "exp(GRF l=0.05 var=1)",
+                   "rhs": "N(0,1)", "tol": 1e-10,
+                   "precision": {"mixed": "FP64 slab work, FP32 reduced system, FP64 refinement",
+                                 "fp32": "FP32 throughout, FP64 sum forming T, FP64 refinement"}[args.precision]},
+        "max_relres": relres32,
+        "refine_passes": iters32,
+        "phase_ms": {k: v / 1e3 for k, v in ph.items()},
+    }
+    # roofline of the Schur propagation kernel (one launch per factor), timed by
+    # HIP events recorded on the launch stream around that launch only
+    t_schur = ph["schur"] / 1e6
+    fl = schur_flops(w)
+    dt = "f64" if args.precision == "mixed" else "f32"
+    result["roofline"] = {"kernel": f"k_schur<{'double' if dt == 'f64' else 'float'},32>",
+                          "bound": "mfma", "achieved": fl / t_schur / 1e12,
+                          "peak": PEAK_TFLOPS[dt], "unit": "TFLOP/s",
+                          "frac": fl / t_schur / 1e12 / PEAK_TFLOPS[dt], "traffic": None}
+    if not args.skip_other:
+        other = "fp32" if args.precision == "mixed" else "mixed"
+        dto, _, info_o, ph_o = run_gpu(w, {"mixed": S.SLAB_MIXED, "fp32": S.SLAB_FP32_REFINE}[other],
+                                       1, 1, kappa, f)
+        result[f"{other}_form"] = {"value": w.N / dto, "ms_per_step": dto * 1e3,
+                                   "max_relres": max(r for _, r in info_o),
+                                   "refine_passes": max(i for i, _ in info_o),
+                                   "phase_ms": {k: v / 1e3 for k, v in ph_o[0].items()}}
+    tb = ph["block_factor"] / 1e6
+    result["block_factor_tflops"] = block_factor_flops(w) / tb / 1e12
+    if not args.skip_fp64:
+        dt64, u64, info64, ph64 = run_gpu(w, S.SLAB_FP64, 1, 0, kappa, f)
+        result["fp64"] = {"value": w.N / dt64, "ms_per_step": dt64 * 1e3,
+                          "max_relres": max(r for _, r in info64),
+                          "phase_ms": {k: v / 1e3 for k, v in ph64[0].items()}}
+        result["fp32_refine_speedup_vs_fp64"] = dt64 / dt32
+    if not args.skip_cpu:
+        result["cpu_baseline"] = cpu_baseline(w, kappa_np, f_np, args.cpu_slabs)
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

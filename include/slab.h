@@ -62,6 +62,9 @@ typedef struct slab_handle_s* slab_handle;
 #define SLAB_FP64 0          /* every phase in FP64 */
 #define SLAB_FP32_REFINE 1   /* slab factors, T blocks and the block factorization in FP32;
                                 FP64 sum forming T, FP64 residual and update */
+#define SLAB_MIXED 2         /* slab factors, Schur formation and slab sweeps in FP64; the
+                                reduced system (T blocks, block factorization, Alg. 2) in
+                                FP32; FP64 residual and update */
 
 /* option flags */
 #define SLAB_KEEP_REDUCED 1  /* keep FP64 copies of T and of every S_j (Alg. 1) for export */
@@ -77,7 +80,7 @@ typedef struct {
 } slab_problem;
 
 typedef struct {
-  int32_t precision;   /* SLAB_FP64 or SLAB_FP32_REFINE */
+  int32_t precision;   /* SLAB_FP64, SLAB_FP32_REFINE or SLAB_MIXED */
   double tol;          /* target max-over-columns ||f - A u||_2 / ||f||_2 (e.g. 1e-10) */
   int32_t max_iter;    /* refinement iterations allowed (>= 1; FP64 uses at most this too) */
   int32_t flags;       /* SLAB_KEEP_REDUCED | SLAB_COEF_LOG */
@@ -145,8 +148,10 @@ int slab_residual(slab_handle h, const double* f, const double* u, int32_t nrhs,
 int slab_export_reduced(slab_handle h, int32_t which, int32_t j, double* out, void* hip_stream);
 
 /* Sizes and timings of a handle: what = 0 m, 1 n1, 2 n2, 3 b, 4 precision,
-   5 device bytes held, 10+p elapsed microseconds of factor phase p
-   (0 weights, 1 slab factor, 2 Schur formation, 3 assembly, 4 block factor). */
+   5 device bytes held, 10+p elapsed microseconds of factor phase p of the last
+   factorization (0 weights and slab factors, 1 boundary columns of the slab
+   inverses, 2 Schur propagation, 3 assembly of T, 4 block factorization of T),
+   measured with HIP events on the factor's stream. */
 int slab_query(slab_handle h, int32_t what, int64_t* value);
 
 /* Message of the last failure on this thread ("" if none). */

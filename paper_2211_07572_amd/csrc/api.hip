@@ -39,7 +39,8 @@ struct slab_handle_s {
   int max_iter = 10;
   int flags = 0;
   int device = 0;
-  size_t esz = 8;
+  size_t esz = 8;   // slab factors / Schur pieces / slab sweeps
+  size_t esz2 = 8;  // reduced system: T blocks, block factorization, Alg. 2
   double* kappa = nullptr;
   double* wh = nullptr;
   double* wv = nullptr;
@@ -115,14 +116,14 @@ int ensure_workspace(slab_handle h, int nrhs, hipStream_t st) {
                   w.partial};
   for (void* p : ptrs) dev_release(h, p);
   w = Workspace();
-  const size_t n = h->n2, m = h->m, e = h->esz;
+  const size_t n = h->n2, m = h->m, e = h->esz, e2 = h->esz2;
   const size_t N = (size_t)h->n1 * h->n2;
   SLAB_TRY(dev_alloc(h, &w.zbuf, m * nrhs * n * h->BP * e));
   SLAB_TRY(dev_alloc(h, &w.xb, m * 2 * nrhs * n * e));
-  SLAB_TRY(dev_alloc(h, &w.ft, m * nrhs * n * e));
-  SLAB_TRY(dev_alloc(h, &w.yt, m * nrhs * n * e));
-  SLAB_TRY(dev_alloc(h, &w.tt, nrhs * n * e));
-  SLAB_TRY(dev_alloc(h, &w.gemv_work, gemv_work_bytes(h->n2, nrhs < 32 ? nrhs : 32, (int)e)));
+  SLAB_TRY(dev_alloc(h, &w.ft, m * nrhs * n * e2));
+  SLAB_TRY(dev_alloc(h, &w.yt, m * nrhs * n * e2));
+  SLAB_TRY(dev_alloc(h, &w.tt, nrhs * n * e2));
+  SLAB_TRY(dev_alloc(h, &w.gemv_work, gemv_work_bytes(h->n2, nrhs, (int)e2)));
   SLAB_TRY(dev_alloc(h, (void**)&w.gemv_counters, gemv_counter_count(h->n2) * sizeof(int)));
   SLAB_HIP_CHECK(hipMemsetAsync(w.gemv_counters, 0, gemv_counter_count(h->n2) * sizeof(int), st));
   SLAB_TRY(dev_alloc(h, (void**)&w.r, nrhs * N * sizeof(double)));
@@ -144,8 +145,11 @@ SolveArgs solve_args(slab_handle h, int nrhs, int transpose) {
 
 int solve_pass(slab_handle h, const SolveArgs& a, const double* rhs, long long ldr, double* out,
                long long ldo, int acc, hipStream_t st) {
-  if (h->precision == SLAB_FP32_REFINE) return launch_solve_pass<float>(a, rhs, ldr, out, ldo, acc, st);
-  return launch_solve_pass<double>(a, rhs, ldr, out, ldo, acc, st);
+  if (h->precision == SLAB_FP32_REFINE)
+    return launch_solve_pass<float, float>(a, rhs, ldr, out, ldo, acc, st);
+  if (h->precision == SLAB_MIXED)
+    return launch_solve_pass<double, float>(a, rhs, ldr, out, ldo, acc, st);
+  return launch_solve_pass<double, double>(a, rhs, ldr, out, ldo, acc, st);
 }
 
 int residual_host(slab_handle h, const double* f, const double* u, int nrhs, long long ld,
@@ -212,9 +216,9 @@ long long elapsed_us(hipEvent_t a, hipEvent_t b) {
   return (long long)(ms * 1000.0f);
 }
 
-template <typename T>
+template <typename T, typename TR>
 int factor_impl(slab_handle h, const slab_problem* prob, hipStream_t st, slab_solve_info* info) {
-  const size_t n = h->n2, m = h->m, e = sizeof(T), BP = h->BP;
+  const size_t n = h->n2, m = h->m, e = sizeof(T), e2 = sizeof(TR), BP = h->BP;
   const size_t nsq = n * n;
   const size_t ncoef = (size_t)(h->n1 + 2) * (h->n2 + 2);
   SLAB_TRY(dev_alloc(h, (void**)&h->kappa, ncoef * sizeof(double)));
@@ -229,17 +233,17 @@ int factor_impl(slab_handle h, const slab_problem* prob, hipStream_t st, slab_so
   SLAB_TRY(dev_alloc(h, &PLL, m * nsq * e));
   SLAB_TRY(dev_alloc(h, &PLR, m * nsq * e));
   SLAB_TRY(dev_alloc(h, &PRL, m * nsq * e));
-  SLAB_TRY(dev_alloc(h, &Td, m * nsq * e));
-  SLAB_TRY(dev_alloc(h, &To, (m > 1 ? m - 1 : 1) * nsq * e));
-  SLAB_TRY(dev_alloc(h, &h->Linv, m * nsq * e));
-  SLAB_TRY(dev_alloc(h, &h->Z, (m > 1 ? m - 1 : 1) * nsq * e));
+  SLAB_TRY(dev_alloc(h, &Td, m * nsq * e2));
+  SLAB_TRY(dev_alloc(h, &To, (m > 1 ? m - 1 : 1) * nsq * e2));
+  SLAB_TRY(dev_alloc(h, &h->Linv, m * nsq * e2));
+  SLAB_TRY(dev_alloc(h, &h->Z, (m > 1 ? m - 1 : 1) * nsq * e2));
   if (h->flags & SLAB_KEEP_REDUCED) {
     SLAB_TRY(dev_alloc(h, (void**)&h->T64, m * nsq * sizeof(double)));
     SLAB_TRY(dev_alloc(h, (void**)&h->O64, (m > 1 ? m - 1 : 1) * nsq * sizeof(double)));
     SLAB_TRY(dev_alloc(h, (void**)&h->S64, m * nsq * sizeof(double)));
   }
-  hipEvent_t ev[5];
-  for (int i = 0; i < 5; ++i) SLAB_HIP_CHECK(hipEventCreate(&ev[i]));
+  hipEvent_t ev[6];
+  for (int i = 0; i < 6; ++i) SLAB_HIP_CHECK(hipEventCreate(&ev[i]));
   SLAB_HIP_CHECK(hipMemsetAsync(h->status, 0, 4 * sizeof(int), st));
   SLAB_HIP_CHECK(hipEventRecord(ev[0], st));
   SLAB_TRY(launch_coef_weights(prob->kappa, (h->flags & SLAB_COEF_LOG) ? 1 : 0, h->n1, h->n2, h->h,
@@ -256,21 +260,19 @@ int factor_impl(slab_handle h, const slab_problem* prob, hipStream_t st, slab_so
   A.wh = h->wh; A.wv = h->wv; A.Gl = h->Gl; A.Hsw = Hsw; A.sig = sig;
   A.PRR = PRR; A.PLL = PLL; A.PLR = PLR; A.PRL = PRL; A.Tdiag = Td; A.Toff = To;
   A.Tdiag64 = h->T64; A.Toff64 = h->O64; A.status = h->status;
-  A.ev[0] = ev[1]; A.ev[1] = ev[2]; A.ev[2] = ev[3];
-  SLAB_TRY(launch_stage1<T>(A, st));
+  A.ev[0] = ev[1]; A.ev[1] = ev[2]; A.ev[2] = ev[3]; A.ev[3] = ev[4];
+  SLAB_TRY((launch_stage1<T, TR>(A, st)));
   Stage2Args B;
   B.n = h->n2; B.m = h->m; B.Tdiag = Td; B.Toff = To; B.Linv = h->Linv; B.Z = h->Z;
   B.S64 = h->S64; B.status = h->status;
-  SLAB_TRY(launch_stage2<T>(B, st));
-  SLAB_HIP_CHECK(hipEventRecord(ev[4], st));
+  SLAB_TRY(launch_stage2<TR>(B, st));
+  SLAB_HIP_CHECK(hipEventRecord(ev[5], st));
   SLAB_HIP_CHECK(hipMemcpyAsync(hs, h->status, sizeof(hs), hipMemcpyDeviceToHost, st));
   SLAB_HIP_CHECK(hipStreamSynchronize(st));
-  h->phase_us[0] = elapsed_us(ev[0], ev[1]);  // coefficient + slab factor (weights included)
-  h->phase_us[1] = elapsed_us(ev[0], ev[1]);
-  h->phase_us[2] = elapsed_us(ev[1], ev[2]);
-  h->phase_us[3] = elapsed_us(ev[2], ev[3]);
-  h->phase_us[4] = elapsed_us(ev[3], ev[4]);
-  for (int i = 0; i < 5; ++i) (void)hipEventDestroy(ev[i]);
+  // phases: weights + slab factor, boundary columns, Schur propagation (k_schur
+  // alone), assembly of T, block factorization
+  for (int i = 0; i < 5; ++i) h->phase_us[i] = elapsed_us(ev[i], ev[i + 1]);
+  for (int i = 0; i < 6; ++i) (void)hipEventDestroy(ev[i]);
   void* tmp[] = {Hsw, sig, PRR, PLL, PLR, PRL, Td, To};
   for (void* p : tmp) dev_release(h, p);
   if (hs[0] != 0) {
@@ -299,7 +301,8 @@ int slab_check_problem(const slab_problem* prob, const slab_options* opts) {
   if (!prob->kappa) { set_error("null coefficient pointer"); return SLAB_E_INVALID; }
   if ((long long)prob->n1 * prob->n2 > (1LL << 40)) { set_error("grid too large"); return SLAB_E_INVALID; }
   if (opts) {
-    if (opts->precision != SLAB_FP64 && opts->precision != SLAB_FP32_REFINE) {
+    if (opts->precision != SLAB_FP64 && opts->precision != SLAB_FP32_REFINE &&
+        opts->precision != SLAB_MIXED) {
       set_error("unknown precision"); return SLAB_E_INVALID;
     }
     if (!(opts->tol > 0.0) || !std::isfinite(opts->tol)) { set_error("tol must be positive"); return SLAB_E_INVALID; }
@@ -321,14 +324,16 @@ int slab_factor(const slab_problem* prob, const slab_options* opts, void* hip_st
   h->BP = padded_block(prob->b); h->h = prob->h;
   if (opts) { h->precision = opts->precision; h->tol = opts->tol; h->max_iter = opts->max_iter; h->flags = opts->flags; }
   h->esz = h->precision == SLAB_FP32_REFINE ? 4 : 8;
+  h->esz2 = h->precision == SLAB_FP64 ? 8 : 4;
   if (hipGetDevice(&h->device) != hipSuccess) {
     set_error("no HIP device");
     delete h;
     return SLAB_E_HIP;
   }
   hipStream_t st = (hipStream_t)hip_stream;
-  rc = h->precision == SLAB_FP32_REFINE ? factor_impl<float>(h, prob, st, info)
-                                        : factor_impl<double>(h, prob, st, info);
+  if (h->precision == SLAB_FP32_REFINE) rc = factor_impl<float, float>(h, prob, st, info);
+  else if (h->precision == SLAB_MIXED) rc = factor_impl<double, float>(h, prob, st, info);
+  else rc = factor_impl<double, double>(h, prob, st, info);
   if (rc != SLAB_OK) {
     (void)hipStreamSynchronize(st);
     release_all(h);

@@ -154,10 +154,12 @@ template int launch_gemm<double>(bool, bool, int, int, int, double, const double
 // ---------------------------------------------------------------------------
 // Panel of the right-looking factorization of one pivot block S (n x n).
 // Every workgroup first inverts the Cholesky factor of the 64x64 diagonal
-// block [k0, k0+nb) in LDS: Gaussian elimination without pivoting on
-// [S_kk | I], kept in one array (U on and above the diagonal, the unit lower
-// L~^-1 below it), gives S_kk = L~ U with U = D L~^T, hence
-// L_kk^-1 = D^-1/2 L~^-1.  Then, on 16x16x4 MFMA tiles, it either
+// block [k0, k0+nb): Gaussian elimination without pivoting on [S_kk | I],
+// kept in one array (U on and above the diagonal, the unit lower L~^-1 below
+// it), gives S_kk = L~ U with U = D L~^T, hence L_kk^-1 = D^-1/2 L~^-1.  The
+// working matrix lives in registers (thread = row x 16-column quarter); each
+// elimination step exchanges only the pivot row and column through LDS, with
+// one barrier per step.  Then, on 16x16x4 MFMA tiles, it either
 //   * computes 64 rows of L below the block:       L_ik = S_ik L_kk^-T, or
 //   * advances 64 columns of the carried inverse:  X_k = L_kk^-1 X_k.
 // ---------------------------------------------------------------------------
@@ -166,42 +168,78 @@ __global__ __launch_bounds__(256) void k_panel(T* __restrict__ S, T* __restrict_
                                                int k0, int nrow_wg, int* __restrict__ status,
                                                int blk) {
   typedef typename acc4<T>::type V4;
-  __shared__ T E[64][65];   // elimination workspace, then L_kk^-1
+  __shared__ T E[64][65];   // L_kk^-1 after the elimination
   __shared__ T Bt[64][65];  // operand tile
-  __shared__ T fcol[64];
+  __shared__ T rowbuf[2][64];
+  __shared__ T colbuf[2][64];
   const int nb = min(64, n - k0);
   const int tid = threadIdx.x;
-  for (int e = tid; e < 64 * 64; e += 256) {
-    const int i = e >> 6, c = e & 63;
-    T v = (i == c) ? (T)1 : (T)0;
-    if (i < nb && c < nb) v = S[(long long)(k0 + max(i, c)) * n + k0 + min(i, c)];
-    E[i][c] = v;
+  // thread (row i, column quarter q) keeps 16 entries of the working matrix in registers
+  const int i = tid & 63, q = tid >> 6;
+  T a[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    const int col = 16 * q + c;
+    T v = (i == col) ? (T)1 : (T)0;
+    if (i < nb && col < nb) v = S[(long long)(k0 + max(i, col)) * n + k0 + min(i, col)];
+    a[c] = v;
   }
+  if (i == 0) {
+#pragma unroll
+    for (int c = 0; c < 16; ++c) rowbuf[0][16 * q + c] = a[c];
+  }
+  if (q == 0) colbuf[0][i] = a[0];
   __syncthreads();
-  for (int p = 0; p < nb; ++p) {
-    if (tid < 64) fcol[tid] = (tid > p) ? E[tid][p] / E[p][p] : (T)0;
-    __syncthreads();
-    for (int e = tid; e < 64 * 64; e += 256) {
-      const int i = e >> 6, c = e & 63;
-      if (i > p) {
-        if (c == p) E[i][c] = -fcol[i];
-        else E[i][c] -= fcol[i] * E[p][c];
+  // pivot p = 16 pb + pp: the register index pp is a compile-time constant and
+  // the owner of column p is the wave q == pb (uniform branches only)
+  for (int pb = 0; pb < 4; ++pb) {
+#pragma unroll
+    for (int pp = 0; pp < 16; ++pp) {
+      const int p = 16 * pb + pp;
+      if (p >= nb) break;
+      const int buf = p & 1;
+      const T ipiv = (T)1 / rowbuf[buf][p];
+      T rp[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) rp[c] = rowbuf[buf][16 * q + c];
+      const T f = (i > p) ? colbuf[buf][i] * ipiv : (T)0;  // f = 0 keeps rows <= p
+#pragma unroll
+      for (int c = 0; c < 16; ++c) a[c] -= f * rp[c];
+      if (q == pb && i > p) a[pp] = -f;
+      if (p + 1 < nb) {  // publish the next pivot row and pivot column
+        if (i == p + 1) {
+#pragma unroll
+          for (int c = 0; c < 16; ++c) rowbuf[buf ^ 1][16 * q + c] = a[c];
+        }
+        if (pp < 15) {
+          if (q == pb) colbuf[buf ^ 1][i] = a[(pp + 1) & 15];
+        } else {
+          if (q == pb + 1) colbuf[buf ^ 1][i] = a[0];
+        }
       }
+      __syncthreads();
     }
-    __syncthreads();
   }
-  if (tid < 64) {
-    const T d = E[tid][tid];
-    if (tid < nb && (!(d > (T)0) || !isfinite((double)d))) {
+  // diagonal of U is D; L_kk^-1 = D^-1/2 L~^-1
+  if (q == (i >> 4)) {
+    T d = (T)1;
+#pragma unroll
+    for (int c = 0; c < 16; ++c)
+      if (c == (i & 15)) d = a[c];
+    if (i < nb && (!(d > (T)0) || !isfinite((double)d))) {
       status[0] = 3;
       status[1] = blk;
     }
-    fcol[tid] = (T)1 / sqrt(d);
+    colbuf[0][i] = (T)1 / sqrt(d);
   }
   __syncthreads();
-  for (int e = tid; e < 64 * 64; e += 256) {
-    const int i = e >> 6, c = e & 63;
-    E[i][c] = (c < i) ? E[i][c] * fcol[i] : ((c == i) ? fcol[i] : (T)0);
+  {
+    const T rs = colbuf[0][i];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      const int col = 16 * q + c;
+      E[i][col] = (col < i) ? a[c] * rs : ((col == i) ? rs : (T)0);
+    }
   }
   __syncthreads();
 
@@ -264,6 +302,105 @@ __global__ __launch_bounds__(256) void k_panel(T* __restrict__ S, T* __restrict_
       }
 }
 
+// ---------------------------------------------------------------------------
+// Update after panel [k0, k0+nb) of the factorization of one pivot block:
+//   trailing  S_ij -= L_i L_j^T     (lower 64x64 tiles of rows/cols >= k0+nb)
+//   carried   X_ic -= L_i X_k,c     (rows >= k0+nb, columns < k0+nb)
+// with L_i = S[i, k0:k0+nb] (just computed by the panel) and X_k the panel's
+// rows of the carried inverse.  One launch covers both tile kinds; every
+// workgroup issues all its loads (A, B and the C tile) before the first MFMA.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_rank64(T* __restrict__ S, T* __restrict__ Lv, int n,
+                                                int k0, int nb, int ntrail) {
+  typedef typename acc4<T>::type V4;
+  __shared__ T As[64][65];  // As[row][k]
+  __shared__ T Bs[64][65];  // Bs[col][k]
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int g = lane >> 4, nn = lane & 15;
+  const int wm = wave >> 1, wn = wave & 1;
+  const long long base = (long long)k0 + nb;
+  long long r0, c0;
+  T* C;
+  bool trail = (int)blockIdx.x < ntrail;
+  if (trail) {
+    const long long t = blockIdx.x;
+    int r = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while ((long long)(r + 1) * (r + 2) / 2 <= t) ++r;
+    while ((long long)r * (r + 1) / 2 > t) --r;
+    r0 = base + 64LL * r;
+    c0 = base + 64LL * (t - (long long)r * (r + 1) / 2);
+    C = S;
+  } else {
+    const long long t = blockIdx.x - ntrail;
+    const long long ncb = (base + 63) / 64;
+    r0 = base + 64LL * (t / ncb);
+    c0 = 64LL * (t % ncb);
+    C = Lv;
+  }
+  const long long cmax = trail ? n : base;
+  // A: L rows r0.., panel columns
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int rr = e >> 6, k = e & 63;
+    As[rr][k] = (r0 + rr < n && k < nb) ? S[(r0 + rr) * n + k0 + k] : (T)0;
+  }
+  // B: trailing -> L rows c0.. (B(k, j) = L[j][k]); carried -> X_k rows (B(k, c) = X[k0+k][c])
+  if (trail) {
+    for (int e = tid; e < 64 * 64; e += 256) {
+      const int cc = e >> 6, k = e & 63;
+      Bs[cc][k] = (c0 + cc < n && k < nb) ? S[(c0 + cc) * n + k0 + k] : (T)0;
+    }
+  } else {
+    for (int e = tid; e < 64 * 64; e += 256) {
+      const int k = e >> 6, cc = e & 63;
+      Bs[cc][k] = (k < nb && c0 + cc < cmax) ? Lv[(long long)(k0 + k) * n + c0 + cc] : (T)0;
+    }
+  }
+  // C is loaded up front; the 64 products are summed first and subtracted once
+  // (adding them one by one into the larger C would lose accuracy in FP32)
+  T cin[2][2][4];
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const long long row = r0 + wm * 32 + 16 * mt + acc_row<T>(g, i);
+        const long long col = c0 + wn * 32 + 16 * nt + nn;
+        cin[mt][nt][i] = (row < n && col < cmax) ? C[row * n + col] : (T)0;
+      }
+  V4 acc[2][2];
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) acc[mt][nt] = V4{0, 0, 0, 0};
+  __syncthreads();
+#pragma unroll 4
+  for (int ks = 0; ks < 16; ++ks) {
+    const int k = 4 * ks + g;
+    T av[2], bv[2];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) av[mt] = As[wm * 32 + 16 * mt + nn][k];
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) bv[nt] = Bs[wn * 32 + 16 * nt + nn][k];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt) acc[mt][nt] = mfma16(av[mt], bv[nt], acc[mt][nt]);
+  }
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const long long row = r0 + wm * 32 + 16 * mt + acc_row<T>(g, i);
+        const long long col = c0 + wn * 32 + 16 * nt + nn;
+        if (row < n && col < cmax) C[row * n + col] = cin[mt][nt][i] - acc[mt][nt][i];
+      }
+}
+
 template <typename T>
 __global__ void k_identity(T* __restrict__ X, int n) {
   const long long tot = (long long)n * n;
@@ -318,15 +455,12 @@ int launch_stage2(const Stage2Args& a, hipStream_t st) {
                          nrow_wg, a.status, j);
       SLAB_LAUNCH_CHECK();
       if (nrow > 0) {
-        const T* P = S + (long long)(k0 + nb) * n + k0;  // rows below, panel columns
-        int rc = launch_gemm<T>(false, true, nrow, nrow, nb, (T)-1, P, n, 0, P, n, 0, (T)1,
-                                S + (long long)(k0 + nb) * n + (k0 + nb), n, 0, 1, GEMM_LOWER_C,
-                                st);
-        if (rc) return rc;
-        rc = launch_gemm<T>(false, false, nrow, k0 + nb, nb, (T)-1, P, n, 0,
-                            Li + (long long)k0 * n, n, 0, (T)1, Li + (long long)(k0 + nb) * n, n,
-                            0, 1, 0, st);
-        if (rc) return rc;
+        const long long tr = (nrow + 63) / 64;
+        const int ntrail = (int)(tr * (tr + 1) / 2);
+        const int naug = (int)(tr * ((k0 + nb + 63) / 64));
+        hipLaunchKernelGGL((k_rank64<T>), dim3(ntrail + naug), dim3(256), 0, st, S, Li, n, k0, nb,
+                           ntrail);
+        SLAB_LAUNCH_CHECK();
       }
     }
     if (j < m - 1) {
@@ -343,129 +477,104 @@ template int launch_stage2<double>(const Stage2Args&, hipStream_t);
 // ---------------------------------------------------------------------------
 // Block-vector product for the sweeping solve (Alg. 2):
 //   y = beta * xin + alpha * M x,  x and y hold nrhs columns of length n.
-// Grid: 64-row tiles x k-splits; each k-split writes a partial sum, and the
-// last workgroup of a row tile (atomic ticket) adds the partials in fixed
-// order, so the result is deterministic.
+// 16 columns at a time on 16x16x4 MFMA tiles.  A workgroup owns 16 rows; its
+// eight waves split k and are reduced through LDS, so no result crosses a
+// workgroup (a device-scope fence would write back every L2 of the chip).
+// Each lane loads 16 contiguous bytes of M and of x per step, which feed
+// VEC consecutive MFMA k-steps (k permuted consistently in A and B).
 // ---------------------------------------------------------------------------
-constexpr int GEMV_MAXC = 32;
+constexpr int BMV_COLS = 16;
+constexpr int BMV_WAVES = 8;
 
-static int gemv_splits(int n) {
-  const int tiles = (n + 63) / 64;
-  int nks = std::max(1, 512 / tiles);
-  return std::min(nks, tiles);
-}
 size_t gemv_work_bytes(int n, int nrhs, int elem) {
-  return (size_t)gemv_splits(n) * nrhs * n * elem;
+  (void)n; (void)nrhs; (void)elem;
+  return 256;
 }
-int gemv_counter_count(int n) { return (n + 63) / 64; }
+int gemv_counter_count(int n) { (void)n; return 1; }
 
 template <typename T, bool TR, bool LOWER>
-__global__ __launch_bounds__(256) void k_gemv(int n, int nrhs, T alpha, const T* __restrict__ M,
-                                              const T* __restrict__ x, T beta,
-                                              const T* __restrict__ xin, T* __restrict__ y,
-                                              T* __restrict__ work, int* __restrict__ counters,
-                                              int nks) {
-  __shared__ T Ms[64][65];
-  __shared__ T xs[GEMV_MAXC][64];
-  __shared__ int last;
-  const int tile = blockIdx.x, ks = blockIdx.y;
-  const int i0 = tile * 64;
+__global__ __launch_bounds__(512) void k_bmv(int n, int nc, T alpha, const T* __restrict__ M,
+                                             const T* __restrict__ x, T beta,
+                                             const T* __restrict__ xin, T* __restrict__ y) {
+  typedef typename acc4<T>::type V4;
+  constexpr int VEC = 16 / sizeof(T);   // elements per 16-byte load
+  constexpr int KS = 4 * VEC;           // k covered by one load per lane
+  __shared__ T red[BMV_WAVES][16][17];
+  const int row0 = blockIdx.x * 16;
   const int tid = threadIdx.x;
-  const int ii = tid & 63, cg = tid >> 6;
-  const int ktiles = (n + 63) / 64;
-  const int per = (ktiles + nks - 1) / nks;
-  int kt0 = ks * per, kt1 = std::min(ktiles, kt0 + per);
+  const int wave = tid >> 6, lane = tid & 63;
+  const int g = lane >> 4, nn = lane & 15;
+  int klo = 0, khi = n;
   if (LOWER) {
-    if (!TR) kt1 = std::min(kt1, tile + 1);   // k <= i
-    else kt0 = std::max(kt0, tile);           // k >= i
+    if (!TR) khi = min(n, row0 + 16);      // M(i,k) = 0 for k > i
+    else klo = row0;                       // M(i,k) = 0 for k < i
   }
-  T acc[GEMV_MAXC / 4];
+  // split [klo, khi) over the waves in whole KS chunks
+  const int nch = (khi - klo + KS - 1) / KS;
+  const int per = (nch + BMV_WAVES - 1) / BMV_WAVES;
+  const int c_begin = wave * per, c_end = min(nch, c_begin + per);
+  const int row = row0 + nn;
+  const bool rowok = row < n;
+  const bool colok = nn < nc;
+  V4 acc = V4{0, 0, 0, 0};
+#pragma unroll 4
+  for (int ch = c_begin; ch < c_end; ++ch) {
+    const int kb = klo + ch * KS + VEC * g;   // this lane's first k of the chunk
+    T av[VEC], bv[VEC];
+    if (!TR && rowok && kb + VEC <= n && ((((size_t)row * n + kb) * sizeof(T)) & 15) == 0) {
+      typedef T vt __attribute__((ext_vector_type(VEC)));
+      const vt v = *(const vt*)(M + (size_t)row * n + kb);
 #pragma unroll
-  for (int q = 0; q < GEMV_MAXC / 4; ++q) acc[q] = (T)0;
-  for (int kt = kt0; kt < kt1; ++kt) {
-    const int k0 = kt * 64;
-    for (int e = tid; e < 64 * 64; e += 256) {
-      const int a = e >> 6, bq = e & 63;  // a slow, bq fast (coalesced)
-      T v;
-      if (!TR) {  // M(i0+a, k0+bq) = M[(i0+a)*n + k0+bq]
-        v = (i0 + a < n && k0 + bq < n) ? M[(long long)(i0 + a) * n + k0 + bq] : (T)0;
-        Ms[a][bq] = v;
-      } else {    // M(i0+bq, k0+a) = M[(k0+a)*n + i0+bq]
-        v = (i0 + bq < n && k0 + a < n) ? M[(long long)(k0 + a) * n + i0 + bq] : (T)0;
-        Ms[bq][a] = v;
+      for (int t = 0; t < VEC; ++t) av[t] = v[t];
+    } else {
+#pragma unroll
+      for (int t = 0; t < VEC; ++t) {
+        const int k = kb + t;
+        av[t] = (rowok && k < n) ? (TR ? M[(size_t)k * n + row] : M[(size_t)row * n + k]) : (T)0;
       }
     }
-    for (int e = tid; e < nrhs * 64; e += 256) {
-      const int c = e >> 6, kk = e & 63;
-      xs[c][kk] = (k0 + kk < n) ? x[(long long)c * n + k0 + kk] : (T)0;
-    }
-    __syncthreads();
 #pragma unroll
-    for (int q = 0; q < GEMV_MAXC / 4; ++q) {
-      const int c = cg + 4 * q;
-      if (c < nrhs) {
-        T s = acc[q];
-#pragma unroll 16
-        for (int kk = 0; kk < 64; ++kk) s += Ms[ii][kk] * xs[c][kk];
-        acc[q] = s;
-      }
+    for (int t = 0; t < VEC; ++t) {
+      const int k = kb + t;
+      bv[t] = (colok && k < n) ? x[(size_t)nn * n + k] : (T)0;
     }
-    __syncthreads();
-  }
-  const int i = i0 + ii;
-  if (nks == 1) {
 #pragma unroll
-    for (int q = 0; q < GEMV_MAXC / 4; ++q) {
-      const int c = cg + 4 * q;
-      if (c < nrhs && i < n) {
-        T v = alpha * acc[q];
-        if (xin) v += beta * xin[(long long)c * n + i];
-        y[(long long)c * n + i] = v;
-      }
-    }
-    return;
+    for (int t = 0; t < VEC; ++t) acc = mfma16(av[t], bv[t], acc);
   }
+  // acc[i]: row 16 blockIdx + acc_row(g, i), column nn; reduce the waves
 #pragma unroll
-  for (int q = 0; q < GEMV_MAXC / 4; ++q) {
-    const int c = cg + 4 * q;
-    if (c < nrhs && i < n) work[((long long)ks * nrhs + c) * n + i] = acc[q];
-  }
-  __threadfence();
+  for (int i = 0; i < 4; ++i) red[wave][acc_row<T>(g, i)][nn] = acc[i];
   __syncthreads();
-  if (tid == 0) last = (atomicAdd(&counters[tile], 1) == nks - 1);
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
+  if (tid < 256) {
+    const int rr = tid >> 4, c = tid & 15;
+    const int r = row0 + rr;
+    if (r < n && c < nc) {
+      T sum = (T)0;
 #pragma unroll
-  for (int q = 0; q < GEMV_MAXC / 4; ++q) {
-    const int c = cg + 4 * q;
-    if (c < nrhs && i < n) {
-      T s = (T)0;
-      for (int k = 0; k < nks; ++k) s += work[((long long)k * nrhs + c) * n + i];
-      T v = alpha * s;
-      if (xin) v += beta * xin[(long long)c * n + i];
-      y[(long long)c * n + i] = v;
+      for (int w = 0; w < BMV_WAVES; ++w) sum += red[w][rr][c];
+      T v = alpha * sum;
+      if (xin) v += beta * xin[(size_t)c * n + r];
+      y[(size_t)c * n + r] = v;
     }
   }
-  if (tid == 0) counters[tile] = 0;
 }
 
 template <typename T>
 int launch_gemv(bool tr, bool lower, int n, int nrhs, T alpha, const T* M, const T* x, T beta,
                 const T* xin, T* y, void* work, int* counters, hipStream_t st) {
-  const int nks = gemv_splits(n);
-  for (int c0 = 0; c0 < nrhs; c0 += GEMV_MAXC) {
-    const int nc = std::min(GEMV_MAXC, nrhs - c0);
+  (void)work; (void)counters;
+  for (int c0 = 0; c0 < nrhs; c0 += BMV_COLS) {
+    const int nc = std::min(BMV_COLS, nrhs - c0);
     const long long off = (long long)c0 * n;
-    dim3 grid((n + 63) / 64, nks);
-#define SLAB_GEMV_CASE(TRV, LOV)                                                                \
-  hipLaunchKernelGGL((k_gemv<T, TRV, LOV>), grid, dim3(256), 0, st, n, nc, alpha, M, x + off,  \
-                     beta, xin ? xin + off : nullptr, y + off, (T*)work, counters, nks)
-    if (!tr && !lower) SLAB_GEMV_CASE(false, false);
-    else if (!tr && lower) SLAB_GEMV_CASE(false, true);
-    else if (tr && !lower) SLAB_GEMV_CASE(true, false);
-    else SLAB_GEMV_CASE(true, true);
-#undef SLAB_GEMV_CASE
+    dim3 grid((n + 15) / 16);
+#define SLAB_BMV_CASE(TRV, LOV)                                                                 \
+  hipLaunchKernelGGL((k_bmv<T, TRV, LOV>), grid, dim3(64 * BMV_WAVES), 0, st, n, nc, alpha, M, \
+                     x + off, beta, xin ? xin + off : nullptr, y + off)
+    if (!tr && !lower) SLAB_BMV_CASE(false, false);
+    else if (!tr && lower) SLAB_BMV_CASE(false, true);
+    else if (tr && !lower) SLAB_BMV_CASE(true, false);
+    else SLAB_BMV_CASE(true, true);
+#undef SLAB_BMV_CASE
     SLAB_LAUNCH_CHECK();
   }
   return SLAB_OK;

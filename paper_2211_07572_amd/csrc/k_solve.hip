@@ -11,15 +11,18 @@ namespace slab {
 // Gl_r of the top-down block recursion (A_ee = L U, L_{r,r-1} = -W_r Gl_{r-1},
 // U_rr = Gl_r^-1, U_{r-1,r} = -W_r):
 //   A_ee x = y:   z_r = y_r + W_r Gl_{r-1} z_{r-1};   x_r = Gl_r (z_r + W_{r+1} x_{r+1})
-//   A_ee^T x = y: z_r = Gl_r^T (y_r + W_r z_{r-1});  x_{r-1} = z_{r-1} + Gl_{r-1}^T W_r x_r
+//   A_ee^T x = y: z_r = Gl_r^T (y_r + W_r z_{r-1});  x_r = z_r + Gl_r^T W_{r+1} x_{r+1}
 // MODE 0 (reduced right-hand side): y = f_e; emits w * x at the slab's first
 //   and last column, xb[s][0|1][c][r].
-// MODE 1 (interior): y = f_e + wL u_o(s-1) + wR u_o(s); writes (or adds) x and
-//   the interface values u_o(s) into the natural-order output.
-// One workgroup per (slab, group of NCG columns); thread = (row i, column slot).
+// MODE 1 (interior): y = f_e + wL u_o(s-1) + wR u_o(s); writes (or adds) x
+//   into the natural-order output (the interface values go through
+//   k_interface_out).
+// One workgroup per (slab, group of 256/BP columns); thread = (row i, column).
+// Software pipeline: while row step r is computed, the block inverse, edge
+// weights and right-hand side of the next step are loaded into registers and
+// then parked in the other half of double-buffered LDS, so each step costs one
+// barrier and no exposed global-memory latency.
 // ---------------------------------------------------------------------------
-constexpr int NCG = 16;
-
 struct SweepArgs {
   int n1, n2, b, m, nrhs;
   long long ld;       // leading dimension of rhs
@@ -35,191 +38,196 @@ struct SweepArgs {
   int accumulate;
 };
 
-template <typename T, int BP, bool TRANS, int MODE>
+template <typename T, typename TU, int BP, bool TRANS, int MODE>
 __global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
-  constexpr int SLOTS = 256 / BP;
-  constexpr int Q = (NCG + SLOTS - 1) / SLOTS;
-  __shared__ T Gs[BP][BP + 1];
-  __shared__ T Va[NCG][BP];
-  __shared__ T Vb[NCG][BP];
+  constexpr int NC = 256 / BP;            // columns per workgroup
+  constexpr int GPT = BP * BP / 256;      // block-inverse elements loaded per thread
+  constexpr int D = BP == 64 ? 4 : 8;     // prefetch depth in row steps
+  __shared__ T Gs[2][BP][BP + 1];
+  __shared__ T Ws[2][BP];
+  __shared__ T Ys[2][NC][BP + 1];
+  __shared__ T Vs[2][NC][BP + 1];
   const int s = blockIdx.x;
-  const int cbase = blockIdx.y * NCG;
-  const int n2 = a.n2, b = a.b;
+  // kernel-argument fields copied to locals (the lambdas below must not take
+  // the address of the argument block)
+  const int n2 = a.n2, b = a.b, nrhs = a.nrhs;
+  const long long ld = a.ld, ldo = a.ldo;
+  const double* __restrict__ wh = a.wh;
+  const double* __restrict__ wv = a.wv;
+  const double* __restrict__ rhs = a.rhs;
+  double* __restrict__ out_g = a.out;
+  T* __restrict__ xbuf = (T*)a.xb;
   const int tid = threadIdx.x;
-  const int i = tid % BP, slot = tid / BP;
-  const long long c0 = (long long)s * (b + 1);
-  const long long ci = c0 + (i < b ? i : 0);
+  const int i = tid % BP, cl = tid / BP;
+  const int c = blockIdx.y * NC + cl;
+  const bool valid = c < nrhs;
   const bool act = i < b;
+  const long long c0 = (long long)s * (b + 1);
+  const long long ci = c0 + (act ? i : 0);
   const T* Gl = (const T*)a.Gl + (size_t)s * n2 * BP * BP;
-  T* zbuf = (T*)a.zbuf + (size_t)s * a.nrhs * n2 * BP;
-  const T* uo = (const T*)a.uo;
+  T* zbuf = (T*)a.zbuf + (size_t)s * nrhs * n2 * BP;
+  const TU* uo = (const TU*)a.uo;
+  const bool acc_out = MODE == 1 && a.accumulate;
 
-  auto loadG = [&](int r) {
-    const T* G = Gl + (size_t)r * BP * BP;
-    for (int e = tid; e < BP * BP; e += 256) Gs[e / BP][e % BP] = G[e];
-  };
-  auto wv_at = [&](int r) -> T {  // edge between rows r-1 and r of column ci; 0 outside
-    return (act && r >= 0 && r <= n2 - 1 + 1) ? (T)a.wv[ci * (n2 + 1) + r] : (T)0;
-  };
-  auto rhs_at = [&](int c, int r) -> T {
-    if (!act) return (T)0;
-    double v = a.rhs[(long long)c * a.ld + ci * n2 + r];
+  // register ring: operands of the next D row steps
+  T rg[D][GPT];
+  T rw[D], ry[D];
+  double ru[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+#pragma unroll
+    for (int e = 0; e < GPT; ++e) rg[d][e] = (T)0;
+    rw[d] = ry[d] = (T)0;
+    ru[d] = 0.0;
+  }
+  auto load_y = [&](int r) __attribute__((always_inline)) -> T {
+    if (!valid || !act) return (T)0;
+    double v = rhs[(long long)c * ld + ci * n2 + r];
     if (MODE == 1) {
       if (i == 0 && s > 0)
-        v += a.wh[c0 * n2 + r] * (double)uo[((size_t)(s - 1) * a.nrhs + c) * n2 + r];
-      if (i == b - 1) v += a.wh[(c0 + b) * n2 + r] * (double)uo[((size_t)s * a.nrhs + c) * n2 + r];
+        v += wh[c0 * n2 + r] * (double)uo[((size_t)(s - 1) * nrhs + c) * n2 + r];
+      if (i == b - 1) v += wh[(c0 + b) * n2 + r] * (double)uo[((size_t)s * nrhs + c) * n2 + r];
     }
     return (T)v;
   };
-
-  // ---------------- forward sweep: z_r, stored in zbuf ----------------
-  for (int r = 0; r < n2; ++r) {
-    __syncthreads();
-    const T w = (r > 0) ? wv_at(r) : (T)0;
-    if (!TRANS) {
-      if (r > 0) loadG(r - 1);
-      __syncthreads();
+  auto load_w = [&](int r) __attribute__((always_inline)) -> T {  // edge between rows r-1 and r (0 outside 1..n2-1)
+    return (tid < BP && act && r >= 1 && r <= n2 - 1) ? (T)wv[ci * (n2 + 1) + r] : (T)0;
+  };
+  // forward step r: G = Gl_{r-1} (A x) or Gl_r (A^T x), w = W_r, y = y_r
+  auto load_fwd = [&](int d, int r) __attribute__((always_inline)) {
+    const int gr = TRANS ? r : r - 1;
+    if (gr >= 0) {
+      const T* G = Gl + (size_t)gr * BP * BP;
 #pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        const int cl = slot + q * SLOTS;
-        const int c = cbase + cl;
-        if (cl < NCG && c < a.nrhs) {
-          T t = (T)0;
-          if (r > 0) {
-#pragma unroll 8
-            for (int k = 0; k < BP; ++k) t += Gs[i][k] * Va[cl][k];
-          }
-          const T z = rhs_at(c, r) + w * t;
-          Vb[cl][i] = z;
-          zbuf[((size_t)c * n2 + r) * BP + i] = z;
-        }
-      }
-    } else {
-      loadG(r);
-#pragma unroll
-      for (int q = 0; q < Q; ++q) {  // u = y_r + W_r z_{r-1}
-        const int cl = slot + q * SLOTS;
-        const int c = cbase + cl;
-        if (cl < NCG && c < a.nrhs) Vb[cl][i] = rhs_at(c, r) + (r > 0 ? w * Va[cl][i] : (T)0);
-      }
-      __syncthreads();
-#pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        const int cl = slot + q * SLOTS;
-        const int c = cbase + cl;
-        T z = (T)0;
-        if (cl < NCG && c < a.nrhs) {
-#pragma unroll 8
-          for (int k = 0; k < BP; ++k) z += Gs[k][i] * Vb[cl][k];
-          zbuf[((size_t)c * n2 + r) * BP + i] = z;
-        }
-        __syncthreads();
-        if (cl < NCG && c < a.nrhs) Vb[cl][i] = z;
-      }
+      for (int e = 0; e < GPT; ++e) rg[d][e] = G[tid + 256 * e];
     }
-    __syncthreads();
-    // Vb -> Va
+    rw[d] = load_w(r);
+    ry[d] = load_y(r);
+  };
+  // backward step r: G = Gl_r, w = W_{r+1}, z = z_r (+ old outputs when accumulating)
+  auto load_bwd = [&](int d, int r) __attribute__((always_inline)) {
+    const T* G = Gl + (size_t)r * BP * BP;
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int cl = slot + q * SLOTS;
-      if (cl < NCG) Va[cl][i] = Vb[cl][i];
+    for (int e = 0; e < GPT; ++e) rg[d][e] = G[tid + 256 * e];
+    rw[d] = load_w(r + 1);
+    ry[d] = valid ? zbuf[((size_t)c * n2 + r) * BP + i] : (T)0;
+    ru[d] = (MODE == 1 && valid && acc_out && act) ? out_g[(long long)c * ldo + ci * n2 + r] : 0.0;
+  };
+  auto park = [&](int d, int buf) __attribute__((always_inline)) {
+#pragma unroll
+    for (int e = 0; e < GPT; ++e) {
+      const int idx = tid + 256 * e;
+      Gs[buf][idx / BP][idx % BP] = rg[d][e];
+    }
+    if (tid < BP) Ws[buf][tid] = rw[d];
+    Ys[buf][cl][i] = ry[d];
+  };
+
+  // ---------------- forward sweep: z_r (stored in zbuf) ----------------
+#pragma unroll
+  for (int d = 0; d < D; ++d)
+    if (d < n2) load_fwd(d, d);
+  Vs[0][cl][i] = (T)0;
+  for (int r0 = 0; r0 < n2; r0 += D) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const int r = r0 + d;
+      if (r < n2) {  // uniform
+      const int cur = r & 1;
+      park(d, cur);
+      if (r + D < n2) load_fwd(d, r + D);
+      __syncthreads();
+      T out;
+      if (!TRANS) {
+        T t = (T)0;
+        if (r > 0) {
+#pragma unroll 8
+          for (int k = 0; k < BP; ++k) t += Gs[cur][i][k] * Vs[cur][cl][k];
+        }
+        out = Ys[cur][cl][i] + Ws[cur][i] * t;
+      } else {
+        T t = (T)0;
+#pragma unroll 8
+        for (int k = 0; k < BP; ++k)
+          t += Gs[cur][k][i] * (Ys[cur][cl][k] + Ws[cur][k] * Vs[cur][cl][k]);
+        out = t;
+      }
+      if (valid) zbuf[((size_t)c * n2 + r) * BP + i] = out;
+      Vs[cur ^ 1][cl][i] = out;
+      }
     }
   }
+  __syncthreads();
 
-  // ---------------- backward sweep ----------------
-  for (int r = n2 - 1; r >= 0; --r) {
-    __syncthreads();
-    if (!TRANS) {
-      // u = z_r + W_{r+1} x_{r+1};  x_r = Gl_r u
-      loadG(r);
-      const T w = (r + 1 <= n2 - 1) ? wv_at(r + 1) : (T)0;
+  // ---------------- backward sweep: x_r ----------------
 #pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        const int cl = slot + q * SLOTS;
-        const int c = cbase + cl;
-        if (cl < NCG && c < a.nrhs) {
-          const T z = zbuf[((size_t)c * n2 + r) * BP + i];
-          Vb[cl][i] = z + (r < n2 - 1 ? w * Va[cl][i] : (T)0);
-        }
-      }
+  for (int d = 0; d < D; ++d)
+    if (d < n2) load_bwd(d, n2 - 1 - d);
+  Vs[0][cl][i] = (T)0;
+  for (int t0 = 0; t0 < n2; t0 += D) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const int it = t0 + d;
+      if (it < n2) {  // uniform
+      const int r = n2 - 1 - it;
+      const int cur = it & 1;
+      park(d, cur);
+      const double uold = ru[d];
+      if (it + D < n2) load_bwd(d, r - D);
       __syncthreads();
-#pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        const int cl = slot + q * SLOTS;
-        const int c = cbase + cl;
-        T x = (T)0;
-        if (cl < NCG && c < a.nrhs) {
+      T x;
+      if (!TRANS) {
+        T t = (T)0;
 #pragma unroll 8
-          for (int k = 0; k < BP; ++k) x += Gs[i][k] * Vb[cl][k];
-        }
-        __syncthreads();
-        if (cl < NCG && c < a.nrhs) Vb[cl][i] = x;
-      }
-    } else {
-      // x_{n-1} = z_{n-1};  x_r = z_r + Gl_r^T W_{r+1} x_{r+1}
-      if (r < n2 - 1) {
-        loadG(r);
-        const T w = wv_at(r + 1);
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-          const int cl = slot + q * SLOTS;
-          if (cl < NCG) Vb[cl][i] = w * Va[cl][i];
-        }
-        __syncthreads();
-      }
-#pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        const int cl = slot + q * SLOTS;
-        const int c = cbase + cl;
-        T x = (T)0;
-        if (cl < NCG && c < a.nrhs) {
-          x = zbuf[((size_t)c * n2 + r) * BP + i];
-          if (r < n2 - 1) {
+        for (int k = 0; k < BP; ++k)
+          t += Gs[cur][i][k] * (Ys[cur][cl][k] + Ws[cur][k] * Vs[cur][cl][k]);
+        x = t;
+      } else {
+        T t = (T)0;
 #pragma unroll 8
-            for (int k = 0; k < BP; ++k) x += Gs[k][i] * Vb[cl][k];
-          }
-        }
-        __syncthreads();
-        if (cl < NCG && c < a.nrhs) Vb[cl][i] = x;
+        for (int k = 0; k < BP; ++k) t += Gs[cur][k][i] * (Ws[cur][k] * Vs[cur][cl][k]);
+        x = Ys[cur][cl][i] + t;
       }
-    }
-    __syncthreads();
-    // outputs of row r, then Vb -> Va
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int cl = slot + q * SLOTS;
-      const int c = cbase + cl;
-      if (cl < NCG && c < a.nrhs) {
-        const T x = Vb[cl][i];
+      Vs[cur ^ 1][cl][i] = x;
+      if (valid) {
         if (MODE == 0) {
-          T* xb = (T*)a.xb;
           if (i == 0)
-            xb[(((size_t)s * 2 + 0) * a.nrhs + c) * n2 + r] = (T)(a.wh[c0 * n2 + r] * (double)x);
+            xbuf[(((size_t)s * 2 + 0) * nrhs + c) * n2 + r] = (T)(wh[c0 * n2 + r] * (double)x);
           if (i == b - 1)
-            xb[(((size_t)s * 2 + 1) * a.nrhs + c) * n2 + r] =
-                (T)(a.wh[(c0 + b) * n2 + r] * (double)x);
-        } else {
-          if (act) {
-            double* o = a.out + (long long)c * a.ldo + ci * n2 + r;
-            *o = a.accumulate ? *o + (double)x : (double)x;
-          }
-          if (i == 0) {
-            double* o = a.out + (long long)c * a.ldo + (c0 + b) * n2 + r;
-            const double v = (double)uo[((size_t)s * a.nrhs + c) * n2 + r];
-            *o = a.accumulate ? *o + v : v;
-          }
+            xbuf[(((size_t)s * 2 + 1) * nrhs + c) * n2 + r] =
+                (T)(wh[(c0 + b) * n2 + r] * (double)x);
+        } else if (act) {
+          out_g[(long long)c * ldo + ci * n2 + r] = acc_out ? uold + (double)x : (double)x;
         }
       }
-      if (cl < NCG) Va[cl][i] = Vb[cl][i];
+      }
     }
   }
 }
 
+// Interface values u_o(j) (reduced solution, [j][c][r]) into the natural-order
+// output column j(b+1)+b, written or added.
+template <typename TR>
+__global__ void k_interface_out(int n2, int b, int m, int nrhs, long long ldo,
+                                const TR* __restrict__ uo, double* __restrict__ out,
+                                int accumulate) {
+  const long long tot = (long long)m * nrhs * n2;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long r = e % n2;
+    const long long c = (e / n2) % nrhs;
+    const long long j = e / ((long long)n2 * nrhs);
+    double* o = out + c * ldo + (j * (b + 1) + b) * n2 + r;
+    const double v = (double)uo[e];
+    *o = accumulate ? *o + v : v;
+  }
+}
+
 // f~_j = f_o(j) + xb[j][right] + xb[j+1][left]   (FP64 sum, stored in T)
-template <typename T>
+template <typename T, typename TR>
 __global__ void k_reduced_rhs(int n2, int b, int m, int nrhs, long long ld,
                               const double* __restrict__ rhs, const T* __restrict__ xb,
-                              T* __restrict__ ft) {
+                              TR* __restrict__ ft) {
   const long long tot = (long long)m * nrhs * n2;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot;
        e += (long long)gridDim.x * blockDim.x) {
@@ -230,11 +238,11 @@ __global__ void k_reduced_rhs(int n2, int b, int m, int nrhs, long long ld,
     double v = rhs[c * ld + cj * n2 + r];
     v += (double)xb[((j * 2 + 1) * nrhs + c) * n2 + r];
     if (j + 1 < m) v += (double)xb[(((j + 1) * 2 + 0) * nrhs + c) * n2 + r];
-    ft[e] = (T)v;
+    ft[e] = (TR)v;
   }
 }
 
-template <typename T, int BP>
+template <typename T, typename TR, int BP>
 static int sweeps_bp(const SolveArgs& A, const double* rhs, long long ld_rhs, double* out,
                      long long ld_out, int accumulate, hipStream_t st) {
   SweepArgs s;
@@ -243,69 +251,78 @@ static int sweeps_bp(const SolveArgs& A, const double* rhs, long long ld_rhs, do
   s.uo = A.ft; s.rhs = rhs; s.out = out; s.accumulate = accumulate;
   const int n = A.n2, m = A.m, nrhs = A.nrhs;
   const long long nsq = (long long)n * n;
-  dim3 grid(m, (nrhs + NCG - 1) / NCG);
+  dim3 grid(m, (nrhs + 256 / BP - 1) / (256 / BP));
   // (i) reduced right-hand side
-  if (A.transpose) hipLaunchKernelGGL((k_sweep<T, BP, true, 0>), grid, dim3(256), 0, st, s);
-  else hipLaunchKernelGGL((k_sweep<T, BP, false, 0>), grid, dim3(256), 0, st, s);
+  if (A.transpose) hipLaunchKernelGGL((k_sweep<T, TR, BP, true, 0>), grid, dim3(256), 0, st, s);
+  else hipLaunchKernelGGL((k_sweep<T, TR, BP, false, 0>), grid, dim3(256), 0, st, s);
   SLAB_LAUNCH_CHECK();
   {
     long long tot = (long long)m * nrhs * n;
     unsigned g = (unsigned)std::min<long long>((tot + 255) / 256, 16384);
-    hipLaunchKernelGGL((k_reduced_rhs<T>), dim3(g), dim3(256), 0, st, n, A.b, m, nrhs, ld_rhs, rhs,
-                       (const T*)A.xb, (T*)A.ft);
+    hipLaunchKernelGGL((k_reduced_rhs<T, TR>), dim3(g), dim3(256), 0, st, n, A.b, m, nrhs, ld_rhs,
+                       rhs, (const T*)A.xb, (TR*)A.ft);
     SLAB_LAUNCH_CHECK();
   }
   // (ii) Alg. 2 with the block Cholesky factors: T = R R^T, R_jj = L_j, R_{j+1,j} = Z_j^T
-  T* ft = (T*)A.ft;
-  T* yt = (T*)A.yt;
-  T* tt = (T*)A.tt;
-  const T* Li = (const T*)A.Linv;
-  const T* Z = (const T*)A.Z;
+  TR* ft = (TR*)A.ft;
+  TR* yt = (TR*)A.yt;
+  TR* tt = (TR*)A.tt;
+  const TR* Li = (const TR*)A.Linv;
+  const TR* Z = (const TR*)A.Z;
   const long long vs = (long long)nrhs * n;
   for (int j = 0; j < m; ++j) {
-    const T* src = ft + j * vs;
+    const TR* src = ft + j * vs;
     if (j > 0) {
-      int rc = launch_gemv<T>(true, false, n, nrhs, (T)-1, Z + (j - 1) * nsq, yt + (j - 1) * vs,
-                              (T)1, ft + j * vs, tt, A.gemv_work, A.gemv_counters, st);
+      int rc = launch_gemv<TR>(true, false, n, nrhs, (TR)-1, Z + (j - 1) * nsq, yt + (j - 1) * vs,
+                              (TR)1, ft + j * vs, tt, A.gemv_work, A.gemv_counters, st);
       if (rc) return rc;
       src = tt;
     }
-    int rc = launch_gemv<T>(false, true, n, nrhs, (T)1, Li + j * nsq, src, (T)0, nullptr,
+    int rc = launch_gemv<TR>(false, true, n, nrhs, (TR)1, Li + j * nsq, src, (TR)0, nullptr,
                             yt + j * vs, A.gemv_work, A.gemv_counters, st);
     if (rc) return rc;
   }
   for (int j = m - 1; j >= 0; --j) {
-    const T* src = yt + j * vs;
+    const TR* src = yt + j * vs;
     if (j < m - 1) {
-      int rc = launch_gemv<T>(false, false, n, nrhs, (T)-1, Z + j * nsq, ft + (j + 1) * vs, (T)1,
+      int rc = launch_gemv<TR>(false, false, n, nrhs, (TR)-1, Z + j * nsq, ft + (j + 1) * vs, (TR)1,
                               yt + j * vs, tt, A.gemv_work, A.gemv_counters, st);
       if (rc) return rc;
       src = tt;
     }
-    int rc = launch_gemv<T>(true, true, n, nrhs, (T)1, Li + j * nsq, src, (T)0, nullptr,
+    int rc = launch_gemv<TR>(true, true, n, nrhs, (TR)1, Li + j * nsq, src, (TR)0, nullptr,
                             ft + j * vs, A.gemv_work, A.gemv_counters, st);
     if (rc) return rc;
   }
-  // (iii) interior back substitution, interface values written alongside
-  if (A.transpose) hipLaunchKernelGGL((k_sweep<T, BP, true, 1>), grid, dim3(256), 0, st, s);
-  else hipLaunchKernelGGL((k_sweep<T, BP, false, 1>), grid, dim3(256), 0, st, s);
+  // (iii) interior back substitution, and the interface values
+  if (A.transpose) hipLaunchKernelGGL((k_sweep<T, TR, BP, true, 1>), grid, dim3(256), 0, st, s);
+  else hipLaunchKernelGGL((k_sweep<T, TR, BP, false, 1>), grid, dim3(256), 0, st, s);
   SLAB_LAUNCH_CHECK();
+  {
+    long long tot = (long long)m * nrhs * n;
+    unsigned g = (unsigned)std::min<long long>((tot + 255) / 256, 16384);
+    hipLaunchKernelGGL((k_interface_out<TR>), dim3(g), dim3(256), 0, st, n, A.b, m, nrhs, ld_out,
+                       (const TR*)A.ft, out, accumulate);
+    SLAB_LAUNCH_CHECK();
+  }
   return SLAB_OK;
 }
 
-template <typename T>
+template <typename T, typename TR>
 int launch_solve_pass(const SolveArgs& a, const double* rhs, long long ld_rhs, double* out,
                       long long ld_out, int accumulate, hipStream_t st) {
   switch (padded_block(a.b)) {
-    case 16: return sweeps_bp<T, 16>(a, rhs, ld_rhs, out, ld_out, accumulate, st);
-    case 32: return sweeps_bp<T, 32>(a, rhs, ld_rhs, out, ld_out, accumulate, st);
-    default: return sweeps_bp<T, 64>(a, rhs, ld_rhs, out, ld_out, accumulate, st);
+    case 16: return sweeps_bp<T, TR, 16>(a, rhs, ld_rhs, out, ld_out, accumulate, st);
+    case 32: return sweeps_bp<T, TR, 32>(a, rhs, ld_rhs, out, ld_out, accumulate, st);
+    default: return sweeps_bp<T, TR, 64>(a, rhs, ld_rhs, out, ld_out, accumulate, st);
   }
 }
-template int launch_solve_pass<float>(const SolveArgs&, const double*, long long, double*,
-                                      long long, int, hipStream_t);
-template int launch_solve_pass<double>(const SolveArgs&, const double*, long long, double*,
-                                       long long, int, hipStream_t);
+template int launch_solve_pass<float, float>(const SolveArgs&, const double*, long long, double*,
+                                             long long, int, hipStream_t);
+template int launch_solve_pass<double, double>(const SolveArgs&, const double*, long long,
+                                               double*, long long, int, hipStream_t);
+template int launch_solve_pass<double, float>(const SolveArgs&, const double*, long long,
+                                              double*, long long, int, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Residual r = f - A u (FP64) with per-column partial sums of r^2 and f^2.

@@ -384,7 +384,8 @@ __global__ __launch_bounds__(256) void k_schur(const double* __restrict__ wh, in
 //   T_{j,j+1} = -PLR[j+1] (lower part), -PRL[j+1]^T (upper part)
 // A_oo(j): diagonal of the interface column, -w on the vertical edges.
 // 32x32 tiles; upper tiles read the transposed source tile through LDS.
-// Outputs in the working precision T, and in FP64 when T64 pointers are given.
+// Outputs in the precision TO of the block factorization, and in FP64 when the
+// T64 pointers are given.
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ double diag_value(const double* __restrict__ wh,
@@ -404,14 +405,14 @@ __device__ __forceinline__ double diag_value(const double* __restrict__ wh,
   return v;
 }
 
-template <typename T>
+template <typename T, typename TO>
 __global__ __launch_bounds__(256) void k_assemble(const double* __restrict__ wh,
                                                   const double* __restrict__ wv, int n2, int b,
                                                   int m, const T* __restrict__ PRR,
                                                   const T* __restrict__ PLL,
                                                   const T* __restrict__ PLR,
-                                                  const T* __restrict__ PRL, T* __restrict__ Tdiag,
-                                                  T* __restrict__ Toff, double* __restrict__ Tdiag64,
+                                                  const T* __restrict__ PRL, TO* __restrict__ Tdiag,
+                                                  TO* __restrict__ Toff, double* __restrict__ Tdiag64,
                                                   double* __restrict__ Toff64) {
   __shared__ double tile[32][33];
   const int j = blockIdx.y;
@@ -447,10 +448,10 @@ __global__ __launch_bounds__(256) void k_assemble(const double* __restrict__ wh,
     }
     const size_t o = (size_t)j * nsq + (size_t)r * n2 + rho;
     if (!off) {
-      Tdiag[o] = (T)v;
+      Tdiag[o] = (TO)v;
       if (Tdiag64) Tdiag64[o] = v;
     } else {
-      Toff[o] = (T)v;
+      Toff[o] = (TO)v;
       if (Toff64) Toff64[o] = v;
     }
   }
@@ -459,7 +460,7 @@ __global__ __launch_bounds__(256) void k_assemble(const double* __restrict__ wh,
 // ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
-template <typename T, int BP>
+template <typename T, typename TO, int BP>
 static int stage1_bp(const Stage1Args& A, hipStream_t st) {
   const int m = A.m, n2 = A.n2, b = A.b;
   hipLaunchKernelGGL((k_slab_factor<T, BP>), dim3(2 * m), dim3(64), 0, st, A.wh, A.wv, n2, b,
@@ -470,30 +471,32 @@ static int stage1_bp(const Stage1Args& A, hipStream_t st) {
   hipLaunchKernelGGL((k_sigma<T, BP>), dim3(ceil_div(waves, 4)), dim3(256), 0, st, A.wh, A.wv, n2,
                      b, m, (const T*)A.Gl, (const T*)A.Hsw, (T*)A.sig, A.status);
   SLAB_LAUNCH_CHECK();
+  if (A.ev[1]) SLAB_HIP_CHECK(hipEventRecord((hipEvent_t)A.ev[1], st));
   const int nchunk = (n2 + 63) / 64;
   hipLaunchKernelGGL((k_schur<T, BP>), dim3(nchunk * m), dim3(256), 0, st, A.wh, n2, b, m,
                      (const T*)A.Hsw, (const T*)A.sig, (T*)A.PRR, (T*)A.PLL, (T*)A.PLR,
                      (T*)A.PRL);
   SLAB_LAUNCH_CHECK();
-  if (A.ev[1]) SLAB_HIP_CHECK(hipEventRecord((hipEvent_t)A.ev[1], st));
-  const int ntl = (n2 + 31) / 32;
-  hipLaunchKernelGGL((k_assemble<T>), dim3(ntl * ntl, m, 2), dim3(256), 0, st, A.wh, A.wv, n2, b,
-                     m, (const T*)A.PRR, (const T*)A.PLL, (const T*)A.PLR, (const T*)A.PRL,
-                     (T*)A.Tdiag, (T*)A.Toff, A.Tdiag64, A.Toff64);
-  SLAB_LAUNCH_CHECK();
   if (A.ev[2]) SLAB_HIP_CHECK(hipEventRecord((hipEvent_t)A.ev[2], st));
+  const int ntl = (n2 + 31) / 32;
+  hipLaunchKernelGGL((k_assemble<T, TO>), dim3(ntl * ntl, m, 2), dim3(256), 0, st, A.wh, A.wv, n2,
+                     b, m, (const T*)A.PRR, (const T*)A.PLL, (const T*)A.PLR, (const T*)A.PRL,
+                     (TO*)A.Tdiag, (TO*)A.Toff, A.Tdiag64, A.Toff64);
+  SLAB_LAUNCH_CHECK();
+  if (A.ev[3]) SLAB_HIP_CHECK(hipEventRecord((hipEvent_t)A.ev[3], st));
   return SLAB_OK;
 }
 
-template <typename T>
+template <typename T, typename TO>
 int launch_stage1(const Stage1Args& A, hipStream_t st) {
   switch (padded_block(A.b)) {
-    case 16: return stage1_bp<T, 16>(A, st);
-    case 32: return stage1_bp<T, 32>(A, st);
-    default: return stage1_bp<T, 64>(A, st);
+    case 16: return stage1_bp<T, TO, 16>(A, st);
+    case 32: return stage1_bp<T, TO, 32>(A, st);
+    default: return stage1_bp<T, TO, 64>(A, st);
   }
 }
-template int launch_stage1<float>(const Stage1Args&, hipStream_t);
-template int launch_stage1<double>(const Stage1Args&, hipStream_t);
+template int launch_stage1<float, float>(const Stage1Args&, hipStream_t);
+template int launch_stage1<double, double>(const Stage1Args&, hipStream_t);
+template int launch_stage1<double, float>(const Stage1Args&, hipStream_t);
 
 }  // namespace slab

@@ -30,9 +30,10 @@ struct Stage1Args {
   double* Tdiag64;  // optional FP64 copies
   double* Toff64;
   int* status;
-  void* ev[3];      // optional events after slab factor, Schur, assembly
+  void* ev[4];      // optional events after slab factor, boundary columns, Schur, assembly
 };
-template <typename T> int launch_stage1(const Stage1Args& a, hipStream_t st);
+// T: slab factors and Schur pieces; TO: the assembled T blocks (block factorization).
+template <typename T, typename TO> int launch_stage1(const Stage1Args& a, hipStream_t st);
 
 // ---- dense kernels ------------------------------------------------------------
 enum { GEMM_LOWER_C = 1, GEMM_A_LOWER = 2, GEMM_B_LOWER = 4 };
@@ -73,18 +74,19 @@ struct SolveArgs {
   const void* Gl;
   const void* Linv;
   const void* Z;
-  void* zbuf;      // m * nrhs * n2 * BP scratch (working precision)
-  void* xb;        // m * 2 * nrhs * n2 boundary values (working precision)
-  void* ft;        // m * nrhs * n2 reduced vectors (working precision)
+  void* zbuf;      // m * nrhs * n2 * BP scratch (slab precision)
+  void* xb;        // m * 2 * nrhs * n2 boundary values (slab precision)
+  void* ft;        // m * nrhs * n2 reduced vectors (reduced-system precision)
   void* yt;        // m * nrhs * n2
   void* tt;        // nrhs * n2 temporary
   void* gemv_work;
   int* gemv_counters;
   int transpose;   // 1: adjoint (A^T) sweeps
 };
-// One pass of Alg. 4 in the working precision: rhs (FP64) -> out (FP64);
+// One pass of Alg. 4: slab sweeps in T (the slab factors' type), the reduced
+// system in TR (the block factorization's type); rhs (FP64) -> out (FP64);
 // accumulate=0 writes out, 1 adds to out.
-template <typename T>
+template <typename T, typename TR>
 int launch_solve_pass(const SolveArgs& a, const double* rhs, long long ld_rhs, double* out,
                       long long ld_out, int accumulate, hipStream_t st);
 

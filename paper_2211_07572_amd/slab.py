@@ -24,6 +24,7 @@ SLAB_E_HIP = -5
 
 SLAB_FP64 = 0
 SLAB_FP32_REFINE = 1
+SLAB_MIXED = 2
 
 SLAB_KEEP_REDUCED = 1
 SLAB_COEF_LOG = 2
@@ -143,7 +144,7 @@ class SlabHandle:
         return v.value
 
     def phase_us(self) -> dict:
-        names = ["weights+slab_factor", "slab_factor", "schur", "assemble", "block_factor"]
+        names = ["slab_factor", "boundary_columns", "schur", "assemble", "block_factor"]
         return {n: self.query(10 + i) for i, n in enumerate(names)}
 
 
