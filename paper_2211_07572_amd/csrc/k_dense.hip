@@ -478,13 +478,13 @@ template int launch_stage2<double>(const Stage2Args&, hipStream_t);
 // Block-vector product for the sweeping solve (Alg. 2):
 //   y = beta * xin + alpha * M x,  x and y hold nrhs columns of length n.
 // 16 columns at a time on 16x16x4 MFMA tiles.  A workgroup owns 16 rows; its
-// eight waves split k and are reduced through LDS, so no result crosses a
+// sixteen waves split k and are reduced through LDS, so no result crosses a
 // workgroup (a device-scope fence would write back every L2 of the chip).
 // Each lane loads 16 contiguous bytes of M and of x per step, which feed
 // VEC consecutive MFMA k-steps (k permuted consistently in A and B).
 // ---------------------------------------------------------------------------
 constexpr int BMV_COLS = 16;
-constexpr int BMV_WAVES = 8;
+constexpr int BMV_WAVES = 16;
 
 size_t gemv_work_bytes(int n, int nrhs, int elem) {
   (void)n; (void)nrhs; (void)elem;
@@ -493,7 +493,7 @@ size_t gemv_work_bytes(int n, int nrhs, int elem) {
 int gemv_counter_count(int n) { (void)n; return 1; }
 
 template <typename T, bool TR, bool LOWER>
-__global__ __launch_bounds__(512) void k_bmv(int n, int nc, T alpha, const T* __restrict__ M,
+__global__ __launch_bounds__(1024) void k_bmv(int n, int nc, T alpha, const T* __restrict__ M,
                                              const T* __restrict__ x, T beta,
                                              const T* __restrict__ xin, T* __restrict__ y) {
   typedef typename acc4<T>::type V4;
@@ -517,7 +517,7 @@ __global__ __launch_bounds__(512) void k_bmv(int n, int nc, T alpha, const T* __
   const bool rowok = row < n;
   const bool colok = nn < nc;
   V4 acc = V4{0, 0, 0, 0};
-#pragma unroll 4
+#pragma unroll 8
   for (int ch = c_begin; ch < c_end; ++ch) {
     const int kb = klo + ch * KS + VEC * g;   // this lane's first k of the chunk
     T av[VEC], bv[VEC];

@@ -14,9 +14,9 @@ namespace slab {
 //   A_ee^T x = y: z_r = Gl_r^T (y_r + W_r z_{r-1});  x_r = z_r + Gl_r^T W_{r+1} x_{r+1}
 // MODE 0 (reduced right-hand side): y = f_e; emits w * x at the slab's first
 //   and last column, xb[s][0|1][c][r].
-// MODE 1 (interior): y = f_e + wL u_o(s-1) + wR u_o(s); writes (or adds) x
-//   into the natural-order output (the interface values go through
-//   k_interface_out).
+// MODE 1 (interior): y = f_e + wL u_o(s-1) + wR u_o(s) (the coupling terms
+//   precomputed by k_coupling into xb); writes (or adds) x into the
+//   natural-order output (the interface values go through k_interface_out).
 // One workgroup per (slab, group of 256/BP columns); thread = (row i, column).
 // Software pipeline: while row step r is computed, the block inverse, edge
 // weights and right-hand side of the next step are loaded into registers and
@@ -42,7 +42,7 @@ template <typename T, typename TU, int BP, bool TRANS, int MODE>
 __global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
   constexpr int NC = 256 / BP;            // columns per workgroup
   constexpr int GPT = BP * BP / 256;      // block-inverse elements loaded per thread
-  constexpr int D = BP == 64 ? 4 : 8;     // prefetch depth in row steps
+  constexpr int D = BP == 64 ? (sizeof(T) == 8 ? 2 : 4) : 8;  // prefetch depth (row steps)
   __shared__ T Gs[2][BP][BP + 1];
   __shared__ T Ws[2][BP];
   __shared__ T Ys[2][NC][BP + 1];
@@ -66,32 +66,25 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
   const long long ci = c0 + (act ? i : 0);
   const T* Gl = (const T*)a.Gl + (size_t)s * n2 * BP * BP;
   T* zbuf = (T*)a.zbuf + (size_t)s * nrhs * n2 * BP;
-  const TU* uo = (const TU*)a.uo;
   const bool acc_out = MODE == 1 && a.accumulate;
 
-  // register ring: operands of the next D row steps
+  // register ring: RAW loaded operands of the next D row steps (no arithmetic on
+  // them until they are parked, so the loads stay in flight across steps)
   T rg[D][GPT];
-  T rw[D], ry[D];
-  double ru[D];
+  double rw[D], ry[D], ru[D], rbl[D], rbr[D];
+  T rx[D], rz[D];
 #pragma unroll
   for (int d = 0; d < D; ++d) {
 #pragma unroll
     for (int e = 0; e < GPT; ++e) rg[d][e] = (T)0;
-    rw[d] = ry[d] = (T)0;
-    ru[d] = 0.0;
+    rw[d] = ry[d] = ru[d] = rbl[d] = rbr[d] = 0.0;
+    rx[d] = rz[d] = (T)0;
   }
-  auto load_y = [&](int r) __attribute__((always_inline)) -> T {
-    if (!valid || !act) return (T)0;
-    double v = rhs[(long long)c * ld + ci * n2 + r];
-    if (MODE == 1) {
-      if (i == 0 && s > 0)
-        v += wh[c0 * n2 + r] * (double)uo[((size_t)(s - 1) * nrhs + c) * n2 + r];
-      if (i == b - 1) v += wh[(c0 + b) * n2 + r] * (double)uo[((size_t)s * nrhs + c) * n2 + r];
-    }
-    return (T)v;
-  };
-  auto load_w = [&](int r) __attribute__((always_inline)) -> T {  // edge between rows r-1 and r (0 outside 1..n2-1)
-    return (tid < BP && act && r >= 1 && r <= n2 - 1) ? (T)wv[ci * (n2 + 1) + r] : (T)0;
+  // MODE 1: the interface coupling w u_o was precomputed into xb (lane 0 reads
+  // slot 0, lane b-1 slot 1; for b = 1 slot 0 carries both terms)
+  const int xslot = (i == 0) ? 0 : ((i == b - 1) ? 1 : -1);
+  auto load_w = [&](int r) __attribute__((always_inline)) -> double {
+    return (tid < BP && act && r >= 1 && r <= n2 - 1) ? wv[ci * (n2 + 1) + r] : 0.0;
   };
   // forward step r: G = Gl_{r-1} (A x) or Gl_r (A^T x), w = W_r, y = y_r
   auto load_fwd = [&](int d, int r) __attribute__((always_inline)) {
@@ -102,7 +95,10 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
       for (int e = 0; e < GPT; ++e) rg[d][e] = G[tid + 256 * e];
     }
     rw[d] = load_w(r);
-    ry[d] = load_y(r);
+    ry[d] = (valid && act) ? rhs[(long long)c * ld + ci * n2 + r] : 0.0;
+    if (MODE == 1)
+      rx[d] = (valid && act && xslot >= 0)
+                  ? xbuf[(((size_t)s * 2 + xslot) * nrhs + c) * n2 + r] : (T)0;
   };
   // backward step r: G = Gl_r, w = W_{r+1}, z = z_r (+ old outputs when accumulating)
   auto load_bwd = [&](int d, int r) __attribute__((always_inline)) {
@@ -110,17 +106,28 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
 #pragma unroll
     for (int e = 0; e < GPT; ++e) rg[d][e] = G[tid + 256 * e];
     rw[d] = load_w(r + 1);
-    ry[d] = valid ? zbuf[((size_t)c * n2 + r) * BP + i] : (T)0;
+    rz[d] = valid ? zbuf[((size_t)c * n2 + r) * BP + i] : (T)0;
     ru[d] = (MODE == 1 && valid && acc_out && act) ? out_g[(long long)c * ldo + ci * n2 + r] : 0.0;
+    if (MODE == 0) {  // interface edge weights of the boundary outputs
+      rbl[d] = (valid && i == 0) ? wh[c0 * n2 + r] : 0.0;
+      rbr[d] = (valid && i == b - 1) ? wh[(c0 + b) * n2 + r] : 0.0;
+    }
   };
-  auto park = [&](int d, int buf) __attribute__((always_inline)) {
+  auto parkG = [&](int d, int buf) __attribute__((always_inline)) {
 #pragma unroll
     for (int e = 0; e < GPT; ++e) {
       const int idx = tid + 256 * e;
       Gs[buf][idx / BP][idx % BP] = rg[d][e];
     }
-    if (tid < BP) Ws[buf][tid] = rw[d];
-    Ys[buf][cl][i] = ry[d];
+    if (tid < BP) Ws[buf][tid] = (T)rw[d];
+  };
+  auto park_fwd = [&](int d, int buf) __attribute__((always_inline)) {
+    parkG(d, buf);
+    Ys[buf][cl][i] = (T)(ry[d] + (MODE == 1 ? (double)rx[d] : 0.0));
+  };
+  auto park_bwd = [&](int d, int buf) __attribute__((always_inline)) {
+    parkG(d, buf);
+    Ys[buf][cl][i] = rz[d];
   };
 
   // ---------------- forward sweep: z_r (stored in zbuf) ----------------
@@ -134,23 +141,24 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
       const int r = r0 + d;
       if (r < n2) {  // uniform
       const int cur = r & 1;
-      park(d, cur);
+      park_fwd(d, cur);
       if (r + D < n2) load_fwd(d, r + D);
       __syncthreads();
+      // dot products over k in four independent partial sums (short FMA chains)
       T out;
       if (!TRANS) {
-        T t = (T)0;
+        T t[4] = {(T)0, (T)0, (T)0, (T)0};
         if (r > 0) {
-#pragma unroll 8
-          for (int k = 0; k < BP; ++k) t += Gs[cur][i][k] * Vs[cur][cl][k];
+#pragma unroll
+          for (int k = 0; k < BP; ++k) t[k & 3] += Gs[cur][i][k] * Vs[cur][cl][k];
         }
-        out = Ys[cur][cl][i] + Ws[cur][i] * t;
+        out = Ys[cur][cl][i] + Ws[cur][i] * ((t[0] + t[1]) + (t[2] + t[3]));
       } else {
-        T t = (T)0;
-#pragma unroll 8
+        T t[4] = {(T)0, (T)0, (T)0, (T)0};
+#pragma unroll
         for (int k = 0; k < BP; ++k)
-          t += Gs[cur][k][i] * (Ys[cur][cl][k] + Ws[cur][k] * Vs[cur][cl][k]);
-        out = t;
+          t[k & 3] += Gs[cur][k][i] * (Ys[cur][cl][k] + Ws[cur][k] * Vs[cur][cl][k]);
+        out = (t[0] + t[1]) + (t[2] + t[3]);
       }
       if (valid) zbuf[((size_t)c * n2 + r) * BP + i] = out;
       Vs[cur ^ 1][cl][i] = out;
@@ -171,37 +179,56 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
       if (it < n2) {  // uniform
       const int r = n2 - 1 - it;
       const int cur = it & 1;
-      park(d, cur);
-      const double uold = ru[d];
+      park_bwd(d, cur);
+      const double uold = ru[d], wbl = rbl[d], wbr = rbr[d];
       if (it + D < n2) load_bwd(d, r - D);
       __syncthreads();
       T x;
       if (!TRANS) {
-        T t = (T)0;
-#pragma unroll 8
+        T t[4] = {(T)0, (T)0, (T)0, (T)0};
+#pragma unroll
         for (int k = 0; k < BP; ++k)
-          t += Gs[cur][i][k] * (Ys[cur][cl][k] + Ws[cur][k] * Vs[cur][cl][k]);
-        x = t;
+          t[k & 3] += Gs[cur][i][k] * (Ys[cur][cl][k] + Ws[cur][k] * Vs[cur][cl][k]);
+        x = (t[0] + t[1]) + (t[2] + t[3]);
       } else {
-        T t = (T)0;
-#pragma unroll 8
-        for (int k = 0; k < BP; ++k) t += Gs[cur][k][i] * (Ws[cur][k] * Vs[cur][cl][k]);
-        x = Ys[cur][cl][i] + t;
+        T t[4] = {(T)0, (T)0, (T)0, (T)0};
+#pragma unroll
+        for (int k = 0; k < BP; ++k) t[k & 3] += Gs[cur][k][i] * (Ws[cur][k] * Vs[cur][cl][k]);
+        x = Ys[cur][cl][i] + ((t[0] + t[1]) + (t[2] + t[3]));
       }
       Vs[cur ^ 1][cl][i] = x;
       if (valid) {
         if (MODE == 0) {
-          if (i == 0)
-            xbuf[(((size_t)s * 2 + 0) * nrhs + c) * n2 + r] = (T)(wh[c0 * n2 + r] * (double)x);
-          if (i == b - 1)
-            xbuf[(((size_t)s * 2 + 1) * nrhs + c) * n2 + r] =
-                (T)(wh[(c0 + b) * n2 + r] * (double)x);
+          if (i == 0) xbuf[(((size_t)s * 2 + 0) * nrhs + c) * n2 + r] = (T)(wbl * (double)x);
+          if (i == b - 1) xbuf[(((size_t)s * 2 + 1) * nrhs + c) * n2 + r] = (T)(wbr * (double)x);
         } else if (act) {
           out_g[(long long)c * ldo + ci * n2 + r] = acc_out ? uold + (double)x : (double)x;
         }
       }
       }
     }
+  }
+}
+
+// Interface coupling of the interior solve (eq. (usol_even)): for slab s,
+//   xb[s][0][c][r] = wL_r u_o(s-1)[c][r]   (+ wR_r u_o(s)[c][r] when b = 1)
+//   xb[s][1][c][r] = wR_r u_o(s)[c][r]
+// with wL, wR the edge weights between the slab and its two interfaces.
+template <typename T, typename TR>
+__global__ void k_coupling(int n2, int b, int m, int nrhs, const double* __restrict__ wh,
+                           const TR* __restrict__ uo, T* __restrict__ xb) {
+  const long long tot = (long long)m * nrhs * n2;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long r = e % n2;
+    const long long c = (e / n2) % nrhs;
+    const long long s = e / ((long long)n2 * nrhs);
+    const long long c0 = s * (b + 1);
+    const double right = wh[(c0 + b) * n2 + r] * (double)uo[(s * nrhs + c) * n2 + r];
+    double left = s > 0 ? wh[c0 * n2 + r] * (double)uo[((s - 1) * nrhs + c) * n2 + r] : 0.0;
+    if (b == 1) left += right;
+    xb[((s * 2 + 0) * nrhs + c) * n2 + r] = (T)left;
+    xb[((s * 2 + 1) * nrhs + c) * n2 + r] = (T)right;
   }
 }
 
@@ -295,6 +322,13 @@ static int sweeps_bp(const SolveArgs& A, const double* rhs, long long ld_rhs, do
     if (rc) return rc;
   }
   // (iii) interior back substitution, and the interface values
+  {
+    long long tot = (long long)m * nrhs * n;
+    unsigned g = (unsigned)std::min<long long>((tot + 255) / 256, 16384);
+    hipLaunchKernelGGL((k_coupling<T, TR>), dim3(g), dim3(256), 0, st, n, A.b, m, nrhs, A.wh,
+                       (const TR*)A.ft, (T*)A.xb);
+    SLAB_LAUNCH_CHECK();
+  }
   if (A.transpose) hipLaunchKernelGGL((k_sweep<T, TR, BP, true, 1>), grid, dim3(256), 0, st, s);
   else hipLaunchKernelGGL((k_sweep<T, TR, BP, false, 1>), grid, dim3(256), 0, st, s);
   SLAB_LAUNCH_CHECK();
