@@ -16,18 +16,24 @@ namespace slab {
 
 // ---------------------------------------------------------------------------
 // Tiled MFMA GEMM: C = beta*C + alpha * op(A) op(B).
-// 64x64 output tile per workgroup, four waves of 32x32, k chunks of 16.
+// 64x64 output tile per workgroup, four waves of 32x32, k chunks of 32.  The
+// next chunk is loaded into registers (16-byte vector loads when the leading
+// dimension allows) while the current one is multiplied out of LDS; one
+// barrier per chunk (double-buffered LDS).
 // ---------------------------------------------------------------------------
-template <typename T, bool AK, bool BN>
+template <typename T, bool AK, bool BN, bool VECOK>
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, T alpha,
                                               const T* __restrict__ A, long long lda,
                                               long long sa, const T* __restrict__ B,
                                               long long ldb, long long sb, T beta, T* C,
                                               long long ldc, long long sc, int flags) {
   typedef typename acc4<T>::type V4;
-  constexpr int TM = 64, TN = 64, TK = 16;
-  __shared__ T As[TK][TM + 4];
-  __shared__ T Bs[TK][TN + 4];
+  constexpr int TM = 64, TN = 64, TK = 32;
+  constexpr int VEC = 16 / sizeof(T);
+  constexpr int NV = TM * TK / 256 / VEC;  // vectors per thread per operand and chunk
+  typedef T vt __attribute__((ext_vector_type(VEC)));
+  __shared__ T As[2][TK][TM + 4];
+  __shared__ T Bs[2][TK][TN + 4];
   int ti, tj;
   if (flags & GEMM_LOWER_C) {
     const long long t = blockIdx.x;
@@ -49,8 +55,83 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, T alpha,
   const int g = lane >> 4, nn = lane & 15;
   const int wm = wave >> 1, wn = wave & 1;
   int kmin = (flags & GEMM_B_LOWER) ? j0 : 0;
-  int kmax = (flags & GEMM_A_LOWER) ? min(K, i0 + TM) : K;
+  const int kmax = (flags & GEMM_A_LOWER) ? min(K, i0 + TM) : K;
   kmin = (kmin / TK) * TK;
+
+  vt ra[NV], rb[NV];
+  // A chunk: !AK -> vectors along k (row-major); AK -> vectors along i
+  auto load = [&](int k0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const int v = tid + 256 * q;
+      int row, kk;
+      if (!AK) { row = v / (TK / VEC); kk = (v % (TK / VEC)) * VEC; }
+      else { kk = v / (TM / VEC); row = (v % (TM / VEC)) * VEC; }
+      const long long gi = i0 + row, gk = k0 + kk;
+      if (VECOK) {
+        const bool in = !AK ? (gi < M && gk < kmax) : (gk < kmax && gi < M);
+        ra[q] = in ? *(const vt*)(!AK ? A + gi * lda + gk : A + gk * lda + gi) : vt(0);
+        if (in) {  // partial vectors at the edges
+#pragma unroll
+          for (int e = 0; e < VEC; ++e)
+            if (!AK ? (gk + e >= kmax) : (gi + e >= M)) ra[q][e] = (T)0;
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+          const long long ii = !AK ? gi : gi + e, kq = !AK ? gk + e : gk;
+          ra[q][e] = (ii < M && kq < kmax) ? A[!AK ? ii * lda + kq : kq * lda + ii] : (T)0;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const int v = tid + 256 * q;
+      int col, kk;
+      if (!BN) { kk = v / (TN / VEC); col = (v % (TN / VEC)) * VEC; }
+      else { col = v / (TK / VEC); kk = (v % (TK / VEC)) * VEC; }
+      const long long gj = j0 + col, gk = k0 + kk;
+      if (VECOK) {
+        const bool in = gj < N && gk < kmax;
+        rb[q] = in ? *(const vt*)(!BN ? B + gk * ldb + gj : B + gj * ldb + gk) : vt(0);
+        if (in) {
+#pragma unroll
+          for (int e = 0; e < VEC; ++e)
+            if (!BN ? (gj + e >= N) : (gk + e >= kmax)) rb[q][e] = (T)0;
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+          const long long jj = !BN ? gj + e : gj, kq = !BN ? gk : gk + e;
+          rb[q][e] = (jj < N && kq < kmax) ? B[!BN ? kq * ldb + jj : jj * ldb + kq] : (T)0;
+        }
+      }
+    }
+  };
+  auto park = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const int v = tid + 256 * q;
+      if (!AK) {
+        const int row = v / (TK / VEC), kk = (v % (TK / VEC)) * VEC;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) As[buf][kk + e][row] = ra[q][e];
+      } else {
+        const int kk = v / (TM / VEC), row = (v % (TM / VEC)) * VEC;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) As[buf][kk][row + e] = ra[q][e];
+      }
+      if (!BN) {
+        const int kk = v / (TN / VEC), col = (v % (TN / VEC)) * VEC;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) Bs[buf][kk][col + e] = rb[q][e];
+      } else {
+        const int col = v / (TK / VEC), kk = (v % (TK / VEC)) * VEC;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) Bs[buf][kk + e][col] = rb[q][e];
+      }
+    }
+  };
 
   V4 acc[2][2];
 #pragma unroll
@@ -58,55 +139,30 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, T alpha,
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = V4{0, 0, 0, 0};
 
-  for (int k0 = kmin; k0 < kmax; k0 += TK) {
-    if (!AK) {
-      const int row = tid >> 2, kq = (tid & 3) * 4;
-      const long long gi = i0 + row;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int gk = k0 + kq + e;
-        As[kq + e][row] = (gi < M && gk < kmax) ? A[gi * lda + gk] : (T)0;
-      }
-    } else {
-      const int kk = tid >> 4, iq = (tid & 15) * 4;
-      const long long gk = k0 + kk;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int gi = i0 + iq + e;
-        As[kk][iq + e] = (gi < M && gk < kmax) ? A[gk * lda + gi] : (T)0;
-      }
-    }
-    if (!BN) {
-      const int kk = tid >> 4, jq = (tid & 15) * 4;
-      const long long gk = k0 + kk;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int gj = j0 + jq + e;
-        Bs[kk][jq + e] = (gj < N && gk < kmax) ? B[gk * ldb + gj] : (T)0;
-      }
-    } else {
-      const int col = tid >> 2, kq = (tid & 3) * 4;
-      const long long gj = j0 + col;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int gk = k0 + kq + e;
-        Bs[kq + e][col] = (gj < N && gk < kmax) ? B[gj * ldb + gk] : (T)0;
-      }
-    }
+  if (kmin < kmax) {
+    load(kmin);
+    park(0);
     __syncthreads();
+    int it = 0;
+    for (int k0 = kmin; k0 < kmax; k0 += TK, ++it) {
+      const int cur = it & 1;
+      const bool more = k0 + TK < kmax;
+      if (more) load(k0 + TK);
 #pragma unroll
-    for (int ks = 0; ks < TK / 4; ++ks) {
-      T av[2], bv[2];
+      for (int ks = 0; ks < TK / 4; ++ks) {
+        T av[2], bv[2];
 #pragma unroll
-      for (int mt = 0; mt < 2; ++mt) av[mt] = As[4 * ks + g][wm * 32 + 16 * mt + nn];
+        for (int mt = 0; mt < 2; ++mt) av[mt] = As[cur][4 * ks + g][wm * 32 + 16 * mt + nn];
 #pragma unroll
-      for (int nt = 0; nt < 2; ++nt) bv[nt] = Bs[4 * ks + g][wn * 32 + 16 * nt + nn];
+        for (int nt = 0; nt < 2; ++nt) bv[nt] = Bs[cur][4 * ks + g][wn * 32 + 16 * nt + nn];
 #pragma unroll
-      for (int mt = 0; mt < 2; ++mt)
+        for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-        for (int nt = 0; nt < 2; ++nt) acc[mt][nt] = mfma16(av[mt], bv[nt], acc[mt][nt]);
+          for (int nt = 0; nt < 2; ++nt) acc[mt][nt] = mfma16(av[mt], bv[nt], acc[mt][nt]);
+      }
+      if (more) park(cur ^ 1);
+      __syncthreads();
     }
-    __syncthreads();
   }
 #pragma unroll
   for (int mt = 0; mt < 2; ++mt)
@@ -133,9 +189,19 @@ int launch_gemm(bool ak, bool bn, int M, int N, int K, T alpha, const T* A, long
   dim3 grid;
   if (flags & GEMM_LOWER_C) grid = dim3((unsigned)((long long)tm * (tm + 1) / 2), 1, batch);
   else grid = dim3(tn, tm, batch);
-#define SLAB_GEMM_CASE(AKV, BNV)                                                          \
-  hipLaunchKernelGGL((k_gemm<T, AKV, BNV>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, sa, \
-                     B, ldb, sb, beta, C, ldc, sc, flags)
+  // 16-byte vector loads need 16-byte aligned bases, strides and batch strides
+  const long long vec = 16 / (long long)sizeof(T);
+  const bool vecok = lda % vec == 0 && ldb % vec == 0 && sa % vec == 0 && sb % vec == 0 &&
+                     ((uintptr_t)A & 15) == 0 && ((uintptr_t)B & 15) == 0;
+#define SLAB_GEMM_CASE(AKV, BNV)                                                              \
+  do {                                                                                        \
+    if (vecok)                                                                                \
+      hipLaunchKernelGGL((k_gemm<T, AKV, BNV, true>), grid, dim3(256), 0, st, M, N, K, alpha, \
+                         A, lda, sa, B, ldb, sb, beta, C, ldc, sc, flags);                    \
+    else                                                                                      \
+      hipLaunchKernelGGL((k_gemm<T, AKV, BNV, false>), grid, dim3(256), 0, st, M, N, K,       \
+                         alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc, flags);             \
+  } while (0)
   if (!ak && !bn) SLAB_GEMM_CASE(false, false);
   else if (!ak && bn) SLAB_GEMM_CASE(false, true);
   else if (ak && !bn) SLAB_GEMM_CASE(true, false);
