@@ -32,6 +32,10 @@ garbled):
     T_57 in the fourth row of eq. (dell3) is T_75.
   * Alg. 1's loop bounds skip S_3; the sweep used is S_0 = T_00,
     S_j = T_jj - T_{j,j-1} S_{j-1}^-1 T_{j-1,j} for j = 1 .. m-1.
+  * Odd-even order (Remark in Sec. 4, concluding section; no formulas given):
+    at every level the interfaces at even positions of the remaining list are
+    eliminated together and those at odd positions are kept (see
+    odd_even_build).
 """
 from __future__ import annotations
 
@@ -398,6 +402,104 @@ def sweeping_solve(s1: StageOne, s2: StageTwo, ft: np.ndarray) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
+# Stage two in odd-even order (the elimination order proposed in the Remark of
+# Sec. 4 and in the concluding section: every other interface block is
+# eliminated, level by level, instead of the sweep of Alg. 1).
+#
+# Reading (the paper gives no formulas for it): the interfaces still present
+# at a level form a list a_0, a_1, ..., a_{k-1}; the blocks at even positions
+# a_0, a_2, ... are eliminated together, those at odd positions stay.  The
+# Schur complement that remains is again block tridiagonal in the kept order:
+# eliminating e between its neighbours l (before it) and r (after it) changes
+#   T_ll -= T_le T_ee^-1 T_el,   T_rr -= T_re T_ee^-1 T_er,
+#   T_lr  = -T_le T_ee^-1 T_er,  T_rl  = -T_re T_ee^-1 T_el
+# (T_lr and T_rl were zero).  Levels repeat until no interface is left; the
+# last one eliminated is the last interface when m is a power of two.
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Elimination:
+    e: int                 # interface eliminated
+    l: int | None          # neighbour before it in the list of its level (kept), or None
+    r: int | None          # neighbour after it (kept), or None
+    D: np.ndarray          # its pivot block T_ee at the time of elimination
+    lu: tuple              # LAPACK LU of D
+    T_el: np.ndarray | None
+    T_le: np.ndarray | None
+    T_er: np.ndarray | None
+    T_re: np.ndarray | None
+
+
+@dataclass
+class OddEven:
+    levels: list           # list of levels, each a list of Elimination
+
+    def pivot(self, j: int) -> np.ndarray:
+        for lev in self.levels:
+            for el in lev:
+                if el.e == j:
+                    return el.D
+        raise KeyError(j)
+
+
+def odd_even_build(s1: StageOne) -> OddEven:
+    """Odd-even elimination of the block-tridiagonal T (see the comment above)."""
+    m = len(s1.T_diag)
+    D = {j: s1.T_diag[j].copy() for j in range(m)}
+    up = {j: s1.T_up[j].copy() for j in range(m - 1)}   # T_{x, next(x)}
+    lo = {j: s1.T_lo[j].copy() for j in range(m - 1)}   # T_{next(x), x}
+    active = list(range(m))
+    levels = []
+    while active:
+        level = []
+        for p in range(0, len(active), 2):
+            e = active[p]
+            l = active[p - 1] if p > 0 else None
+            r = active[p + 1] if p + 1 < len(active) else None
+            level.append(Elimination(e, l, r, D[e].copy(), sla.lu_factor(D[e]),
+                                     lo[l] if l is not None else None,
+                                     up[l] if l is not None else None,
+                                     up[e] if r is not None else None,
+                                     lo[e] if r is not None else None))
+        for el in level:
+            if el.l is not None:
+                D[el.l] = D[el.l] - el.T_le @ sla.lu_solve(el.lu, el.T_el)
+            if el.r is not None:
+                D[el.r] = D[el.r] - el.T_re @ sla.lu_solve(el.lu, el.T_er)
+            if el.l is not None and el.r is not None:
+                up[el.l] = -el.T_le @ sla.lu_solve(el.lu, el.T_er)
+                lo[el.l] = -el.T_re @ sla.lu_solve(el.lu, el.T_el)
+        levels.append(level)
+        active = active[1::2]
+    return OddEven(levels)
+
+
+def odd_even_solve(oe: OddEven, ft: np.ndarray) -> np.ndarray:
+    """Solve T x = f~ with the odd-even elimination: the right-hand side is
+    reduced level by level as T was, then the eliminated blocks are recovered
+    from the top level down, x_e = T_ee^-1 (g_e - T_el x_l - T_er x_r)."""
+    m = ft.shape[1]
+    g = [ft[:, j, :].T.copy() for j in range(m)]
+    for level in oe.levels:
+        for el in level:
+            z = sla.lu_solve(el.lu, g[el.e])
+            if el.l is not None:
+                g[el.l] = g[el.l] - el.T_le @ z
+            if el.r is not None:
+                g[el.r] = g[el.r] - el.T_re @ z
+    x = [None] * m
+    for level in reversed(oe.levels):
+        for el in level:
+            rhs = g[el.e].copy()
+            if el.l is not None:
+                rhs -= el.T_el @ x[el.l]
+            if el.r is not None:
+                rhs -= el.T_er @ x[el.r]
+            x[el.e] = sla.lu_solve(el.lu, rhs)
+    return np.stack([xj.T for xj in x], axis=1)
+
+
+# ---------------------------------------------------------------------------
 # Alg. 3 (factor) and Alg. 4 (solve), and the adjoint.
 # ---------------------------------------------------------------------------
 
@@ -405,14 +507,20 @@ def sweeping_solve(s1: StageOne, s2: StageTwo, ft: np.ndarray) -> np.ndarray:
 class Factorization:
     prob: Problem
     s1: StageOne
-    s2: StageTwo
+    s2: "StageTwo | OddEven"
     transpose: bool = False
 
 
-def factor(prob: Problem, transpose: bool = False) -> Factorization:
-    """Alg. 3: slab factorizations, reduced blocks T (formed densely), Alg. 1."""
+def factor(prob: Problem, transpose: bool = False, order: str = "sweep") -> Factorization:
+    """Alg. 3: slab factorizations, reduced blocks T (formed densely), then
+    stage two by Alg. 1 (order="sweep") or in odd-even order (order="odd_even")."""
     s1 = stage_one(prob, transpose)
-    s2 = sweeping_build(s1)
+    if order == "sweep":
+        s2 = sweeping_build(s1)
+    elif order == "odd_even":
+        s2 = odd_even_build(s1)
+    else:
+        raise ValueError(order)
     return Factorization(prob, s1, s2, transpose)
 
 
@@ -423,15 +531,19 @@ def solve(fac: Factorization, f: np.ndarray) -> np.ndarray:
     if squeeze:
         f = f[None]
     ft = reduced_rhs(fac.prob, fac.s1, f, fac.transpose)
-    uo = sweeping_solve(fac.s1, fac.s2, ft)
+    if isinstance(fac.s2, OddEven):
+        uo = odd_even_solve(fac.s2, ft)
+    else:
+        uo = sweeping_solve(fac.s1, fac.s2, ft)
     u = interior_solve(fac.prob, fac.s1, f, uo, fac.transpose)
     return u[0] if squeeze else u
 
 
-def solve_adjoint(prob: Problem, g: np.ndarray, fac_T: Factorization | None = None) -> np.ndarray:
+def solve_adjoint(prob: Problem, g: np.ndarray, fac_T: Factorization | None = None,
+                  order: str = "sweep") -> np.ndarray:
     """lambda = A^-T g through the same two-level elimination applied to A^T."""
     if fac_T is None:
-        fac_T = factor(prob, transpose=True)
+        fac_T = factor(prob, transpose=True, order=order)
     return solve(fac_T, g)
 
 

@@ -344,7 +344,8 @@ def test_adjoint_symmetric_and_duality():
     assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
 
 
-def test_adjoint_transposes_nonsymmetric():
+@pytest.mark.parametrize("order", ["sweep", "odd_even"])
+def test_adjoint_transposes_nonsymmetric(order):
     """The transpose path really uses A^T: on a non-symmetric operator with the
     same 5-point pattern it must agree with a sparse solve of A^T."""
     import scipy.sparse as sp
@@ -355,10 +356,10 @@ def test_adjoint_transposes_nonsymmetric():
     vals = A.data * np.where(A.row != A.col, 1 + 0.3 * rng.uniform(-1, 1, A.nnz), 1.0)
     p.A = sp.csr_matrix((vals, (A.row, A.col)), shape=A.shape)
     g = G.rhs_normal(n2, n1, 2, 5)
-    lam = O.solve_adjoint(p, g)
+    lam = O.solve_adjoint(p, g, order=order)
     ref = spla.spsolve(p.A.T.tocsc(), g.reshape(2, -1).T).T.reshape(g.shape)
     assert np.abs(lam - ref).max() <= 1e-12 * np.abs(ref).max()
-    u = O.solve(O.factor(p), g)
+    u = O.solve(O.factor(p, order=order), g)
     ref_u = spla.spsolve(p.A.tocsc(), g.reshape(2, -1).T).T.reshape(g.shape)
     assert np.abs(u - ref_u).max() <= 1e-12 * np.abs(ref_u).max()
     assert np.abs(u - lam).max() > 1e-6 * np.abs(ref).max()
@@ -409,3 +410,67 @@ def test_superlu_crosscheck_lognormal():
     for k in range(2):
         assert np.linalg.norm(u[k] - u_ref[k]) <= 1e-12 * np.linalg.norm(u_ref[k])
     assert O.relres(p, u, f).max() <= 1e-12
+
+
+# ------------------------------------------------ odd-even order of stage two
+# (Remark in Sec. 4 and the concluding section: every other interface block
+# eliminated, level by level)
+
+ODD_EVEN_CASES = [(5, 4, 3), (6, 8, 3), (7, 9, 2), (6, 10, 1), (5, 24, 3), (4, 16, 1), (9, 40, 4),
+                  (3, 14, 1)]
+
+
+@pytest.mark.parametrize("n2,n1,b", ODD_EVEN_CASES)
+def test_odd_even_brute_force(n2, n1, b):
+    """Odd-even stage two solves A u = f exactly (dense LAPACK solve of A)."""
+    p = O.make_problem(G.kappa_lognormal(n2, n1, 3), n2, n1, b)
+    f = G.rhs_uniform(n2, n1, 2, 11)
+    u = O.solve(O.factor(p, order="odd_even"), f)
+    ref = np.linalg.solve(p.A.toarray(), f.reshape(2, -1).T).T.reshape(f.shape)
+    assert np.abs(u - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("n2,n1,b", [(4, 16, 1), (5, 24, 3), (6, 10, 1), (3, 14, 1)])
+def test_odd_even_blocks_are_schur_complements(n2, n1, b):
+    """At every level the pivot and coupling blocks are blocks of the Schur
+    complement of A onto the interfaces still present, ((A^-1)_aa)^-1 from a
+    dense inverse; that complement is block tridiagonal in the kept order."""
+    p = O.make_problem(G.kappa_lognormal(n2, n1, 5), n2, n1, b)
+    oe = O.factor(p, order="odd_even").s2
+    Ainv = np.linalg.inv(p.A.toarray())
+    active = list(range(p.m))
+    for level in oe.levels:
+        assert [el.e for el in level] == active[0::2]
+        idx = np.concatenate([p.I_o(j) for j in active])
+        Sa = np.linalg.inv(Ainv[np.ix_(idx, idx)])
+        pos = {j: k for k, j in enumerate(active)}
+
+        def blk(x, y):
+            return Sa[pos[x] * n2:(pos[x] + 1) * n2, pos[y] * n2:(pos[y] + 1) * n2]
+        scale = np.abs(Sa).max()
+        for x in active:
+            for y in active:
+                if abs(pos[x] - pos[y]) > 1:
+                    assert np.abs(blk(x, y)).max() <= 1e-10 * scale
+        for el in level:
+            assert np.abs(el.D - blk(el.e, el.e)).max() <= 1e-10 * scale
+            if el.l is not None:
+                assert np.abs(el.T_el - blk(el.e, el.l)).max() <= 1e-10 * scale
+                assert np.abs(el.T_le - blk(el.l, el.e)).max() <= 1e-10 * scale
+            if el.r is not None:
+                assert np.abs(el.T_er - blk(el.e, el.r)).max() <= 1e-10 * scale
+                assert np.abs(el.T_re - blk(el.r, el.e)).max() <= 1e-10 * scale
+        active = active[1::2]
+    assert active == []
+
+
+def test_odd_even_last_pivot_matches_sweep():
+    """With m a power of two the last interface is eliminated last; its pivot
+    is then the Schur complement of A onto it, as is S_{m-1} of Alg. 1."""
+    n2, n1, b = 6, 32, 3
+    p = O.make_problem(G.kappa_lognormal(n2, n1, 7), n2, n1, b)
+    oe = O.factor(p, order="odd_even").s2
+    sw = O.factor(p).s2
+    assert [el.e for el in oe.levels[-1]] == [p.m - 1]
+    D = oe.pivot(p.m - 1)
+    assert np.abs(D - sw.S[-1]).max() <= 1e-12 * np.abs(D).max()
