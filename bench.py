@@ -5,7 +5,9 @@ slab width b = 31 (128 slabs, interfaces of 2048 points), kappa = exp(GRF)
 (squared-exponential covariance, length 0.05, variance 1), 16 right-hand sides
 N(0,1).  One step = slab_factor + slab_solve of all 16 right-hand sides to a
 max relative residual of 1e-10 + slab_free.  The headline value is the
-FP32 + FP64-refinement form; the plain FP64 form is timed beside it.
+mixed form (FP64 slab work, FP32 reduced system, FP64 refinement) with stage
+two in odd-even order; the all-FP32 form, the sweep of Alg. 1 and the plain
+FP64 form are timed beside it.
 
 Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -38,6 +40,8 @@ def parse():
     ap.add_argument("--precision", choices=["mixed", "fp32"], default="mixed",
                     help="mixed: FP64 slab work + FP32 reduced system; fp32: FP32 throughout "
                          "(both with FP64 refinement to 1e-10)")
+    ap.add_argument("--order", choices=["odd_even", "sweep"], default="odd_even",
+                    help="stage two: odd-even elimination order or the sweep of Alg. 1")
     ap.add_argument("--skip-other", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--cpu-slabs", type=int, default=1)
@@ -57,15 +61,27 @@ def schur_flops(w: G.Workload) -> float:
     return 2.0 * b * b * n * (n - 1) * (m - 0.5)
 
 
-def block_factor_flops(w: G.Workload) -> float:
-    """Algorithmic flops of the block factorization: per interface block the
-    Cholesky factor (n^3/3) and its inverse (n^3/3); per coupling Z_j = L_j^-1 T_{j,j+1}
-    (n^3) and the symmetric update of S_{j+1} (n^3)."""
+def block_factor_flops(w: G.Workload, odd_even: bool) -> float:
+    """Algorithmic flops of the block factorization.  Every pivot block: the
+    Cholesky factor (n^3/3) and its inverse (n^3/3).  Alg. 1: per coupling
+    Z_j = L_j^-1 T_{j,j+1} (n^3) and the symmetric update of S_{j+1} (n^3).
+    Odd-even: per eliminated block with a neighbour before it U = L^-1 C^T (n^3)
+    and D_l -= U^T U (n^3), likewise V and D_r with a neighbour after it, and
+    the new coupling -U^T V (2n^3) with both."""
     n, m = w.n2, w.m
-    return m * (2.0 / 3.0) * n ** 3 + (m - 1) * 2.0 * n ** 3
+    if not odd_even:
+        return m * (2.0 / 3.0) * n ** 3 + (m - 1) * 2.0 * n ** 3
+    total, s = 0.0, 1
+    while m // s >= 1:
+        k = m // s
+        E, NR = (k + 1) // 2, k // 2
+        total += E * (2.0 / 3.0) * n ** 3 + (E - 1) * 2.0 * n ** 3 + NR * 2.0 * n ** 3
+        total += max(NR - 1, 0) * 2.0 * n ** 3
+        s *= 2
+    return total
 
 
-def run_gpu(w: G.Workload, precision: int, steps: int, warmup: int, kappa, f):
+def run_gpu(w: G.Workload, precision: int, steps: int, warmup: int, kappa, f, odd_even: bool):
     import torch
     from paper_2211_07572_amd import slab as S
     torch.cuda.synchronize()
@@ -73,7 +89,8 @@ def run_gpu(w: G.Workload, precision: int, steps: int, warmup: int, kappa, f):
     phases = []
 
     def one():
-        h = S.slab_factor(kappa, w.n2, w.n1, w.b, w.h, precision=precision, tol=1e-10, max_iter=10)
+        h = S.slab_factor(kappa, w.n2, w.n1, w.b, w.h, precision=precision, tol=1e-10, max_iter=10,
+                          odd_even=odd_even)
         u = S.slab_solve(h, f)
         infos.append((h.last_info.iterations, h.last_info.max_relres))
         phases.append(h.phase_us())
@@ -163,7 +180,8 @@ def main():
     torch.cuda.synchronize()
 
     prec = {"mixed": S.SLAB_MIXED, "fp32": S.SLAB_FP32_REFINE}[args.precision]
-    dt32, u32, info32, ph32 = run_gpu(w, prec, args.steps, args.warmup, kappa, f)
+    oe = args.order == "odd_even"
+    dt32, u32, info32, ph32 = run_gpu(w, prec, args.steps, args.warmup, kappa, f, oe)
     relres32 = max(r for _, r in info32)
     iters32 = max(i for i, _ in info32)
     ph = {k: float(np.median([p[k] for p in ph32])) for k in ph32[0]}
@@ -184,7 +202,9 @@ def main():
                    "nrhs": w.nrhs, "N": w.N, "kappa": "exp(GRF l=0.05 var=1)",
                    "rhs": "N(0,1)", "tol": 1e-10,
                    "precision": {"mixed": "FP64 slab work, FP32 reduced system, FP64 refinement",
-                                 "fp32": "FP32 throughout, FP64 sum forming T, FP64 refinement"}[args.precision]},
+                                 "fp32": "FP32 throughout, FP64 sum forming T, FP64 refinement"}[args.precision],
+                   "stage_two": {"odd_even": "odd-even elimination order",
+                                 "sweep": "sweep of Alg. 1"}[args.order]},
         "max_relres": relres32,
         "refine_passes": iters32,
         "phase_ms": {k: v / 1e3 for k, v in ph.items()},
@@ -198,21 +218,24 @@ def main():
                           "bound": "mfma", "achieved": fl / t_schur / 1e12,
                           "peak": PEAK_TFLOPS[dt], "unit": "TFLOP/s",
                           "frac": fl / t_schur / 1e12 / PEAK_TFLOPS[dt], "traffic": None}
+    tb = ph["block_factor"] / 1e6
+    result["block_factor_tflops"] = block_factor_flops(w, oe) / tb / 1e12
+
+    def form(precision, odd_even, steps, warmup):
+        dto, _, info_o, ph_o = run_gpu(w, precision, steps, warmup, kappa, f, odd_even)
+        pm = {k: float(np.median([p[k] for p in ph_o])) / 1e3 for k in ph_o[0]}
+        return dto, {"value": w.N / dto, "ms_per_step": dto * 1e3,
+                     "max_relres": max(r for _, r in info_o),
+                     "refine_passes": max(i for i, _ in info_o), "phase_ms": pm,
+                     "block_factor_tflops": block_factor_flops(w, odd_even) / (pm["block_factor"] / 1e3) / 1e12}
     if not args.skip_other:
         other = "fp32" if args.precision == "mixed" else "mixed"
-        dto, _, info_o, ph_o = run_gpu(w, {"mixed": S.SLAB_MIXED, "fp32": S.SLAB_FP32_REFINE}[other],
-                                       1, 1, kappa, f)
-        result[f"{other}_form"] = {"value": w.N / dto, "ms_per_step": dto * 1e3,
-                                   "max_relres": max(r for _, r in info_o),
-                                   "refine_passes": max(i for i, _ in info_o),
-                                   "phase_ms": {k: v / 1e3 for k, v in ph_o[0].items()}}
-    tb = ph["block_factor"] / 1e6
-    result["block_factor_tflops"] = block_factor_flops(w) / tb / 1e12
+        result[f"{other}_form"] = form({"mixed": S.SLAB_MIXED, "fp32": S.SLAB_FP32_REFINE}[other], oe, 1, 1)[1]
+        other_order = "sweep" if oe else "odd_even"
+        result[f"{other_order}_order"] = form(prec, not oe, 1, 1)[1]
     if not args.skip_fp64:
-        dt64, u64, info64, ph64 = run_gpu(w, S.SLAB_FP64, 1, 0, kappa, f)
-        result["fp64"] = {"value": w.N / dt64, "ms_per_step": dt64 * 1e3,
-                          "max_relres": max(r for _, r in info64),
-                          "phase_ms": {k: v / 1e3 for k, v in ph64[0].items()}}
+        dt64, res64 = form(S.SLAB_FP64, oe, 1, 0)
+        result["fp64"] = res64
         result["fp32_refine_speedup_vs_fp64"] = dt64 / dt32
     if not args.skip_cpu:
         result["cpu_baseline"] = cpu_baseline(w, kappa_np, f_np, args.cpu_slabs)

@@ -12,7 +12,8 @@
  *
  *   slab_factor         Alg. 3: eliminate every slab interior (stage one,
  *                       Sec. 3.1) and factor the block-tridiagonal reduced
- *                       matrix T of n2 x n2 dense blocks (stage two, Alg. 1).
+ *                       matrix T of n2 x n2 dense blocks (stage two, Alg. 1
+ *                       or the odd-even order of the Sec. 4 remark).
  *   slab_solve          Alg. 4: reduced right-hand side (eqs. (f1)-(f5)), the
  *                       sweeping solve (Alg. 2) and the interior back
  *                       substitution (eq. (usol_even)); in mixed precision
@@ -69,6 +70,11 @@ typedef struct slab_handle_s* slab_handle;
 /* option flags */
 #define SLAB_KEEP_REDUCED 1  /* keep FP64 copies of T and of every S_j (Alg. 1) for export */
 #define SLAB_COEF_LOG 2      /* the field passed is theta = log(kappa), not kappa */
+#define SLAB_ODD_EVEN 4      /* stage two in odd-even order (Sec. 4 remark, concluding
+                                section): at every level the interfaces at even
+                                positions of those left are eliminated together, so
+                                a level is one batch of independent block
+                                factorizations; without it, the sweep of Alg. 1 */
 
 typedef struct {
   int32_t n1;          /* interior columns (slab direction); n1 % (b+1) == 0, n1 >= 2 */
@@ -83,7 +89,7 @@ typedef struct {
   int32_t precision;   /* SLAB_FP64, SLAB_FP32_REFINE or SLAB_MIXED */
   double tol;          /* target max-over-columns ||f - A u||_2 / ||f||_2 (e.g. 1e-10) */
   int32_t max_iter;    /* refinement iterations allowed (>= 1; FP64 uses at most this too) */
-  int32_t flags;       /* SLAB_KEEP_REDUCED | SLAB_COEF_LOG */
+  int32_t flags;       /* SLAB_KEEP_REDUCED | SLAB_COEF_LOG | SLAB_ODD_EVEN */
 } slab_options;
 
 typedef struct {
@@ -143,8 +149,10 @@ int slab_residual(slab_handle h, const double* f, const double* u, int32_t nrhs,
                   double* relres, void* hip_stream);
 
 /* Export a reduced block as FP64 n2 x n2 row-major into device memory out:
-   which = 0: T_jj, 1: T_{j,j+1} (j < m-1), 2: S_j of Alg. 1 before its
-   factorization.  Needs SLAB_KEEP_REDUCED at factor time. */
+   which = 0: T_jj, 1: T_{j,j+1} (j < m-1), 2: the pivot block of interface j
+   before its factorization (S_j of Alg. 1, or with SLAB_ODD_EVEN the block of
+   the Schur complement left at the level where j is eliminated).  Needs
+   SLAB_KEEP_REDUCED at factor time. */
 int slab_export_reduced(slab_handle h, int32_t which, int32_t j, double* out, void* hip_stream);
 
 /* Sizes and timings of a handle: what = 0 m, 1 n1, 2 n2, 3 b, 4 precision,

@@ -24,8 +24,6 @@ struct Workspace {
   void* ft = nullptr;
   void* yt = nullptr;
   void* tt = nullptr;
-  void* gemv_work = nullptr;
-  int* gemv_counters = nullptr;
   double* r = nullptr;
   double* norms = nullptr;
   double* partial = nullptr;
@@ -48,6 +46,8 @@ struct slab_handle_s {
   void* Gl = nullptr;
   void* Linv = nullptr;
   void* Z = nullptr;
+  void* Td = nullptr;  // odd-even order: U_e blocks (kept for the solve)
+  int odd_even = 0;
   double* T64 = nullptr;
   double* O64 = nullptr;
   double* S64 = nullptr;
@@ -112,8 +112,7 @@ int check_vec_args(slab_handle h, const void* in, const void* out, int32_t nrhs,
 int ensure_workspace(slab_handle h, int nrhs, hipStream_t st) {
   Workspace& w = h->ws;
   if (w.nrhs >= nrhs) return SLAB_OK;
-  void* ptrs[] = {w.zbuf, w.xb, w.ft, w.yt, w.tt, w.gemv_work, w.gemv_counters, w.r, w.norms,
-                  w.partial};
+  void* ptrs[] = {w.zbuf, w.xb, w.ft, w.yt, w.tt, w.r, w.norms, w.partial};
   for (void* p : ptrs) dev_release(h, p);
   w = Workspace();
   const size_t n = h->n2, m = h->m, e = h->esz, e2 = h->esz2;
@@ -123,9 +122,6 @@ int ensure_workspace(slab_handle h, int nrhs, hipStream_t st) {
   SLAB_TRY(dev_alloc(h, &w.ft, m * nrhs * n * e2));
   SLAB_TRY(dev_alloc(h, &w.yt, m * nrhs * n * e2));
   SLAB_TRY(dev_alloc(h, &w.tt, nrhs * n * e2));
-  SLAB_TRY(dev_alloc(h, &w.gemv_work, gemv_work_bytes(h->n2, nrhs, (int)e2)));
-  SLAB_TRY(dev_alloc(h, (void**)&w.gemv_counters, gemv_counter_count(h->n2) * sizeof(int)));
-  SLAB_HIP_CHECK(hipMemsetAsync(w.gemv_counters, 0, gemv_counter_count(h->n2) * sizeof(int), st));
   SLAB_TRY(dev_alloc(h, (void**)&w.r, nrhs * N * sizeof(double)));
   SLAB_TRY(dev_alloc(h, (void**)&w.norms, 2 * nrhs * sizeof(double)));
   SLAB_TRY(dev_alloc(h, (void**)&w.partial, residual_partial_count(h->n1, h->n2, nrhs) * sizeof(double)));
@@ -136,10 +132,10 @@ int ensure_workspace(slab_handle h, int nrhs, hipStream_t st) {
 SolveArgs solve_args(slab_handle h, int nrhs, int transpose) {
   SolveArgs a;
   a.n1 = h->n1; a.n2 = h->n2; a.b = h->b; a.m = h->m; a.nrhs = nrhs;
-  a.wh = h->wh; a.wv = h->wv; a.Gl = h->Gl; a.Linv = h->Linv; a.Z = h->Z;
+  a.wh = h->wh; a.wv = h->wv; a.Gl = h->Gl; a.Linv = h->Linv; a.Z = h->Z; a.Td = h->Td;
   a.zbuf = h->ws.zbuf; a.xb = h->ws.xb; a.ft = h->ws.ft; a.yt = h->ws.yt; a.tt = h->ws.tt;
-  a.gemv_work = h->ws.gemv_work; a.gemv_counters = h->ws.gemv_counters;
   a.transpose = transpose;
+  a.odd_even = h->odd_even;
   return a;
 }
 
@@ -264,7 +260,7 @@ int factor_impl(slab_handle h, const slab_problem* prob, hipStream_t st, slab_so
   SLAB_TRY((launch_stage1<T, TR>(A, st)));
   Stage2Args B;
   B.n = h->n2; B.m = h->m; B.Tdiag = Td; B.Toff = To; B.Linv = h->Linv; B.Z = h->Z;
-  B.S64 = h->S64; B.status = h->status;
+  B.S64 = h->S64; B.status = h->status; B.odd_even = h->odd_even;
   SLAB_TRY(launch_stage2<TR>(B, st));
   SLAB_HIP_CHECK(hipEventRecord(ev[5], st));
   SLAB_HIP_CHECK(hipMemcpyAsync(hs, h->status, sizeof(hs), hipMemcpyDeviceToHost, st));
@@ -273,8 +269,10 @@ int factor_impl(slab_handle h, const slab_problem* prob, hipStream_t st, slab_so
   // alone), assembly of T, block factorization
   for (int i = 0; i < 5; ++i) h->phase_us[i] = elapsed_us(ev[i], ev[i + 1]);
   for (int i = 0; i < 6; ++i) (void)hipEventDestroy(ev[i]);
-  void* tmp[] = {Hsw, sig, PRR, PLL, PLR, PRL, Td, To};
+  void* tmp[] = {Hsw, sig, PRR, PLL, PLR, PRL, To};
   for (void* p : tmp) dev_release(h, p);
+  if (h->odd_even) h->Td = Td;
+  else dev_release(h, Td);
   if (hs[0] != 0) {
     if (info) info->failed_block = hs[1];
     set_error(hs[0] == 2 ? "slab factorization breakdown in slab " + std::to_string(hs[1])
@@ -307,7 +305,7 @@ int slab_check_problem(const slab_problem* prob, const slab_options* opts) {
     }
     if (!(opts->tol > 0.0) || !std::isfinite(opts->tol)) { set_error("tol must be positive"); return SLAB_E_INVALID; }
     if (opts->max_iter < 1) { set_error("max_iter must be >= 1"); return SLAB_E_INVALID; }
-    if (opts->flags & ~(SLAB_KEEP_REDUCED | SLAB_COEF_LOG)) { set_error("unknown flag"); return SLAB_E_INVALID; }
+    if (opts->flags & ~(SLAB_KEEP_REDUCED | SLAB_COEF_LOG | SLAB_ODD_EVEN)) { set_error("unknown flag"); return SLAB_E_INVALID; }
   }
   return SLAB_OK;
 }
@@ -323,6 +321,7 @@ int slab_factor(const slab_problem* prob, const slab_options* opts, void* hip_st
   h->n1 = prob->n1; h->n2 = prob->n2; h->b = prob->b; h->m = prob->n1 / (prob->b + 1);
   h->BP = padded_block(prob->b); h->h = prob->h;
   if (opts) { h->precision = opts->precision; h->tol = opts->tol; h->max_iter = opts->max_iter; h->flags = opts->flags; }
+  h->odd_even = (h->flags & SLAB_ODD_EVEN) ? 1 : 0;
   h->esz = h->precision == SLAB_FP32_REFINE ? 4 : 8;
   h->esz2 = h->precision == SLAB_FP64 ? 8 : 4;
   if (hipGetDevice(&h->device) != hipSuccess) {

@@ -218,7 +218,8 @@ template int launch_gemm<double>(bool, bool, int, int, int, double, const double
                                  long long, long long, int, int, hipStream_t);
 
 // ---------------------------------------------------------------------------
-// Panel of the right-looking factorization of one pivot block S (n x n).
+// Panel of the right-looking factorization of a pivot block S (n x n), for
+// gridDim.y independent blocks at once.
 // Every workgroup first inverts the Cholesky factor of the 64x64 diagonal
 // block [k0, k0+nb): Gaussian elimination without pivoting on [S_kk | I],
 // kept in one array (U on and above the diagonal, the unit lower L~^-1 below
@@ -232,8 +233,12 @@ template int launch_gemm<double>(bool, bool, int, int, int, double, const double
 template <typename T>
 __global__ __launch_bounds__(256) void k_panel(T* __restrict__ S, T* __restrict__ Lv, int n,
                                                int k0, int nrow_wg, int* __restrict__ status,
-                                               int blk) {
+                                               int blk, long long bs, int blk_step) {
   typedef typename acc4<T>::type V4;
+  // blockIdx.y selects one of several independent pivot blocks, bs elements apart
+  S += (long long)blockIdx.y * bs;
+  Lv += (long long)blockIdx.y * bs;
+  blk += (int)blockIdx.y * blk_step;
   __shared__ T E[64][65];   // L_kk^-1 after the elimination
   __shared__ T Bt[64][65];  // operand tile
   __shared__ T rowbuf[2][64];
@@ -378,8 +383,10 @@ __global__ __launch_bounds__(256) void k_panel(T* __restrict__ S, T* __restrict_
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_rank64(T* __restrict__ S, T* __restrict__ Lv, int n,
-                                                int k0, int nb, int ntrail) {
+                                                int k0, int nb, int ntrail, long long bs) {
   typedef typename acc4<T>::type V4;
+  S += (long long)blockIdx.y * bs;
+  Lv += (long long)blockIdx.y * bs;
   __shared__ T As[64][65];  // As[row][k]
   __shared__ T Bs[64][65];  // Bs[col][k]
   const int tid = threadIdx.x;
@@ -468,7 +475,8 @@ __global__ __launch_bounds__(256) void k_rank64(T* __restrict__ S, T* __restrict
 }
 
 template <typename T>
-__global__ void k_identity(T* __restrict__ X, int n) {
+__global__ void k_identity(T* __restrict__ X, int n, long long bs) {
+  X += (long long)blockIdx.y * bs;
   const long long tot = (long long)n * n;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot;
        e += (long long)gridDim.x * blockDim.x) {
@@ -478,13 +486,51 @@ __global__ void k_identity(T* __restrict__ X, int n) {
 
 // FP64 copy of a symmetric block stored in its lower triangle.
 template <typename T>
-__global__ void k_sym_to_f64(const T* __restrict__ S, double* __restrict__ out, int n) {
+__global__ void k_sym_to_f64(const T* __restrict__ S, double* __restrict__ out, int n,
+                             long long bs) {
+  S += (long long)blockIdx.y * bs;
+  out += (long long)blockIdx.y * bs;
   const long long tot = (long long)n * n;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot;
        e += (long long)gridDim.x * blockDim.x) {
     const long long i = e / n, k = e % n;
     out[e] = (double)(k <= i ? S[e] : S[k * n + i]);
   }
+}
+
+// Cholesky factorization with carried inverse of `count` pivot blocks S_q =
+// S + q*bs (n x n, lower triangles), L_q^-1 into Li + q*bs; breakdown of block
+// q is reported as blk0 + q*blk_step.
+template <typename T>
+static int factor_blocks(T* S, T* Li, int n, int count, long long bs, int blk0, int blk_step,
+                         double* S64, int* status, hipStream_t st) {
+  if (count <= 0) return SLAB_OK;
+  const long long nsq = (long long)n * n;
+  const unsigned fill_grid = (unsigned)std::min<long long>((nsq + 255) / 256, 4096);
+  if (S64) {
+    hipLaunchKernelGGL((k_sym_to_f64<T>), dim3(fill_grid, count), dim3(256), 0, st, S, S64, n, bs);
+    SLAB_LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL((k_identity<T>), dim3(fill_grid, count), dim3(256), 0, st, Li, n, bs);
+  SLAB_LAUNCH_CHECK();
+  for (int k0 = 0; k0 < n; k0 += 64) {
+    const int nb = std::min(64, n - k0);
+    const int nrow = n - k0 - nb;
+    const int nrow_wg = (nrow + 63) / 64;
+    const int ncol_wg = (k0 + nb + 63) / 64;
+    hipLaunchKernelGGL((k_panel<T>), dim3(nrow_wg + ncol_wg, count), dim3(256), 0, st, S, Li, n,
+                       k0, nrow_wg, status, blk0, bs, blk_step);
+    SLAB_LAUNCH_CHECK();
+    if (nrow > 0) {
+      const long long tr = (nrow + 63) / 64;
+      const int ntrail = (int)(tr * (tr + 1) / 2);
+      const int naug = (int)(tr * ((k0 + nb + 63) / 64));
+      hipLaunchKernelGGL((k_rank64<T>), dim3(ntrail + naug, count), dim3(256), 0, st, S, Li, n,
+                         k0, nb, ntrail, bs);
+      SLAB_LAUNCH_CHECK();
+    }
+  }
+  return SLAB_OK;
 }
 
 template <typename T>
@@ -495,43 +541,68 @@ int launch_stage2(const Stage2Args& a, hipStream_t st) {
   T* Toff = (T*)a.Toff;
   T* Linv = (T*)a.Linv;
   T* Z = (T*)a.Z;
-  const unsigned fill_grid = (unsigned)std::min<long long>((nsq + 255) / 256, 16384);
-  for (int j = 0; j < m; ++j) {
-    T* S = Tdiag + (long long)j * nsq;
-    T* Li = Linv + (long long)j * nsq;
-    if (j > 0) {
-      const T* Zp = Z + (long long)(j - 1) * nsq;
-      int rc = launch_gemm<T>(true, false, n, n, n, (T)-1, Zp, n, 0, Zp, n, 0, (T)1, S, n, 0, 1,
-                              GEMM_LOWER_C, st);
+  if (!a.odd_even) {
+    // Alg. 1 in block Cholesky form: S_j = T_jj - Z_{j-1}^T Z_{j-1}, S_j = L_j L_j^T,
+    // Z_j = L_j^-1 T_{j,j+1}
+    for (int j = 0; j < m; ++j) {
+      T* S = Tdiag + (long long)j * nsq;
+      T* Li = Linv + (long long)j * nsq;
+      if (j > 0) {
+        const T* Zp = Z + (long long)(j - 1) * nsq;
+        int rc = launch_gemm<T>(true, false, n, n, n, (T)-1, Zp, n, 0, Zp, n, 0, (T)1, S, n, 0, 1,
+                                GEMM_LOWER_C, st);
+        if (rc) return rc;
+      }
+      int rc = factor_blocks<T>(S, Li, n, 1, 0, j, 0, a.S64 ? a.S64 + (long long)j * nsq : nullptr,
+                                a.status, st);
       if (rc) return rc;
-    }
-    if (a.S64) {
-      hipLaunchKernelGGL((k_sym_to_f64<T>), dim3(fill_grid), dim3(256), 0, st, S,
-                         a.S64 + (long long)j * nsq, n);
-      SLAB_LAUNCH_CHECK();
-    }
-    hipLaunchKernelGGL((k_identity<T>), dim3(fill_grid), dim3(256), 0, st, Li, n);
-    SLAB_LAUNCH_CHECK();
-    for (int k0 = 0; k0 < n; k0 += 64) {
-      const int nb = std::min(64, n - k0);
-      const int nrow = n - k0 - nb;
-      const int nrow_wg = (nrow + 63) / 64;
-      const int ncol_wg = (k0 + nb + 63) / 64;
-      hipLaunchKernelGGL((k_panel<T>), dim3(nrow_wg + ncol_wg), dim3(256), 0, st, S, Li, n, k0,
-                         nrow_wg, a.status, j);
-      SLAB_LAUNCH_CHECK();
-      if (nrow > 0) {
-        const long long tr = (nrow + 63) / 64;
-        const int ntrail = (int)(tr * (tr + 1) / 2);
-        const int naug = (int)(tr * ((k0 + nb + 63) / 64));
-        hipLaunchKernelGGL((k_rank64<T>), dim3(ntrail + naug), dim3(256), 0, st, S, Li, n, k0, nb,
-                           ntrail);
-        SLAB_LAUNCH_CHECK();
+      if (j < m - 1) {
+        rc = launch_gemm<T>(false, false, n, n, n, (T)1, Li, n, 0, Toff + (long long)j * nsq, n,
+                            0, (T)0, Z + (long long)j * nsq, n, 0, 1, GEMM_A_LOWER, st);
+        if (rc) return rc;
       }
     }
-    if (j < m - 1) {
-      int rc = launch_gemm<T>(false, false, n, n, n, (T)1, Li, n, 0, Toff + (long long)j * nsq, n,
-                              0, (T)0, Z + (long long)j * nsq, n, 0, 1, GEMM_A_LOWER, st);
+    return SLAB_OK;
+  }
+  // Odd-even order.  At level l (stride s = 2^l) the interfaces still present
+  // are a_p = (p+1)s - 1, p < k = floor(m/s); those at even positions,
+  // e_q = (2q+1)s - 1, q < E = ceil(k/2), are eliminated together.  e_q has a
+  // kept neighbour l = e_q - s when q >= 1 and r = e_q + s when q < floor(k/2).
+  // With D_e = L L^T:  U_e = L^-1 C_l^T (stored over D_e), V_e = L^-1 C_e (in Z),
+  //   D_l -= U_e^T U_e,  D_r -= V_e^T V_e,  C_l = -U_e^T V_e,
+  // where C_x (in Toff) is the coupling of x to the next interface present.
+  for (long long s = 1; m / s >= 1; s *= 2) {
+    const int k = (int)(m / s);
+    const int E = (k + 1) / 2, NR = k / 2;
+    const long long e0 = s - 1, es = 2 * s * nsq;
+    int rc = factor_blocks<T>(Tdiag + e0 * nsq, Linv + e0 * nsq, n, E, es, (int)e0, (int)(2 * s),
+                              a.S64 ? a.S64 + e0 * nsq : nullptr, a.status, st);
+    if (rc) return rc;
+    const long long e1 = e0 + 2 * s;  // first eliminated interface with a left neighbour
+    if (E > 1) {  // U_e = L_e^-1 C_{e-s}^T
+      rc = launch_gemm<T>(false, true, n, n, n, (T)1, Linv + e1 * nsq, n, es,
+                          Toff + (e1 - s) * nsq, n, es, (T)0, Tdiag + e1 * nsq, n, es, E - 1,
+                          GEMM_A_LOWER, st);
+      if (rc) return rc;
+    }
+    if (NR > 0) {  // V_e = L_e^-1 C_e
+      rc = launch_gemm<T>(false, false, n, n, n, (T)1, Linv + e0 * nsq, n, es, Toff + e0 * nsq, n,
+                          es, (T)0, Z + e0 * nsq, n, es, NR, GEMM_A_LOWER, st);
+      if (rc) return rc;
+    }
+    if (E > 1) {  // D_l -= U_e^T U_e
+      rc = launch_gemm<T>(true, false, n, n, n, (T)-1, Tdiag + e1 * nsq, n, es, Tdiag + e1 * nsq,
+                          n, es, (T)1, Tdiag + (e1 - s) * nsq, n, es, E - 1, GEMM_LOWER_C, st);
+      if (rc) return rc;
+    }
+    if (NR > 0) {  // D_r -= V_e^T V_e
+      rc = launch_gemm<T>(true, false, n, n, n, (T)-1, Z + e0 * nsq, n, es, Z + e0 * nsq, n, es,
+                          (T)1, Tdiag + (e0 + s) * nsq, n, es, NR, GEMM_LOWER_C, st);
+      if (rc) return rc;
+    }
+    if (NR > 1) {  // C_l = -U_e^T V_e for the interfaces with both neighbours
+      rc = launch_gemm<T>(true, false, n, n, n, (T)-1, Tdiag + e1 * nsq, n, es, Z + e1 * nsq, n,
+                          es, (T)0, Toff + (e1 - s) * nsq, n, es, NR - 1, 0, st);
       if (rc) return rc;
     }
   }
@@ -549,19 +620,25 @@ template int launch_stage2<double>(const Stage2Args&, hipStream_t);
 // Each lane loads 16 contiguous bytes of M and of x per step, which feed
 // VEC consecutive MFMA k-steps (k permuted consistently in A and B).
 // ---------------------------------------------------------------------------
-constexpr int BMV_COLS = 16;
 constexpr int BMV_WAVES = 16;
 
-size_t gemv_work_bytes(int n, int nrhs, int elem) {
-  (void)n; (void)nrhs; (void)elem;
-  return 256;
-}
-int gemv_counter_count(int n) { (void)n; return 1; }
+
 
 template <typename T, bool TR, bool LOWER>
-__global__ __launch_bounds__(1024) void k_bmv(int n, int nc, T alpha, const T* __restrict__ M,
-                                             const T* __restrict__ x, T beta,
-                                             const T* __restrict__ xin, T* __restrict__ y) {
+__global__ __launch_bounds__(1024) void k_bmv(int n, int nrhs, T alpha, const T* __restrict__ M,
+                                             long long sM, const T* __restrict__ x, long long sx,
+                                             T beta, const T* xin, long long sxin, T* y,
+                                             long long sy) {
+  // blockIdx.z: independent product q (operands sM, sx, sxin, sy elements
+  // apart); blockIdx.y: group of 16 columns.  xin may alias y.
+  M += (long long)blockIdx.z * sM;
+  {
+    const long long c0 = (long long)blockIdx.y * 16 * n;
+    x += (long long)blockIdx.z * sx + c0;
+    if (xin) xin += (long long)blockIdx.z * sxin + c0;
+    y += (long long)blockIdx.z * sy + c0;
+  }
+  const int nc = min(16, nrhs - 16 * (int)blockIdx.y);
   typedef typename acc4<T>::type V4;
   constexpr int VEC = 16 / sizeof(T);   // elements per 16-byte load
   constexpr int KS = 4 * VEC;           // k covered by one load per lane
@@ -626,29 +703,28 @@ __global__ __launch_bounds__(1024) void k_bmv(int n, int nc, T alpha, const T* _
 }
 
 template <typename T>
-int launch_gemv(bool tr, bool lower, int n, int nrhs, T alpha, const T* M, const T* x, T beta,
-                const T* xin, T* y, void* work, int* counters, hipStream_t st) {
-  (void)work; (void)counters;
-  for (int c0 = 0; c0 < nrhs; c0 += BMV_COLS) {
-    const int nc = std::min(BMV_COLS, nrhs - c0);
-    const long long off = (long long)c0 * n;
-    dim3 grid((n + 15) / 16);
-#define SLAB_BMV_CASE(TRV, LOV)                                                                 \
-  hipLaunchKernelGGL((k_bmv<T, TRV, LOV>), grid, dim3(64 * BMV_WAVES), 0, st, n, nc, alpha, M, \
-                     x + off, beta, xin ? xin + off : nullptr, y + off)
-    if (!tr && !lower) SLAB_BMV_CASE(false, false);
-    else if (!tr && lower) SLAB_BMV_CASE(false, true);
-    else if (tr && !lower) SLAB_BMV_CASE(true, false);
-    else SLAB_BMV_CASE(true, true);
+int launch_gemv(bool tr, bool lower, int n, int nrhs, T alpha, const T* M, long long sM,
+                const T* x, long long sx, T beta, const T* xin, long long sxin, T* y, long long sy,
+                int batch, hipStream_t st) {
+  if (batch <= 0 || nrhs <= 0 || n <= 0) return SLAB_OK;
+  dim3 grid((n + 15) / 16, (nrhs + 15) / 16, batch);
+#define SLAB_BMV_CASE(TRV, LOV)                                                                   \
+  hipLaunchKernelGGL((k_bmv<T, TRV, LOV>), grid, dim3(64 * BMV_WAVES), 0, st, n, nrhs, alpha, M, \
+                     sM, x, sx, beta, xin, sxin, y, sy)
+  if (!tr && !lower) SLAB_BMV_CASE(false, false);
+  else if (!tr && lower) SLAB_BMV_CASE(false, true);
+  else if (tr && !lower) SLAB_BMV_CASE(true, false);
+  else SLAB_BMV_CASE(true, true);
 #undef SLAB_BMV_CASE
-    SLAB_LAUNCH_CHECK();
-  }
+  SLAB_LAUNCH_CHECK();
   return SLAB_OK;
 }
-template int launch_gemv<float>(bool, bool, int, int, float, const float*, const float*, float,
-                                const float*, float*, void*, int*, hipStream_t);
-template int launch_gemv<double>(bool, bool, int, int, double, const double*, const double*,
-                                 double, const double*, double*, void*, int*, hipStream_t);
+template int launch_gemv<float>(bool, bool, int, int, float, const float*, long long,
+                                const float*, long long, float, const float*, long long, float*,
+                                long long, int, hipStream_t);
+template int launch_gemv<double>(bool, bool, int, int, double, const double*, long long,
+                                 const double*, long long, double, const double*, long long,
+                                 double*, long long, int, hipStream_t);
 
 // ---------------------------------------------------------------------------
 __global__ void k_cast_f64(const void* __restrict__ src, int is_float, double* __restrict__ dst,

@@ -290,36 +290,75 @@ static int sweeps_bp(const SolveArgs& A, const double* rhs, long long ld_rhs, do
                        rhs, (const T*)A.xb, (TR*)A.ft);
     SLAB_LAUNCH_CHECK();
   }
-  // (ii) Alg. 2 with the block Cholesky factors: T = R R^T, R_jj = L_j, R_{j+1,j} = Z_j^T
+  // (ii) the reduced system
   TR* ft = (TR*)A.ft;
   TR* yt = (TR*)A.yt;
   TR* tt = (TR*)A.tt;
   const TR* Li = (const TR*)A.Linv;
   const TR* Z = (const TR*)A.Z;
+  const TR* U = (const TR*)A.Td;
   const long long vs = (long long)nrhs * n;
-  for (int j = 0; j < m; ++j) {
-    const TR* src = ft + j * vs;
-    if (j > 0) {
-      int rc = launch_gemv<TR>(true, false, n, nrhs, (TR)-1, Z + (j - 1) * nsq, yt + (j - 1) * vs,
-                              (TR)1, ft + j * vs, tt, A.gemv_work, A.gemv_counters, st);
+  if (!A.odd_even) {
+    // Alg. 2 with the block Cholesky factors: T = R R^T, R_jj = L_j, R_{j+1,j} = Z_j^T
+    for (int j = 0; j < m; ++j) {
+      const TR* src = ft + j * vs;
+      if (j > 0) {
+        int rc = launch_gemv<TR>(true, false, n, nrhs, (TR)-1, Z + (j - 1) * nsq, 0,
+                                 yt + (j - 1) * vs, 0, (TR)1, ft + j * vs, 0, tt, 0, 1, st);
+        if (rc) return rc;
+        src = tt;
+      }
+      int rc = launch_gemv<TR>(false, true, n, nrhs, (TR)1, Li + j * nsq, 0, src, 0, (TR)0,
+                               nullptr, 0, yt + j * vs, 0, 1, st);
       if (rc) return rc;
-      src = tt;
     }
-    int rc = launch_gemv<TR>(false, true, n, nrhs, (TR)1, Li + j * nsq, src, (TR)0, nullptr,
-                            yt + j * vs, A.gemv_work, A.gemv_counters, st);
-    if (rc) return rc;
-  }
-  for (int j = m - 1; j >= 0; --j) {
-    const TR* src = yt + j * vs;
-    if (j < m - 1) {
-      int rc = launch_gemv<TR>(false, false, n, nrhs, (TR)-1, Z + j * nsq, ft + (j + 1) * vs, (TR)1,
-                              yt + j * vs, tt, A.gemv_work, A.gemv_counters, st);
+    for (int j = m - 1; j >= 0; --j) {
+      const TR* src = yt + j * vs;
+      if (j < m - 1) {
+        int rc = launch_gemv<TR>(false, false, n, nrhs, (TR)-1, Z + j * nsq, 0, ft + (j + 1) * vs,
+                                 0, (TR)1, yt + j * vs, 0, tt, 0, 1, st);
+        if (rc) return rc;
+        src = tt;
+      }
+      int rc = launch_gemv<TR>(true, true, n, nrhs, (TR)1, Li + j * nsq, 0, src, 0, (TR)0,
+                               nullptr, 0, ft + j * vs, 0, 1, st);
       if (rc) return rc;
-      src = tt;
     }
-    int rc = launch_gemv<TR>(true, true, n, nrhs, (TR)1, Li + j * nsq, src, (TR)0, nullptr,
-                            ft + j * vs, A.gemv_work, A.gemv_counters, st);
-    if (rc) return rc;
+  } else {
+    // odd-even order (same levels as the factorization): reduce the
+    // right-hand side level by level, y_e = L_e^-1 g_e, g_l -= U_e^T y_e,
+    // g_r -= V_e^T y_e; then from the top level down
+    // x_e = L_e^-T (y_e - U_e x_l - V_e x_r), x_e overwriting g_e.
+    int nlev = 0;
+    for (long long s = 1; m / s >= 1; s *= 2) ++nlev;
+    for (int lev = 0; lev < nlev; ++lev) {
+      const long long s = 1LL << lev;
+      const int k = (int)(m / s), E = (k + 1) / 2, NR = k / 2;
+      const long long e0 = s - 1, e1 = e0 + 2 * s, ms = 2 * s * nsq, v2 = 2 * s * vs;
+      int rc = launch_gemv<TR>(false, true, n, nrhs, (TR)1, Li + e0 * nsq, ms, ft + e0 * vs, v2,
+                               (TR)0, nullptr, 0, yt + e0 * vs, v2, E, st);
+      if (rc) return rc;
+      rc = launch_gemv<TR>(true, false, n, nrhs, (TR)-1, Z + e0 * nsq, ms, yt + e0 * vs, v2, (TR)1,
+                           ft + (e0 + s) * vs, v2, ft + (e0 + s) * vs, v2, NR, st);
+      if (rc) return rc;
+      rc = launch_gemv<TR>(true, false, n, nrhs, (TR)-1, U + e1 * nsq, ms, yt + e1 * vs, v2, (TR)1,
+                           ft + (e1 - s) * vs, v2, ft + (e1 - s) * vs, v2, E - 1, st);
+      if (rc) return rc;
+    }
+    for (int lev = nlev - 1; lev >= 0; --lev) {
+      const long long s = 1LL << lev;
+      const int k = (int)(m / s), E = (k + 1) / 2, NR = k / 2;
+      const long long e0 = s - 1, e1 = e0 + 2 * s, ms = 2 * s * nsq, v2 = 2 * s * vs;
+      int rc = launch_gemv<TR>(false, false, n, nrhs, (TR)-1, Z + e0 * nsq, ms, ft + (e0 + s) * vs,
+                               v2, (TR)1, yt + e0 * vs, v2, yt + e0 * vs, v2, NR, st);
+      if (rc) return rc;
+      rc = launch_gemv<TR>(false, false, n, nrhs, (TR)-1, U + e1 * nsq, ms, ft + (e1 - s) * vs, v2,
+                           (TR)1, yt + e1 * vs, v2, yt + e1 * vs, v2, E - 1, st);
+      if (rc) return rc;
+      rc = launch_gemv<TR>(true, true, n, nrhs, (TR)1, Li + e0 * nsq, ms, yt + e0 * vs, v2, (TR)0,
+                           nullptr, 0, ft + e0 * vs, v2, E, st);
+      if (rc) return rc;
+    }
   }
   // (iii) interior back substitution, and the interface values
   {

@@ -48,23 +48,31 @@ int launch_gemm(bool ak, bool bn, int M, int N, int K, T alpha, const T* A, long
 
 struct Stage2Args {
   int n, m;
-  void* Tdiag;   // in: T_jj (working precision), overwritten (S_j, then factor scratch)
-  void* Toff;    // in: T_{j,j+1}
-  void* Linv;    // out: m blocks, L_j^{-1} (lower), L_j L_j^T = S_j
-  void* Z;       // out: m-1 blocks, Z_j = L_j^{-1} T_{j,j+1}
-  double* S64;   // optional: FP64 copy of each S_j before its factorization
+  // Alg. 1:    Tdiag in T_jj, overwritten; Linv_j = L_j^-1 with L_j L_j^T = S_j;
+  //            Z_j = L_j^-1 T_{j,j+1}; Toff unchanged.
+  // odd-even:  Linv_e = L_e^-1 of the pivot block of interface e; Tdiag_e is
+  //            overwritten by U_e = L_e^-1 C^T (coupling to the neighbour
+  //            before e), Z_e = V_e = L_e^-1 C_e (to the neighbour after e);
+  //            Toff holds the couplings of the last level that used them.
+  void* Tdiag;   // m blocks of n x n
+  void* Toff;    // m-1 blocks, T_{j,j+1} on entry
+  void* Linv;    // m blocks
+  void* Z;       // m-1 blocks
+  double* S64;   // optional: FP64 copy of each pivot block before its factorization
   int* status;
+  int odd_even;  // 0: Alg. 1 sweep; 1: odd-even elimination order
 };
 template <typename T> int launch_stage2(const Stage2Args& a, hipStream_t st);
 
-// y = beta*x_in + alpha * M x over nrhs columns of length n (column c of a
-// block vector at c*n); M(i,k) = M[i*n+k] (tr=false) or M[k*n+i] (tr=true);
-// lower=true restricts M to its triangle (k <= i for tr=false, k >= i for tr=true).
+// y_q = beta*xin_q + alpha * M_q x_q for q < batch (M_q = M + q*sM, likewise
+// x, xin, y) over nrhs columns of length n (column c of a block vector at
+// c*n); M(i,k) = M[i*n+k] (tr=false) or M[k*n+i] (tr=true); lower=true
+// restricts M to its triangle (k <= i for tr=false, k >= i for tr=true).
+// xin may be null (beta ignored) or equal to y.
 template <typename T>
-int launch_gemv(bool tr, bool lower, int n, int nrhs, T alpha, const T* M, const T* x, T beta,
-                const T* xin, T* y, void* work, int* counters, hipStream_t st);
-size_t gemv_work_bytes(int n, int nrhs, int elem);
-int gemv_counter_count(int n);
+int launch_gemv(bool tr, bool lower, int n, int nrhs, T alpha, const T* M, long long sM,
+                const T* x, long long sx, T beta, const T* xin, long long sxin, T* y, long long sy,
+                int batch, hipStream_t st);
 
 // ---- solve kernels -----------------------------------------------------------
 struct SolveArgs {
@@ -74,14 +82,14 @@ struct SolveArgs {
   const void* Gl;
   const void* Linv;
   const void* Z;
+  const void* Td;  // odd-even order: U_e blocks
   void* zbuf;      // m * nrhs * n2 * BP scratch (slab precision)
   void* xb;        // m * 2 * nrhs * n2 boundary values (slab precision)
   void* ft;        // m * nrhs * n2 reduced vectors (reduced-system precision)
   void* yt;        // m * nrhs * n2
   void* tt;        // nrhs * n2 temporary
-  void* gemv_work;
-  int* gemv_counters;
   int transpose;   // 1: adjoint (A^T) sweeps
+  int odd_even;    // reduced system factored in odd-even order
 };
 // One pass of Alg. 4: slab sweeps in T (the slab factors' type), the reduced
 // system in TR (the block factorization's type); rhs (FP64) -> out (FP64);

@@ -28,6 +28,7 @@ SLAB_MIXED = 2
 
 SLAB_KEEP_REDUCED = 1
 SLAB_COEF_LOG = 2
+SLAB_ODD_EVEN = 4
 
 _STATUS_NAMES = {0: "SLAB_OK", -1: "SLAB_E_INVALID", -2: "SLAB_E_NOMEM", -3: "SLAB_E_BREAKDOWN",
                  -4: "SLAB_E_NOCONV", -5: "SLAB_E_HIP"}
@@ -158,7 +159,7 @@ def _vec_shape(t, n2, n1):
 
 def slab_factor(kappa, n2: int, n1: int, b: int, h: float | None = None, precision: int = SLAB_FP64,
                 tol: float = 1e-10, max_iter: int = 10, keep_reduced: bool = False,
-                coef_log: bool = False, stream=None) -> SlabHandle:
+                coef_log: bool = False, odd_even: bool = False, stream=None) -> SlabHandle:
     """Alg. 3 on the device field kappa (or theta = log kappa), shape (n1+2, n2+2)."""
     L = load_library()
     if h is None:
@@ -166,7 +167,8 @@ def slab_factor(kappa, n2: int, n1: int, b: int, h: float | None = None, precisi
     if tuple(kappa.shape) != (n1 + 2, n2 + 2):
         raise ValueError(f"kappa must have shape {(n1 + 2, n2 + 2)}")
     prob = slab_problem(n1, n2, b, float(h), _dev_f64(kappa, "kappa"))
-    flags = (SLAB_KEEP_REDUCED if keep_reduced else 0) | (SLAB_COEF_LOG if coef_log else 0)
+    flags = ((SLAB_KEEP_REDUCED if keep_reduced else 0) | (SLAB_COEF_LOG if coef_log else 0)
+             | (SLAB_ODD_EVEN if odd_even else 0))
     opts = slab_options(precision, float(tol), int(max_iter), flags)
     out = ctypes.c_void_p()
     info = slab_solve_info()
@@ -246,7 +248,8 @@ def slab_residual(handle: SlabHandle, f, u, stream=None) -> list[float]:
 
 
 def slab_export_reduced(handle: SlabHandle, which: int, j: int, stream=None):
-    """FP64 copy of T_jj (which=0), T_{j,j+1} (1) or S_j (2); needs keep_reduced."""
+    """FP64 copy of T_jj (which=0), T_{j,j+1} (1) or the pivot block of interface j
+    before its factorization (2: S_j of Alg. 1, or the odd-even pivot); needs keep_reduced."""
     import torch
     out = torch.empty((handle.n2, handle.n2), dtype=torch.float64, device="cuda")
     _check(load_library().slab_export_reduced(handle.ptr, which, j, _dev_f64(out, "out"),

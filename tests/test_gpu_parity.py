@@ -45,6 +45,20 @@ CASES = [
     (1, 8, 1),
     (64, 64, 7),
 ]
+# odd-even order: odd m and a deeper level tree on top of the cases above
+CASES_OE = CASES + [(40, 52, 3), (64, 256, 7)]
+ORDERS = ["sweep", "odd_even"]
+
+
+def _pivot(fac, j):
+    return fac.s2.pivot(j) if isinstance(fac.s2, O.OddEven) else fac.s2.S[j]
+
+
+def _cases(order):
+    return CASES_OE if order == "odd_even" else CASES
+
+
+ORDER_CASES = [(o,) + c for o in ORDERS for c in _cases(o)]
 
 
 @pytest.mark.parametrize("n2,n1,b", [(64, 64, 7), (1, 2, 1), (1024, 1024, 31), (2048, 4096, 31),
@@ -59,18 +73,18 @@ def test_index_maps_bit_exact(n2, n1, b):
         assert np.array_equal(g, ref[key]), key
 
 
-@pytest.mark.parametrize("n2,n1,b", CASES)
-def test_fp64_reduced_blocks_and_solve(n2, n1, b):
-    print(f"case fp64 n2={n2} n1={n1} b={b}", flush=True)
+@pytest.mark.parametrize("order,n2,n1,b", ORDER_CASES)
+def test_fp64_reduced_blocks_and_solve(order, n2, n1, b):
+    print(f"case fp64 {order} n2={n2} n1={n1} b={b}", flush=True)
     kap = G.kappa_lognormal(n2, n1, 3)
     prob = O.make_problem(kap, n2, n1, b)
-    fac = O.factor(prob)
-    h = S.slab_factor(_dev(kap), n2, n1, b, keep_reduced=True)
+    fac = O.factor(prob, order=order)
+    h = S.slab_factor(_dev(kap), n2, n1, b, keep_reduced=True, odd_even=order == "odd_even")
     for j in range(prob.m):
         T = S.slab_export_reduced(h, 0, j).cpu().numpy()
         assert _rel_fro(T, fac.s1.T_diag[j]) <= 1e-12, ("T_jj", j)
         Sj = S.slab_export_reduced(h, 2, j).cpu().numpy()
-        assert _rel_fro(Sj, fac.s2.S[j]) <= 1e-12, ("S_j", j)
+        assert _rel_fro(Sj, _pivot(fac, j)) <= 1e-12, ("pivot", j)
     for j in range(prob.m - 1):
         Tu = S.slab_export_reduced(h, 1, j).cpu().numpy()
         assert _rel_fro(Tu, fac.s1.T_up[j]) <= 1e-12, ("T_j,j+1", j)
@@ -84,13 +98,13 @@ def test_fp64_reduced_blocks_and_solve(n2, n1, b):
 
 
 @pytest.mark.parametrize("precision", [S.SLAB_FP32_REFINE, S.SLAB_MIXED])
-@pytest.mark.parametrize("n2,n1,b", CASES)
-def test_fp32_refinement(n2, n1, b, precision):
-    print(f"case precision={precision} n2={n2} n1={n1} b={b}", flush=True)
+@pytest.mark.parametrize("order,n2,n1,b", ORDER_CASES)
+def test_fp32_refinement(order, n2, n1, b, precision):
+    print(f"case precision={precision} {order} n2={n2} n1={n1} b={b}", flush=True)
     kap = G.kappa_lognormal(n2, n1, 4)
     prob = O.make_problem(kap, n2, n1, b)
     h = S.slab_factor(_dev(kap), n2, n1, b, precision=precision, tol=1e-10,
-                      keep_reduced=True)
+                      keep_reduced=True, odd_even=order == "odd_even")
     f = G.rhs_normal(n2, n1, 4, 8)
     u = S.slab_solve(h, _dev(f)).cpu().numpy()
     rr = O.relres(prob, u, f)
@@ -99,24 +113,25 @@ def test_fp32_refinement(n2, n1, b, precision):
     assert 1 <= h.last_info.iterations <= 6
     # FP32 slab work with an FP64 sum gives T to about 1e-6; FP64 slab work gives
     # T to FP64 accuracy (the block factorization itself runs in FP32 in both)
-    fac = O.factor(prob)
+    fac = O.factor(prob, order=order)
     errT = max(_rel_fro(S.slab_export_reduced(h, 0, j).cpu().numpy(), fac.s1.T_diag[j])
                for j in range(prob.m))
     assert errT <= (1e-5 if precision == S.SLAB_FP32_REFINE else 1e-12), errT
-    errS = max(_rel_fro(S.slab_export_reduced(h, 2, j).cpu().numpy(), fac.s2.S[j])
+    errS = max(_rel_fro(S.slab_export_reduced(h, 2, j).cpu().numpy(), _pivot(fac, j))
                for j in range(prob.m))
     assert errS <= 1e-4, errS
     h.free()
 
 
+@pytest.mark.parametrize("order", ORDERS)
 @pytest.mark.parametrize("n2,n1,b", [(200, 80, 7), (70, 96, 15), (33, 24, 1)])
-def test_adjoint_matches_oracle(n2, n1, b):
+def test_adjoint_matches_oracle(n2, n1, b, order):
     kap = G.kappa_lognormal(n2, n1, 5)
     prob = O.make_problem(kap, n2, n1, b)
-    h = S.slab_factor(_dev(kap), n2, n1, b)
+    h = S.slab_factor(_dev(kap), n2, n1, b, odd_even=order == "odd_even")
     g = G.rhs_normal(n2, n1, 2, 9)
     lam = S.slab_solve_adjoint(h, _dev(g)).cpu().numpy()
-    lam_ref = O.solve_adjoint(prob, g)
+    lam_ref = O.solve_adjoint(prob, g, order=order)
     assert _col_rel(lam, lam_ref).max() <= 1e-12
     u = S.slab_solve(h, _dev(g)).cpu().numpy()
     assert _col_rel(lam, u).max() <= 1e-12          # A is symmetric
@@ -232,12 +247,13 @@ def test_run_to_run_determinism():
     assert np.array_equal(outs[0], outs[1])
 
 
-def test_many_rhs_column_groups():
-    """nrhs = 40 crosses the 16-column sweep groups and 32-column product groups."""
+@pytest.mark.parametrize("order", ORDERS)
+def test_many_rhs_column_groups(order):
+    """nrhs = 40 crosses the 16-column sweep and product column groups."""
     n2, n1, b = 70, 48, 7
     kap = G.kappa_lognormal(n2, n1, 7)
     prob = O.make_problem(kap, n2, n1, b)
-    h = S.slab_factor(_dev(kap), n2, n1, b)
+    h = S.slab_factor(_dev(kap), n2, n1, b, odd_even=order == "odd_even")
     f = G.rhs_uniform(n2, n1, 40, 3)
     u = S.slab_solve(h, _dev(f)).cpu().numpy()
     assert _col_rel(u, O.solve(O.factor(prob), f)).max() <= 1e-12
