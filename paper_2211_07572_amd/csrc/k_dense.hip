@@ -15,22 +15,30 @@
 namespace slab {
 
 // ---------------------------------------------------------------------------
-// Tiled MFMA GEMM: C = beta*C + alpha * op(A) op(B).
-// 64x64 output tile per workgroup, four waves of 32x32, k chunks of 32.  The
-// next chunk is loaded into registers (16-byte vector loads when the leading
-// dimension allows) while the current one is multiplied out of LDS; one
-// barrier per chunk (double-buffered LDS).
+// Tiled MFMA GEMM: C = beta*C + alpha * op(A) op(B) for gridDim.z independent
+// products (operands sa, sb, sc elements apart).
+// TILE x TILE output tile per workgroup, four waves of (TILE/2)^2, k chunks of
+// TK.  The next chunk is loaded into registers (16-byte vector loads when the
+// leading dimensions allow) while the current one is multiplied out of LDS;
+// one barrier per chunk (double-buffered LDS).
+//   op(A)(i,k) = A[i*lda+k] (AK=false) or A[k*lda+i] (AK=true)
+//   op(B)(k,j) = B[k*ldb+j] (BN=false) or B[j*ldb+k] (BN=true)
+// flags: GEMM_LOWER_C computes only tiles on or below the diagonal (a linear
+// tile index over the lower triangle); GEMM_A_LOWER / GEMM_B_LOWER skip the
+// k ranges where op(A) / op(B) is known to be zero (lower-triangular factors).
 // ---------------------------------------------------------------------------
-template <typename T, bool AK, bool BN, bool VECOK>
+template <typename T, int TILE, int TK, bool AK, bool BN, bool VECOK>
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, T alpha,
                                               const T* __restrict__ A, long long lda,
                                               long long sa, const T* __restrict__ B,
                                               long long ldb, long long sb, T beta, T* C,
                                               long long ldc, long long sc, int flags) {
   typedef typename acc4<T>::type V4;
-  constexpr int TM = 64, TN = 64, TK = 32;
+  constexpr int TM = TILE, TN = TILE;
+  constexpr int FM = TILE / 32, FN = TILE / 32;  // 16x16 MFMA tiles per wave and direction
   constexpr int VEC = 16 / sizeof(T);
   constexpr int NV = TM * TK / 256 / VEC;  // vectors per thread per operand and chunk
+  static_assert(NV >= 1 && TM * TK == NV * VEC * 256, "tile shape");
   typedef T vt __attribute__((ext_vector_type(VEC)));
   __shared__ T As[2][TK][TM + 4];
   __shared__ T Bs[2][TK][TN + 4];
@@ -43,7 +51,9 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, T alpha,
     ti = r;
     tj = (int)(t - (long long)r * (r + 1) / 2);
   } else {
-    ti = blockIdx.y;
+    // with A lower triangular the last tile rows carry the longest k ranges:
+    // hand them out first
+    ti = (flags & GEMM_A_LOWER) ? (int)(gridDim.y - 1 - blockIdx.y) : (int)blockIdx.y;
     tj = blockIdx.x;
   }
   A += (long long)blockIdx.z * sa;
@@ -59,7 +69,6 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, T alpha,
   kmin = (kmin / TK) * TK;
 
   vt ra[NV], rb[NV];
-  // A chunk: !AK -> vectors along k (row-major); AK -> vectors along i
   auto load = [&](int k0) __attribute__((always_inline)) {
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
@@ -69,7 +78,7 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, T alpha,
       else { kk = v / (TM / VEC); row = (v % (TM / VEC)) * VEC; }
       const long long gi = i0 + row, gk = k0 + kk;
       if (VECOK) {
-        const bool in = !AK ? (gi < M && gk < kmax) : (gk < kmax && gi < M);
+        const bool in = gi < M && gk < kmax;
         ra[q] = in ? *(const vt*)(!AK ? A + gi * lda + gk : A + gk * lda + gi) : vt(0);
         if (in) {  // partial vectors at the edges
 #pragma unroll
@@ -133,11 +142,11 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, T alpha,
     }
   };
 
-  V4 acc[2][2];
+  V4 acc[FM][FN];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < FM; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = V4{0, 0, 0, 0};
+    for (int b = 0; b < FN; ++b) acc[a][b] = V4{0, 0, 0, 0};
 
   if (kmin < kmax) {
     load(kmin);
@@ -150,28 +159,28 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, T alpha,
       if (more) load(k0 + TK);
 #pragma unroll
       for (int ks = 0; ks < TK / 4; ++ks) {
-        T av[2], bv[2];
+        T av[FM], bv[FN];
 #pragma unroll
-        for (int mt = 0; mt < 2; ++mt) av[mt] = As[cur][4 * ks + g][wm * 32 + 16 * mt + nn];
+        for (int mt = 0; mt < FM; ++mt) av[mt] = As[cur][4 * ks + g][wm * (TM / 2) + 16 * mt + nn];
 #pragma unroll
-        for (int nt = 0; nt < 2; ++nt) bv[nt] = Bs[cur][4 * ks + g][wn * 32 + 16 * nt + nn];
+        for (int nt = 0; nt < FN; ++nt) bv[nt] = Bs[cur][4 * ks + g][wn * (TN / 2) + 16 * nt + nn];
 #pragma unroll
-        for (int mt = 0; mt < 2; ++mt)
+        for (int mt = 0; mt < FM; ++mt)
 #pragma unroll
-          for (int nt = 0; nt < 2; ++nt) acc[mt][nt] = mfma16(av[mt], bv[nt], acc[mt][nt]);
+          for (int nt = 0; nt < FN; ++nt) acc[mt][nt] = mfma16(av[mt], bv[nt], acc[mt][nt]);
       }
       if (more) park(cur ^ 1);
       __syncthreads();
     }
   }
 #pragma unroll
-  for (int mt = 0; mt < 2; ++mt)
+  for (int mt = 0; mt < FM; ++mt)
 #pragma unroll
-    for (int nt = 0; nt < 2; ++nt)
+    for (int nt = 0; nt < FN; ++nt)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const long long gi = i0 + wm * 32 + 16 * mt + acc_row<T>(g, i);
-        const long long gj = j0 + wn * 32 + 16 * nt + nn;
+        const long long gi = i0 + wm * (TM / 2) + 16 * mt + acc_row<T>(g, i);
+        const long long gj = j0 + wn * (TN / 2) + 16 * nt + nn;
         if (gi < M && gj < N) {
           T v = alpha * acc[mt][nt][i];
           if (beta != (T)0) v += beta * C[gi * ldc + gj];
@@ -180,12 +189,35 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, T alpha,
       }
 }
 
+template <typename T, int TILE, int TK>
+static void gemm_tile(bool ak, bool bn, bool vecok, dim3 grid, int M, int N, int K, T alpha,
+                      const T* A, long long lda, long long sa, const T* B, long long ldb,
+                      long long sb, T beta, T* C, long long ldc, long long sc, int flags,
+                      hipStream_t st) {
+#define SLAB_GEMM_CASE(AKV, BNV)                                                                 \
+  do {                                                                                           \
+    if (vecok)                                                                                   \
+      hipLaunchKernelGGL((k_gemm<T, TILE, TK, AKV, BNV, true>), grid, dim3(256), 0, st, M, N, K, \
+                         alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc, flags);                \
+    else                                                                                         \
+      hipLaunchKernelGGL((k_gemm<T, TILE, TK, AKV, BNV, false>), grid, dim3(256), 0, st, M, N,   \
+                         K, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc, flags);             \
+  } while (0)
+  if (!ak && !bn) SLAB_GEMM_CASE(false, false);
+  else if (!ak && bn) SLAB_GEMM_CASE(false, true);
+  else if (ak && !bn) SLAB_GEMM_CASE(true, false);
+  else SLAB_GEMM_CASE(true, true);
+#undef SLAB_GEMM_CASE
+}
+
 template <typename T>
 int launch_gemm(bool ak, bool bn, int M, int N, int K, T alpha, const T* A, long long lda,
                 long long sa, const T* B, long long ldb, long long sb, T beta, T* C,
                 long long ldc, long long sc, int batch, int flags, hipStream_t st) {
-  if (M <= 0 || N <= 0) return SLAB_OK;
-  const int tm = (M + 63) / 64, tn = (N + 63) / 64;
+  if (M <= 0 || N <= 0 || batch <= 0) return SLAB_OK;
+  // 128-wide tiles once there are enough of them for four per compute unit
+  const int tile = (sizeof(T) == 4 && (long long)M * N * batch >= 1024LL * 128 * 128) ? 128 : 64;
+  const int tm = (M + tile - 1) / tile, tn = (N + tile - 1) / tile;
   dim3 grid;
   if (flags & GEMM_LOWER_C) grid = dim3((unsigned)((long long)tm * (tm + 1) / 2), 1, batch);
   else grid = dim3(tn, tm, batch);
@@ -193,20 +225,12 @@ int launch_gemm(bool ak, bool bn, int M, int N, int K, T alpha, const T* A, long
   const long long vec = 16 / (long long)sizeof(T);
   const bool vecok = lda % vec == 0 && ldb % vec == 0 && sa % vec == 0 && sb % vec == 0 &&
                      ((uintptr_t)A & 15) == 0 && ((uintptr_t)B & 15) == 0;
-#define SLAB_GEMM_CASE(AKV, BNV)                                                              \
-  do {                                                                                        \
-    if (vecok)                                                                                \
-      hipLaunchKernelGGL((k_gemm<T, AKV, BNV, true>), grid, dim3(256), 0, st, M, N, K, alpha, \
-                         A, lda, sa, B, ldb, sb, beta, C, ldc, sc, flags);                    \
-    else                                                                                      \
-      hipLaunchKernelGGL((k_gemm<T, AKV, BNV, false>), grid, dim3(256), 0, st, M, N, K,       \
-                         alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc, flags);             \
-  } while (0)
-  if (!ak && !bn) SLAB_GEMM_CASE(false, false);
-  else if (!ak && bn) SLAB_GEMM_CASE(false, true);
-  else if (ak && !bn) SLAB_GEMM_CASE(true, false);
-  else SLAB_GEMM_CASE(true, true);
-#undef SLAB_GEMM_CASE
+  if (tile == 128)
+    gemm_tile<T, 128, 16>(ak, bn, vecok, grid, M, N, K, alpha, A, lda, sa, B, ldb, sb, beta, C,
+                          ldc, sc, flags, st);
+  else
+    gemm_tile<T, 64, 32>(ak, bn, vecok, grid, M, N, K, alpha, A, lda, sa, B, ldb, sb, beta, C,
+                         ldc, sc, flags, st);
   SLAB_LAUNCH_CHECK();
   return SLAB_OK;
 }
