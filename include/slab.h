@@ -50,6 +50,7 @@ extern "C" {
 #endif
 
 typedef struct slab_handle_s* slab_handle;
+typedef struct slab_batch_s* slab_batch;
 
 /* status codes */
 #define SLAB_OK 0
@@ -75,6 +76,8 @@ typedef struct slab_handle_s* slab_handle;
                                 positions of those left are eliminated together, so
                                 a level is one batch of independent block
                                 factorizations; without it, the sweep of Alg. 1 */
+#define SLAB_GRAPH 8         /* batched solves: capture each refinement pass of the
+                                batch as a HIP graph on first use and replay it */
 
 typedef struct {
   int32_t n1;          /* interior columns (slab direction); n1 % (b+1) == 0, n1 >= 2 */
@@ -89,7 +92,7 @@ typedef struct {
   int32_t precision;   /* SLAB_FP64, SLAB_FP32_REFINE or SLAB_MIXED */
   double tol;          /* target max-over-columns ||f - A u||_2 / ||f||_2 (e.g. 1e-10) */
   int32_t max_iter;    /* refinement iterations allowed (>= 1; FP64 uses at most this too) */
-  int32_t flags;       /* SLAB_KEEP_REDUCED | SLAB_COEF_LOG | SLAB_ODD_EVEN */
+  int32_t flags;       /* SLAB_KEEP_REDUCED | SLAB_COEF_LOG | SLAB_ODD_EVEN | SLAB_GRAPH */
 } slab_options;
 
 typedef struct {
@@ -124,6 +127,42 @@ int slab_solve_adjoint(slab_handle h, const double* g, double* lam, int32_t nrhs
 
 /* Release the handle and its device memory (NULL is a no-op). */
 int slab_free(slab_handle h);
+
+/* ---- batches of independent problems ------------------------------------- */
+
+/* Alg. 3 for `count` independent problems of any sizes and slab widths, all
+   with the same options, in one set of grouped launches: every phase of stage
+   one is one launch over all (problem, slab, column chunk) work units of a
+   padded block order, and stage two advances all problems together (one
+   launch per panel step and update product over every pivot block of every
+   problem).  probs is a HOST array; each kappa is a device pointer read during
+   the call only.  On failure no batch is returned and the message names the
+   problem.  infos (host, count entries) may be NULL. */
+int slab_factor_batch(const slab_problem* probs, int32_t count, const slab_options* opts,
+                      void* hip_stream, slab_batch* out, slab_solve_info* infos);
+
+/* Alg. 4 with refinement for every problem of the batch: f[i], u[i] (host
+   arrays of device pointers), nrhs[i] and ld[i] (host arrays) as in
+   slab_solve.  Every refinement pass of the batch is one set of grouped
+   launches; a problem drops out once its residual meets tol.  With SLAB_GRAPH
+   a pass is captured as a HIP graph the first time and replayed while the
+   arguments and the set of unfinished problems stay the same (the graph and
+   its tables live until slab_batch_free).  SLAB_E_NOCONV if any problem
+   misses tol. */
+int slab_solve_batch(slab_batch bt, const double* const* f, double* const* u, const int32_t* nrhs,
+                     const int64_t* ld, void* hip_stream, slab_solve_info* infos);
+
+/* Handle of problem i of the batch (owned by the batch: do not free it).
+   slab_solve, slab_solve_adjoint, slab_kappa_grad, slab_residual,
+   slab_export_reduced and slab_query work on it as on any handle. */
+int slab_batch_handle(slab_batch bt, int32_t i, slab_handle* out);
+
+/* what = 0 number of problems, 5 device bytes held, 10+p phase times (as in
+   slab_query) of the batched factorization. */
+int slab_batch_query(slab_batch bt, int32_t what, int64_t* value);
+
+/* Release the batch and all of its problems (NULL is a no-op). */
+int slab_batch_free(slab_batch bt);
 
 /* ---- auxiliary entry points ---------------------------------------------- */
 

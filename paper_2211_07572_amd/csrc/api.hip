@@ -1,11 +1,19 @@
-// C ABI of the slab solver: argument checks, device memory of a handle, phase
-// orchestration of Alg. 3 (factor) and Alg. 4 (solve) with FP64 iterative
-// refinement around the working-precision solve.
+// C ABI of the slab solver: argument checks, device memory of handles and
+// batches, and the orchestration of Alg. 3 (factor) and Alg. 4 (solve) with
+// FP64 iterative refinement around the working-precision solve.
+//
+// Every factorization and solve is planned for a group of problems (a single
+// problem is a group of one): the planners record grouped launches, the plan's
+// descriptor tables go to the device in one copy, and the launches are issued
+// in order.  Batched solves can capture a refinement pass into a HIP graph and
+// replay it.
 #include "launch.h"
 
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <memory>
 #include <vector>
 
 namespace slab {
@@ -16,6 +24,86 @@ void set_error(const std::string& msg) { g_last_error = msg; }
 }  // namespace slab
 
 using namespace slab;
+
+namespace {
+
+// Device allocations owned by a handle or a batch.
+struct Owner {
+  std::vector<void*> owned;
+  size_t bytes = 0;
+  void* table = nullptr;   // uploaded plan tables
+  size_t table_cap = 0;
+
+  int alloc(void** p, size_t n) {
+    *p = nullptr;
+    if (n == 0) n = 256;
+    hipError_t e = hipMalloc(p, n);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      set_error("device allocation of " + std::to_string(n) + " bytes failed: " +
+                hipGetErrorString(e));
+      *p = nullptr;
+      return SLAB_E_NOMEM;
+    }
+    owned.push_back(*p);
+    bytes += n;
+    return SLAB_OK;
+  }
+  void release(void* p) {
+    if (!p) return;
+    for (size_t i = 0; i < owned.size(); ++i)
+      if (owned[i] == p) {
+        (void)hipFree(p);
+        owned.erase(owned.begin() + i);
+        return;
+      }
+  }
+  void release_all() {
+    for (void* p : owned) (void)hipFree(p);
+    owned.clear();
+    table = nullptr;
+    table_cap = 0;
+  }
+};
+
+#define SLAB_TRY(expr)              \
+  do {                              \
+    int rc_ = (expr);               \
+    if (rc_ != SLAB_OK) return rc_; \
+  } while (0)
+
+// Upload the plan's tables into the owner's table buffer (grown as needed).
+// The copy is ordered on the stream before the plan's launches.
+int upload_plan(Owner& o, const Plan& plan, hipStream_t st, const char** dev) {
+  if (plan.bytes() > o.table_cap) {
+    if (o.table) {
+      SLAB_HIP_CHECK(hipStreamSynchronize(st));
+      o.release(o.table);
+      o.table = nullptr;
+    }
+    const size_t cap = std::max<size_t>(plan.bytes() * 2, 1 << 16);
+    SLAB_TRY(o.alloc(&o.table, cap));
+    o.table_cap = cap;
+  }
+  if (plan.bytes())
+    SLAB_HIP_CHECK(hipMemcpyAsync(o.table, plan.host(), plan.bytes(), hipMemcpyHostToDevice, st));
+  *dev = (const char*)o.table;
+  return SLAB_OK;
+}
+
+int run_plan(Owner& o, const Plan& plan, hipStream_t st) {
+  const char* dev = nullptr;
+  SLAB_TRY(upload_plan(o, plan, st, &dev));
+  return plan.run(dev, st);
+}
+
+long long elapsed_us(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return -1;
+  return (long long)(ms * 1000.0f);
+}
+
+}  // namespace
 
 struct Workspace {
   int nrhs = 0;
@@ -37,6 +125,7 @@ struct slab_handle_s {
   int max_iter = 10;
   int flags = 0;
   int device = 0;
+  int odd_even = 0;
   size_t esz = 8;   // slab factors / Schur pieces / slab sweeps
   size_t esz2 = 8;  // reduced system: T blocks, block factorization, Alg. 2
   double* kappa = nullptr;
@@ -47,54 +136,42 @@ struct slab_handle_s {
   void* Linv = nullptr;
   void* Z = nullptr;
   void* Td = nullptr;  // odd-even order: U_e blocks (kept for the solve)
-  int odd_even = 0;
   double* T64 = nullptr;
   double* O64 = nullptr;
   double* S64 = nullptr;
-  size_t bytes = 0;
   long long phase_us[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  std::vector<void*> owned;
+  Owner mem;
   Workspace ws;
 };
 
-namespace {
-
-int dev_alloc(slab_handle h, void** p, size_t bytes) {
-  *p = nullptr;
-  if (bytes == 0) bytes = 256;
-  hipError_t e = hipMalloc(p, bytes);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    set_error("device allocation of " + std::to_string(bytes) + " bytes failed: " +
-              hipGetErrorString(e));
-    *p = nullptr;
-    return SLAB_E_NOMEM;
+// A solve pass captured as a HIP graph, valid for one set of arguments.
+struct GraphCache {
+  std::vector<long long> key;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void* tables = nullptr;   // descriptor tables the captured launches read
+  void clear(Owner& o) {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (tables) o.release(tables);
+    exec = nullptr;
+    graph = nullptr;
+    tables = nullptr;
+    key.clear();
   }
-  h->owned.push_back(*p);
-  h->bytes += bytes;
-  return SLAB_OK;
-}
+};
 
-void dev_release(slab_handle h, void* p) {
-  if (!p) return;
-  for (size_t i = 0; i < h->owned.size(); ++i)
-    if (h->owned[i] == p) {
-      (void)hipFree(p);
-      h->owned.erase(h->owned.begin() + i);
-      return;
-    }
-}
+struct slab_batch_s {
+  std::vector<slab_handle> items;
+  int precision = SLAB_FP64;
+  int flags = 0;
+  int device = 0;
+  long long phase_us[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  Owner mem;            // plan tables of batched factorizations and solves
+  GraphCache graphs[2]; // first pass, later passes
+};
 
-void release_all(slab_handle h) {
-  for (void* p : h->owned) (void)hipFree(p);
-  h->owned.clear();
-}
-
-#define SLAB_TRY(expr)           \
-  do {                           \
-    int rc_ = (expr);            \
-    if (rc_ != SLAB_OK) return rc_; \
-  } while (0)
+namespace {
 
 int check_vec_args(slab_handle h, const void* in, const void* out, int32_t nrhs, int64_t ld) {
   if (!h) { set_error("null handle"); return SLAB_E_INVALID; }
@@ -109,177 +186,353 @@ int check_vec_args(slab_handle h, const void* in, const void* out, int32_t nrhs,
   return SLAB_OK;
 }
 
-int ensure_workspace(slab_handle h, int nrhs, hipStream_t st) {
+int ensure_workspace(slab_handle h, int nrhs) {
   Workspace& w = h->ws;
   if (w.nrhs >= nrhs) return SLAB_OK;
   void* ptrs[] = {w.zbuf, w.xb, w.ft, w.yt, w.tt, w.r, w.norms, w.partial};
-  for (void* p : ptrs) dev_release(h, p);
+  for (void* p : ptrs) h->mem.release(p);
   w = Workspace();
   const size_t n = h->n2, m = h->m, e = h->esz, e2 = h->esz2;
   const size_t N = (size_t)h->n1 * h->n2;
-  SLAB_TRY(dev_alloc(h, &w.zbuf, m * nrhs * n * h->BP * e));
-  SLAB_TRY(dev_alloc(h, &w.xb, m * 2 * nrhs * n * e));
-  SLAB_TRY(dev_alloc(h, &w.ft, m * nrhs * n * e2));
-  SLAB_TRY(dev_alloc(h, &w.yt, m * nrhs * n * e2));
-  SLAB_TRY(dev_alloc(h, &w.tt, nrhs * n * e2));
-  SLAB_TRY(dev_alloc(h, (void**)&w.r, nrhs * N * sizeof(double)));
-  SLAB_TRY(dev_alloc(h, (void**)&w.norms, 2 * nrhs * sizeof(double)));
-  SLAB_TRY(dev_alloc(h, (void**)&w.partial, residual_partial_count(h->n1, h->n2, nrhs) * sizeof(double)));
+  SLAB_TRY(h->mem.alloc(&w.zbuf, m * nrhs * n * h->BP * e));
+  SLAB_TRY(h->mem.alloc(&w.xb, m * 2 * nrhs * n * e));
+  SLAB_TRY(h->mem.alloc(&w.ft, m * nrhs * n * e2));
+  SLAB_TRY(h->mem.alloc(&w.yt, m * nrhs * n * e2));
+  SLAB_TRY(h->mem.alloc(&w.tt, nrhs * n * e2));
+  SLAB_TRY(h->mem.alloc((void**)&w.r, nrhs * N * sizeof(double)));
+  SLAB_TRY(h->mem.alloc((void**)&w.norms, 2 * nrhs * sizeof(double)));
+  SLAB_TRY(h->mem.alloc((void**)&w.partial,
+                        residual_partial_count(h->n1, h->n2, nrhs) * sizeof(double)));
   w.nrhs = nrhs;
   return SLAB_OK;
 }
 
-SolveArgs solve_args(slab_handle h, int nrhs, int transpose) {
-  SolveArgs a;
-  a.n1 = h->n1; a.n2 = h->n2; a.b = h->b; a.m = h->m; a.nrhs = nrhs;
-  a.wh = h->wh; a.wv = h->wv; a.Gl = h->Gl; a.Linv = h->Linv; a.Z = h->Z; a.Td = h->Td;
-  a.zbuf = h->ws.zbuf; a.xb = h->ws.xb; a.ft = h->ws.ft; a.yt = h->ws.yt; a.tt = h->ws.tt;
-  a.transpose = transpose;
-  a.odd_even = h->odd_even;
-  return a;
-}
-
-int solve_pass(slab_handle h, const SolveArgs& a, const double* rhs, long long ldr, double* out,
-               long long ldo, int acc, hipStream_t st) {
-  if (h->precision == SLAB_FP32_REFINE)
-    return launch_solve_pass<float, float>(a, rhs, ldr, out, ldo, acc, st);
-  if (h->precision == SLAB_MIXED)
-    return launch_solve_pass<double, float>(a, rhs, ldr, out, ldo, acc, st);
-  return launch_solve_pass<double, double>(a, rhs, ldr, out, ldo, acc, st);
-}
-
-int residual_host(slab_handle h, const double* f, const double* u, int nrhs, long long ld,
-                  double* r, std::vector<double>& relres, hipStream_t st) {
-  SLAB_TRY(launch_residual(h->n1, h->n2, nrhs, ld, h->wh, h->wv, f, u, r,
-                           (long long)h->n1 * h->n2, h->ws.norms, h->ws.partial, st));
-  std::vector<double> nrm(2 * nrhs);
-  SLAB_HIP_CHECK(hipMemcpyAsync(nrm.data(), h->ws.norms, 2 * nrhs * sizeof(double),
-                                hipMemcpyDeviceToHost, st));
-  SLAB_HIP_CHECK(hipStreamSynchronize(st));
-  relres.resize(nrhs);
-  for (int c = 0; c < nrhs; ++c) {
-    const double fn = std::sqrt(nrm[2 * c + 1]);
-    relres[c] = fn > 0 ? std::sqrt(nrm[2 * c]) / fn : std::sqrt(nrm[2 * c]);
-  }
-  return SLAB_OK;
-}
-
-// Alg. 4 with FP64 refinement: u = 0, r = f; repeat { d = solve(r); u += d; r = f - A u }.
-int solve_common(slab_handle h, const double* f, double* u, int32_t nrhs, int64_t ld,
-                 void* stream, slab_solve_info* info, int transpose) {
-  SLAB_TRY(check_vec_args(h, f, u, nrhs, ld));
-  hipStream_t st = (hipStream_t)stream;
-  SLAB_HIP_CHECK(hipSetDevice(h->device));
-  SLAB_TRY(ensure_workspace(h, nrhs, st));
-  const SolveArgs a = solve_args(h, nrhs, transpose);
-  const long long N = (long long)h->n1 * h->n2;
-  std::vector<double> rr;
-  int it = 0;
-  double worst = 0.0;
-  SLAB_TRY(solve_pass(h, a, f, ld, u, ld, 0, st));
-  ++it;
-  while (true) {
-    // the transposed residual equals A^T u = A u (A is symmetric)
-    SLAB_TRY(residual_host(h, f, u, nrhs, ld, h->ws.r, rr, st));
-    worst = 0.0;
-    bool finite = true;
-    for (double v : rr) {
-      if (!std::isfinite(v)) finite = false;
-      worst = std::max(worst, v);
-    }
-    if (!finite) worst = NAN;
-    if (!finite || worst <= h->tol || it >= h->max_iter) break;
-    SLAB_TRY(solve_pass(h, a, h->ws.r, N, u, ld, 1, st));
-    ++it;
-  }
-  SLAB_HIP_CHECK(hipStreamSynchronize(st));
-  if (info) {
-    info->iterations = it;
-    info->max_relres = worst;
-    info->failed_block = -1;
-  }
-  if (!(worst <= h->tol)) {
-    set_error("refinement stopped at relative residual " + std::to_string(worst) + " after " +
-              std::to_string(it) + " passes (tol " + std::to_string(h->tol) + ")");
-    return SLAB_E_NOCONV;
-  }
-  return SLAB_OK;
-}
-
-long long elapsed_us(hipEvent_t a, hipEvent_t b) {
-  float ms = 0.f;
-  if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return -1;
-  return (long long)(ms * 1000.0f);
-}
+// ---------------------------------------------------------------------------
+// Factorization of a group of handles of one precision and elimination order.
+// ---------------------------------------------------------------------------
+struct FactorTemps {
+  void *Hsw = nullptr, *sig = nullptr, *PRR = nullptr, *PLL = nullptr, *PLR = nullptr,
+       *PRL = nullptr, *Td = nullptr, *To = nullptr;
+};
 
 template <typename T, typename TR>
-int factor_impl(slab_handle h, const slab_problem* prob, hipStream_t st, slab_solve_info* info) {
+int alloc_factor(slab_handle h, FactorTemps& t) {
   const size_t n = h->n2, m = h->m, e = sizeof(T), e2 = sizeof(TR), BP = h->BP;
   const size_t nsq = n * n;
   const size_t ncoef = (size_t)(h->n1 + 2) * (h->n2 + 2);
-  SLAB_TRY(dev_alloc(h, (void**)&h->kappa, ncoef * sizeof(double)));
-  SLAB_TRY(dev_alloc(h, (void**)&h->wh, (size_t)(h->n1 + 1) * n * sizeof(double)));
-  SLAB_TRY(dev_alloc(h, (void**)&h->wv, (size_t)h->n1 * (n + 1) * sizeof(double)));
-  SLAB_TRY(dev_alloc(h, (void**)&h->status, 4 * sizeof(int)));
-  SLAB_TRY(dev_alloc(h, &h->Gl, m * n * BP * BP * e));
-  void *Hsw, *sig, *PRR, *PLL, *PLR, *PRL, *Td, *To;
-  SLAB_TRY(dev_alloc(h, &Hsw, m * n * BP * BP * e));
-  SLAB_TRY(dev_alloc(h, &sig, m * n * 2 * BP * e));
-  SLAB_TRY(dev_alloc(h, &PRR, m * nsq * e));
-  SLAB_TRY(dev_alloc(h, &PLL, m * nsq * e));
-  SLAB_TRY(dev_alloc(h, &PLR, m * nsq * e));
-  SLAB_TRY(dev_alloc(h, &PRL, m * nsq * e));
-  SLAB_TRY(dev_alloc(h, &Td, m * nsq * e2));
-  SLAB_TRY(dev_alloc(h, &To, (m > 1 ? m - 1 : 1) * nsq * e2));
-  SLAB_TRY(dev_alloc(h, &h->Linv, m * nsq * e2));
-  SLAB_TRY(dev_alloc(h, &h->Z, (m > 1 ? m - 1 : 1) * nsq * e2));
+  Owner& o = h->mem;
+  SLAB_TRY(o.alloc((void**)&h->kappa, ncoef * sizeof(double)));
+  SLAB_TRY(o.alloc((void**)&h->wh, (size_t)(h->n1 + 1) * n * sizeof(double)));
+  SLAB_TRY(o.alloc((void**)&h->wv, (size_t)h->n1 * (n + 1) * sizeof(double)));
+  SLAB_TRY(o.alloc((void**)&h->status, 4 * sizeof(int)));
+  SLAB_TRY(o.alloc(&h->Gl, m * n * BP * BP * e));
+  SLAB_TRY(o.alloc(&t.Hsw, m * n * BP * BP * e));
+  SLAB_TRY(o.alloc(&t.sig, m * n * 2 * BP * e));
+  SLAB_TRY(o.alloc(&t.PRR, m * nsq * e));
+  SLAB_TRY(o.alloc(&t.PLL, m * nsq * e));
+  SLAB_TRY(o.alloc(&t.PLR, m * nsq * e));
+  SLAB_TRY(o.alloc(&t.PRL, m * nsq * e));
+  SLAB_TRY(o.alloc(&t.Td, m * nsq * e2));
+  SLAB_TRY(o.alloc(&t.To, (m > 1 ? m - 1 : 1) * nsq * e2));
+  SLAB_TRY(o.alloc(&h->Linv, m * nsq * e2));
+  SLAB_TRY(o.alloc(&h->Z, (m > 1 ? m - 1 : 1) * nsq * e2));
   if (h->flags & SLAB_KEEP_REDUCED) {
-    SLAB_TRY(dev_alloc(h, (void**)&h->T64, m * nsq * sizeof(double)));
-    SLAB_TRY(dev_alloc(h, (void**)&h->O64, (m > 1 ? m - 1 : 1) * nsq * sizeof(double)));
-    SLAB_TRY(dev_alloc(h, (void**)&h->S64, m * nsq * sizeof(double)));
+    SLAB_TRY(o.alloc((void**)&h->T64, m * nsq * sizeof(double)));
+    SLAB_TRY(o.alloc((void**)&h->O64, (m > 1 ? m - 1 : 1) * nsq * sizeof(double)));
+    SLAB_TRY(o.alloc((void**)&h->S64, m * nsq * sizeof(double)));
+  }
+  return SLAB_OK;
+}
+
+// Factor every handle of hs (sizes set) from probs[i]->kappa.  Per problem,
+// fail[i] receives 0 (ok), 1 (invalid kappa), 2 (slab breakdown) or 3 (block
+// breakdown) and blk[i] the slab / interface index; ph the group's phase times.
+template <typename T, typename TR>
+int factor_group(const std::vector<slab_handle>& hs, const std::vector<const slab_problem*>& probs,
+                 hipStream_t st, Owner& plan_mem, std::vector<int>& fail, std::vector<int>& blk,
+                 long long* ph) {
+  const size_t cnt = hs.size();
+  fail.assign(cnt, 0);
+  blk.assign(cnt, -1);
+  std::vector<FactorTemps> tmp(cnt);
+  for (size_t i = 0; i < cnt; ++i) SLAB_TRY((alloc_factor<T, TR>(hs[i], tmp[i])));
+  std::vector<ProbDev> pd(cnt);
+  std::vector<Stage2Prob> s2(cnt);
+  for (size_t i = 0; i < cnt; ++i) {
+    slab_handle h = hs[i];
+    ProbDev& d = pd[i];
+    std::memset(&d, 0, sizeof(d));
+    d.n1 = h->n1; d.n2 = h->n2; d.b = h->b; d.m = h->m; d.h = h->h;
+    d.is_log = (h->flags & SLAB_COEF_LOG) ? 1 : 0;
+    d.coef = probs[i]->kappa; d.kappa = h->kappa; d.wh = h->wh; d.wv = h->wv;
+    d.Gl = h->Gl; d.Hsw = tmp[i].Hsw; d.sig = tmp[i].sig;
+    d.PRR = tmp[i].PRR; d.PLL = tmp[i].PLL; d.PLR = tmp[i].PLR; d.PRL = tmp[i].PRL;
+    d.Td = tmp[i].Td; d.To = tmp[i].To; d.T64 = h->T64; d.O64 = h->O64; d.status = h->status;
+    Stage2Prob& q = s2[i];
+    q.n = h->n2; q.m = h->m; q.Td = tmp[i].Td; q.To = tmp[i].To; q.Linv = h->Linv; q.Z = h->Z;
+    q.S64 = h->S64; q.status = h->status;
+    SLAB_HIP_CHECK(hipMemsetAsync(h->status, 0, 4 * sizeof(int), st));
   }
   hipEvent_t ev[6];
   for (int i = 0; i < 6; ++i) SLAB_HIP_CHECK(hipEventCreate(&ev[i]));
-  SLAB_HIP_CHECK(hipMemsetAsync(h->status, 0, 4 * sizeof(int), st));
-  SLAB_HIP_CHECK(hipEventRecord(ev[0], st));
-  SLAB_TRY(launch_coef_weights(prob->kappa, (h->flags & SLAB_COEF_LOG) ? 1 : 0, h->n1, h->n2, h->h,
-                               h->kappa, h->wh, h->wv, h->status, st));
-  int hs[4] = {0, 0, 0, 0};
-  SLAB_HIP_CHECK(hipMemcpyAsync(hs, h->status, sizeof(hs), hipMemcpyDeviceToHost, st));
-  SLAB_HIP_CHECK(hipStreamSynchronize(st));
-  if (hs[0] == 1) {
-    set_error("coefficient field has a value that is not positive and finite");
-    return SLAB_E_INVALID;
+  struct EvGuard {
+    hipEvent_t* e;
+    ~EvGuard() { for (int i = 0; i < 6; ++i) (void)hipEventDestroy(e[i]); }
+  } guard{ev};
+  // coefficients first: an invalid field is reported before any factor work
+  {
+    Plan p;
+    plan_coef_weights(p, pd);
+    SLAB_HIP_CHECK(hipEventRecord(ev[0], st));
+    SLAB_TRY(run_plan(plan_mem, p, st));
   }
-  Stage1Args A;
-  A.n1 = h->n1; A.n2 = h->n2; A.b = h->b; A.m = h->m;
-  A.wh = h->wh; A.wv = h->wv; A.Gl = h->Gl; A.Hsw = Hsw; A.sig = sig;
-  A.PRR = PRR; A.PLL = PLL; A.PLR = PLR; A.PRL = PRL; A.Tdiag = Td; A.Toff = To;
-  A.Tdiag64 = h->T64; A.Toff64 = h->O64; A.status = h->status;
-  A.ev[0] = ev[1]; A.ev[1] = ev[2]; A.ev[2] = ev[3]; A.ev[3] = ev[4];
-  SLAB_TRY((launch_stage1<T, TR>(A, st)));
-  Stage2Args B;
-  B.n = h->n2; B.m = h->m; B.Tdiag = Td; B.Toff = To; B.Linv = h->Linv; B.Z = h->Z;
-  B.S64 = h->S64; B.status = h->status; B.odd_even = h->odd_even;
-  SLAB_TRY(launch_stage2<TR>(B, st));
-  SLAB_HIP_CHECK(hipEventRecord(ev[5], st));
-  SLAB_HIP_CHECK(hipMemcpyAsync(hs, h->status, sizeof(hs), hipMemcpyDeviceToHost, st));
+  std::vector<int> hs_status(4 * cnt, 0);
+  for (size_t i = 0; i < cnt; ++i)
+    SLAB_HIP_CHECK(hipMemcpyAsync(&hs_status[4 * i], hs[i]->status, 4 * sizeof(int),
+                                  hipMemcpyDeviceToHost, st));
   SLAB_HIP_CHECK(hipStreamSynchronize(st));
-  // phases: weights + slab factor, boundary columns, Schur propagation (k_schur
-  // alone), assembly of T, block factorization
-  for (int i = 0; i < 5; ++i) h->phase_us[i] = elapsed_us(ev[i], ev[i + 1]);
-  for (int i = 0; i < 6; ++i) (void)hipEventDestroy(ev[i]);
-  void* tmp[] = {Hsw, sig, PRR, PLL, PLR, PRL, To};
-  for (void* p : tmp) dev_release(h, p);
-  if (h->odd_even) h->Td = Td;
-  else dev_release(h, Td);
-  if (hs[0] != 0) {
-    if (info) info->failed_block = hs[1];
-    set_error(hs[0] == 2 ? "slab factorization breakdown in slab " + std::to_string(hs[1])
-                         : "block factorization breakdown at interface " + std::to_string(hs[1]));
-    return SLAB_E_BREAKDOWN;
+  bool any_bad = false;
+  for (size_t i = 0; i < cnt; ++i)
+    if (hs_status[4 * i] == 1) { fail[i] = 1; any_bad = true; }
+  if (any_bad) return SLAB_E_INVALID;
+  {
+    Plan p;
+    plan_stage1<T, TR>(p, pd, ev + 1);
+    plan_stage2<TR>(p, s2, hs[0]->odd_even != 0);
+    SLAB_TRY(run_plan(plan_mem, p, st));
+    SLAB_HIP_CHECK(hipEventRecord(ev[5], st));
+  }
+  for (size_t i = 0; i < cnt; ++i)
+    SLAB_HIP_CHECK(hipMemcpyAsync(&hs_status[4 * i], hs[i]->status, 4 * sizeof(int),
+                                  hipMemcpyDeviceToHost, st));
+  SLAB_HIP_CHECK(hipStreamSynchronize(st));
+  // phases: weights + slab factor, boundary columns, Schur propagation, assembly
+  // of T, block factorization
+  for (int i = 0; i < 5; ++i) ph[i] = elapsed_us(ev[i], ev[i + 1]);
+  for (size_t i = 0; i < cnt; ++i) {
+    slab_handle h = hs[i];
+    void* t[] = {tmp[i].Hsw, tmp[i].sig, tmp[i].PRR, tmp[i].PLL, tmp[i].PLR, tmp[i].PRL, tmp[i].To};
+    for (void* p : t) h->mem.release(p);
+    if (h->odd_even) h->Td = tmp[i].Td;
+    else h->mem.release(tmp[i].Td);
+    if (hs_status[4 * i] != 0) {
+      fail[i] = hs_status[4 * i];
+      blk[i] = hs_status[4 * i + 1];
+    }
   }
   return SLAB_OK;
+}
+
+int factor_dispatch(int precision, const std::vector<slab_handle>& hs,
+                    const std::vector<const slab_problem*>& probs, hipStream_t st, Owner& mem,
+                    std::vector<int>& fail, std::vector<int>& blk, long long* ph) {
+  if (precision == SLAB_FP32_REFINE)
+    return factor_group<float, float>(hs, probs, st, mem, fail, blk, ph);
+  if (precision == SLAB_MIXED)
+    return factor_group<double, float>(hs, probs, st, mem, fail, blk, ph);
+  return factor_group<double, double>(hs, probs, st, mem, fail, blk, ph);
+}
+
+std::string fail_message(int code, int blk) {
+  if (code == 1) return "coefficient field has a value that is not positive and finite";
+  if (code == 2) return "slab factorization breakdown in slab " + std::to_string(blk);
+  return "block factorization breakdown at interface " + std::to_string(blk);
+}
+
+slab_handle new_handle(const slab_problem* prob, const slab_options* opts, int device) {
+  slab_handle h = new slab_handle_s();
+  h->n1 = prob->n1; h->n2 = prob->n2; h->b = prob->b; h->m = prob->n1 / (prob->b + 1);
+  h->BP = padded_block(prob->b); h->h = prob->h;
+  if (opts) { h->precision = opts->precision; h->tol = opts->tol; h->max_iter = opts->max_iter; h->flags = opts->flags; }
+  h->odd_even = (h->flags & SLAB_ODD_EVEN) ? 1 : 0;
+  h->esz = h->precision == SLAB_FP32_REFINE ? 4 : 8;
+  h->esz2 = h->precision == SLAB_FP64 ? 8 : 4;
+  h->device = device;
+  return h;
+}
+
+void delete_handle(slab_handle h) {
+  h->mem.release_all();
+  delete h;
+}
+
+// ---------------------------------------------------------------------------
+// Solves with FP64 refinement for a group of handles of one precision:
+//   pass 1: u = solve(f); later passes: u += solve(r); r = f - A u after each.
+// A problem leaves the group once its residual meets its tolerance.
+// ---------------------------------------------------------------------------
+struct SolveJob {
+  slab_handle h;
+  const double* f;
+  double* u;
+  int nrhs;
+  long long ld;
+  slab_solve_info* info;
+};
+
+template <typename T, typename TR>
+void plan_pass(Plan& p, const std::vector<SolveJob>& jobs, bool first, bool trans) {
+  std::vector<SolveDev> sd(jobs.size());
+  std::vector<ReducedDev> red(jobs.size());
+  for (size_t i = 0; i < jobs.size(); ++i) {
+    const SolveJob& j = jobs[i];
+    slab_handle h = j.h;
+    SolveDev& d = sd[i];
+    std::memset(&d, 0, sizeof(d));
+    d.n1 = h->n1; d.n2 = h->n2; d.b = h->b; d.m = h->m; d.nrhs = j.nrhs;
+    d.wh = h->wh; d.wv = h->wv; d.Gl = h->Gl;
+    d.zbuf = h->ws.zbuf; d.xb = h->ws.xb; d.ft = h->ws.ft;
+    const long long N = (long long)h->n1 * h->n2;
+    d.rhs = first ? j.f : h->ws.r;
+    d.ld = first ? j.ld : N;
+    d.out = j.u; d.ldo = j.ld; d.accumulate = first ? 0 : 1;
+    d.f = j.f; d.u = j.u; d.r = h->ws.r; d.ldf = j.ld; d.norms = h->ws.norms;
+    d.partial = h->ws.partial;
+    ReducedDev& r = red[i];
+    r.n = h->n2; r.m = h->m; r.nrhs = j.nrhs; r.Linv = h->Linv; r.Z = h->Z; r.Td = h->Td;
+    r.ft = h->ws.ft; r.yt = h->ws.yt; r.tt = h->ws.tt;
+  }
+  plan_solve_pass<T, TR>(p, sd, red, trans, jobs[0].h->odd_even != 0);
+  // the transposed residual equals A^T u = A u (A is symmetric)
+  plan_residual(p, sd);
+}
+
+void plan_pass_dispatch(int precision, Plan& p, const std::vector<SolveJob>& jobs, bool first,
+                        bool trans) {
+  if (precision == SLAB_FP32_REFINE) plan_pass<float, float>(p, jobs, first, trans);
+  else if (precision == SLAB_MIXED) plan_pass<double, float>(p, jobs, first, trans);
+  else plan_pass<double, double>(p, jobs, first, trans);
+}
+
+int read_relres(const std::vector<SolveJob>& jobs, hipStream_t st,
+                std::vector<std::vector<double>>& rr) {
+  std::vector<std::vector<double>> nrm(jobs.size());
+  for (size_t i = 0; i < jobs.size(); ++i) {
+    nrm[i].resize(2 * jobs[i].nrhs);
+    SLAB_HIP_CHECK(hipMemcpyAsync(nrm[i].data(), jobs[i].h->ws.norms,
+                                  2 * jobs[i].nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+  }
+  SLAB_HIP_CHECK(hipStreamSynchronize(st));
+  rr.resize(jobs.size());
+  for (size_t i = 0; i < jobs.size(); ++i) {
+    rr[i].resize(jobs[i].nrhs);
+    for (int c = 0; c < jobs[i].nrhs; ++c) {
+      const double fn = std::sqrt(nrm[i][2 * c + 1]);
+      rr[i][c] = fn > 0 ? std::sqrt(nrm[i][2 * c]) / fn : std::sqrt(nrm[i][2 * c]);
+    }
+  }
+  return SLAB_OK;
+}
+
+double worst_of(const std::vector<double>& v) {
+  double w = 0.0;
+  for (double x : v) {
+    if (!std::isfinite(x)) return NAN;
+    w = std::max(w, x);
+  }
+  return w;
+}
+
+// One refinement pass of `jobs`, eagerly or through a cached graph.
+int run_pass(Owner& mem, GraphCache* gc, const std::vector<SolveJob>& jobs, int precision,
+             bool first, bool trans, hipStream_t st) {
+  Plan p;
+  plan_pass_dispatch(precision, p, jobs, first, trans);
+  if (!gc) return run_plan(mem, p, st);
+  std::vector<long long> key;
+  key.push_back(first);
+  key.push_back(trans);
+  for (const SolveJob& j : jobs) {
+    key.push_back((long long)(uintptr_t)j.h);
+    key.push_back((long long)(uintptr_t)j.f);
+    key.push_back((long long)(uintptr_t)j.u);
+    key.push_back(j.nrhs);
+    key.push_back(j.ld);
+  }
+  if (gc->exec && gc->key == key) {
+    SLAB_HIP_CHECK(hipGraphLaunch(gc->exec, st));
+    return SLAB_OK;
+  }
+  SLAB_HIP_CHECK(hipStreamSynchronize(st));
+  gc->clear(mem);
+  // the tables stay in place while the graph lives
+  SLAB_TRY(mem.alloc(&gc->tables, std::max<size_t>(p.bytes(), 256)));
+  SLAB_HIP_CHECK(hipMemcpyAsync(gc->tables, p.host(), p.bytes(), hipMemcpyHostToDevice, st));
+  SLAB_HIP_CHECK(hipStreamSynchronize(st));
+  SLAB_HIP_CHECK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  const int rc = p.run((const char*)gc->tables, st);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(st, &g);
+  if (rc != SLAB_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) {
+    set_error(std::string("graph capture failed: ") + hipGetErrorString(e));
+    return SLAB_E_HIP;
+  }
+  gc->graph = g;
+  SLAB_HIP_CHECK(hipGraphInstantiate(&gc->exec, g, nullptr, nullptr, 0));
+  gc->key = key;
+  SLAB_HIP_CHECK(hipGraphLaunch(gc->exec, st));
+  return SLAB_OK;
+}
+
+int solve_group(std::vector<SolveJob>& jobs, int precision, bool trans, hipStream_t st,
+                Owner& mem, GraphCache* graphs) {
+  for (SolveJob& j : jobs) SLAB_TRY(ensure_workspace(j.h, j.nrhs));
+  std::vector<int> it(jobs.size(), 0);
+  std::vector<double> worst(jobs.size(), 0.0);
+  std::vector<SolveJob> live = jobs;
+  std::vector<size_t> idx(jobs.size());
+  for (size_t i = 0; i < jobs.size(); ++i) idx[i] = i;
+  bool first = true;
+  while (!live.empty()) {
+    GraphCache* gc = graphs ? &graphs[first ? 0 : 1] : nullptr;
+    SLAB_TRY(run_pass(mem, gc, live, precision, first, trans, st));
+    std::vector<std::vector<double>> rr;
+    SLAB_TRY(read_relres(live, st, rr));
+    std::vector<SolveJob> next;
+    std::vector<size_t> nidx;
+    for (size_t k = 0; k < live.size(); ++k) {
+      const size_t i = idx[k];
+      ++it[i];
+      worst[i] = worst_of(rr[k]);
+      const bool done = !(worst[i] > jobs[i].h->tol) || it[i] >= jobs[i].h->max_iter;
+      if (!done) {
+        next.push_back(live[k]);
+        nidx.push_back(i);
+      }
+    }
+    live.swap(next);
+    idx.swap(nidx);
+    first = false;
+  }
+  int rc = SLAB_OK;
+  for (size_t i = 0; i < jobs.size(); ++i) {
+    if (jobs[i].info) {
+      jobs[i].info->iterations = it[i];
+      jobs[i].info->max_relres = worst[i];
+      jobs[i].info->failed_block = -1;
+    }
+    if (!(worst[i] <= jobs[i].h->tol) && rc == SLAB_OK) {
+      set_error("refinement stopped at relative residual " + std::to_string(worst[i]) +
+                " after " + std::to_string(it[i]) + " passes (tol " +
+                std::to_string(jobs[i].h->tol) + ")" +
+                (jobs.size() > 1 ? " in problem " + std::to_string(i) : std::string()));
+      rc = SLAB_E_NOCONV;
+    }
+  }
+  return rc;
+}
+
+int solve_one(slab_handle h, const double* f, double* u, int32_t nrhs, int64_t ld, void* stream,
+              slab_solve_info* info, bool trans) {
+  SLAB_TRY(check_vec_args(h, f, u, nrhs, ld));
+  hipStream_t st = (hipStream_t)stream;
+  SLAB_HIP_CHECK(hipSetDevice(h->device));
+  std::vector<SolveJob> jobs{{h, f, u, nrhs, ld, info}};
+  return solve_group(jobs, h->precision, trans, st, h->mem, nullptr);
 }
 
 }  // namespace
@@ -305,7 +558,9 @@ int slab_check_problem(const slab_problem* prob, const slab_options* opts) {
     }
     if (!(opts->tol > 0.0) || !std::isfinite(opts->tol)) { set_error("tol must be positive"); return SLAB_E_INVALID; }
     if (opts->max_iter < 1) { set_error("max_iter must be >= 1"); return SLAB_E_INVALID; }
-    if (opts->flags & ~(SLAB_KEEP_REDUCED | SLAB_COEF_LOG | SLAB_ODD_EVEN)) { set_error("unknown flag"); return SLAB_E_INVALID; }
+    if (opts->flags & ~(SLAB_KEEP_REDUCED | SLAB_COEF_LOG | SLAB_ODD_EVEN | SLAB_GRAPH)) {
+      set_error("unknown flag"); return SLAB_E_INVALID;
+    }
   }
   return SLAB_OK;
 }
@@ -317,26 +572,22 @@ int slab_factor(const slab_problem* prob, const slab_options* opts, void* hip_st
   *out = nullptr;
   int rc = slab_check_problem(prob, opts);
   if (rc) return rc;
-  slab_handle h = new slab_handle_s();
-  h->n1 = prob->n1; h->n2 = prob->n2; h->b = prob->b; h->m = prob->n1 / (prob->b + 1);
-  h->BP = padded_block(prob->b); h->h = prob->h;
-  if (opts) { h->precision = opts->precision; h->tol = opts->tol; h->max_iter = opts->max_iter; h->flags = opts->flags; }
-  h->odd_even = (h->flags & SLAB_ODD_EVEN) ? 1 : 0;
-  h->esz = h->precision == SLAB_FP32_REFINE ? 4 : 8;
-  h->esz2 = h->precision == SLAB_FP64 ? 8 : 4;
-  if (hipGetDevice(&h->device) != hipSuccess) {
-    set_error("no HIP device");
-    delete h;
-    return SLAB_E_HIP;
-  }
+  int device = 0;
+  if (hipGetDevice(&device) != hipSuccess) { set_error("no HIP device"); return SLAB_E_HIP; }
+  slab_handle h = new_handle(prob, opts, device);
   hipStream_t st = (hipStream_t)hip_stream;
-  if (h->precision == SLAB_FP32_REFINE) rc = factor_impl<float, float>(h, prob, st, info);
-  else if (h->precision == SLAB_MIXED) rc = factor_impl<double, float>(h, prob, st, info);
-  else rc = factor_impl<double, double>(h, prob, st, info);
+  std::vector<slab_handle> hs{h};
+  std::vector<const slab_problem*> ps{prob};
+  std::vector<int> fail, blk;
+  rc = factor_dispatch(h->precision, hs, ps, st, h->mem, fail, blk, h->phase_us);
+  if ((rc == SLAB_OK || rc == SLAB_E_INVALID) && !fail.empty() && fail[0] != 0) {
+    if (info && fail[0] != 1) info->failed_block = blk[0];
+    set_error(fail_message(fail[0], blk[0]));
+    rc = fail[0] == 1 ? SLAB_E_INVALID : SLAB_E_BREAKDOWN;
+  }
   if (rc != SLAB_OK) {
     (void)hipStreamSynchronize(st);
-    release_all(h);
-    delete h;
+    delete_handle(h);
     return rc;
   }
   *out = h;
@@ -345,22 +596,134 @@ int slab_factor(const slab_problem* prob, const slab_options* opts, void* hip_st
 
 int slab_solve(slab_handle h, const double* f, double* u, int32_t nrhs, int64_t ld,
                void* hip_stream, slab_solve_info* info) {
-  return solve_common(h, f, u, nrhs, ld, hip_stream, info, 0);
+  return solve_one(h, f, u, nrhs, ld, hip_stream, info, false);
 }
 
 int slab_solve_adjoint(slab_handle h, const double* g, double* lam, int32_t nrhs, int64_t ld,
                        void* hip_stream, slab_solve_info* info) {
-  return solve_common(h, g, lam, nrhs, ld, hip_stream, info, 1);
+  return solve_one(h, g, lam, nrhs, ld, hip_stream, info, true);
 }
 
 int slab_free(slab_handle h) {
   if (!h) return SLAB_OK;
   (void)hipSetDevice(h->device);
   (void)hipDeviceSynchronize();
-  release_all(h);
-  delete h;
+  delete_handle(h);
   return SLAB_OK;
 }
+
+// ---- batches ------------------------------------------------------------------
+
+int slab_batch_free(slab_batch bt) {
+  if (!bt) return SLAB_OK;
+  (void)hipSetDevice(bt->device);
+  (void)hipDeviceSynchronize();
+  for (GraphCache& g : bt->graphs) g.clear(bt->mem);
+  for (slab_handle h : bt->items) delete_handle(h);
+  bt->mem.release_all();
+  delete bt;
+  return SLAB_OK;
+}
+
+int slab_factor_batch(const slab_problem* probs, int32_t count, const slab_options* opts,
+                      void* hip_stream, slab_batch* out, slab_solve_info* infos) {
+  if (!out) { set_error("null output batch pointer"); return SLAB_E_INVALID; }
+  *out = nullptr;
+  if (!probs || count < 1) { set_error("need count >= 1 problems"); return SLAB_E_INVALID; }
+  for (int i = 0; i < count; ++i) {
+    if (infos) { infos[i].iterations = 0; infos[i].max_relres = 0.0; infos[i].failed_block = -1; }
+    const int rc = slab_check_problem(&probs[i], opts);
+    if (rc) {
+      set_error("problem " + std::to_string(i) + ": " + g_last_error);
+      return rc;
+    }
+  }
+  int device = 0;
+  if (hipGetDevice(&device) != hipSuccess) { set_error("no HIP device"); return SLAB_E_HIP; }
+  slab_batch bt = new slab_batch_s();
+  bt->device = device;
+  bt->precision = opts ? opts->precision : SLAB_FP64;
+  bt->flags = opts ? opts->flags : 0;
+  std::vector<const slab_problem*> ps;
+  for (int i = 0; i < count; ++i) {
+    bt->items.push_back(new_handle(&probs[i], opts, device));
+    ps.push_back(&probs[i]);
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  std::vector<int> fail, blk;
+  int rc = factor_dispatch(bt->precision, bt->items, ps, st, bt->mem, fail, blk, bt->phase_us);
+  if (rc == SLAB_OK || rc == SLAB_E_INVALID) {
+    for (int i = 0; i < count && i < (int)fail.size(); ++i) {
+      if (fail[i] == 0) continue;
+      if (infos && fail[i] != 1) infos[i].failed_block = blk[i];
+      set_error("problem " + std::to_string(i) + ": " + fail_message(fail[i], blk[i]));
+      rc = fail[i] == 1 ? SLAB_E_INVALID : SLAB_E_BREAKDOWN;
+      break;
+    }
+  }
+  if (rc != SLAB_OK) {
+    (void)hipStreamSynchronize(st);
+    const std::string msg = g_last_error;
+    slab_batch_free(bt);
+    set_error(msg);
+    return rc;
+  }
+  *out = bt;
+  return SLAB_OK;
+}
+
+int slab_solve_batch(slab_batch bt, const double* const* f, double* const* u, const int32_t* nrhs,
+                     const int64_t* ld, void* hip_stream, slab_solve_info* infos) {
+  if (!bt || !f || !u || !nrhs || !ld) { set_error("null argument"); return SLAB_E_INVALID; }
+  std::vector<SolveJob> jobs;
+  for (size_t i = 0; i < bt->items.size(); ++i) {
+    const int rc = check_vec_args(bt->items[i], f[i], u[i], nrhs[i], ld[i]);
+    if (rc) {
+      set_error("problem " + std::to_string(i) + ": " + g_last_error);
+      return rc;
+    }
+    jobs.push_back({bt->items[i], f[i], u[i], nrhs[i], (long long)ld[i],
+                    infos ? &infos[i] : nullptr});
+  }
+  SLAB_HIP_CHECK(hipSetDevice(bt->device));
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (!(bt->flags & SLAB_GRAPH)) return solve_group(jobs, bt->precision, false, st, bt->mem, nullptr);
+  // stream capture needs a stream other than the legacy default stream
+  // (work queued on the default stream, e.g. the inputs, is finished first)
+  hipStream_t cs = st;
+  if (!cs) {
+    SLAB_HIP_CHECK(hipStreamSynchronize(st));
+    SLAB_HIP_CHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  }
+  const int rc = solve_group(jobs, bt->precision, false, cs, bt->mem, bt->graphs);
+  if (!st) {
+    (void)hipStreamSynchronize(cs);
+    (void)hipStreamDestroy(cs);
+  }
+  return rc;
+}
+
+int slab_batch_handle(slab_batch bt, int32_t i, slab_handle* out) {
+  if (!bt || !out || i < 0 || i >= (int)bt->items.size()) { set_error("bad batch index"); return SLAB_E_INVALID; }
+  *out = bt->items[i];
+  return SLAB_OK;
+}
+
+int slab_batch_query(slab_batch bt, int32_t what, int64_t* value) {
+  if (!bt || !value) { set_error("null argument"); return SLAB_E_INVALID; }
+  if (what == 0) { *value = (int64_t)bt->items.size(); return SLAB_OK; }
+  if (what == 5) {
+    int64_t tot = (int64_t)bt->mem.bytes;
+    for (slab_handle h : bt->items) tot += (int64_t)h->mem.bytes;
+    *value = tot;
+    return SLAB_OK;
+  }
+  if (what >= 10 && what < 15) { *value = bt->phase_us[what - 10]; return SLAB_OK; }
+  set_error("unknown query");
+  return SLAB_E_INVALID;
+}
+
+// ---- auxiliary ----------------------------------------------------------------
 
 int slab_index_maps(int32_t n1, int32_t n2, int32_t b, int32_t* col_kind, int32_t* slab_of_col,
                     int32_t* local_of_col, int64_t* perm_even, int64_t* perm_odd,
@@ -398,10 +761,19 @@ int slab_residual(slab_handle h, const double* f, const double* u, int32_t nrhs,
   }
   hipStream_t st = (hipStream_t)hip_stream;
   SLAB_HIP_CHECK(hipSetDevice(h->device));
-  SLAB_TRY(ensure_workspace(h, nrhs, st));
-  std::vector<double> rr;
-  SLAB_TRY(residual_host(h, f, u, nrhs, ld, nullptr, rr, st));
-  for (int c = 0; c < nrhs; ++c) relres[c] = rr[c];
+  SLAB_TRY(ensure_workspace(h, nrhs));
+  SolveDev d;
+  std::memset(&d, 0, sizeof(d));
+  d.n1 = h->n1; d.n2 = h->n2; d.b = h->b; d.m = h->m; d.nrhs = nrhs;
+  d.wh = h->wh; d.wv = h->wv; d.f = f; d.u = u; d.r = nullptr; d.ldf = ld;
+  d.norms = h->ws.norms; d.partial = h->ws.partial;
+  Plan p;
+  plan_residual(p, std::vector<SolveDev>{d});
+  SLAB_TRY(run_plan(h->mem, p, st));
+  std::vector<SolveJob> jobs{{h, f, nullptr, nrhs, ld, nullptr}};
+  std::vector<std::vector<double>> rr;
+  SLAB_TRY(read_relres(jobs, st, rr));
+  for (int c = 0; c < nrhs; ++c) relres[c] = rr[0][c];
   return SLAB_OK;
 }
 
@@ -427,7 +799,7 @@ int slab_query(slab_handle h, int32_t what, int64_t* value) {
     case 2: *value = h->n2; return SLAB_OK;
     case 3: *value = h->b; return SLAB_OK;
     case 4: *value = h->precision; return SLAB_OK;
-    case 5: *value = (int64_t)h->bytes; return SLAB_OK;
+    case 5: *value = (int64_t)h->mem.bytes; return SLAB_OK;
     default:
       if (what >= 10 && what < 15) { *value = h->phase_us[what - 10]; return SLAB_OK; }
   }

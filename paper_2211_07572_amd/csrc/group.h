@@ -1,0 +1,184 @@
+// Grouped launches and launch plans.
+//
+// A grouped launch covers several independent items (problems of a batch,
+// pivot blocks of one elimination level, products of one update step) in one
+// kernel: item i owns the workgroups [offs[i], offs[i+1]) of blockIdx.x, where
+// offs and the item descriptors live in device memory.  A single problem is a
+// group of one, so every factorization and solve runs through these kernels.
+//
+// A Plan collects the descriptor tables of a whole factorization or solve
+// pass on the host, uploads them in one copy, and then issues the recorded
+// launches in order; a recorded solve pass can be captured into a HIP graph
+// and replayed.
+#pragma once
+
+#include "common.h"
+
+#include <cstring>
+#include <functional>
+#include <vector>
+
+namespace slab {
+
+// Item owning workgroup bx: the largest i with offs[i] <= bx.
+__device__ __forceinline__ int group_item(const int* __restrict__ offs, int count, int bx) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (offs[mid] <= bx) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// ---- descriptors ----------------------------------------------------------------
+
+// One problem of stage one (edge weights, slab factors, Schur pieces, assembly).
+struct ProbDev {
+  int n1, n2, b, m;
+  double h;
+  int is_log;
+  const double* coef;  // caller's field (kappa or theta), read once
+  double* kappa;       // working copy
+  double* wh;
+  double* wv;
+  void* Gl;
+  void* Hsw;
+  void* sig;
+  void* PRR;
+  void* PLL;
+  void* PLR;
+  void* PRL;
+  void* Td;            // T_jj (reduced precision)
+  void* To;            // T_{j,j+1}
+  double* T64;         // optional FP64 copies
+  double* O64;
+  int* status;
+};
+
+// One pivot block of the block factorization.
+struct FactorItem {
+  void* S;        // n x n, lower triangle; overwritten by L
+  void* Li;       // n x n, receives L^-1
+  double* S64;    // optional FP64 copy of S before the factorization
+  int* status;
+  int n;
+  int blk;        // interface index reported on breakdown
+};
+
+// One product C = beta C + alpha op(A) op(B) (row-major, leading dimensions).
+struct GemmItem {
+  const void* A;
+  const void* B;
+  void* C;
+  int M, N, K;
+  int lda, ldb, ldc;
+};
+
+// One block-vector product y = beta xin + alpha op(M) x over nrhs columns.
+struct BmvItem {
+  const void* M;
+  const void* x;
+  const void* xin;  // may be null or equal to y
+  void* y;
+  int n;
+  int nrhs;
+};
+
+// One problem of a solve pass (slab sweeps, reduced right-hand side,
+// coupling, interface output, residual).
+struct SolveDev {
+  int n1, n2, b, m, nrhs;
+  int accumulate;
+  long long ld;    // rhs leading dimension
+  long long ldo;   // out leading dimension
+  const double* wh;
+  const double* wv;
+  const void* Gl;
+  void* zbuf;
+  void* xb;
+  void* ft;
+  const double* rhs;
+  double* out;
+  // residual r = f - A u and per-column norms
+  const double* f;
+  const double* u;
+  double* r;
+  long long ldf;   // f and u leading dimension
+  double* norms;
+  double* partial;
+};
+
+// Reduced system of one problem in a solve pass (block factors from stage two
+// and the reduced vectors, nrhs columns of n at [j][c][r]).
+struct ReducedDev {
+  int n, m, nrhs;
+  const void* Linv;
+  const void* Z;
+  const void* Td;   // odd-even order: the U_e blocks
+  void* ft;         // in: f~, out: the interface values
+  void* yt;
+  void* tt;         // nrhs x n temporary
+};
+
+// Stage two of one problem (see plan_stage2).
+struct Stage2Prob {
+  int n, m;
+  void* Td;
+  void* To;
+  void* Linv;
+  void* Z;
+  double* S64;
+  int* status;
+};
+
+// ---- host-side plan -----------------------------------------------------------
+
+class Plan {
+ public:
+  // Stage `bytes` of table data; returns its offset (256-byte aligned).
+  size_t add(const void* data, size_t bytes) {
+    const size_t off = (host_.size() + 255) & ~size_t(255);
+    host_.resize(off + bytes);
+    if (bytes) std::memcpy(host_.data() + off, data, bytes);
+    return off;
+  }
+  template <class V>
+  size_t add_vec(const std::vector<V>& v) { return add(v.data(), v.size() * sizeof(V)); }
+
+  // Offsets table of a grouped launch from per-item workgroup counts.
+  size_t add_offsets(const std::vector<int>& counts, long long* total) {
+    std::vector<int> offs(counts.size() + 1, 0);
+    long long t = 0;
+    for (size_t i = 0; i < counts.size(); ++i) {
+      offs[i] = (int)t;
+      t += counts[i];
+    }
+    offs[counts.size()] = (int)t;
+    *total = t;
+    return add_vec(offs);
+  }
+
+  // A recorded launch: receives the device base of the uploaded tables.
+  typedef std::function<int(const char* dev, hipStream_t st)> Step;
+  void step(Step s) { steps_.push_back(std::move(s)); }
+
+  size_t bytes() const { return host_.size(); }
+  const char* host() const { return host_.data(); }
+  int run(const char* dev, hipStream_t st) const {
+    for (const Step& s : steps_) {
+      const int rc = s(dev, st);
+      if (rc) return rc;
+    }
+    return 0;
+  }
+
+ private:
+  std::vector<char> host_;
+  std::vector<Step> steps_;
+};
+
+template <class V>
+inline const V* dev_at(const char* dev, size_t off) { return (const V*)(dev + off); }
+
+}  // namespace slab

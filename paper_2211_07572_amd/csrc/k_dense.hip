@@ -28,11 +28,9 @@ namespace slab {
 // k ranges where op(A) / op(B) is known to be zero (lower-triangular factors).
 // ---------------------------------------------------------------------------
 template <typename T, int TILE, int TK, bool AK, bool BN, bool VECOK>
-__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, T alpha,
-                                              const T* __restrict__ A, long long lda,
-                                              long long sa, const T* __restrict__ B,
-                                              long long ldb, long long sb, T beta, T* C,
-                                              long long ldc, long long sc, int flags) {
+__global__ __launch_bounds__(256) void k_gemm(const GemmItem* __restrict__ items,
+                                              const int* __restrict__ offs, int count, T alpha,
+                                              T beta, int flags) {
   typedef typename acc4<T>::type V4;
   constexpr int TM = TILE, TN = TILE;
   constexpr int FM = TILE / 32, FN = TILE / 32;  // 16x16 MFMA tiles per wave and direction
@@ -42,23 +40,29 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, T alpha,
   typedef T vt __attribute__((ext_vector_type(VEC)));
   __shared__ T As[2][TK][TM + 4];
   __shared__ T Bs[2][TK][TN + 4];
+  const int itm = group_item(offs, count, blockIdx.x);
+  const long long bx = blockIdx.x - offs[itm];
+  const T* __restrict__ A = (const T*)items[itm].A;
+  const T* __restrict__ B = (const T*)items[itm].B;
+  T* C = (T*)items[itm].C;
+  const int M = items[itm].M, N = items[itm].N, K = items[itm].K;
+  const long long lda = items[itm].lda, ldb = items[itm].ldb, ldc = items[itm].ldc;
   int ti, tj;
   if (flags & GEMM_LOWER_C) {
-    const long long t = blockIdx.x;
+    const long long t = bx;
     int r = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
     while ((long long)(r + 1) * (r + 2) / 2 <= t) ++r;
     while ((long long)r * (r + 1) / 2 > t) --r;
     ti = r;
     tj = (int)(t - (long long)r * (r + 1) / 2);
   } else {
+    const int tm = (M + TM - 1) / TM, tn = (N + TN - 1) / TN;
     // with A lower triangular the last tile rows carry the longest k ranges:
     // hand them out first
-    ti = (flags & GEMM_A_LOWER) ? (int)(gridDim.y - 1 - blockIdx.y) : (int)blockIdx.y;
-    tj = blockIdx.x;
+    ti = (int)(bx / tn);
+    if (flags & GEMM_A_LOWER) ti = tm - 1 - ti;
+    tj = (int)(bx % tn);
   }
-  A += (long long)blockIdx.z * sa;
-  B += (long long)blockIdx.z * sb;
-  C += (long long)blockIdx.z * sc;
   const int i0 = ti * TM, j0 = tj * TN;
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
@@ -190,18 +194,16 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, T alpha,
 }
 
 template <typename T, int TILE, int TK>
-static void gemm_tile(bool ak, bool bn, bool vecok, dim3 grid, int M, int N, int K, T alpha,
-                      const T* A, long long lda, long long sa, const T* B, long long ldb,
-                      long long sb, T beta, T* C, long long ldc, long long sc, int flags,
-                      hipStream_t st) {
-#define SLAB_GEMM_CASE(AKV, BNV)                                                                 \
-  do {                                                                                           \
-    if (vecok)                                                                                   \
-      hipLaunchKernelGGL((k_gemm<T, TILE, TK, AKV, BNV, true>), grid, dim3(256), 0, st, M, N, K, \
-                         alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc, flags);                \
-    else                                                                                         \
-      hipLaunchKernelGGL((k_gemm<T, TILE, TK, AKV, BNV, false>), grid, dim3(256), 0, st, M, N,   \
-                         K, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc, flags);             \
+static void gemm_tile(bool ak, bool bn, bool vecok, unsigned grid, const GemmItem* items,
+                      const int* offs, int count, T alpha, T beta, int flags, hipStream_t st) {
+#define SLAB_GEMM_CASE(AKV, BNV)                                                                   \
+  do {                                                                                             \
+    if (vecok)                                                                                     \
+      hipLaunchKernelGGL((k_gemm<T, TILE, TK, AKV, BNV, true>), dim3(grid), dim3(256), 0, st,      \
+                         items, offs, count, alpha, beta, flags);                                  \
+    else                                                                                           \
+      hipLaunchKernelGGL((k_gemm<T, TILE, TK, AKV, BNV, false>), dim3(grid), dim3(256), 0, st,     \
+                         items, offs, count, alpha, beta, flags);                                  \
   } while (0)
   if (!ak && !bn) SLAB_GEMM_CASE(false, false);
   else if (!ak && bn) SLAB_GEMM_CASE(false, true);
@@ -211,39 +213,47 @@ static void gemm_tile(bool ak, bool bn, bool vecok, dim3 grid, int M, int N, int
 }
 
 template <typename T>
-int launch_gemm(bool ak, bool bn, int M, int N, int K, T alpha, const T* A, long long lda,
-                long long sa, const T* B, long long ldb, long long sb, T beta, T* C,
-                long long ldc, long long sc, int batch, int flags, hipStream_t st) {
-  if (M <= 0 || N <= 0 || batch <= 0) return SLAB_OK;
+void plan_gemm(Plan& plan, bool ak, bool bn, const std::vector<GemmItem>& items, T alpha, T beta,
+               int flags) {
+  if (items.empty()) return;
   // 128-wide tiles once there are enough of them for four per compute unit
-  const int tile = (sizeof(T) == 4 && (long long)M * N * batch >= 1024LL * 128 * 128) ? 128 : 64;
-  const int tm = (M + tile - 1) / tile, tn = (N + tile - 1) / tile;
-  dim3 grid;
-  if (flags & GEMM_LOWER_C) grid = dim3((unsigned)((long long)tm * (tm + 1) / 2), 1, batch);
-  else grid = dim3(tn, tm, batch);
-  // 16-byte vector loads need 16-byte aligned bases, strides and batch strides
-  const long long vec = 16 / (long long)sizeof(T);
-  const bool vecok = lda % vec == 0 && ldb % vec == 0 && sa % vec == 0 && sb % vec == 0 &&
-                     ((uintptr_t)A & 15) == 0 && ((uintptr_t)B & 15) == 0;
-  if (tile == 128)
-    gemm_tile<T, 128, 16>(ak, bn, vecok, grid, M, N, K, alpha, A, lda, sa, B, ldb, sb, beta, C,
-                          ldc, sc, flags, st);
-  else
-    gemm_tile<T, 64, 32>(ak, bn, vecok, grid, M, N, K, alpha, A, lda, sa, B, ldb, sb, beta, C,
-                         ldc, sc, flags, st);
-  SLAB_LAUNCH_CHECK();
-  return SLAB_OK;
+  long long area = 0;
+  bool vecok = true;
+  const uintptr_t vec = 16;
+  for (const GemmItem& g : items) {
+    area += (long long)g.M * g.N;
+    vecok = vecok && g.lda % (vec / sizeof(T)) == 0 && g.ldb % (vec / sizeof(T)) == 0 &&
+            ((uintptr_t)g.A % vec) == 0 && ((uintptr_t)g.B % vec) == 0;
+  }
+  if (flags & GEMM_LOWER_C) area /= 2;
+  const int tile = (sizeof(T) == 4 && area >= 1024LL * 128 * 128) ? 128 : 64;
+  std::vector<int> c;
+  for (const GemmItem& g : items) {
+    const long long tm = (g.M + tile - 1) / tile, tn = (g.N + tile - 1) / tile;
+    c.push_back((int)((flags & GEMM_LOWER_C) ? tm * (tm + 1) / 2 : tm * tn));
+  }
+  long long tot;
+  const size_t oi = plan.add_vec(items), oo = plan.add_offsets(c, &tot);
+  const int count = (int)items.size();
+  plan.step([=](const char* dev, hipStream_t st) {
+    if (tile == 128)
+      gemm_tile<T, 128, 16>(ak, bn, vecok, (unsigned)tot, dev_at<GemmItem>(dev, oi),
+                            dev_at<int>(dev, oo), count, alpha, beta, flags, st);
+    else
+      gemm_tile<T, 64, 32>(ak, bn, vecok, (unsigned)tot, dev_at<GemmItem>(dev, oi),
+                           dev_at<int>(dev, oo), count, alpha, beta, flags, st);
+    SLAB_LAUNCH_CHECK();
+    return SLAB_OK;
+  });
 }
-template int launch_gemm<float>(bool, bool, int, int, int, float, const float*, long long,
-                                long long, const float*, long long, long long, float, float*,
-                                long long, long long, int, int, hipStream_t);
-template int launch_gemm<double>(bool, bool, int, int, int, double, const double*, long long,
-                                 long long, const double*, long long, long long, double, double*,
-                                 long long, long long, int, int, hipStream_t);
+template void plan_gemm<float>(Plan&, bool, bool, const std::vector<GemmItem>&, float, float,
+                              int);
+template void plan_gemm<double>(Plan&, bool, bool, const std::vector<GemmItem>&, double, double,
+                               int);
 
 // ---------------------------------------------------------------------------
-// Panel of the right-looking factorization of a pivot block S (n x n), for
-// gridDim.y independent blocks at once.
+// Panel of the right-looking factorization of a pivot block S (n x n), grouped
+// over independent pivot blocks (items).
 // Every workgroup first inverts the Cholesky factor of the 64x64 diagonal
 // block [k0, k0+nb): Gaussian elimination without pivoting on [S_kk | I],
 // kept in one array (U on and above the diagonal, the unit lower L~^-1 below
@@ -255,14 +265,16 @@ template int launch_gemm<double>(bool, bool, int, int, int, double, const double
 //   * advances 64 columns of the carried inverse:  X_k = L_kk^-1 X_k.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_panel(T* __restrict__ S, T* __restrict__ Lv, int n,
-                                               int k0, int nrow_wg, int* __restrict__ status,
-                                               int blk, long long bs, int blk_step) {
+__global__ __launch_bounds__(256) void k_panel(const FactorItem* __restrict__ items,
+                                               const int* __restrict__ offs, int count, int k0) {
   typedef typename acc4<T>::type V4;
-  // blockIdx.y selects one of several independent pivot blocks, bs elements apart
-  S += (long long)blockIdx.y * bs;
-  Lv += (long long)blockIdx.y * bs;
-  blk += (int)blockIdx.y * blk_step;
+  const int itm = group_item(offs, count, blockIdx.x);
+  const int bx = blockIdx.x - offs[itm];
+  T* __restrict__ S = (T*)items[itm].S;
+  T* __restrict__ Lv = (T*)items[itm].Li;
+  int* __restrict__ status = items[itm].status;
+  const int n = items[itm].n, blk = items[itm].blk;
+  const int nrow_wg = (n - k0 - min(64, n - k0) + 63) / 64;
   __shared__ T E[64][65];   // L_kk^-1 after the elimination
   __shared__ T Bt[64][65];  // operand tile
   __shared__ T rowbuf[2][64];
@@ -346,9 +358,9 @@ __global__ __launch_bounds__(256) void k_panel(T* __restrict__ S, T* __restrict_
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = V4{0, 0, 0, 0};
-  const bool rows = (int)blockIdx.x < nrow_wg;
-  const long long r0 = (long long)k0 + nb + (long long)blockIdx.x * 64;  // rows case
-  const long long c0 = (long long)(blockIdx.x - nrow_wg) * 64;            // columns case
+  const bool rows = bx < nrow_wg;
+  const long long r0 = (long long)k0 + nb + (long long)bx * 64;  // rows case
+  const long long c0 = (long long)(bx - nrow_wg) * 64;            // columns case
   const long long ncols = (long long)k0 + nb;
   if (rows) {
     for (int e = tid; e < 64 * 64; e += 256) {
@@ -406,11 +418,17 @@ __global__ __launch_bounds__(256) void k_panel(T* __restrict__ S, T* __restrict_
 // workgroup issues all its loads (A, B and the C tile) before the first MFMA.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_rank64(T* __restrict__ S, T* __restrict__ Lv, int n,
-                                                int k0, int nb, int ntrail, long long bs) {
+__global__ __launch_bounds__(256) void k_rank64(const FactorItem* __restrict__ items,
+                                                const int* __restrict__ offs, int count, int k0) {
   typedef typename acc4<T>::type V4;
-  S += (long long)blockIdx.y * bs;
-  Lv += (long long)blockIdx.y * bs;
+  const int itm = group_item(offs, count, blockIdx.x);
+  const int bx = blockIdx.x - offs[itm];
+  T* __restrict__ S = (T*)items[itm].S;
+  T* __restrict__ Lv = (T*)items[itm].Li;
+  const int n = items[itm].n;
+  const int nb = min(64, n - k0);
+  const long long ntr = (n - k0 - nb + 63) / 64;
+  const int ntrail = (int)(ntr * (ntr + 1) / 2);
   __shared__ T As[64][65];  // As[row][k]
   __shared__ T Bs[64][65];  // Bs[col][k]
   const int tid = threadIdx.x;
@@ -420,9 +438,9 @@ __global__ __launch_bounds__(256) void k_rank64(T* __restrict__ S, T* __restrict
   const long long base = (long long)k0 + nb;
   long long r0, c0;
   T* C;
-  bool trail = (int)blockIdx.x < ntrail;
+  bool trail = bx < ntrail;
   if (trail) {
-    const long long t = blockIdx.x;
+    const long long t = bx;
     int r = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
     while ((long long)(r + 1) * (r + 2) / 2 <= t) ++r;
     while ((long long)r * (r + 1) / 2 > t) --r;
@@ -430,7 +448,7 @@ __global__ __launch_bounds__(256) void k_rank64(T* __restrict__ S, T* __restrict
     c0 = base + 64LL * (t - (long long)r * (r + 1) / 2);
     C = S;
   } else {
-    const long long t = blockIdx.x - ntrail;
+    const long long t = bx - ntrail;
     const long long ncb = (base + 63) / 64;
     r0 = base + 64LL * (t / ncb);
     c0 = 64LL * (t % ncb);
@@ -499,94 +517,134 @@ __global__ __launch_bounds__(256) void k_rank64(T* __restrict__ S, T* __restrict
 }
 
 template <typename T>
-__global__ void k_identity(T* __restrict__ X, int n, long long bs) {
-  X += (long long)blockIdx.y * bs;
+__global__ void k_identity(const FactorItem* __restrict__ items, const int* __restrict__ offs,
+                           int count) {
+  const int itm = group_item(offs, count, blockIdx.x);
+  const long long nwg = offs[itm + 1] - offs[itm];
+  T* __restrict__ X = (T*)items[itm].Li;
+  const int n = items[itm].n;
   const long long tot = (long long)n * n;
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot;
-       e += (long long)gridDim.x * blockDim.x) {
+  for (long long e = (blockIdx.x - offs[itm]) * (long long)blockDim.x + threadIdx.x; e < tot;
+       e += nwg * blockDim.x) {
     X[e] = (e / n == e % n) ? (T)1 : (T)0;
   }
 }
 
 // FP64 copy of a symmetric block stored in its lower triangle.
 template <typename T>
-__global__ void k_sym_to_f64(const T* __restrict__ S, double* __restrict__ out, int n,
-                             long long bs) {
-  S += (long long)blockIdx.y * bs;
-  out += (long long)blockIdx.y * bs;
+__global__ void k_sym_to_f64(const FactorItem* __restrict__ items, const int* __restrict__ offs,
+                             int count) {
+  const int itm = group_item(offs, count, blockIdx.x);
+  const long long nwg = offs[itm + 1] - offs[itm];
+  const T* __restrict__ S = (const T*)items[itm].S;
+  double* __restrict__ out = items[itm].S64;
+  const int n = items[itm].n;
   const long long tot = (long long)n * n;
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot;
-       e += (long long)gridDim.x * blockDim.x) {
+  for (long long e = (blockIdx.x - offs[itm]) * (long long)blockDim.x + threadIdx.x; e < tot;
+       e += nwg * blockDim.x) {
     const long long i = e / n, k = e % n;
     out[e] = (double)(k <= i ? S[e] : S[k * n + i]);
   }
 }
 
-// Cholesky factorization with carried inverse of `count` pivot blocks S_q =
-// S + q*bs (n x n, lower triangles), L_q^-1 into Li + q*bs; breakdown of block
-// q is reported as blk0 + q*blk_step.
+// Cholesky factorization with carried inverse of independent pivot blocks
+// (items, any sizes): L^-1 into item.Li, breakdown of an item reported as
+// status = {3, item.blk}.
 template <typename T>
-static int factor_blocks(T* S, T* Li, int n, int count, long long bs, int blk0, int blk_step,
-                         double* S64, int* status, hipStream_t st) {
-  if (count <= 0) return SLAB_OK;
-  const long long nsq = (long long)n * n;
-  const unsigned fill_grid = (unsigned)std::min<long long>((nsq + 255) / 256, 4096);
-  if (S64) {
-    hipLaunchKernelGGL((k_sym_to_f64<T>), dim3(fill_grid, count), dim3(256), 0, st, S, S64, n, bs);
-    SLAB_LAUNCH_CHECK();
-  }
-  hipLaunchKernelGGL((k_identity<T>), dim3(fill_grid, count), dim3(256), 0, st, Li, n, bs);
-  SLAB_LAUNCH_CHECK();
-  for (int k0 = 0; k0 < n; k0 += 64) {
-    const int nb = std::min(64, n - k0);
-    const int nrow = n - k0 - nb;
-    const int nrow_wg = (nrow + 63) / 64;
-    const int ncol_wg = (k0 + nb + 63) / 64;
-    hipLaunchKernelGGL((k_panel<T>), dim3(nrow_wg + ncol_wg, count), dim3(256), 0, st, S, Li, n,
-                       k0, nrow_wg, status, blk0, bs, blk_step);
-    SLAB_LAUNCH_CHECK();
-    if (nrow > 0) {
-      const long long tr = (nrow + 63) / 64;
-      const int ntrail = (int)(tr * (tr + 1) / 2);
-      const int naug = (int)(tr * ((k0 + nb + 63) / 64));
-      hipLaunchKernelGGL((k_rank64<T>), dim3(ntrail + naug, count), dim3(256), 0, st, S, Li, n,
-                         k0, nb, ntrail, bs);
+void plan_factor_blocks(Plan& plan, std::vector<FactorItem> items) {
+  if (items.empty()) return;
+  std::sort(items.begin(), items.end(),
+            [](const FactorItem& a, const FactorItem& b) { return a.n > b.n; });
+  const size_t oi = plan.add_vec(items);
+  const int count = (int)items.size();
+  std::vector<int> c;
+  long long tot;
+  // FP64 copies (items without one get no workgroups), then identities
+  for (const FactorItem& f : items)
+    c.push_back(f.S64 ? (int)std::min<long long>(((long long)f.n * f.n + 255) / 256, 1024) : 0);
+  const size_t oc = plan.add_offsets(c, &tot);
+  if (tot > 0) {
+    const long long t = tot;
+    plan.step([=](const char* dev, hipStream_t st) {
+      hipLaunchKernelGGL((k_sym_to_f64<T>), dim3((unsigned)t), dim3(256), 0, st,
+                         dev_at<FactorItem>(dev, oi), dev_at<int>(dev, oc), count);
       SLAB_LAUNCH_CHECK();
-    }
+      return SLAB_OK;
+    });
   }
-  return SLAB_OK;
+  c.clear();
+  for (const FactorItem& f : items)
+    c.push_back((int)std::min<long long>(((long long)f.n * f.n + 255) / 256, 1024));
+  const size_t od = plan.add_offsets(c, &tot);
+  {
+    const long long t = tot;
+    plan.step([=](const char* dev, hipStream_t st) {
+      hipLaunchKernelGGL((k_identity<T>), dim3((unsigned)t), dim3(256), 0, st,
+                         dev_at<FactorItem>(dev, oi), dev_at<int>(dev, od), count);
+      SLAB_LAUNCH_CHECK();
+      return SLAB_OK;
+    });
+  }
+  // panels of 64 columns; at step k0 the items with n > k0 form a prefix
+  for (int k0 = 0; k0 < items[0].n; k0 += 64) {
+    int live = 0;
+    while (live < count && items[live].n > k0) ++live;
+    std::vector<int> cp, cr;
+    for (int i = 0; i < live; ++i) {
+      const int n = items[i].n, nb = std::min(64, n - k0), nrow = n - k0 - nb;
+      const long long tr = (nrow + 63) / 64;
+      cp.push_back((nrow + 63) / 64 + (k0 + nb + 63) / 64);
+      cr.push_back(nrow > 0 ? (int)(tr * (tr + 1) / 2 + tr * ((k0 + nb + 63) / 64)) : 0);
+    }
+    long long tp, trk;
+    const size_t op = plan.add_offsets(cp, &tp), orr = plan.add_offsets(cr, &trk);
+    plan.step([=](const char* dev, hipStream_t st) {
+      hipLaunchKernelGGL((k_panel<T>), dim3((unsigned)tp), dim3(256), 0, st,
+                         dev_at<FactorItem>(dev, oi), dev_at<int>(dev, op), live, k0);
+      SLAB_LAUNCH_CHECK();
+      if (trk > 0) {
+        hipLaunchKernelGGL((k_rank64<T>), dim3((unsigned)trk), dim3(256), 0, st,
+                           dev_at<FactorItem>(dev, oi), dev_at<int>(dev, orr), live, k0);
+        SLAB_LAUNCH_CHECK();
+      }
+      return SLAB_OK;
+    });
+  }
 }
 
 template <typename T>
-int launch_stage2(const Stage2Args& a, hipStream_t st) {
-  const int n = a.n, m = a.m;
-  const long long nsq = (long long)n * n;
-  T* Tdiag = (T*)a.Tdiag;
-  T* Toff = (T*)a.Toff;
-  T* Linv = (T*)a.Linv;
-  T* Z = (T*)a.Z;
-  if (!a.odd_even) {
-    // Alg. 1 in block Cholesky form: S_j = T_jj - Z_{j-1}^T Z_{j-1}, S_j = L_j L_j^T,
-    // Z_j = L_j^-1 T_{j,j+1}
-    for (int j = 0; j < m; ++j) {
-      T* S = Tdiag + (long long)j * nsq;
-      T* Li = Linv + (long long)j * nsq;
-      if (j > 0) {
-        const T* Zp = Z + (long long)(j - 1) * nsq;
-        int rc = launch_gemm<T>(true, false, n, n, n, (T)-1, Zp, n, 0, Zp, n, 0, (T)1, S, n, 0, 1,
-                                GEMM_LOWER_C, st);
-        if (rc) return rc;
+void plan_stage2(Plan& plan, const std::vector<Stage2Prob>& probs, bool odd_even) {
+  auto blk = [](const Stage2Prob& p, void* base, long long j) {
+    return (void*)((T*)base + j * (long long)p.n * p.n);
+  };
+  auto sq = [](const void* A, const void* B, void* C, int n) {
+    GemmItem g;
+    g.A = A; g.B = B; g.C = C; g.M = g.N = g.K = n; g.lda = g.ldb = g.ldc = n;
+    return g;
+  };
+  int mmax = 0;
+  for (const Stage2Prob& p : probs) mmax = std::max(mmax, p.m);
+  if (!odd_even) {
+    // Alg. 1 in block Cholesky form, all problems in lockstep over j:
+    // S_j = T_jj - Z_{j-1}^T Z_{j-1}, S_j = L_j L_j^T, Z_j = L_j^-1 T_{j,j+1}
+    for (int j = 0; j < mmax; ++j) {
+      std::vector<GemmItem> upd, zi;
+      std::vector<FactorItem> fi;
+      for (const Stage2Prob& p : probs) {
+        if (j >= p.m) continue;
+        if (j > 0) upd.push_back(sq(blk(p, p.Z, j - 1), blk(p, p.Z, j - 1), blk(p, p.Td, j), p.n));
+        FactorItem f;
+        f.S = blk(p, p.Td, j); f.Li = blk(p, p.Linv, j);
+        f.S64 = p.S64 ? p.S64 + (long long)j * p.n * p.n : nullptr;
+        f.status = p.status; f.n = p.n; f.blk = j;
+        fi.push_back(f);
+        if (j < p.m - 1) zi.push_back(sq(blk(p, p.Linv, j), blk(p, p.To, j), blk(p, p.Z, j), p.n));
       }
-      int rc = factor_blocks<T>(S, Li, n, 1, 0, j, 0, a.S64 ? a.S64 + (long long)j * nsq : nullptr,
-                                a.status, st);
-      if (rc) return rc;
-      if (j < m - 1) {
-        rc = launch_gemm<T>(false, false, n, n, n, (T)1, Li, n, 0, Toff + (long long)j * nsq, n,
-                            0, (T)0, Z + (long long)j * nsq, n, 0, 1, GEMM_A_LOWER, st);
-        if (rc) return rc;
-      }
+      plan_gemm<T>(plan, true, false, upd, (T)-1, (T)1, GEMM_LOWER_C);
+      plan_factor_blocks<T>(plan, fi);
+      plan_gemm<T>(plan, false, false, zi, (T)1, (T)0, GEMM_A_LOWER);
     }
-    return SLAB_OK;
+    return;
   }
   // Odd-even order.  At level l (stride s = 2^l) the interfaces still present
   // are a_p = (p+1)s - 1, p < k = floor(m/s); those at even positions,
@@ -594,46 +652,43 @@ int launch_stage2(const Stage2Args& a, hipStream_t st) {
   // kept neighbour l = e_q - s when q >= 1 and r = e_q + s when q < floor(k/2).
   // With D_e = L L^T:  U_e = L^-1 C_l^T (stored over D_e), V_e = L^-1 C_e (in Z),
   //   D_l -= U_e^T U_e,  D_r -= V_e^T V_e,  C_l = -U_e^T V_e,
-  // where C_x (in Toff) is the coupling of x to the next interface present.
-  for (long long s = 1; m / s >= 1; s *= 2) {
-    const int k = (int)(m / s);
-    const int E = (k + 1) / 2, NR = k / 2;
-    const long long e0 = s - 1, es = 2 * s * nsq;
-    int rc = factor_blocks<T>(Tdiag + e0 * nsq, Linv + e0 * nsq, n, E, es, (int)e0, (int)(2 * s),
-                              a.S64 ? a.S64 + e0 * nsq : nullptr, a.status, st);
-    if (rc) return rc;
-    const long long e1 = e0 + 2 * s;  // first eliminated interface with a left neighbour
-    if (E > 1) {  // U_e = L_e^-1 C_{e-s}^T
-      rc = launch_gemm<T>(false, true, n, n, n, (T)1, Linv + e1 * nsq, n, es,
-                          Toff + (e1 - s) * nsq, n, es, (T)0, Tdiag + e1 * nsq, n, es, E - 1,
-                          GEMM_A_LOWER, st);
-      if (rc) return rc;
+  // where C_x (in To) is the coupling of x to the next interface present.
+  for (long long s = 1; s <= mmax; s *= 2) {
+    std::vector<FactorItem> fi;
+    std::vector<GemmItem> gu, gv, gdl, gdr, gc;
+    for (const Stage2Prob& p : probs) {
+      const int k = (int)(p.m / s);
+      if (k < 1) continue;
+      const int E = (k + 1) / 2, NR = k / 2;
+      for (int q = 0; q < E; ++q) {
+        const long long e = (2 * q + 1) * s - 1;
+        FactorItem f;
+        f.S = blk(p, p.Td, e); f.Li = blk(p, p.Linv, e);
+        f.S64 = p.S64 ? p.S64 + e * p.n * p.n : nullptr;
+        f.status = p.status; f.n = p.n; f.blk = (int)e;
+        fi.push_back(f);
+        if (q >= 1) {
+          gu.push_back(sq(blk(p, p.Linv, e), blk(p, p.To, e - s), blk(p, p.Td, e), p.n));
+          gdl.push_back(sq(blk(p, p.Td, e), blk(p, p.Td, e), blk(p, p.Td, e - s), p.n));
+        }
+        if (q < NR) {
+          gv.push_back(sq(blk(p, p.Linv, e), blk(p, p.To, e), blk(p, p.Z, e), p.n));
+          gdr.push_back(sq(blk(p, p.Z, e), blk(p, p.Z, e), blk(p, p.Td, e + s), p.n));
+        }
+        if (q >= 1 && q < NR)
+          gc.push_back(sq(blk(p, p.Td, e), blk(p, p.Z, e), blk(p, p.To, e - s), p.n));
+      }
     }
-    if (NR > 0) {  // V_e = L_e^-1 C_e
-      rc = launch_gemm<T>(false, false, n, n, n, (T)1, Linv + e0 * nsq, n, es, Toff + e0 * nsq, n,
-                          es, (T)0, Z + e0 * nsq, n, es, NR, GEMM_A_LOWER, st);
-      if (rc) return rc;
-    }
-    if (E > 1) {  // D_l -= U_e^T U_e
-      rc = launch_gemm<T>(true, false, n, n, n, (T)-1, Tdiag + e1 * nsq, n, es, Tdiag + e1 * nsq,
-                          n, es, (T)1, Tdiag + (e1 - s) * nsq, n, es, E - 1, GEMM_LOWER_C, st);
-      if (rc) return rc;
-    }
-    if (NR > 0) {  // D_r -= V_e^T V_e
-      rc = launch_gemm<T>(true, false, n, n, n, (T)-1, Z + e0 * nsq, n, es, Z + e0 * nsq, n, es,
-                          (T)1, Tdiag + (e0 + s) * nsq, n, es, NR, GEMM_LOWER_C, st);
-      if (rc) return rc;
-    }
-    if (NR > 1) {  // C_l = -U_e^T V_e for the interfaces with both neighbours
-      rc = launch_gemm<T>(true, false, n, n, n, (T)-1, Tdiag + e1 * nsq, n, es, Z + e1 * nsq, n,
-                          es, (T)0, Toff + (e1 - s) * nsq, n, es, NR - 1, 0, st);
-      if (rc) return rc;
-    }
+    plan_factor_blocks<T>(plan, fi);
+    plan_gemm<T>(plan, false, true, gu, (T)1, (T)0, GEMM_A_LOWER);    // U_e = L^-1 C_l^T
+    plan_gemm<T>(plan, false, false, gv, (T)1, (T)0, GEMM_A_LOWER);   // V_e = L^-1 C_e
+    plan_gemm<T>(plan, true, false, gdl, (T)-1, (T)1, GEMM_LOWER_C);  // D_l -= U^T U
+    plan_gemm<T>(plan, true, false, gdr, (T)-1, (T)1, GEMM_LOWER_C);  // D_r -= V^T V
+    plan_gemm<T>(plan, true, false, gc, (T)-1, (T)0, 0);              // C_l = -U^T V
   }
-  return SLAB_OK;
 }
-template int launch_stage2<float>(const Stage2Args&, hipStream_t);
-template int launch_stage2<double>(const Stage2Args&, hipStream_t);
+template void plan_stage2<float>(Plan&, const std::vector<Stage2Prob>&, bool);
+template void plan_stage2<double>(Plan&, const std::vector<Stage2Prob>&, bool);
 
 // ---------------------------------------------------------------------------
 // Block-vector product for the sweeping solve (Alg. 2):
@@ -649,25 +704,26 @@ constexpr int BMV_WAVES = 16;
 
 
 template <typename T, bool TR, bool LOWER>
-__global__ __launch_bounds__(1024) void k_bmv(int n, int nrhs, T alpha, const T* __restrict__ M,
-                                             long long sM, const T* __restrict__ x, long long sx,
-                                             T beta, const T* xin, long long sxin, T* y,
-                                             long long sy) {
-  // blockIdx.z: independent product q (operands sM, sx, sxin, sy elements
-  // apart); blockIdx.y: group of 16 columns.  xin may alias y.
-  M += (long long)blockIdx.z * sM;
-  {
-    const long long c0 = (long long)blockIdx.y * 16 * n;
-    x += (long long)blockIdx.z * sx + c0;
-    if (xin) xin += (long long)blockIdx.z * sxin + c0;
-    y += (long long)blockIdx.z * sy + c0;
-  }
-  const int nc = min(16, nrhs - 16 * (int)blockIdx.y);
+__global__ __launch_bounds__(1024) void k_bmv(const BmvItem* __restrict__ items,
+                                             const int* __restrict__ offs, int count, T alpha,
+                                             T beta) {
+  // item: one product; workgroup: 16 rows x 16 columns of it.  xin may alias y.
+  const int itm = group_item(offs, count, blockIdx.x);
+  const int bx = blockIdx.x - offs[itm];
+  const int n = items[itm].n, nrhs = items[itm].nrhs;
+  const int nrt = (n + 15) / 16;
+  const int rt = bx % nrt, cg = bx / nrt;
+  const T* __restrict__ M = (const T*)items[itm].M;
+  const T* __restrict__ x = (const T*)items[itm].x + (long long)cg * 16 * n;
+  const T* xin = (const T*)items[itm].xin;
+  if (xin) xin += (long long)cg * 16 * n;
+  T* y = (T*)items[itm].y + (long long)cg * 16 * n;
+  const int nc = min(16, nrhs - 16 * cg);
   typedef typename acc4<T>::type V4;
   constexpr int VEC = 16 / sizeof(T);   // elements per 16-byte load
   constexpr int KS = 4 * VEC;           // k covered by one load per lane
   __shared__ T red[BMV_WAVES][16][17];
-  const int row0 = blockIdx.x * 16;
+  const int row0 = rt * 16;
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int g = lane >> 4, nn = lane & 15;
@@ -727,28 +783,31 @@ __global__ __launch_bounds__(1024) void k_bmv(int n, int nrhs, T alpha, const T*
 }
 
 template <typename T>
-int launch_gemv(bool tr, bool lower, int n, int nrhs, T alpha, const T* M, long long sM,
-                const T* x, long long sx, T beta, const T* xin, long long sxin, T* y, long long sy,
-                int batch, hipStream_t st) {
-  if (batch <= 0 || nrhs <= 0 || n <= 0) return SLAB_OK;
-  dim3 grid((n + 15) / 16, (nrhs + 15) / 16, batch);
-#define SLAB_BMV_CASE(TRV, LOV)                                                                   \
-  hipLaunchKernelGGL((k_bmv<T, TRV, LOV>), grid, dim3(64 * BMV_WAVES), 0, st, n, nrhs, alpha, M, \
-                     sM, x, sx, beta, xin, sxin, y, sy)
-  if (!tr && !lower) SLAB_BMV_CASE(false, false);
-  else if (!tr && lower) SLAB_BMV_CASE(false, true);
-  else if (tr && !lower) SLAB_BMV_CASE(true, false);
-  else SLAB_BMV_CASE(true, true);
+void plan_gemv(Plan& plan, bool tr, bool lower, const std::vector<BmvItem>& items, T alpha,
+               T beta) {
+  if (items.empty()) return;
+  std::vector<int> c;
+  for (const BmvItem& b : items) c.push_back(((b.n + 15) / 16) * ((b.nrhs + 15) / 16));
+  long long tot;
+  const size_t oi = plan.add_vec(items), oo = plan.add_offsets(c, &tot);
+  const int count = (int)items.size();
+  plan.step([=](const char* dev, hipStream_t st) {
+    const BmvItem* it = dev_at<BmvItem>(dev, oi);
+    const int* of = dev_at<int>(dev, oo);
+#define SLAB_BMV_CASE(TRV, LOV)                                                            \
+  hipLaunchKernelGGL((k_bmv<T, TRV, LOV>), dim3((unsigned)tot), dim3(64 * BMV_WAVES), 0, st, \
+                     it, of, count, alpha, beta)
+    if (!tr && !lower) SLAB_BMV_CASE(false, false);
+    else if (!tr && lower) SLAB_BMV_CASE(false, true);
+    else if (tr && !lower) SLAB_BMV_CASE(true, false);
+    else SLAB_BMV_CASE(true, true);
 #undef SLAB_BMV_CASE
-  SLAB_LAUNCH_CHECK();
-  return SLAB_OK;
+    SLAB_LAUNCH_CHECK();
+    return SLAB_OK;
+  });
 }
-template int launch_gemv<float>(bool, bool, int, int, float, const float*, long long,
-                                const float*, long long, float, const float*, long long, float*,
-                                long long, int, hipStream_t);
-template int launch_gemv<double>(bool, bool, int, int, double, const double*, long long,
-                                 const double*, long long, double, const double*, long long,
-                                 double*, long long, int, hipStream_t);
+template void plan_gemv<float>(Plan&, bool, bool, const std::vector<BmvItem>&, float, float);
+template void plan_gemv<double>(Plan&, bool, bool, const std::vector<BmvItem>&, double, double);
 
 // ---------------------------------------------------------------------------
 __global__ void k_cast_f64(const void* __restrict__ src, int is_float, double* __restrict__ dst,

@@ -17,29 +17,16 @@ namespace slab {
 // MODE 1 (interior): y = f_e + wL u_o(s-1) + wR u_o(s) (the coupling terms
 //   precomputed by k_coupling into xb); writes (or adds) x into the
 //   natural-order output (the interface values go through k_interface_out).
-// One workgroup per (slab, group of 256/BP columns); thread = (row i, column).
+// One workgroup per (problem, slab, group of 256/BP columns); thread = (row i,
+// column).
 // Software pipeline: while row step r is computed, the block inverse, edge
 // weights and right-hand side of the next step are loaded into registers and
 // then parked in the other half of double-buffered LDS, so each step costs one
 // barrier and no exposed global-memory latency.
 // ---------------------------------------------------------------------------
-struct SweepArgs {
-  int n1, n2, b, m, nrhs;
-  long long ld;       // leading dimension of rhs
-  long long ldo;      // leading dimension of out
-  const double* wh;
-  const double* wv;
-  const void* Gl;
-  void* zbuf;
-  void* xb;
-  const void* uo;     // interface values [j][c][r] (MODE 1)
-  const double* rhs;  // natural order FP64
-  double* out;        // natural order FP64 (MODE 1)
-  int accumulate;
-};
-
 template <typename T, typename TU, int BP, bool TRANS, int MODE>
-__global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
+__global__ __launch_bounds__(256) void k_sweep(const SolveDev* __restrict__ P,
+                                               const int* __restrict__ offs, int count) {
   constexpr int NC = 256 / BP;            // columns per workgroup
   constexpr int GPT = BP * BP / 256;      // block-inverse elements loaded per thread
   constexpr int D = BP == 64 ? (sizeof(T) == 8 ? 2 : 4) : 8;  // prefetch depth (row steps)
@@ -47,26 +34,28 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
   __shared__ T Ws[2][BP];
   __shared__ T Ys[2][NC][BP + 1];
   __shared__ T Vs[2][NC][BP + 1];
-  const int s = blockIdx.x;
-  // kernel-argument fields copied to locals (the lambdas below must not take
-  // the address of the argument block)
-  const int n2 = a.n2, b = a.b, nrhs = a.nrhs;
-  const long long ld = a.ld, ldo = a.ldo;
-  const double* __restrict__ wh = a.wh;
-  const double* __restrict__ wv = a.wv;
-  const double* __restrict__ rhs = a.rhs;
-  double* __restrict__ out_g = a.out;
-  T* __restrict__ xbuf = (T*)a.xb;
+  const int itm = group_item(offs, count, blockIdx.x);
+  const int bx = blockIdx.x - offs[itm];
+  const int m = P[itm].m;
+  const int s = bx % m;
+  // descriptor fields copied to locals (the lambdas below capture locals only)
+  const int n2 = P[itm].n2, b = P[itm].b, nrhs = P[itm].nrhs;
+  const long long ld = P[itm].ld, ldo = P[itm].ldo;
+  const double* __restrict__ wh = P[itm].wh;
+  const double* __restrict__ wv = P[itm].wv;
+  const double* __restrict__ rhs = P[itm].rhs;
+  double* __restrict__ out_g = P[itm].out;
+  T* __restrict__ xbuf = (T*)P[itm].xb;
   const int tid = threadIdx.x;
   const int i = tid % BP, cl = tid / BP;
-  const int c = blockIdx.y * NC + cl;
+  const int c = (bx / m) * NC + cl;
   const bool valid = c < nrhs;
   const bool act = i < b;
   const long long c0 = (long long)s * (b + 1);
   const long long ci = c0 + (act ? i : 0);
-  const T* Gl = (const T*)a.Gl + (size_t)s * n2 * BP * BP;
-  T* zbuf = (T*)a.zbuf + (size_t)s * nrhs * n2 * BP;
-  const bool acc_out = MODE == 1 && a.accumulate;
+  const T* Gl = (const T*)P[itm].Gl + (size_t)s * n2 * BP * BP;
+  T* zbuf = (T*)P[itm].zbuf + (size_t)s * nrhs * n2 * BP;
+  const bool acc_out = MODE == 1 && P[itm].accumulate;
 
   // register ring: RAW loaded operands of the next D row steps (no arithmetic on
   // them until they are parked, so the loads stay in flight across steps)
@@ -214,12 +203,24 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
 //   xb[s][0][c][r] = wL_r u_o(s-1)[c][r]   (+ wR_r u_o(s)[c][r] when b = 1)
 //   xb[s][1][c][r] = wR_r u_o(s)[c][r]
 // with wL, wR the edge weights between the slab and its two interfaces.
+// Grid-stride loop over m * nrhs * n2 entries of a problem with its own
+// workgroups of a grouped launch.
+#define SLAB_ITEM_LOOP(e, tot)                                                        \
+  const int itm = group_item(offs, count, blockIdx.x);                                \
+  const long long nwg_ = offs[itm + 1] - offs[itm];                                   \
+  const SolveDev& d = P[itm];                                                         \
+  const int n2 = d.n2, b = d.b, m = d.m, nrhs = d.nrhs;                               \
+  const long long tot = (long long)m * nrhs * n2;                                     \
+  for (long long e = (blockIdx.x - offs[itm]) * (long long)blockDim.x + threadIdx.x; \
+       e < tot; e += nwg_ * blockDim.x)
+
 template <typename T, typename TR>
-__global__ void k_coupling(int n2, int b, int m, int nrhs, const double* __restrict__ wh,
-                           const TR* __restrict__ uo, T* __restrict__ xb) {
-  const long long tot = (long long)m * nrhs * n2;
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot;
-       e += (long long)gridDim.x * blockDim.x) {
+__global__ void k_coupling(const SolveDev* __restrict__ P, const int* __restrict__ offs,
+                           int count) {
+  SLAB_ITEM_LOOP(e, tot) {
+    const double* __restrict__ wh = d.wh;
+    const TR* __restrict__ uo = (const TR*)d.ft;
+    T* __restrict__ xb = (T*)d.xb;
     const long long r = e % n2;
     const long long c = (e / n2) % nrhs;
     const long long s = e / ((long long)n2 * nrhs);
@@ -235,190 +236,255 @@ __global__ void k_coupling(int n2, int b, int m, int nrhs, const double* __restr
 // Interface values u_o(j) (reduced solution, [j][c][r]) into the natural-order
 // output column j(b+1)+b, written or added.
 template <typename TR>
-__global__ void k_interface_out(int n2, int b, int m, int nrhs, long long ldo,
-                                const TR* __restrict__ uo, double* __restrict__ out,
-                                int accumulate) {
-  const long long tot = (long long)m * nrhs * n2;
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot;
-       e += (long long)gridDim.x * blockDim.x) {
+__global__ void k_interface_out(const SolveDev* __restrict__ P, const int* __restrict__ offs,
+                                int count) {
+  SLAB_ITEM_LOOP(e, tot) {
     const long long r = e % n2;
     const long long c = (e / n2) % nrhs;
     const long long j = e / ((long long)n2 * nrhs);
-    double* o = out + c * ldo + (j * (b + 1) + b) * n2 + r;
-    const double v = (double)uo[e];
-    *o = accumulate ? *o + v : v;
+    double* o = d.out + c * d.ldo + (j * (b + 1) + b) * n2 + r;
+    const double v = (double)((const TR*)d.ft)[e];
+    *o = d.accumulate ? *o + v : v;
   }
 }
 
-// f~_j = f_o(j) + xb[j][right] + xb[j+1][left]   (FP64 sum, stored in T)
+// f~_j = f_o(j) + xb[j][right] + xb[j+1][left]   (FP64 sum, stored in TR)
 template <typename T, typename TR>
-__global__ void k_reduced_rhs(int n2, int b, int m, int nrhs, long long ld,
-                              const double* __restrict__ rhs, const T* __restrict__ xb,
-                              TR* __restrict__ ft) {
-  const long long tot = (long long)m * nrhs * n2;
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot;
-       e += (long long)gridDim.x * blockDim.x) {
+__global__ void k_reduced_rhs(const SolveDev* __restrict__ P, const int* __restrict__ offs,
+                              int count) {
+  SLAB_ITEM_LOOP(e, tot) {
+    const T* __restrict__ xb = (const T*)d.xb;
     const long long r = e % n2;
     const long long c = (e / n2) % nrhs;
     const long long j = e / ((long long)n2 * nrhs);
     const long long cj = j * (b + 1) + b;
-    double v = rhs[c * ld + cj * n2 + r];
+    double v = d.rhs[c * d.ld + cj * n2 + r];
     v += (double)xb[((j * 2 + 1) * nrhs + c) * n2 + r];
     if (j + 1 < m) v += (double)xb[(((j + 1) * 2 + 0) * nrhs + c) * n2 + r];
-    ft[e] = (TR)v;
+    ((TR*)d.ft)[e] = (TR)v;
+  }
+}
+#undef SLAB_ITEM_LOOP
+
+static long long item_wgs(long long elems) { return std::min<long long>((elems + 255) / 256, 1024); }
+
+// Reduced system T x = f~ of every problem (in place in ft): Alg. 2 with the
+// block Cholesky factors, or the odd-even order, as factored.
+template <typename TR>
+static void plan_reduced(Plan& plan, const std::vector<ReducedDev>& R, bool odd_even) {
+  auto at = [](const void* base, long long j, long long stride) {
+    return (void*)((TR*)base + j * stride);
+  };
+  auto item = [](const void* M, const void* x, const void* xin, void* y, int n, int nrhs) {
+    BmvItem b;
+    b.M = M; b.x = x; b.xin = xin; b.y = y; b.n = n; b.nrhs = nrhs;
+    return b;
+  };
+  int mmax = 0;
+  for (const ReducedDev& r : R) mmax = std::max(mmax, r.m);
+  if (!odd_even) {
+    // T = R R^T with R_jj = L_j, R_{j+1,j} = Z_j^T: forward y_j = L_j^-1 (f~_j - Z_{j-1}^T y_{j-1}),
+    // backward x_j = L_j^-T (y_j - Z_j x_{j+1}), x overwriting f~
+    for (int j = 0; j < mmax; ++j) {
+      std::vector<BmvItem> a, bb;
+      for (const ReducedDev& r : R) {
+        if (j >= r.m) continue;
+        const long long nsq = (long long)r.n * r.n, vs = (long long)r.nrhs * r.n;
+        const void* src = at(r.ft, j, vs);
+        if (j > 0) {
+          a.push_back(item(at(r.Z, j - 1, nsq), at(r.yt, j - 1, vs), at(r.ft, j, vs), r.tt, r.n,
+                           r.nrhs));
+          src = r.tt;
+        }
+        bb.push_back(item(at(r.Linv, j, nsq), src, nullptr, at(r.yt, j, vs), r.n, r.nrhs));
+      }
+      plan_gemv<TR>(plan, true, false, a, (TR)-1, (TR)1);
+      plan_gemv<TR>(plan, false, true, bb, (TR)1, (TR)0);
+    }
+    for (int j = mmax - 1; j >= 0; --j) {
+      std::vector<BmvItem> a, bb;
+      for (const ReducedDev& r : R) {
+        if (j >= r.m) continue;
+        const long long nsq = (long long)r.n * r.n, vs = (long long)r.nrhs * r.n;
+        const void* src = at(r.yt, j, vs);
+        if (j < r.m - 1) {
+          a.push_back(item(at(r.Z, j, nsq), at(r.ft, j + 1, vs), at(r.yt, j, vs), r.tt, r.n,
+                           r.nrhs));
+          src = r.tt;
+        }
+        bb.push_back(item(at(r.Linv, j, nsq), src, nullptr, at(r.ft, j, vs), r.n, r.nrhs));
+      }
+      plan_gemv<TR>(plan, false, false, a, (TR)-1, (TR)1);
+      plan_gemv<TR>(plan, true, true, bb, (TR)1, (TR)0);
+    }
+    return;
+  }
+  // odd-even order (levels as in the factorization): reduce the right-hand
+  // side level by level, y_e = L_e^-1 g_e, g_l -= U_e^T y_e, g_r -= V_e^T y_e;
+  // then from the top level down x_e = L_e^-T (y_e - U_e x_l - V_e x_r),
+  // x_e overwriting g_e.
+  std::vector<long long> strides;
+  for (long long s = 1; s <= mmax; s *= 2) strides.push_back(s);
+  for (int pass = 0; pass < 2; ++pass) {
+    for (size_t li = 0; li < strides.size(); ++li) {
+      const long long s = pass == 0 ? strides[li] : strides[strides.size() - 1 - li];
+      std::vector<BmvItem> a, bb, cc;
+      for (const ReducedDev& r : R) {
+        const int k = (int)(r.m / s);
+        if (k < 1) continue;
+        const int E = (k + 1) / 2, NR = k / 2;
+        const long long nsq = (long long)r.n * r.n, vs = (long long)r.nrhs * r.n;
+        for (int q = 0; q < E; ++q) {
+          const long long e = (2 * q + 1) * s - 1;
+          if (pass == 0) {
+            a.push_back(item(at(r.Linv, e, nsq), at(r.ft, e, vs), nullptr, at(r.yt, e, vs), r.n,
+                             r.nrhs));
+            if (q < NR)
+              bb.push_back(item(at(r.Z, e, nsq), at(r.yt, e, vs), at(r.ft, e + s, vs),
+                                at(r.ft, e + s, vs), r.n, r.nrhs));
+            if (q >= 1)
+              cc.push_back(item(at(r.Td, e, nsq), at(r.yt, e, vs), at(r.ft, e - s, vs),
+                                at(r.ft, e - s, vs), r.n, r.nrhs));
+          } else {
+            if (q < NR)
+              a.push_back(item(at(r.Z, e, nsq), at(r.ft, e + s, vs), at(r.yt, e, vs),
+                               at(r.yt, e, vs), r.n, r.nrhs));
+            if (q >= 1)
+              bb.push_back(item(at(r.Td, e, nsq), at(r.ft, e - s, vs), at(r.yt, e, vs),
+                                at(r.yt, e, vs), r.n, r.nrhs));
+            cc.push_back(item(at(r.Linv, e, nsq), at(r.yt, e, vs), nullptr, at(r.ft, e, vs), r.n,
+                              r.nrhs));
+          }
+        }
+      }
+      if (pass == 0) {
+        plan_gemv<TR>(plan, false, true, a, (TR)1, (TR)0);    // y_e = L^-1 g_e
+        plan_gemv<TR>(plan, true, false, bb, (TR)-1, (TR)1);  // g_r -= V^T y_e
+        plan_gemv<TR>(plan, true, false, cc, (TR)-1, (TR)1);  // g_l -= U^T y_e
+      } else {
+        plan_gemv<TR>(plan, false, false, a, (TR)-1, (TR)1);  // y_e -= V x_r
+        plan_gemv<TR>(plan, false, false, bb, (TR)-1, (TR)1); // y_e -= U x_l
+        plan_gemv<TR>(plan, true, true, cc, (TR)1, (TR)0);    // x_e = L^-T y_e
+      }
+    }
   }
 }
 
 template <typename T, typename TR, int BP>
-static int sweeps_bp(const SolveArgs& A, const double* rhs, long long ld_rhs, double* out,
-                     long long ld_out, int accumulate, hipStream_t st) {
-  SweepArgs s;
-  s.n1 = A.n1; s.n2 = A.n2; s.b = A.b; s.m = A.m; s.nrhs = A.nrhs; s.ld = ld_rhs; s.ldo = ld_out;
-  s.wh = A.wh; s.wv = A.wv; s.Gl = A.Gl; s.zbuf = A.zbuf; s.xb = A.xb;
-  s.uo = A.ft; s.rhs = rhs; s.out = out; s.accumulate = accumulate;
-  const int n = A.n2, m = A.m, nrhs = A.nrhs;
-  const long long nsq = (long long)n * n;
-  dim3 grid(m, (nrhs + 256 / BP - 1) / (256 / BP));
-  // (i) reduced right-hand side
-  if (A.transpose) hipLaunchKernelGGL((k_sweep<T, TR, BP, true, 0>), grid, dim3(256), 0, st, s);
-  else hipLaunchKernelGGL((k_sweep<T, TR, BP, false, 0>), grid, dim3(256), 0, st, s);
-  SLAB_LAUNCH_CHECK();
-  {
-    long long tot = (long long)m * nrhs * n;
-    unsigned g = (unsigned)std::min<long long>((tot + 255) / 256, 16384);
-    hipLaunchKernelGGL((k_reduced_rhs<T, TR>), dim3(g), dim3(256), 0, st, n, A.b, m, nrhs, ld_rhs,
-                       rhs, (const T*)A.xb, (TR*)A.ft);
+static void plan_sweep(Plan& plan, const std::vector<SolveDev>& probs, size_t pd, bool trans,
+                       int mode) {
+  constexpr int NC = 256 / BP;
+  std::vector<int> c;
+  for (const SolveDev& d : probs) c.push_back(d.m * ((d.nrhs + NC - 1) / NC));
+  long long tot;
+  const size_t oo = plan.add_offsets(c, &tot);
+  const int count = (int)probs.size();
+  plan.step([=](const char* dev, hipStream_t st) {
+    const SolveDev* P = dev_at<SolveDev>(dev, pd);
+    const int* of = dev_at<int>(dev, oo);
+    if (mode == 0) {
+      if (trans) hipLaunchKernelGGL((k_sweep<T, TR, BP, true, 0>), dim3((unsigned)tot), dim3(256), 0, st, P, of, count);
+      else hipLaunchKernelGGL((k_sweep<T, TR, BP, false, 0>), dim3((unsigned)tot), dim3(256), 0, st, P, of, count);
+    } else {
+      if (trans) hipLaunchKernelGGL((k_sweep<T, TR, BP, true, 1>), dim3((unsigned)tot), dim3(256), 0, st, P, of, count);
+      else hipLaunchKernelGGL((k_sweep<T, TR, BP, false, 1>), dim3((unsigned)tot), dim3(256), 0, st, P, of, count);
+    }
     SLAB_LAUNCH_CHECK();
-  }
-  // (ii) the reduced system
-  TR* ft = (TR*)A.ft;
-  TR* yt = (TR*)A.yt;
-  TR* tt = (TR*)A.tt;
-  const TR* Li = (const TR*)A.Linv;
-  const TR* Z = (const TR*)A.Z;
-  const TR* U = (const TR*)A.Td;
-  const long long vs = (long long)nrhs * n;
-  if (!A.odd_even) {
-    // Alg. 2 with the block Cholesky factors: T = R R^T, R_jj = L_j, R_{j+1,j} = Z_j^T
-    for (int j = 0; j < m; ++j) {
-      const TR* src = ft + j * vs;
-      if (j > 0) {
-        int rc = launch_gemv<TR>(true, false, n, nrhs, (TR)-1, Z + (j - 1) * nsq, 0,
-                                 yt + (j - 1) * vs, 0, (TR)1, ft + j * vs, 0, tt, 0, 1, st);
-        if (rc) return rc;
-        src = tt;
-      }
-      int rc = launch_gemv<TR>(false, true, n, nrhs, (TR)1, Li + j * nsq, 0, src, 0, (TR)0,
-                               nullptr, 0, yt + j * vs, 0, 1, st);
-      if (rc) return rc;
-    }
-    for (int j = m - 1; j >= 0; --j) {
-      const TR* src = yt + j * vs;
-      if (j < m - 1) {
-        int rc = launch_gemv<TR>(false, false, n, nrhs, (TR)-1, Z + j * nsq, 0, ft + (j + 1) * vs,
-                                 0, (TR)1, yt + j * vs, 0, tt, 0, 1, st);
-        if (rc) return rc;
-        src = tt;
-      }
-      int rc = launch_gemv<TR>(true, true, n, nrhs, (TR)1, Li + j * nsq, 0, src, 0, (TR)0,
-                               nullptr, 0, ft + j * vs, 0, 1, st);
-      if (rc) return rc;
-    }
-  } else {
-    // odd-even order (same levels as the factorization): reduce the
-    // right-hand side level by level, y_e = L_e^-1 g_e, g_l -= U_e^T y_e,
-    // g_r -= V_e^T y_e; then from the top level down
-    // x_e = L_e^-T (y_e - U_e x_l - V_e x_r), x_e overwriting g_e.
-    int nlev = 0;
-    for (long long s = 1; m / s >= 1; s *= 2) ++nlev;
-    for (int lev = 0; lev < nlev; ++lev) {
-      const long long s = 1LL << lev;
-      const int k = (int)(m / s), E = (k + 1) / 2, NR = k / 2;
-      const long long e0 = s - 1, e1 = e0 + 2 * s, ms = 2 * s * nsq, v2 = 2 * s * vs;
-      int rc = launch_gemv<TR>(false, true, n, nrhs, (TR)1, Li + e0 * nsq, ms, ft + e0 * vs, v2,
-                               (TR)0, nullptr, 0, yt + e0 * vs, v2, E, st);
-      if (rc) return rc;
-      rc = launch_gemv<TR>(true, false, n, nrhs, (TR)-1, Z + e0 * nsq, ms, yt + e0 * vs, v2, (TR)1,
-                           ft + (e0 + s) * vs, v2, ft + (e0 + s) * vs, v2, NR, st);
-      if (rc) return rc;
-      rc = launch_gemv<TR>(true, false, n, nrhs, (TR)-1, U + e1 * nsq, ms, yt + e1 * vs, v2, (TR)1,
-                           ft + (e1 - s) * vs, v2, ft + (e1 - s) * vs, v2, E - 1, st);
-      if (rc) return rc;
-    }
-    for (int lev = nlev - 1; lev >= 0; --lev) {
-      const long long s = 1LL << lev;
-      const int k = (int)(m / s), E = (k + 1) / 2, NR = k / 2;
-      const long long e0 = s - 1, e1 = e0 + 2 * s, ms = 2 * s * nsq, v2 = 2 * s * vs;
-      int rc = launch_gemv<TR>(false, false, n, nrhs, (TR)-1, Z + e0 * nsq, ms, ft + (e0 + s) * vs,
-                               v2, (TR)1, yt + e0 * vs, v2, yt + e0 * vs, v2, NR, st);
-      if (rc) return rc;
-      rc = launch_gemv<TR>(false, false, n, nrhs, (TR)-1, U + e1 * nsq, ms, ft + (e1 - s) * vs, v2,
-                           (TR)1, yt + e1 * vs, v2, yt + e1 * vs, v2, E - 1, st);
-      if (rc) return rc;
-      rc = launch_gemv<TR>(true, true, n, nrhs, (TR)1, Li + e0 * nsq, ms, yt + e0 * vs, v2, (TR)0,
-                           nullptr, 0, ft + e0 * vs, v2, E, st);
-      if (rc) return rc;
-    }
-  }
-  // (iii) interior back substitution, and the interface values
-  {
-    long long tot = (long long)m * nrhs * n;
-    unsigned g = (unsigned)std::min<long long>((tot + 255) / 256, 16384);
-    hipLaunchKernelGGL((k_coupling<T, TR>), dim3(g), dim3(256), 0, st, n, A.b, m, nrhs, A.wh,
-                       (const TR*)A.ft, (T*)A.xb);
-    SLAB_LAUNCH_CHECK();
-  }
-  if (A.transpose) hipLaunchKernelGGL((k_sweep<T, TR, BP, true, 1>), grid, dim3(256), 0, st, s);
-  else hipLaunchKernelGGL((k_sweep<T, TR, BP, false, 1>), grid, dim3(256), 0, st, s);
-  SLAB_LAUNCH_CHECK();
-  {
-    long long tot = (long long)m * nrhs * n;
-    unsigned g = (unsigned)std::min<long long>((tot + 255) / 256, 16384);
-    hipLaunchKernelGGL((k_interface_out<TR>), dim3(g), dim3(256), 0, st, n, A.b, m, nrhs, ld_out,
-                       (const TR*)A.ft, out, accumulate);
-    SLAB_LAUNCH_CHECK();
-  }
-  return SLAB_OK;
+    return SLAB_OK;
+  });
 }
 
 template <typename T, typename TR>
-int launch_solve_pass(const SolveArgs& a, const double* rhs, long long ld_rhs, double* out,
-                      long long ld_out, int accumulate, hipStream_t st) {
-  switch (padded_block(a.b)) {
-    case 16: return sweeps_bp<T, TR, 16>(a, rhs, ld_rhs, out, ld_out, accumulate, st);
-    case 32: return sweeps_bp<T, TR, 32>(a, rhs, ld_rhs, out, ld_out, accumulate, st);
-    default: return sweeps_bp<T, TR, 64>(a, rhs, ld_rhs, out, ld_out, accumulate, st);
+void plan_solve_pass(Plan& plan, const std::vector<SolveDev>& probs,
+                     const std::vector<ReducedDev>& red, bool trans, bool odd_even) {
+  if (probs.empty()) return;
+  // problems split by padded block order for the sweeps
+  std::vector<SolveDev> cls[3];
+  for (const SolveDev& d : probs) {
+    const int bp = padded_block(d.b);
+    cls[bp == 16 ? 0 : (bp == 32 ? 1 : 2)].push_back(d);
   }
+  size_t pcls[3] = {0, 0, 0};
+  for (int k = 0; k < 3; ++k)
+    if (!cls[k].empty()) pcls[k] = plan.add_vec(cls[k]);
+  const size_t pall = plan.add_vec(probs);
+  const int count = (int)probs.size();
+  std::vector<int> cw;
+  for (const SolveDev& d : probs) cw.push_back((int)item_wgs((long long)d.m * d.nrhs * d.n2));
+  long long tw;
+  const size_t ow = plan.add_offsets(cw, &tw);
+  auto sweeps = [&](int mode) {
+    for (int k = 0; k < 3; ++k) {
+      if (cls[k].empty()) continue;
+      if (k == 0) plan_sweep<T, TR, 16>(plan, cls[k], pcls[k], trans, mode);
+      else if (k == 1) plan_sweep<T, TR, 32>(plan, cls[k], pcls[k], trans, mode);
+      else plan_sweep<T, TR, 64>(plan, cls[k], pcls[k], trans, mode);
+    }
+  };
+  // (i) reduced right-hand side
+  sweeps(0);
+  plan.step([=](const char* dev, hipStream_t st) {
+    hipLaunchKernelGGL((k_reduced_rhs<T, TR>), dim3((unsigned)tw), dim3(256), 0, st,
+                       dev_at<SolveDev>(dev, pall), dev_at<int>(dev, ow), count);
+    SLAB_LAUNCH_CHECK();
+    return SLAB_OK;
+  });
+  // (ii) the reduced system
+  plan_reduced<TR>(plan, red, odd_even);
+  // (iii) interior back substitution, and the interface values
+  plan.step([=](const char* dev, hipStream_t st) {
+    hipLaunchKernelGGL((k_coupling<T, TR>), dim3((unsigned)tw), dim3(256), 0, st,
+                       dev_at<SolveDev>(dev, pall), dev_at<int>(dev, ow), count);
+    SLAB_LAUNCH_CHECK();
+    return SLAB_OK;
+  });
+  sweeps(1);
+  plan.step([=](const char* dev, hipStream_t st) {
+    hipLaunchKernelGGL((k_interface_out<TR>), dim3((unsigned)tw), dim3(256), 0, st,
+                       dev_at<SolveDev>(dev, pall), dev_at<int>(dev, ow), count);
+    SLAB_LAUNCH_CHECK();
+    return SLAB_OK;
+  });
 }
-template int launch_solve_pass<float, float>(const SolveArgs&, const double*, long long, double*,
-                                             long long, int, hipStream_t);
-template int launch_solve_pass<double, double>(const SolveArgs&, const double*, long long,
-                                               double*, long long, int, hipStream_t);
-template int launch_solve_pass<double, float>(const SolveArgs&, const double*, long long,
-                                              double*, long long, int, hipStream_t);
+template void plan_solve_pass<float, float>(Plan&, const std::vector<SolveDev>&,
+                                            const std::vector<ReducedDev>&, bool, bool);
+template void plan_solve_pass<double, double>(Plan&, const std::vector<SolveDev>&,
+                                              const std::vector<ReducedDev>&, bool, bool);
+template void plan_solve_pass<double, float>(Plan&, const std::vector<SolveDev>&,
+                                             const std::vector<ReducedDev>&, bool, bool);
 
 // ---------------------------------------------------------------------------
 // Residual r = f - A u (FP64) with per-column partial sums of r^2 and f^2.
-// Grid: (chunks, nrhs); partial[(c*chunks + blk)*2 + {0,1}].
+// Per problem: chunks x nrhs workgroups, partial[(c*chunks + blk)*2 + {0,1}],
+// then norms[2c] = sum r^2, norms[2c+1] = sum f^2.
 // ---------------------------------------------------------------------------
 constexpr int RES_CHUNKS = 256;
 
 size_t residual_partial_count(int n1, int n2, int nrhs) { return (size_t)nrhs * RES_CHUNKS * 2; }
 
-__global__ __launch_bounds__(256) void k_residual(int n1, int n2, long long ld,
-                                                  const double* __restrict__ wh,
-                                                  const double* __restrict__ wv,
-                                                  const double* __restrict__ f,
-                                                  const double* __restrict__ u,
-                                                  double* __restrict__ r, long long ldr,
-                                                  double* __restrict__ partial) {
-  __shared__ double red[2][256];
-  const int c = blockIdx.y;
+__host__ __device__ inline int res_chunks(int n1, int n2) {
   const long long N = (long long)n1 * n2;
-  const double* fc = f + c * ld;
-  const double* uc = u + c * ld;
+  const long long c = (N + 255) / 256;
+  return (int)(c < RES_CHUNKS ? c : RES_CHUNKS);
+}
+
+__global__ __launch_bounds__(256) void k_residual(const SolveDev* __restrict__ P,
+                                                  const int* __restrict__ offs, int count) {
+  __shared__ double red[2][256];
+  const int itm = group_item(offs, count, blockIdx.x);
+  const int bx = blockIdx.x - offs[itm];
+  const int n1 = P[itm].n1, n2 = P[itm].n2;
+  const int chunks = res_chunks(n1, n2);
+  const int c = bx / chunks, blk = bx % chunks;
+  const long long ld = P[itm].ldf;
+  const double* __restrict__ wh = P[itm].wh;
+  const double* __restrict__ wv = P[itm].wv;
+  const long long N = (long long)n1 * n2;
+  const double* fc = P[itm].f + c * ld;
+  const double* uc = P[itm].u + c * ld;
+  double* r = P[itm].r;
   double sr = 0.0, sf = 0.0;
-  for (long long p = blockIdx.x * 256LL + threadIdx.x; p < N; p += (long long)gridDim.x * 256) {
+  for (long long p = blk * 256LL + threadIdx.x; p < N; p += (long long)chunks * 256) {
     const long long col = p / n2, row = p % n2;
     const double w_l = wh[col * n2 + row], w_r = wh[(col + 1) * n2 + row];
     const double w_d = wv[col * (n2 + 1) + row], w_u = wv[col * (n2 + 1) + row + 1];
@@ -430,7 +496,7 @@ __global__ __launch_bounds__(256) void k_residual(int n1, int n2, long long ld,
     if (row < n2 - 1) au -= w_u * uc[p + 1];
     const double fv = fc[p];
     const double rv = fv - au;
-    if (r) r[c * ldr + p] = rv;
+    if (r) r[c * N + p] = rv;
     sr += rv * rv;
     sf += fv * fv;
   }
@@ -445,36 +511,50 @@ __global__ __launch_bounds__(256) void k_residual(int n1, int n2, long long ld,
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    partial[((long long)c * gridDim.x + blockIdx.x) * 2 + 0] = red[0][0];
-    partial[((long long)c * gridDim.x + blockIdx.x) * 2 + 1] = red[1][0];
+    double* partial = P[itm].partial;
+    partial[((long long)c * chunks + blk) * 2 + 0] = red[0][0];
+    partial[((long long)c * chunks + blk) * 2 + 1] = red[1][0];
   }
 }
 
-__global__ void k_norms(int nrhs, int chunks, const double* __restrict__ partial,
-                        double* __restrict__ norms) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_norms(const SolveDev* __restrict__ P, const int* __restrict__ offs, int count) {
+  const int itm = group_item(offs, count, blockIdx.x);
+  const int c = (blockIdx.x - offs[itm]) * blockDim.x + threadIdx.x;
+  const int nrhs = P[itm].nrhs;
   if (c >= nrhs) return;
+  const int chunks = res_chunks(P[itm].n1, P[itm].n2);
+  const double* __restrict__ partial = P[itm].partial;
   double sr = 0.0, sf = 0.0;
   for (int k = 0; k < chunks; ++k) {
     sr += partial[((long long)c * chunks + k) * 2 + 0];
     sf += partial[((long long)c * chunks + k) * 2 + 1];
   }
-  norms[2 * c + 0] = sr;
-  norms[2 * c + 1] = sf;
+  P[itm].norms[2 * c + 0] = sr;
+  P[itm].norms[2 * c + 1] = sf;
 }
 
-int launch_residual(int n1, int n2, int nrhs, long long ld, const double* wh, const double* wv,
-                    const double* f, const double* u, double* r, long long ldr, double* norms,
-                    double* partial, hipStream_t st) {
-  const long long N = (long long)n1 * n2;
-  const int chunks = (int)std::min<long long>(RES_CHUNKS, (N + 255) / 256);
-  hipLaunchKernelGGL(k_residual, dim3(chunks, nrhs), dim3(256), 0, st, n1, n2, ld, wh, wv, f, u, r,
-                     ldr, partial);
-  SLAB_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_norms, dim3((nrhs + 63) / 64), dim3(64), 0, st, nrhs, chunks, partial,
-                     norms);
-  SLAB_LAUNCH_CHECK();
-  return SLAB_OK;
+// r = f - A u and the norms of every problem (r of problem i: nrhs x n1 n2,
+// leading dimension n1 n2; r may be null).
+void plan_residual(Plan& plan, const std::vector<SolveDev>& probs) {
+  if (probs.empty()) return;
+  std::vector<int> c1, c2;
+  for (const SolveDev& d : probs) {
+    c1.push_back(res_chunks(d.n1, d.n2) * d.nrhs);
+    c2.push_back((d.nrhs + 63) / 64);
+  }
+  long long t1, t2;
+  const size_t pd = plan.add_vec(probs);
+  const size_t o1 = plan.add_offsets(c1, &t1), o2 = plan.add_offsets(c2, &t2);
+  const int count = (int)probs.size();
+  plan.step([=](const char* dev, hipStream_t st) {
+    hipLaunchKernelGGL(k_residual, dim3((unsigned)t1), dim3(256), 0, st,
+                       dev_at<SolveDev>(dev, pd), dev_at<int>(dev, o1), count);
+    SLAB_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_norms, dim3((unsigned)t2), dim3(64), 0, st, dev_at<SolveDev>(dev, pd),
+                       dev_at<int>(dev, o2), count);
+    SLAB_LAUNCH_CHECK();
+    return SLAB_OK;
+  });
 }
 
 // ---------------------------------------------------------------------------

@@ -11,29 +11,44 @@ namespace slab {
 // ---------------------------------------------------------------------------
 // Coefficient field: copy (or exponentiate theta) and check positivity.
 // status[0] is set to 1 when some kappa is not > 0 or not finite.
+// Grouped: each problem owns a fixed number of workgroups and strides over
+// its (n1+2)(n2+2) nodes with them.
 // ---------------------------------------------------------------------------
-__global__ void k_coef(const double* __restrict__ coef, long long count, int is_log,
-                       double* __restrict__ kappa, int* __restrict__ status) {
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count;
-       i += (long long)gridDim.x * blockDim.x) {
-    double v = coef[i];
-    double k = is_log ? exp(v) : v;
-    if (!(k > 0.0) || !isfinite(k)) status[0] = 1;
+__global__ void k_coef(const ProbDev* __restrict__ P, const int* __restrict__ offs, int count) {
+  const int it = group_item(offs, count, blockIdx.x);
+  const ProbDev& d = P[it];
+  const long long nwg = offs[it + 1] - offs[it];
+  const long long tot = (long long)(d.n1 + 2) * (d.n2 + 2);
+  const double* coef = d.coef;
+  double* kappa = d.kappa;
+  bool bad = false;
+  for (long long i = (blockIdx.x - offs[it]) * (long long)blockDim.x + threadIdx.x; i < tot;
+       i += nwg * blockDim.x) {
+    const double v = coef[i];
+    const double k = d.is_log ? exp(v) : v;
+    if (!(k > 0.0) || !isfinite(k)) bad = true;
     kappa[i] = k;
   }
+  if (bad) d.status[0] = 1;
 }
 
 // Edge weights w = (kappa_p + kappa_q) / (2 h^2) of the 5-point stencil.
 // wh[c*n2 + r], c = 0..n1: edge (c-1, r)-(c, r); wv[c*(n2+1) + r], r = 0..n2:
 // edge (c, r-1)-(c, r).  Columns/rows -1 and n1/n2 are the Dirichlet ring.
-__global__ void k_weights(const double* __restrict__ kappa, int n1, int n2, double h,
-                          double* __restrict__ wh, double* __restrict__ wv) {
+__global__ void k_weights(const ProbDev* __restrict__ P, const int* __restrict__ offs, int count) {
+  const int it = group_item(offs, count, blockIdx.x);
+  const ProbDev& d = P[it];
+  const long long nwg = offs[it + 1] - offs[it];
+  const int n1 = d.n1, n2 = d.n2;
   const long long nh = (long long)(n1 + 1) * n2;
   const long long nv = (long long)n1 * (n2 + 1);
   const long long ld = n2 + 2;
-  const double hh = h * h;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < nh + nv;
-       i += (long long)gridDim.x * blockDim.x) {
+  const double hh = d.h * d.h;
+  const double* kappa = d.kappa;
+  double* wh = d.wh;
+  double* wv = d.wv;
+  for (long long i = (blockIdx.x - offs[it]) * (long long)blockDim.x + threadIdx.x; i < nh + nv;
+       i += nwg * blockDim.x) {
     if (i < nh) {
       long long c = i / n2, r = i % n2;  // edge between ring-padded columns c and c+1
       wh[i] = 0.5 * (kappa[c * ld + r + 1] + kappa[(c + 1) * ld + r + 1]) / hh;
@@ -43,19 +58,6 @@ __global__ void k_weights(const double* __restrict__ kappa, int n1, int n2, doub
       wv[j] = 0.5 * (kappa[(c + 1) * ld + r] + kappa[(c + 1) * ld + r + 1]) / hh;
     }
   }
-}
-
-int launch_coef_weights(const double* coef, int is_log, int n1, int n2, double h, double* kappa,
-                        double* wh, double* wv, int* status, hipStream_t st) {
-  long long count = (long long)(n1 + 2) * (n2 + 2);
-  unsigned grid = (unsigned)std::min<long long>((count + 255) / 256, 65536);
-  hipLaunchKernelGGL(k_coef, dim3(grid), dim3(256), 0, st, coef, count, is_log, kappa, status);
-  SLAB_LAUNCH_CHECK();
-  long long tot = (long long)(n1 + 1) * n2 + (long long)n1 * (n2 + 1);
-  grid = (unsigned)std::min<long long>((tot + 255) / 256, 65536);
-  hipLaunchKernelGGL(k_weights, dim3(grid), dim3(256), 0, st, kappa, n1, n2, h, wh, wv);
-  SLAB_LAUNCH_CHECK();
-  return SLAB_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -159,11 +161,17 @@ __device__ __forceinline__ bool sweep_inverse(T (&a)[BP], T (*colbuf)[BP], int l
 // order (Schur propagation).  One wave per (slab, direction).
 // ---------------------------------------------------------------------------
 template <typename T, int BP>
-__global__ __launch_bounds__(64) void k_slab_factor(const double* __restrict__ wh,
-                                                    const double* __restrict__ wv, int n2, int b,
-                                                    T* __restrict__ Gl, T* __restrict__ Hsw,
-                                                    int* __restrict__ status) {
-  const int s = blockIdx.x >> 1, dir = blockIdx.x & 1;
+__global__ __launch_bounds__(64) void k_slab_factor(const ProbDev* __restrict__ P,
+                                                    const int* __restrict__ offs, int count) {
+  const int it = group_item(offs, count, blockIdx.x);
+  const int bx = blockIdx.x - offs[it];
+  const double* __restrict__ wh = P[it].wh;
+  const double* __restrict__ wv = P[it].wv;
+  const int n2 = P[it].n2, b = P[it].b;
+  T* __restrict__ Gl = (T*)P[it].Gl;
+  T* __restrict__ Hsw = (T*)P[it].Hsw;
+  int* __restrict__ status = P[it].status;
+  const int s = bx >> 1, dir = bx & 1;
   const int lane = threadIdx.x;
   const int c0 = s * (b + 1);
   const long long c = c0 + (lane < b ? lane : 0);
@@ -220,12 +228,19 @@ __global__ __launch_bounds__(64) void k_slab_factor(const double* __restrict__ w
 // Four waves per block, one (slab, rho) per wave.
 // ---------------------------------------------------------------------------
 template <typename T, int BP>
-__global__ __launch_bounds__(256) void k_sigma(const double* __restrict__ wh,
-                                               const double* __restrict__ wv, int n2, int b, int m,
-                                               const T* __restrict__ Gl, const T* __restrict__ Hsw,
-                                               T* __restrict__ sig, int* __restrict__ status) {
+__global__ __launch_bounds__(256) void k_sigma(const ProbDev* __restrict__ P,
+                                               const int* __restrict__ offs, int count) {
+  const int it = group_item(offs, count, blockIdx.x);
+  const int bx = blockIdx.x - offs[it];
+  const double* __restrict__ wh = P[it].wh;
+  const double* __restrict__ wv = P[it].wv;
+  const int n2 = P[it].n2, b = P[it].b, m = P[it].m;
+  const T* __restrict__ Gl = (const T*)P[it].Gl;
+  const T* __restrict__ Hsw = (const T*)P[it].Hsw;
+  T* __restrict__ sig = (T*)P[it].sig;
+  int* __restrict__ status = P[it].status;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const long long idx = (long long)blockIdx.x * 4 + wave;
+  const long long idx = (long long)bx * 4 + wave;
   const bool valid = idx < (long long)m * n2;
   const int s = valid ? (int)(idx / n2) : 0;
   const int rho = valid ? (int)(idx % n2) : 0;
@@ -290,13 +305,21 @@ __global__ __launch_bounds__(256) void k_sigma(const double* __restrict__ wh,
 //   PRL[s][r][rho] = wR_r (A_ee^-1)[(r,b-1),(rho,0)] wL_rho   (-> T_{s,s-1})
 // ---------------------------------------------------------------------------
 template <typename T, int BP>
-__global__ __launch_bounds__(256) void k_schur(const double* __restrict__ wh, int n2, int b, int m,
-                                               const T* __restrict__ Hsw, const T* __restrict__ sig,
-                                               T* __restrict__ PRR, T* __restrict__ PLL,
-                                               T* __restrict__ PLR, T* __restrict__ PRL) {
+__global__ __launch_bounds__(256) void k_schur(const ProbDev* __restrict__ P,
+                                               const int* __restrict__ offs, int count) {
   typedef typename acc4<T>::type V4;
   constexpr int NM = BP / 16, NK = BP / 4;
-  const int q = blockIdx.x / m, s = blockIdx.x % m;
+  const int it = group_item(offs, count, blockIdx.x);
+  const int bx = blockIdx.x - offs[it];
+  const double* __restrict__ wh = P[it].wh;
+  const int n2 = P[it].n2, b = P[it].b, m = P[it].m;
+  const T* __restrict__ Hsw = (const T*)P[it].Hsw;
+  const T* __restrict__ sig = (const T*)P[it].sig;
+  T* __restrict__ PRR = (T*)P[it].PRR;
+  T* __restrict__ PLL = (T*)P[it].PLL;
+  T* __restrict__ PLR = (T*)P[it].PLR;
+  T* __restrict__ PRL = (T*)P[it].PRL;
+  const int q = bx / m, s = bx % m;
   const int rho0 = q * 64;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = lane >> 4, nn = lane & 15;
@@ -406,20 +429,29 @@ __device__ __forceinline__ double diag_value(const double* __restrict__ wh,
 }
 
 template <typename T, typename TO>
-__global__ __launch_bounds__(256) void k_assemble(const double* __restrict__ wh,
-                                                  const double* __restrict__ wv, int n2, int b,
-                                                  int m, const T* __restrict__ PRR,
-                                                  const T* __restrict__ PLL,
-                                                  const T* __restrict__ PLR,
-                                                  const T* __restrict__ PRL, TO* __restrict__ Tdiag,
-                                                  TO* __restrict__ Toff, double* __restrict__ Tdiag64,
-                                                  double* __restrict__ Toff64) {
+__global__ __launch_bounds__(256) void k_assemble(const ProbDev* __restrict__ P,
+                                                  const int* __restrict__ offs, int count) {
   __shared__ double tile[32][33];
-  const int j = blockIdx.y;
-  const bool off = blockIdx.z == 1;
-  if (off && j >= m - 1) return;
+  const int it = group_item(offs, count, blockIdx.x);
+  const int bx = blockIdx.x - offs[it];
+  const double* __restrict__ wh = P[it].wh;
+  const double* __restrict__ wv = P[it].wv;
+  const int n2 = P[it].n2, b = P[it].b, m = P[it].m;
+  const T* __restrict__ PRR = (const T*)P[it].PRR;
+  const T* __restrict__ PLL = (const T*)P[it].PLL;
+  const T* __restrict__ PLR = (const T*)P[it].PLR;
+  const T* __restrict__ PRL = (const T*)P[it].PRL;
+  TO* __restrict__ Tdiag = (TO*)P[it].Td;
+  TO* __restrict__ Toff = (TO*)P[it].To;
+  double* __restrict__ Tdiag64 = P[it].T64;
+  double* __restrict__ Toff64 = P[it].O64;
+  // workgroup bx: tile (ti, tj) of block j, kind off (0: T_jj, 1: T_{j,j+1})
   const int ntl = (n2 + 31) / 32;
-  const int ti = blockIdx.x / ntl, tj = blockIdx.x % ntl;
+  const int per = ntl * ntl;
+  const int j = (bx / per) % m;
+  const bool off = bx / (per * m) == 1;
+  if (off && j >= m - 1) return;
+  const int ti = (bx % per) / ntl, tj = (bx % per) % ntl;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   const size_t nsq = (size_t)n2 * n2;
   const int s = j + 1;
@@ -458,45 +490,110 @@ __global__ __launch_bounds__(256) void k_assemble(const double* __restrict__ wh,
 }
 
 // ---------------------------------------------------------------------------
-// Launchers.
+// Launchers: record stage one of a group of problems into a plan.
 // ---------------------------------------------------------------------------
+static long long fill_wgs(long long elems) { return std::min<long long>((elems + 255) / 256, 1024); }
+
+void plan_coef_weights(Plan& plan, const std::vector<ProbDev>& probs) {
+  const size_t pd = plan.add_vec(probs);
+  std::vector<int> cc, cw;
+  for (const ProbDev& d : probs) {
+    cc.push_back((int)fill_wgs((long long)(d.n1 + 2) * (d.n2 + 2)));
+    cw.push_back((int)fill_wgs((long long)(d.n1 + 1) * d.n2 + (long long)d.n1 * (d.n2 + 1)));
+  }
+  long long tc, tw;
+  const size_t oc = plan.add_offsets(cc, &tc), ow = plan.add_offsets(cw, &tw);
+  const int count = (int)probs.size();
+  plan.step([=](const char* dev, hipStream_t st) {
+    hipLaunchKernelGGL(k_coef, dim3((unsigned)tc), dim3(256), 0, st, dev_at<ProbDev>(dev, pd),
+                       dev_at<int>(dev, oc), count);
+    SLAB_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_weights, dim3((unsigned)tw), dim3(256), 0, st, dev_at<ProbDev>(dev, pd),
+                       dev_at<int>(dev, ow), count);
+    SLAB_LAUNCH_CHECK();
+    return SLAB_OK;
+  });
+}
+
 template <typename T, typename TO, int BP>
-static int stage1_bp(const Stage1Args& A, hipStream_t st) {
-  const int m = A.m, n2 = A.n2, b = A.b;
-  hipLaunchKernelGGL((k_slab_factor<T, BP>), dim3(2 * m), dim3(64), 0, st, A.wh, A.wv, n2, b,
-                     (T*)A.Gl, (T*)A.Hsw, A.status);
-  SLAB_LAUNCH_CHECK();
-  if (A.ev[0]) SLAB_HIP_CHECK(hipEventRecord((hipEvent_t)A.ev[0], st));
-  const long long waves = (long long)m * n2;
-  hipLaunchKernelGGL((k_sigma<T, BP>), dim3(ceil_div(waves, 4)), dim3(256), 0, st, A.wh, A.wv, n2,
-                     b, m, (const T*)A.Gl, (const T*)A.Hsw, (T*)A.sig, A.status);
-  SLAB_LAUNCH_CHECK();
-  if (A.ev[1]) SLAB_HIP_CHECK(hipEventRecord((hipEvent_t)A.ev[1], st));
-  const int nchunk = (n2 + 63) / 64;
-  hipLaunchKernelGGL((k_schur<T, BP>), dim3(nchunk * m), dim3(256), 0, st, A.wh, n2, b, m,
-                     (const T*)A.Hsw, (const T*)A.sig, (T*)A.PRR, (T*)A.PLL, (T*)A.PLR,
-                     (T*)A.PRL);
-  SLAB_LAUNCH_CHECK();
-  if (A.ev[2]) SLAB_HIP_CHECK(hipEventRecord((hipEvent_t)A.ev[2], st));
-  const int ntl = (n2 + 31) / 32;
-  hipLaunchKernelGGL((k_assemble<T, TO>), dim3(ntl * ntl, m, 2), dim3(256), 0, st, A.wh, A.wv, n2,
-                     b, m, (const T*)A.PRR, (const T*)A.PLL, (const T*)A.PLR, (const T*)A.PRL,
-                     (TO*)A.Tdiag, (TO*)A.Toff, A.Tdiag64, A.Toff64);
-  SLAB_LAUNCH_CHECK();
-  if (A.ev[3]) SLAB_HIP_CHECK(hipEventRecord((hipEvent_t)A.ev[3], st));
-  return SLAB_OK;
+static void plan_stage1_bp(Plan& plan, const std::vector<ProbDev>& probs, int phase,
+                           hipEvent_t ev) {
+  const size_t pd = plan.add_vec(probs);
+  const int count = (int)probs.size();
+  std::vector<int> c;
+  long long tot = 0;
+  size_t off = 0;
+  auto counts = [&](auto f) {
+    c.clear();
+    for (const ProbDev& d : probs) c.push_back((int)f(d));
+    off = plan.add_offsets(c, &tot);
+  };
+  if (phase == 0) {
+    counts([](const ProbDev& d) { return 2LL * d.m; });
+    plan.step([=](const char* dev, hipStream_t st) {
+      hipLaunchKernelGGL((k_slab_factor<T, BP>), dim3((unsigned)tot), dim3(64), 0, st,
+                         dev_at<ProbDev>(dev, pd), dev_at<int>(dev, off), count);
+      SLAB_LAUNCH_CHECK();
+      if (ev) SLAB_HIP_CHECK(hipEventRecord(ev, st));
+      return SLAB_OK;
+    });
+  } else if (phase == 1) {
+    counts([](const ProbDev& d) { return ceil_div((long long)d.m * d.n2, 4); });
+    plan.step([=](const char* dev, hipStream_t st) {
+      hipLaunchKernelGGL((k_sigma<T, BP>), dim3((unsigned)tot), dim3(256), 0, st,
+                         dev_at<ProbDev>(dev, pd), dev_at<int>(dev, off), count);
+      SLAB_LAUNCH_CHECK();
+      if (ev) SLAB_HIP_CHECK(hipEventRecord(ev, st));
+      return SLAB_OK;
+    });
+  } else if (phase == 2) {
+    counts([](const ProbDev& d) { return (long long)((d.n2 + 63) / 64) * d.m; });
+    plan.step([=](const char* dev, hipStream_t st) {
+      hipLaunchKernelGGL((k_schur<T, BP>), dim3((unsigned)tot), dim3(256), 0, st,
+                         dev_at<ProbDev>(dev, pd), dev_at<int>(dev, off), count);
+      SLAB_LAUNCH_CHECK();
+      if (ev) SLAB_HIP_CHECK(hipEventRecord(ev, st));
+      return SLAB_OK;
+    });
+  } else {
+    counts([](const ProbDev& d) {
+      const long long ntl = (d.n2 + 31) / 32;
+      return ntl * ntl * d.m * 2;
+    });
+    plan.step([=](const char* dev, hipStream_t st) {
+      hipLaunchKernelGGL((k_assemble<T, TO>), dim3((unsigned)tot), dim3(256), 0, st,
+                         dev_at<ProbDev>(dev, pd), dev_at<int>(dev, off), count);
+      SLAB_LAUNCH_CHECK();
+      if (ev) SLAB_HIP_CHECK(hipEventRecord(ev, st));
+      return SLAB_OK;
+    });
+  }
 }
 
 template <typename T, typename TO>
-int launch_stage1(const Stage1Args& A, hipStream_t st) {
-  switch (padded_block(A.b)) {
-    case 16: return stage1_bp<T, TO, 16>(A, st);
-    case 32: return stage1_bp<T, TO, 32>(A, st);
-    default: return stage1_bp<T, TO, 64>(A, st);
+void plan_stage1(Plan& plan, const std::vector<ProbDev>& probs, const hipEvent_t* ev) {
+  // one launch per phase and padded block order; the event of a phase is
+  // recorded after its last launch
+  std::vector<ProbDev> cls[3];
+  for (const ProbDev& d : probs) {
+    const int bp = padded_block(d.b);
+    cls[bp == 16 ? 0 : (bp == 32 ? 1 : 2)].push_back(d);
+  }
+  for (int phase = 0; phase < 4; ++phase) {
+    int last = -1;
+    for (int k = 0; k < 3; ++k)
+      if (!cls[k].empty()) last = k;
+    for (int k = 0; k < 3; ++k) {
+      if (cls[k].empty()) continue;
+      const hipEvent_t e = (ev && k == last) ? ev[phase] : nullptr;
+      if (k == 0) plan_stage1_bp<T, TO, 16>(plan, cls[k], phase, e);
+      else if (k == 1) plan_stage1_bp<T, TO, 32>(plan, cls[k], phase, e);
+      else plan_stage1_bp<T, TO, 64>(plan, cls[k], phase, e);
+    }
   }
 }
-template int launch_stage1<float, float>(const Stage1Args&, hipStream_t);
-template int launch_stage1<double, double>(const Stage1Args&, hipStream_t);
-template int launch_stage1<double, float>(const Stage1Args&, hipStream_t);
+template void plan_stage1<float, float>(Plan&, const std::vector<ProbDev>&, const hipEvent_t*);
+template void plan_stage1<double, double>(Plan&, const std::vector<ProbDev>&, const hipEvent_t*);
+template void plan_stage1<double, float>(Plan&, const std::vector<ProbDev>&, const hipEvent_t*);
 
 }  // namespace slab

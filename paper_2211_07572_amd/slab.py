@@ -29,6 +29,7 @@ SLAB_MIXED = 2
 SLAB_KEEP_REDUCED = 1
 SLAB_COEF_LOG = 2
 SLAB_ODD_EVEN = 4
+SLAB_GRAPH = 8
 
 _STATUS_NAMES = {0: "SLAB_OK", -1: "SLAB_E_INVALID", -2: "SLAB_E_NOMEM", -3: "SLAB_E_BREAKDOWN",
                  -4: "SLAB_E_NOCONV", -5: "SLAB_E_HIP"}
@@ -86,6 +87,14 @@ def load_library(path: str = LIB_PATH):
     L.slab_residual.argtypes = [vp, vp, vp, i32, i64, ctypes.POINTER(dp), vp]
     L.slab_export_reduced.argtypes = [vp, i32, i32, vp, vp]
     L.slab_query.argtypes = [vp, i32, ctypes.POINTER(i64)]
+    L.slab_factor_batch.argtypes = [ctypes.POINTER(slab_problem), i32, ctypes.POINTER(slab_options),
+                                    vp, ctypes.POINTER(vp), ctypes.POINTER(slab_solve_info)]
+    L.slab_solve_batch.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                   ctypes.POINTER(i32), ctypes.POINTER(i64), vp,
+                                   ctypes.POINTER(slab_solve_info)]
+    L.slab_batch_handle.argtypes = [vp, i32, ctypes.POINTER(vp)]
+    L.slab_batch_query.argtypes = [vp, i32, ctypes.POINTER(i64)]
+    L.slab_batch_free.argtypes = [vp]
     for name in header_functions():
         if name != "slab_last_error":
             getattr(L, name).restype = ctypes.c_int
@@ -114,13 +123,14 @@ def _dev_f64(t, name):
 
 
 class SlabHandle:
-    """Owns one factorization (an opaque slab_handle)."""
+    """One factorization (an opaque slab_handle); owned unless it belongs to a batch."""
 
-    def __init__(self, ptr, n2, n1, b, h, precision):
+    def __init__(self, ptr, n2, n1, b, h, precision, owned=True):
         self._ptr = ptr
         self.n2, self.n1, self.b, self.h, self.precision = n2, n1, b, h, precision
         self.m = n1 // (b + 1)
         self.last_info = slab_solve_info()
+        self._owned = owned
 
     @property
     def ptr(self):
@@ -130,7 +140,8 @@ class SlabHandle:
 
     def free(self):
         if self._ptr:
-            load_library().slab_free(self._ptr)
+            if self._owned:
+                load_library().slab_free(self._ptr)
             self._ptr = None
 
     def __del__(self):
@@ -309,3 +320,107 @@ def solve_theta(theta, f, n2: int, n1: int, b: int, h: float | None = None,
     if h is None:
         h = 1.0 / (n2 + 1)
     return _fn.apply(theta, f, n2, n1, b, h, precision, tol)
+
+
+# ---- batches -----------------------------------------------------------------
+
+class SlabBatch:
+    """Owns the factorizations of a batch of independent problems (slab_batch)."""
+
+    def __init__(self, ptr, dims, precision):
+        self._ptr = ptr
+        self.dims = list(dims)          # (n2, n1, b, h) per problem
+        self.precision = precision
+        self.last_infos = [slab_solve_info() for _ in dims]
+
+    @property
+    def ptr(self):
+        if not self._ptr:
+            raise ValueError("batch already freed")
+        return self._ptr
+
+    def __len__(self):
+        return len(self.dims)
+
+    def handle(self, i: int) -> SlabHandle:
+        """Handle of problem i (owned by the batch)."""
+        out = ctypes.c_void_p()
+        _check(load_library().slab_batch_handle(self.ptr, i, ctypes.byref(out)))
+        n2, n1, b, h = self.dims[i]
+        return SlabHandle(out, n2, n1, b, h, self.precision, owned=False)
+
+    def query(self, what: int) -> int:
+        v = ctypes.c_int64()
+        _check(load_library().slab_batch_query(self.ptr, what, ctypes.byref(v)))
+        return v.value
+
+    def phase_us(self) -> dict:
+        names = ["slab_factor", "boundary_columns", "schur", "assemble", "block_factor"]
+        return {n: self.query(10 + i) for i, n in enumerate(names)}
+
+    def free(self):
+        if self._ptr:
+            load_library().slab_batch_free(self._ptr)
+            self._ptr = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def slab_factor_batch(kappas, dims, precision: int = SLAB_FP64, tol: float = 1e-10,
+                      max_iter: int = 10, odd_even: bool = True, graph: bool = False,
+                      keep_reduced: bool = False, stream=None) -> SlabBatch:
+    """Factor independent problems together.  kappas: CUDA float64 tensors of
+    shape (n1+2, n2+2); dims: (n2, n1, b) or (n2, n1, b, h) per problem."""
+    L = load_library()
+    full = []
+    for d in dims:
+        n2, n1, b = d[:3]
+        h = d[3] if len(d) > 3 else 1.0 / (n2 + 1)
+        full.append((int(n2), int(n1), int(b), float(h)))
+    if len(kappas) != len(full):
+        raise ValueError("one coefficient field per problem")
+    arr = (slab_problem * len(full))()
+    for i, ((n2, n1, b, h), k) in enumerate(zip(full, kappas)):
+        if tuple(k.shape) != (n1 + 2, n2 + 2):
+            raise ValueError(f"kappa {i} must have shape {(n1 + 2, n2 + 2)}")
+        arr[i] = slab_problem(n1, n2, b, h, _dev_f64(k, f"kappa[{i}]"))
+    flags = ((SLAB_ODD_EVEN if odd_even else 0) | (SLAB_GRAPH if graph else 0)
+             | (SLAB_KEEP_REDUCED if keep_reduced else 0))
+    opts = slab_options(precision, float(tol), int(max_iter), flags)
+    infos = (slab_solve_info * len(full))()
+    out = ctypes.c_void_p()
+    _check(L.slab_factor_batch(arr, len(full), ctypes.byref(opts), _stream_ptr(stream),
+                               ctypes.byref(out), infos))
+    return SlabBatch(out, full, precision)
+
+
+def slab_solve_batch(batch: SlabBatch, fs, outs=None, stream=None, check=True):
+    """Solve every problem of the batch: fs[i] of shape (nrhs_i, n1_i, n2_i)
+    (or (n1_i, n2_i)), CUDA float64.  Returns the list of solutions."""
+    import torch
+    L = load_library()
+    cnt = len(batch)
+    if len(fs) != cnt:
+        raise ValueError("one right-hand side block per problem")
+    f3, us = [], []
+    for i, f in enumerate(fs):
+        n2, n1 = batch.dims[i][0], batch.dims[i][1]
+        t = _vec_shape(f, n2, n1)
+        if not t.is_contiguous():
+            t = t.contiguous()
+        f3.append(t)
+        us.append(torch.empty_like(t) if outs is None else _vec_shape(outs[i], n2, n1))
+    fp = (ctypes.c_void_p * cnt)(*[_dev_f64(t, f"f[{i}]").value for i, t in enumerate(f3)])
+    up = (ctypes.c_void_p * cnt)(*[_dev_f64(t, f"u[{i}]").value for i, t in enumerate(us)])
+    nr = (ctypes.c_int32 * cnt)(*[t.shape[0] for t in f3])
+    ld = (ctypes.c_int64 * cnt)(*[batch.dims[i][0] * batch.dims[i][1] for i in range(cnt)])
+    infos = (slab_solve_info * cnt)()
+    rc = L.slab_solve_batch(batch.ptr, fp, up, nr, ld, _stream_ptr(stream), infos)
+    batch.last_infos = list(infos)
+    if check:
+        _check(rc)
+    return [u.view(f.shape) if f.dim() == 2 else u for u, f in zip(us, fs)]

@@ -258,3 +258,86 @@ def test_many_rhs_column_groups(order):
     u = S.slab_solve(h, _dev(f)).cpu().numpy()
     assert _col_rel(u, O.solve(O.factor(prob), f)).max() <= 1e-12
     h.free()
+
+
+# ---------------------------------------------------- batches of uneven problems
+
+BATCH_DIMS = [(40, 48, 7, 2), (70, 96, 15, 1), (130, 128, 31, 3), (33, 24, 1, 4), (64, 64, 7, 5),
+              (5, 4, 3, 1), (96, 160, 15, 2)]
+
+
+def _batch_inputs(dims, seed0):
+    kaps = [G.kappa_lognormal(n2, n1, seed0 + i) for i, (n2, n1, b, _) in enumerate(dims)]
+    fs = [G.rhs_uniform(n2, n1, nr, seed0 + 50 + i) for i, (n2, n1, b, nr) in enumerate(dims)]
+    return kaps, fs
+
+
+@pytest.mark.parametrize("order", ORDERS)
+def test_batch_fp64_matches_oracle(order):
+    """Uneven problems (three padded block orders, 1-5 right-hand sides) factored
+    and solved as one batch equal the oracle problem by problem."""
+    kaps, fs = _batch_inputs(BATCH_DIMS, 20)
+    bt = S.slab_factor_batch([_dev(k) for k in kaps], [d[:3] for d in BATCH_DIMS],
+                             precision=S.SLAB_FP64, odd_even=order == "odd_even",
+                             keep_reduced=True)
+    us = S.slab_solve_batch(bt, [_dev(f) for f in fs])
+    for i, (n2, n1, b, nr) in enumerate(BATCH_DIMS):
+        print(f"batch problem {i}: n2={n2} n1={n1} b={b} nrhs={nr}", flush=True)
+        prob = O.make_problem(kaps[i], n2, n1, b)
+        fac = O.factor(prob, order=order)
+        assert _col_rel(us[i].cpu().numpy(), O.solve(fac, fs[i])).max() <= 1e-12, i
+        h = bt.handle(i)
+        for j in range(prob.m):
+            Sj = S.slab_export_reduced(h, 2, j).cpu().numpy()
+            assert _rel_fro(Sj, _pivot(fac, j)) <= 1e-12, (i, j)
+    bt.free()
+
+
+@pytest.mark.parametrize("precision", [S.SLAB_FP32_REFINE, S.SLAB_MIXED])
+def test_batch_refinement(precision):
+    kaps, fs = _batch_inputs(BATCH_DIMS, 40)
+    bt = S.slab_factor_batch([_dev(k) for k in kaps], [d[:3] for d in BATCH_DIMS],
+                             precision=precision, tol=1e-10)
+    us = S.slab_solve_batch(bt, [_dev(f) for f in fs])
+    for i, (n2, n1, b, nr) in enumerate(BATCH_DIMS):
+        prob = O.make_problem(kaps[i], n2, n1, b)
+        rr = O.relres(prob, us[i].cpu().numpy(), fs[i])
+        assert rr.max() <= 1e-10, (i, rr)
+        assert 1 <= bt.last_infos[i].iterations <= 6
+    bt.free()
+
+
+def test_batch_graph_replays_match_eager():
+    """The captured refinement passes, replayed on later calls with eager work
+    and synchronizations in between, give exactly the eager batch's results."""
+    dims = BATCH_DIMS[:5]
+    kaps, fs = _batch_inputs(dims, 60)
+    kd = [_dev(k) for k in kaps]
+    fd = [_dev(f) for f in fs]
+    eager = S.slab_factor_batch(kd, [d[:3] for d in dims], precision=S.SLAB_MIXED)
+    ref = [u.cpu().numpy() for u in S.slab_solve_batch(eager, fd)]
+    ref_it = [inf.iterations for inf in eager.last_infos]
+    eager.free()
+    bt = S.slab_factor_batch(kd, [d[:3] for d in dims], precision=S.SLAB_MIXED, graph=True)
+    outs = [torch.empty_like(f) for f in fd]
+    for rep in range(3):
+        for o in outs:
+            o.fill_(float(rep + 1))          # eager work between the replays
+        torch.cuda.synchronize()
+        us = S.slab_solve_batch(bt, fd, outs=outs)
+        torch.cuda.synchronize()
+        for i in range(len(dims)):
+            assert np.array_equal(us[i].cpu().numpy(), ref[i]), (rep, i)
+            assert bt.last_infos[i].iterations == ref_it[i]
+    bt.free()
+
+
+def test_batch_reports_failing_problem():
+    dims = BATCH_DIMS[:3]
+    kaps, _ = _batch_inputs(dims, 80)
+    kaps[1] = kaps[1].copy()
+    kaps[1][3, 4] = -1.0
+    with pytest.raises(S.SlabError) as ei:
+        S.slab_factor_batch([_dev(k) for k in kaps], [d[:3] for d in dims])
+    assert ei.value.status == S.SLAB_E_INVALID
+    assert "problem 1" in str(ei.value)
