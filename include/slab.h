@@ -201,6 +201,13 @@ int slab_export_reduced(slab_handle h, int32_t which, int32_t j, double* out, vo
    measured with HIP events on the factor's stream. */
 int slab_query(slab_handle h, int32_t what, int64_t* value);
 
+/* Device memory released by handles and batches is cached by the library and
+   reused by later factorizations and solves of about the same size (mapping
+   fresh device memory costs more than factoring a small problem).  This call
+   returns the cached, unused memory of the current device to HIP.  It waits
+   for the device to be idle. */
+int slab_release_cache(void);
+
 /* Message of the last failure on this thread ("" if none). */
 const char* slab_last_error(void);
 

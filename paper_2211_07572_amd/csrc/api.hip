@@ -14,6 +14,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <vector>
 
 namespace slab {
@@ -27,6 +28,91 @@ using namespace slab;
 
 namespace {
 
+// Caching device allocator.  Mapping fresh device memory costs far more than
+// the factorization of a small problem (tens of GB for a large batch), so
+// blocks released by a handle, a batch or a finished factorization are kept
+// per device and handed out again for requests of about the same size.  A
+// failed hipMalloc empties the cache and retries; slab_release_cache() empties
+// it on request.  Blocks are released only after the work using them is
+// finished (every entry point synchronizes before it releases).
+class Pool {
+ public:
+  static Pool& get() {
+    static Pool p;
+    return p;
+  }
+  hipError_t alloc(void** p, size_t n) {
+    n = round(n);
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      auto& fb = free_[dev];
+      auto it = fb.lower_bound(n);
+      if (it != fb.end() && it->first <= n + std::max<size_t>(n / 8, 2 << 20)) {
+        *p = it->second;
+        size_[*p] = it->first;
+        cached_ -= it->first;
+        fb.erase(it);
+        return hipSuccess;
+      }
+    }
+    hipError_t e = hipMalloc(p, n);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      trim(dev);
+      e = hipMalloc(p, n);
+    }
+    if (e == hipSuccess) {
+      std::lock_guard<std::mutex> lk(mu_);
+      size_[*p] = n;
+      dev_[*p] = dev;
+    }
+    return e;
+  }
+  void release(void* p) {
+    std::lock_guard<std::mutex> lk(mu_);
+    auto it = size_.find(p);
+    if (it == size_.end()) return;
+    const size_t n = it->second;
+    size_.erase(it);
+    free_[dev_[p]].insert({n, p});
+    cached_ += n;
+  }
+  void trim(int dev) {
+    std::lock_guard<std::mutex> lk(mu_);
+    auto& fb = free_[dev];
+    for (auto& kv : fb) {
+      cached_ -= kv.first;
+      dev_.erase(kv.second);
+      (void)hipFree(kv.second);
+    }
+    fb.clear();
+  }
+  size_t cached(int dev) {
+    std::lock_guard<std::mutex> lk(mu_);
+    size_t t = 0;
+    for (auto& kv : free_[dev]) t += kv.first;
+    return t;
+  }
+  size_t size_of(void* p) {
+    std::lock_guard<std::mutex> lk(mu_);
+    auto it = size_.find(p);
+    return it == size_.end() ? 0 : it->second;
+  }
+
+ private:
+  static size_t round(size_t n) {
+    const size_t g = n >= (64u << 20) ? (2u << 20) : 256;
+    return (std::max<size_t>(n, 256) + g - 1) / g * g;
+  }
+  std::mutex mu_;
+  std::map<int, std::multimap<size_t, void*>> free_;
+  std::map<void*, size_t> size_;
+  std::map<void*, int> dev_;
+  size_t cached_ = 0;
+};
+
 // Device allocations owned by a handle or a batch.
 struct Owner {
   std::vector<void*> owned;
@@ -36,31 +122,31 @@ struct Owner {
 
   int alloc(void** p, size_t n) {
     *p = nullptr;
-    if (n == 0) n = 256;
-    hipError_t e = hipMalloc(p, n);
+    const hipError_t e = Pool::get().alloc(p, n);
     if (e != hipSuccess) {
-      (void)hipGetLastError();
       set_error("device allocation of " + std::to_string(n) + " bytes failed: " +
                 hipGetErrorString(e));
       *p = nullptr;
       return SLAB_E_NOMEM;
     }
     owned.push_back(*p);
-    bytes += n;
+    bytes += Pool::get().size_of(*p);
     return SLAB_OK;
   }
   void release(void* p) {
     if (!p) return;
     for (size_t i = 0; i < owned.size(); ++i)
       if (owned[i] == p) {
-        (void)hipFree(p);
+        bytes -= Pool::get().size_of(p);
+        Pool::get().release(p);
         owned.erase(owned.begin() + i);
         return;
       }
   }
   void release_all() {
-    for (void* p : owned) (void)hipFree(p);
+    for (void* p : owned) Pool::get().release(p);
     owned.clear();
+    bytes = 0;
     table = nullptr;
     table_cap = 0;
   }
@@ -71,6 +157,29 @@ struct Owner {
     int rc_ = (expr);               \
     if (rc_ != SLAB_OK) return rc_; \
   } while (0)
+
+// Several buffers carved out of one device allocation (one hipMalloc for a
+// whole batch instead of one per buffer and problem).
+struct Layout {
+  std::vector<std::pair<void**, size_t>> parts;
+  size_t total = 0;
+  template <class P>
+  void add(P** p, size_t n) {
+    parts.push_back({(void**)p, n});
+    total += (std::max<size_t>(n, 1) + 255) & ~size_t(255);
+  }
+  int commit(Owner& o, void** block) {
+    void* base = nullptr;
+    SLAB_TRY(o.alloc(&base, total));
+    char* c = (char*)base;
+    for (auto& pr : parts) {
+      *pr.first = c;
+      c += (std::max<size_t>(pr.second, 1) + 255) & ~size_t(255);
+    }
+    if (block) *block = base;
+    return SLAB_OK;
+  }
+};
 
 // Upload the plan's tables into the owner's table buffer (grown as needed).
 // The copy is ordered on the stream before the plan's launches.
@@ -107,6 +216,8 @@ long long elapsed_us(hipEvent_t a, hipEvent_t b) {
 
 struct Workspace {
   int nrhs = 0;
+  void* block = nullptr;   // allocation holding the buffers below
+  bool own_block = false;  // block belongs to this handle alone
   void* zbuf = nullptr;
   void* xb = nullptr;
   void* ft = nullptr;
@@ -186,25 +297,47 @@ int check_vec_args(slab_handle h, const void* in, const void* out, int32_t nrhs,
   return SLAB_OK;
 }
 
-int ensure_workspace(slab_handle h, int nrhs) {
+// Solve buffers of every job whose handle has none large enough, carved from
+// one allocation of `mem` (the handle's own memory for a single problem, the
+// batch's for a batch).
+void workspace_layout(slab_handle h, int nrhs, Layout& L) {
   Workspace& w = h->ws;
-  if (w.nrhs >= nrhs) return SLAB_OK;
-  void* ptrs[] = {w.zbuf, w.xb, w.ft, w.yt, w.tt, w.r, w.norms, w.partial};
-  for (void* p : ptrs) h->mem.release(p);
-  w = Workspace();
   const size_t n = h->n2, m = h->m, e = h->esz, e2 = h->esz2;
   const size_t N = (size_t)h->n1 * h->n2;
-  SLAB_TRY(h->mem.alloc(&w.zbuf, m * nrhs * n * h->BP * e));
-  SLAB_TRY(h->mem.alloc(&w.xb, m * 2 * nrhs * n * e));
-  SLAB_TRY(h->mem.alloc(&w.ft, m * nrhs * n * e2));
-  SLAB_TRY(h->mem.alloc(&w.yt, m * nrhs * n * e2));
-  SLAB_TRY(h->mem.alloc(&w.tt, nrhs * n * e2));
-  SLAB_TRY(h->mem.alloc((void**)&w.r, nrhs * N * sizeof(double)));
-  SLAB_TRY(h->mem.alloc((void**)&w.norms, 2 * nrhs * sizeof(double)));
-  SLAB_TRY(h->mem.alloc((void**)&w.partial,
-                        residual_partial_count(h->n1, h->n2, nrhs) * sizeof(double)));
-  w.nrhs = nrhs;
+  L.add(&w.zbuf, m * nrhs * n * h->BP * e);
+  L.add(&w.xb, m * 2 * nrhs * n * e);
+  L.add(&w.ft, m * nrhs * n * e2);
+  L.add(&w.yt, m * nrhs * n * e2);
+  L.add(&w.tt, nrhs * n * e2);
+  L.add(&w.r, nrhs * N * sizeof(double));
+  L.add(&w.norms, 2 * nrhs * sizeof(double));
+  L.add(&w.partial, residual_partial_count(h->n1, h->n2, nrhs) * sizeof(double));
+}
+
+int ensure_workspaces(const std::vector<std::pair<slab_handle, int>>& need, Owner& mem) {
+  Layout L;
+  std::vector<std::pair<slab_handle, int>> grow;
+  for (const auto& q : need) {
+    slab_handle h = q.first;
+    if (h->ws.nrhs >= q.second) continue;
+    if (h->ws.own_block) h->mem.release(h->ws.block);
+    h->ws = Workspace();
+    workspace_layout(h, q.second, L);
+    grow.push_back(q);
+  }
+  if (grow.empty()) return SLAB_OK;
+  void* block = nullptr;
+  SLAB_TRY(L.commit(mem, &block));
+  for (const auto& q : grow) {
+    q.first->ws.nrhs = q.second;
+    q.first->ws.block = block;
+    q.first->ws.own_block = grow.size() == 1 && &mem == &q.first->mem;
+  }
   return SLAB_OK;
+}
+
+int ensure_workspace(slab_handle h, int nrhs) {
+  return ensure_workspaces({{h, nrhs}}, h->mem);
 }
 
 // ---------------------------------------------------------------------------
@@ -215,38 +348,48 @@ struct FactorTemps {
        *PRL = nullptr, *Td = nullptr, *To = nullptr;
 };
 
+// Memory a handle keeps after the factorization.
 template <typename T, typename TR>
-int alloc_factor(slab_handle h, FactorTemps& t) {
+void persistent_layout(slab_handle h, Layout& L) {
   const size_t n = h->n2, m = h->m, e = sizeof(T), e2 = sizeof(TR), BP = h->BP;
   const size_t nsq = n * n;
   const size_t ncoef = (size_t)(h->n1 + 2) * (h->n2 + 2);
-  Owner& o = h->mem;
-  SLAB_TRY(o.alloc((void**)&h->kappa, ncoef * sizeof(double)));
-  SLAB_TRY(o.alloc((void**)&h->wh, (size_t)(h->n1 + 1) * n * sizeof(double)));
-  SLAB_TRY(o.alloc((void**)&h->wv, (size_t)h->n1 * (n + 1) * sizeof(double)));
-  SLAB_TRY(o.alloc((void**)&h->status, 4 * sizeof(int)));
-  SLAB_TRY(o.alloc(&h->Gl, m * n * BP * BP * e));
-  SLAB_TRY(o.alloc(&t.Hsw, m * n * BP * BP * e));
-  SLAB_TRY(o.alloc(&t.sig, m * n * 2 * BP * e));
-  SLAB_TRY(o.alloc(&t.PRR, m * nsq * e));
-  SLAB_TRY(o.alloc(&t.PLL, m * nsq * e));
-  SLAB_TRY(o.alloc(&t.PLR, m * nsq * e));
-  SLAB_TRY(o.alloc(&t.PRL, m * nsq * e));
-  SLAB_TRY(o.alloc(&t.Td, m * nsq * e2));
-  SLAB_TRY(o.alloc(&t.To, (m > 1 ? m - 1 : 1) * nsq * e2));
-  SLAB_TRY(o.alloc(&h->Linv, m * nsq * e2));
-  SLAB_TRY(o.alloc(&h->Z, (m > 1 ? m - 1 : 1) * nsq * e2));
+  L.add(&h->kappa, ncoef * sizeof(double));
+  L.add(&h->wh, (size_t)(h->n1 + 1) * n * sizeof(double));
+  L.add(&h->wv, (size_t)h->n1 * (n + 1) * sizeof(double));
+  L.add(&h->status, 4 * sizeof(int));
+  L.add(&h->Gl, m * n * BP * BP * e);
+  L.add(&h->Linv, m * nsq * e2);
+  L.add(&h->Z, (m > 1 ? m - 1 : 1) * nsq * e2);
+  if (h->odd_even) L.add(&h->Td, m * nsq * e2);
   if (h->flags & SLAB_KEEP_REDUCED) {
-    SLAB_TRY(o.alloc((void**)&h->T64, m * nsq * sizeof(double)));
-    SLAB_TRY(o.alloc((void**)&h->O64, (m > 1 ? m - 1 : 1) * nsq * sizeof(double)));
-    SLAB_TRY(o.alloc((void**)&h->S64, m * nsq * sizeof(double)));
+    L.add(&h->T64, m * nsq * sizeof(double));
+    L.add(&h->O64, (m > 1 ? m - 1 : 1) * nsq * sizeof(double));
+    L.add(&h->S64, m * nsq * sizeof(double));
   }
-  return SLAB_OK;
+}
+
+// Memory a handle needs only while it is factored (Schur pieces, propagators,
+// T blocks).
+template <typename T, typename TR>
+void temp_layout(slab_handle h, FactorTemps& t, Layout& L) {
+  const size_t n = h->n2, m = h->m, e = sizeof(T), e2 = sizeof(TR), BP = h->BP;
+  const size_t nsq = n * n;
+  L.add(&t.Hsw, m * n * BP * BP * e);
+  L.add(&t.sig, m * n * 2 * BP * e);
+  L.add(&t.PRR, m * nsq * e);
+  L.add(&t.PLL, m * nsq * e);
+  L.add(&t.PLR, m * nsq * e);
+  L.add(&t.PRL, m * nsq * e);
+  L.add(&t.To, (m > 1 ? m - 1 : 1) * nsq * e2);
+  if (!h->odd_even) L.add(&t.Td, m * nsq * e2);
 }
 
 // Factor every handle of hs (sizes set) from probs[i]->kappa.  Per problem,
 // fail[i] receives 0 (ok), 1 (invalid kappa), 2 (slab breakdown) or 3 (block
 // breakdown) and blk[i] the slab / interface index; ph the group's phase times.
+// The problems are factored in consecutive chunks whose temporaries fit half of
+// the free device memory; every chunk is one set of grouped launches.
 template <typename T, typename TR>
 int factor_group(const std::vector<slab_handle>& hs, const std::vector<const slab_problem*>& probs,
                  hipStream_t st, Owner& plan_mem, std::vector<int>& fail, std::vector<int>& blk,
@@ -254,10 +397,13 @@ int factor_group(const std::vector<slab_handle>& hs, const std::vector<const sla
   const size_t cnt = hs.size();
   fail.assign(cnt, 0);
   blk.assign(cnt, -1);
-  std::vector<FactorTemps> tmp(cnt);
-  for (size_t i = 0; i < cnt; ++i) SLAB_TRY((alloc_factor<T, TR>(hs[i], tmp[i])));
+  for (int i = 0; i < 5; ++i) ph[i] = 0;
+  {
+    Layout L;
+    for (size_t i = 0; i < cnt; ++i) persistent_layout<T, TR>(hs[i], L);
+    SLAB_TRY(L.commit(plan_mem, nullptr));
+  }
   std::vector<ProbDev> pd(cnt);
-  std::vector<Stage2Prob> s2(cnt);
   for (size_t i = 0; i < cnt; ++i) {
     slab_handle h = hs[i];
     ProbDev& d = pd[i];
@@ -265,12 +411,7 @@ int factor_group(const std::vector<slab_handle>& hs, const std::vector<const sla
     d.n1 = h->n1; d.n2 = h->n2; d.b = h->b; d.m = h->m; d.h = h->h;
     d.is_log = (h->flags & SLAB_COEF_LOG) ? 1 : 0;
     d.coef = probs[i]->kappa; d.kappa = h->kappa; d.wh = h->wh; d.wv = h->wv;
-    d.Gl = h->Gl; d.Hsw = tmp[i].Hsw; d.sig = tmp[i].sig;
-    d.PRR = tmp[i].PRR; d.PLL = tmp[i].PLL; d.PLR = tmp[i].PLR; d.PRL = tmp[i].PRL;
-    d.Td = tmp[i].Td; d.To = tmp[i].To; d.T64 = h->T64; d.O64 = h->O64; d.status = h->status;
-    Stage2Prob& q = s2[i];
-    q.n = h->n2; q.m = h->m; q.Td = tmp[i].Td; q.To = tmp[i].To; q.Linv = h->Linv; q.Z = h->Z;
-    q.S64 = h->S64; q.status = h->status;
+    d.Gl = h->Gl; d.T64 = h->T64; d.O64 = h->O64; d.status = h->status;
     SLAB_HIP_CHECK(hipMemsetAsync(h->status, 0, 4 * sizeof(int), st));
   }
   hipEvent_t ev[6];
@@ -279,46 +420,78 @@ int factor_group(const std::vector<slab_handle>& hs, const std::vector<const sla
     hipEvent_t* e;
     ~EvGuard() { for (int i = 0; i < 6; ++i) (void)hipEventDestroy(e[i]); }
   } guard{ev};
+  std::vector<int> hs_status(4 * cnt, 0);
+  auto read_status = [&](size_t lo, size_t hi) -> int {
+    for (size_t i = lo; i < hi; ++i)
+      SLAB_HIP_CHECK(hipMemcpyAsync(&hs_status[4 * i], hs[i]->status, 4 * sizeof(int),
+                                    hipMemcpyDeviceToHost, st));
+    SLAB_HIP_CHECK(hipStreamSynchronize(st));
+    return SLAB_OK;
+  };
   // coefficients first: an invalid field is reported before any factor work
   {
     Plan p;
     plan_coef_weights(p, pd);
-    SLAB_HIP_CHECK(hipEventRecord(ev[0], st));
     SLAB_TRY(run_plan(plan_mem, p, st));
   }
-  std::vector<int> hs_status(4 * cnt, 0);
-  for (size_t i = 0; i < cnt; ++i)
-    SLAB_HIP_CHECK(hipMemcpyAsync(&hs_status[4 * i], hs[i]->status, 4 * sizeof(int),
-                                  hipMemcpyDeviceToHost, st));
-  SLAB_HIP_CHECK(hipStreamSynchronize(st));
+  SLAB_TRY(read_status(0, cnt));
   bool any_bad = false;
   for (size_t i = 0; i < cnt; ++i)
     if (hs_status[4 * i] == 1) { fail[i] = 1; any_bad = true; }
   if (any_bad) return SLAB_E_INVALID;
-  {
+  // temporaries of a chunk: at most half of the memory that is free or cached
+  size_t free_b = 0, total_b = 0;
+  SLAB_HIP_CHECK(hipMemGetInfo(&free_b, &total_b));
+  int dev = 0;
+  SLAB_HIP_CHECK(hipGetDevice(&dev));
+  const size_t budget = std::max<size_t>((free_b + Pool::get().cached(dev)) / 2, (size_t)1 << 30);
+  size_t lo = 0;
+  while (lo < cnt) {
+    size_t hi = lo;
+    Layout L;
+    std::vector<FactorTemps> tmp(cnt);
+    while (hi < cnt) {
+      Layout L1 = L;
+      temp_layout<T, TR>(hs[hi], tmp[hi], L1);
+      if (hi > lo && L1.total > budget) break;
+      L = L1;
+      ++hi;
+    }
+    void* block = nullptr;
+    SLAB_TRY(L.commit(plan_mem, &block));
+    std::vector<ProbDev> cd;
+    std::vector<Stage2Prob> s2;
+    for (size_t i = lo; i < hi; ++i) {
+      FactorTemps& t = tmp[i];
+      if (hs[i]->odd_even) t.Td = hs[i]->Td;
+      ProbDev d = pd[i];
+      d.Hsw = t.Hsw; d.sig = t.sig; d.PRR = t.PRR; d.PLL = t.PLL; d.PLR = t.PLR; d.PRL = t.PRL;
+      d.Td = t.Td; d.To = t.To;
+      cd.push_back(d);
+      Stage2Prob q;
+      q.n = hs[i]->n2; q.m = hs[i]->m; q.Td = t.Td; q.To = t.To; q.Linv = hs[i]->Linv;
+      q.Z = hs[i]->Z; q.S64 = hs[i]->S64; q.status = hs[i]->status;
+      s2.push_back(q);
+    }
     Plan p;
-    plan_stage1<T, TR>(p, pd, ev + 1);
-    plan_stage2<TR>(p, s2, hs[0]->odd_even != 0);
+    plan_stage1<T, TR>(p, cd, ev + 1);
+    plan_stage2<TR>(p, s2, hs[lo]->odd_even != 0);
+    SLAB_HIP_CHECK(hipEventRecord(ev[0], st));
     SLAB_TRY(run_plan(plan_mem, p, st));
     SLAB_HIP_CHECK(hipEventRecord(ev[5], st));
-  }
-  for (size_t i = 0; i < cnt; ++i)
-    SLAB_HIP_CHECK(hipMemcpyAsync(&hs_status[4 * i], hs[i]->status, 4 * sizeof(int),
-                                  hipMemcpyDeviceToHost, st));
-  SLAB_HIP_CHECK(hipStreamSynchronize(st));
-  // phases: weights + slab factor, boundary columns, Schur propagation, assembly
-  // of T, block factorization
-  for (int i = 0; i < 5; ++i) ph[i] = elapsed_us(ev[i], ev[i + 1]);
-  for (size_t i = 0; i < cnt; ++i) {
-    slab_handle h = hs[i];
-    void* t[] = {tmp[i].Hsw, tmp[i].sig, tmp[i].PRR, tmp[i].PLL, tmp[i].PLR, tmp[i].PRL, tmp[i].To};
-    for (void* p : t) h->mem.release(p);
-    if (h->odd_even) h->Td = tmp[i].Td;
-    else h->mem.release(tmp[i].Td);
-    if (hs_status[4 * i] != 0) {
-      fail[i] = hs_status[4 * i];
-      blk[i] = hs_status[4 * i + 1];
+    SLAB_TRY(read_status(lo, hi));
+    // phases: slab factor, boundary columns, Schur propagation, assembly of T,
+    // block factorization (summed over chunks)
+    for (int i = 0; i < 5; ++i) ph[i] += elapsed_us(ev[i], ev[i + 1]);
+    SLAB_HIP_CHECK(hipStreamSynchronize(st));
+    plan_mem.release(block);
+    for (size_t i = lo; i < hi; ++i) {
+      if (hs_status[4 * i] != 0) {
+        fail[i] = hs_status[4 * i];
+        blk[i] = hs_status[4 * i + 1];
+      }
     }
+    lo = hi;
   }
   return SLAB_OK;
 }
@@ -480,7 +653,11 @@ int run_pass(Owner& mem, GraphCache* gc, const std::vector<SolveJob>& jobs, int 
 
 int solve_group(std::vector<SolveJob>& jobs, int precision, bool trans, hipStream_t st,
                 Owner& mem, GraphCache* graphs) {
-  for (SolveJob& j : jobs) SLAB_TRY(ensure_workspace(j.h, j.nrhs));
+  {
+    std::vector<std::pair<slab_handle, int>> need;
+    for (SolveJob& j : jobs) need.push_back({j.h, j.nrhs});
+    SLAB_TRY(ensure_workspaces(need, mem));
+  }
   std::vector<int> it(jobs.size(), 0);
   std::vector<double> worst(jobs.size(), 0.0);
   std::vector<SolveJob> live = jobs;
@@ -724,6 +901,14 @@ int slab_batch_query(slab_batch bt, int32_t what, int64_t* value) {
 }
 
 // ---- auxiliary ----------------------------------------------------------------
+
+int slab_release_cache(void) {
+  int dev = 0;
+  SLAB_HIP_CHECK(hipGetDevice(&dev));
+  SLAB_HIP_CHECK(hipDeviceSynchronize());
+  Pool::get().trim(dev);
+  return SLAB_OK;
+}
 
 int slab_index_maps(int32_t n1, int32_t n2, int32_t b, int32_t* col_kind, int32_t* slab_of_col,
                     int32_t* local_of_col, int64_t* perm_even, int64_t* perm_odd,

@@ -95,6 +95,7 @@ def load_library(path: str = LIB_PATH):
     L.slab_batch_handle.argtypes = [vp, i32, ctypes.POINTER(vp)]
     L.slab_batch_query.argtypes = [vp, i32, ctypes.POINTER(i64)]
     L.slab_batch_free.argtypes = [vp]
+    L.slab_release_cache.argtypes = []
     for name in header_functions():
         if name != "slab_last_error":
             getattr(L, name).restype = ctypes.c_int
@@ -424,3 +425,8 @@ def slab_solve_batch(batch: SlabBatch, fs, outs=None, stream=None, check=True):
     if check:
         _check(rc)
     return [u.view(f.shape) if f.dim() == 2 else u for u, f in zip(us, fs)]
+
+
+def release_cache():
+    """Return the library's cached, unused device memory to HIP."""
+    _check(load_library().slab_release_cache())
