@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--order", choices=["odd_even", "sweep"], default="odd_even",
                     help="stage two: odd-even elimination order or the sweep of Alg. 1")
     ap.add_argument("--skip-other", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="also report the slab width the autotuner picks for the grid")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--cpu-slabs", type=int, default=1)
     return ap.parse_args()
@@ -284,6 +286,13 @@ def main():
         result[f"{other}_form"] = form({"mixed": S.SLAB_MIXED, "fp32": S.SLAB_FP32_REFINE}[other], oe, 1, 1)[1]
         other_order = "sweep" if oe else "odd_even"
         result[f"{other_order}_order"] = form(prec, not oe, 1, 1)[1]
+    if args.autotune:
+        # slab width picked by the autotuner for this grid (the configuration fixes b)
+        t0 = time.perf_counter()
+        bt, times = S.slab_autotune(kappa, w.n2, w.n1, w.h, precision=prec, odd_even=oe,
+                                    nrhs=w.nrhs)
+        result["autotune"] = {"b": bt, "seconds_per_candidate": {str(k): v for k, v in times.items()},
+                              "tuning_s": time.perf_counter() - t0}
     if not args.skip_fp64:
         dt64, res64 = form(S.SLAB_FP64, oe, 1, 0)
         result["fp64"] = res64

@@ -82,7 +82,8 @@ typedef struct slab_batch_s* slab_batch;
 typedef struct {
   int32_t n1;          /* interior columns (slab direction); n1 % (b+1) == 0, n1 >= 2 */
   int32_t n2;          /* interior rows = interface length n; 1 <= n2 */
-  int32_t b;           /* interior columns per slab; 1 <= b <= 63 */
+  int32_t b;           /* interior columns per slab; 1 <= b <= 63, or 0: chosen by
+                          slab_autotune (then n1 must be a multiple of 4) */
   double h;            /* grid spacing, > 0 */
   const double* kappa; /* device, (n1+2)*(n2+2) FP64, r fastest; > 0 and finite
                           (or theta = log kappa, finite, with SLAB_COEF_LOG) */
@@ -200,6 +201,24 @@ int slab_export_reduced(slab_handle h, int32_t which, int32_t j, double* out, vo
    inverses, 2 Schur propagation, 3 assembly of T, 4 block factorization of T),
    measured with HIP events on the factor's stream. */
 int slab_query(slab_handle h, int32_t what, int64_t* value);
+
+/* Slab width for the grid of *prob (prob->b is ignored), chosen by measurement.
+   The cost balance of Sec. 4, eq. (complexity_funcb) -- slab work growing and
+   reduced-system work shrinking with b -- predicts each candidate
+   b in {3, 7, 15, 31, 63} with n1 % (b+1) == 0 at half the nominal
+   peaks plus the row-by-row latency of the slab recursion; candidates predicted
+   more than 3x slower than the best are skipped, and the others are factored
+   (with *opts) and solved for nrhs pseudo-random right-hand sides (uniform in
+   [-1, 1), fixed seed) on the device from
+   prob->kappa and timed.  The fastest converging width goes to *b_out and is
+   cached per (n1, n2, precision, flags, nrhs) for the process.  For FP32
+   reduced systems in odd-even order the FP32 product tile (64 or 128) of
+   n2 x n2 blocks is timed and recorded first.  times (optional, host, 5
+   entries for b = 3, 7, 15, 31, 63) receives the seconds measured, -1 where a
+   width was not tried.  slab_factor and slab_factor_batch call this for every
+   problem given with b = 0. */
+int slab_autotune(const slab_problem* prob, const slab_options* opts, int32_t nrhs,
+                  void* hip_stream, int32_t* b_out, double* times);
 
 /* Device memory released by handles and batches is cached by the library and
    reused by later factorizations and solves of about the same size (mapping

@@ -15,6 +15,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <random>
 #include <vector>
 
 namespace slab {
@@ -712,19 +713,185 @@ int solve_one(slab_handle h, const double* f, double* u, int32_t nrhs, int64_t l
   return solve_group(jobs, h->precision, trans, st, h->mem, nullptr);
 }
 
+// ---------------------------------------------------------------------------
+// Autotuner: slab width b and the FP32 product tile of stage two.
+// ---------------------------------------------------------------------------
+const int kWidths[5] = {3, 7, 15, 31, 63};
+
+// Predicted seconds for slab width b (Sec. 4, eq. (complexity_funcb): the slab
+// work grows and the reduced-system work shrinks with b), at half of the
+// nominal peaks, plus the row-by-row latency of the slab recursion.
+double model_seconds(int n1, int n2, int b, int precision, bool odd_even) {
+  const double m = n1 / (b + 1), n = n2;
+  const double r1 = 0.5 * (precision == SLAB_FP32_REFINE ? 157.3e12 : 78.6e12);
+  const double r2 = 0.5 * (precision == SLAB_FP64 ? 78.6e12 : 157.3e12);
+  const double schur = m * 2.0 * n * n * (double)b * b / r1;
+  const double reduced = m * (odd_even ? 6.67 : 2.67) * n * n * n / r2;
+  const double latency = 0.5e-6 * n * b;
+  return schur + reduced + latency;
+}
+
+std::mutex g_tune_mu;
+std::map<std::vector<long long>, int> g_width_cache;
+std::map<int, bool> g_tile_done;
+
+// Time the two tile widths on `count` products of n x n FP32 blocks shaped
+// like the odd-even update L^-1 C, and record the faster one.
+int tune_tile(int n, int count, hipStream_t st) {
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (g_tile_done[n]) return SLAB_OK;
+  }
+  Owner tmp;
+  struct Free {
+    Owner& o;
+    ~Free() { o.release_all(); }
+  } fr{tmp};
+  const size_t bytes = (size_t)count * n * n * sizeof(float);
+  void *A, *B, *C;
+  SLAB_TRY(tmp.alloc(&A, bytes));
+  SLAB_TRY(tmp.alloc(&B, bytes));
+  SLAB_TRY(tmp.alloc(&C, bytes));
+  SLAB_HIP_CHECK(hipMemsetAsync(A, 0, bytes, st));
+  SLAB_HIP_CHECK(hipMemsetAsync(B, 0, bytes, st));
+  std::vector<GemmItem> items;
+  for (int q = 0; q < count; ++q) {
+    GemmItem g;
+    const size_t off = (size_t)q * n * n;
+    g.A = (float*)A + off; g.B = (float*)B + off; g.C = (float*)C + off;
+    g.M = g.N = g.K = n; g.lda = g.ldb = g.ldc = n;
+    items.push_back(g);
+  }
+  hipEvent_t e0, e1;
+  SLAB_HIP_CHECK(hipEventCreate(&e0));
+  SLAB_HIP_CHECK(hipEventCreate(&e1));
+  double best = 1e300;
+  int best_tile = 64;
+  for (int tile : {64, 128}) {
+    Plan p;
+    plan_gemm<float>(p, false, false, items, 1.f, 0.f, GEMM_A_LOWER, tile);
+    const char* dev = nullptr;
+    SLAB_TRY(upload_plan(tmp, p, st, &dev));
+    SLAB_TRY(p.run(dev, st));  // warm-up
+    SLAB_HIP_CHECK(hipEventRecord(e0, st));
+    for (int r = 0; r < 3; ++r) SLAB_TRY(p.run(dev, st));
+    SLAB_HIP_CHECK(hipEventRecord(e1, st));
+    SLAB_HIP_CHECK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    SLAB_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) { best = ms; best_tile = tile; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  set_gemm_tile(n, best_tile);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tile_done[n] = true;
+  return SLAB_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+int slab_autotune(const slab_problem* prob, const slab_options* opts, int32_t nrhs,
+                  void* hip_stream, int32_t* b_out, double* times) {
+  if (!prob || !b_out || nrhs < 1) { set_error("bad arguments to slab_autotune"); return SLAB_E_INVALID; }
+  slab_problem p = *prob;
+  p.b = 0;
+  SLAB_TRY(slab_check_problem(&p, opts));
+  slab_options o = opts ? *opts : slab_options{SLAB_FP64, 1e-10, 10, 0};
+  o.flags &= ~(SLAB_KEEP_REDUCED | SLAB_GRAPH);
+  const bool odd_even = (o.flags & SLAB_ODD_EVEN) != 0;
+  const std::vector<long long> key{p.n1, p.n2, o.precision, o.flags, nrhs};
+  for (int k = 0; k < 5; ++k)
+    if (times) times[k] = -1.0;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_width_cache.find(key);
+    if (it != g_width_cache.end() && !times) {
+      *b_out = it->second;
+      return SLAB_OK;
+    }
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  // candidates dividing n1, pruned by the model to within 3x of its best
+  double mbest = 1e300;
+  for (int b : kWidths)
+    if (p.n1 % (b + 1) == 0) mbest = std::min(mbest, model_seconds(p.n1, p.n2, b, o.precision, odd_even));
+  if (o.precision != SLAB_FP64 && odd_even && p.n2 >= 256)
+    SLAB_TRY(tune_tile(p.n2, std::min(16, std::max(1, p.n1 / 64)), st));
+  const long long N = (long long)p.n1 * p.n2;
+  Owner tmp;
+  struct Free {
+    Owner& o;
+    ~Free() { o.release_all(); }
+  } fr{tmp};
+  double *f = nullptr, *u = nullptr;
+  SLAB_TRY(tmp.alloc((void**)&f, (size_t)N * nrhs * sizeof(double)));
+  SLAB_TRY(tmp.alloc((void**)&u, (size_t)N * nrhs * sizeof(double)));
+  {
+    // right-hand sides uniform in [-1, 1) (a smooth load such as f = 1 would
+    // put the FP64 residual's rounding floor near the tolerance on fine grids)
+    std::vector<double> rhs((size_t)N * nrhs);
+    std::mt19937_64 gen(12345);
+    std::uniform_real_distribution<double> uni(-1.0, 1.0);
+    for (double& v : rhs) v = uni(gen);
+    SLAB_HIP_CHECK(hipMemcpy(f, rhs.data(), rhs.size() * sizeof(double), hipMemcpyHostToDevice));
+  }
+  hipEvent_t e0, e1;
+  SLAB_HIP_CHECK(hipEventCreate(&e0));
+  SLAB_HIP_CHECK(hipEventCreate(&e1));
+  double best = 1e300;
+  int best_b = -1;
+  for (int k = 0; k < 5; ++k) {
+    const int b = kWidths[k];
+    if (p.n1 % (b + 1) != 0) continue;
+    if (model_seconds(p.n1, p.n2, b, o.precision, odd_even) > 3.0 * mbest) continue;
+    p.b = b;
+    slab_handle h = nullptr;
+    SLAB_HIP_CHECK(hipEventRecord(e0, st));
+    int rc = slab_factor(&p, &o, st, &h, nullptr);
+    if (rc == SLAB_OK) {
+      rc = slab_solve(h, f, u, nrhs, N, st, nullptr);
+      SLAB_HIP_CHECK(hipEventRecord(e1, st));
+      SLAB_HIP_CHECK(hipEventSynchronize(e1));
+      slab_free(h);
+    }
+    if (rc != SLAB_OK && rc != SLAB_E_NOCONV) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      return rc;
+    }
+    if (rc == SLAB_E_NOCONV) continue;  // a width that does not converge is not a choice
+    float ms = 0.f;
+    SLAB_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+    if (times) times[k] = ms * 1e-3;
+    if (ms < best) { best = ms; best_b = b; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (best_b < 0) { set_error("no slab width converged"); return SLAB_E_NOCONV; }
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_width_cache[key] = best_b;
+  }
+  *b_out = best_b;
+  return SLAB_OK;
+}
 
 const char* slab_last_error(void) { return g_last_error.c_str(); }
 
 int slab_check_problem(const slab_problem* prob, const slab_options* opts) {
   if (!prob) { set_error("null problem"); return SLAB_E_INVALID; }
-  if (prob->n2 < 1 || prob->n1 < 2 || prob->b < 1 || prob->b > 63) {
-    set_error("need n2 >= 1, n1 >= 2, 1 <= b <= 63");
+  if (prob->n2 < 1 || prob->n1 < 2 || prob->b < 0 || prob->b > 63) {
+    set_error("need n2 >= 1, n1 >= 2, 0 <= b <= 63");
     return SLAB_E_INVALID;
   }
-  if (prob->n1 % (prob->b + 1) != 0) { set_error("n1 must be a multiple of b+1"); return SLAB_E_INVALID; }
+  if (prob->b == 0 && prob->n1 % 4 != 0) {
+    set_error("b = 0 (autotuned) needs n1 to be a multiple of 4");
+    return SLAB_E_INVALID;
+  }
+  if (prob->b > 0 && prob->n1 % (prob->b + 1) != 0) { set_error("n1 must be a multiple of b+1"); return SLAB_E_INVALID; }
   if (!(prob->h > 0.0) || !std::isfinite(prob->h)) { set_error("h must be positive and finite"); return SLAB_E_INVALID; }
   if (!prob->kappa) { set_error("null coefficient pointer"); return SLAB_E_INVALID; }
   if ((long long)prob->n1 * prob->n2 > (1LL << 40)) { set_error("grid too large"); return SLAB_E_INVALID; }
@@ -751,8 +918,14 @@ int slab_factor(const slab_problem* prob, const slab_options* opts, void* hip_st
   if (rc) return rc;
   int device = 0;
   if (hipGetDevice(&device) != hipSuccess) { set_error("no HIP device"); return SLAB_E_HIP; }
-  slab_handle h = new_handle(prob, opts, device);
   hipStream_t st = (hipStream_t)hip_stream;
+  slab_problem tuned = *prob;
+  if (tuned.b == 0) {
+    rc = slab_autotune(prob, opts, 1, hip_stream, &tuned.b, nullptr);
+    if (rc) return rc;
+    prob = &tuned;
+  }
+  slab_handle h = new_handle(prob, opts, device);
   std::vector<slab_handle> hs{h};
   std::vector<const slab_problem*> ps{prob};
   std::vector<int> fail, blk;
@@ -817,6 +990,13 @@ int slab_factor_batch(const slab_problem* probs, int32_t count, const slab_optio
   }
   int device = 0;
   if (hipGetDevice(&device) != hipSuccess) { set_error("no HIP device"); return SLAB_E_HIP; }
+  std::vector<slab_problem> tuned(probs, probs + count);
+  for (int i = 0; i < count; ++i) {
+    if (tuned[i].b != 0) continue;
+    const int rc = slab_autotune(&probs[i], opts, 1, hip_stream, &tuned[i].b, nullptr);
+    if (rc) return rc;
+  }
+  probs = tuned.data();
   slab_batch bt = new slab_batch_s();
   bt->device = device;
   bt->precision = opts ? opts->precision : SLAB_FP64;

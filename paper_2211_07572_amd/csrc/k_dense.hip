@@ -12,6 +12,9 @@
 // 16x16x4 MFMA tiles in the working precision (FP32 or FP64).
 #include "launch.h"
 
+#include <map>
+#include <mutex>
+
 namespace slab {
 
 // ---------------------------------------------------------------------------
@@ -212,11 +215,28 @@ static void gemm_tile(bool ak, bool bn, bool vecok, unsigned grid, const GemmIte
 #undef SLAB_GEMM_CASE
 }
 
+// Tile width chosen by the autotuner for FP32 products of n x n blocks
+// (0: none recorded, use the size rule below).
+static std::mutex g_tile_mu;
+static std::map<int, int> g_tile_f32;
+
+void set_gemm_tile(int n, int tile) {
+  std::lock_guard<std::mutex> lk(g_tile_mu);
+  g_tile_f32[n] = tile;
+}
+
+static int tuned_tile(int n) {
+  std::lock_guard<std::mutex> lk(g_tile_mu);
+  auto it = g_tile_f32.find(n);
+  return it == g_tile_f32.end() ? 0 : it->second;
+}
+
 template <typename T>
 void plan_gemm(Plan& plan, bool ak, bool bn, const std::vector<GemmItem>& items, T alpha, T beta,
-               int flags) {
+               int flags, int force_tile) {
   if (items.empty()) return;
-  // 128-wide tiles once there are enough of them for four per compute unit
+  // 128-wide tiles once there are enough of them for four per compute unit,
+  // unless the autotuner recorded a choice for this block size
   long long area = 0;
   bool vecok = true;
   const uintptr_t vec = 16;
@@ -226,7 +246,14 @@ void plan_gemm(Plan& plan, bool ak, bool bn, const std::vector<GemmItem>& items,
             ((uintptr_t)g.A % vec) == 0 && ((uintptr_t)g.B % vec) == 0;
   }
   if (flags & GEMM_LOWER_C) area /= 2;
-  const int tile = (sizeof(T) == 4 && area >= 1024LL * 128 * 128) ? 128 : 64;
+  int tile = (sizeof(T) == 4 && area >= 1024LL * 128 * 128) ? 128 : 64;
+  if (sizeof(T) == 4) {
+    bool same_n = true;
+    for (const GemmItem& g : items) same_n = same_n && g.M == items[0].M && g.N == items[0].M;
+    const int tuned = same_n ? tuned_tile(items[0].M) : 0;
+    if (tuned) tile = tuned;
+    if (force_tile) tile = force_tile;
+  }
   std::vector<int> c;
   for (const GemmItem& g : items) {
     const long long tm = (g.M + tile - 1) / tile, tn = (g.N + tile - 1) / tile;
@@ -247,9 +274,9 @@ void plan_gemm(Plan& plan, bool ak, bool bn, const std::vector<GemmItem>& items,
   });
 }
 template void plan_gemm<float>(Plan&, bool, bool, const std::vector<GemmItem>&, float, float,
-                              int);
+                              int, int);
 template void plan_gemm<double>(Plan&, bool, bool, const std::vector<GemmItem>&, double, double,
-                               int);
+                               int, int);
 
 // ---------------------------------------------------------------------------
 // Panel of the right-looking factorization of a pivot block S (n x n), grouped

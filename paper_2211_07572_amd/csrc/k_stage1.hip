@@ -158,11 +158,21 @@ __device__ __forceinline__ bool sweep_inverse(T (&a)[BP], T (*colbuf)[BP], int l
 //   top-down  (dir 0):  Dl_0 = D_0,        Dl_r = D_r - W_r Gl_{r-1} W_r,    Gl_r = Dl_r^-1
 //   bottom-up (dir 1):  Dr_{n-1} = D_{n-1}, Dr_r = D_r - W_{r+1} Gr_{r+1} W_{r+1}
 // Stored: Gl_r row-major (block solves), Hr_r = Gr_r W_r in fragment-major
-// order (Schur propagation).  One wave per (slab, direction).
+// order (Schur propagation).  One wave per (slab, direction): lane = (row i,
+// column group q) holds BP/R entries of row i, R = 64/BP lanes per row.  Each
+// block is inverted in place by the symmetric sweep operator (the swept matrix
+// stays symmetric, so the pivot column needed by every row is the pivot row
+// published through LDS): one barrier per pivot, the same instructions for
+// the pivot row and the others (a select picks the scaled pivot row).  The edge weights of the next rows are loaded
+// D steps ahead into a register ring and used raw, so no load latency sits on
+// the row-to-row chain.
 // ---------------------------------------------------------------------------
 template <typename T, int BP>
 __global__ __launch_bounds__(64) void k_slab_factor(const ProbDev* __restrict__ P,
                                                     const int* __restrict__ offs, int count) {
+  constexpr int R = 64 / BP;   // lanes per row
+  constexpr int C = BP / R;    // columns per lane
+  constexpr int D = 4;         // weight prefetch depth (row steps)
   const int it = group_item(offs, count, blockIdx.x);
   const int bx = blockIdx.x - offs[it];
   const double* __restrict__ wh = P[it].wh;
@@ -173,47 +183,101 @@ __global__ __launch_bounds__(64) void k_slab_factor(const ProbDev* __restrict__ 
   int* __restrict__ status = P[it].status;
   const int s = bx >> 1, dir = bx & 1;
   const int lane = threadIdx.x;
-  const int c0 = s * (b + 1);
-  const long long c = c0 + (lane < b ? lane : 0);
+  const int i = lane % BP, q = lane / BP;
+  const int k0 = q * C;                    // first column of this lane
+  const bool act = i < b;
+  const long long c = (long long)s * (b + 1) + (act ? i : 0);
   __shared__ T colbuf[2][BP];
-  __shared__ T wsh[BP];
-  T g[BP];
-  T a[BP];
+  __shared__ T wsh[BP];   // W of the coupling to the previous row, by column
+  __shared__ T wup[BP];   // W_r by column (Hr_r = Gr_r W_r)
+  T g[C], a[C];
 #pragma unroll
-  for (int k = 0; k < BP; ++k) g[k] = (T)0;
-  bool ok = true;
-  for (int t = 0; t < n2; ++t) {
+  for (int j = 0; j < C; ++j) g[j] = (T)0;
+  // raw edge weights of row r: wh left/right of the node, wv below/above
+  double rl[D], rr[D], rd[D], ru[D];
+  auto load = [&](int d, int t) __attribute__((always_inline)) {
     const int r = dir == 0 ? t : n2 - 1 - t;
-    T wc = (T)0;  // coupling to the previously processed grid row
-    if (t > 0 && lane < b) wc = (T)(dir == 0 ? wv[c * (n2 + 1) + r] : wv[c * (n2 + 1) + r + 1]);
-    if (lane < BP) wsh[lane] = wc;
-    __syncthreads();
-    build_D_row<T, BP>(a, wh, wv, n2, b, c0, r, lane);
+    const bool ld = act && t < n2;
+    rl[d] = ld ? wh[c * n2 + r] : 0.0;
+    rr[d] = ld ? wh[(c + 1) * n2 + r] : 0.0;
+    rd[d] = ld ? wv[c * (n2 + 1) + r] : 0.0;
+    ru[d] = ld ? wv[c * (n2 + 1) + r + 1] : 0.0;
+  };
 #pragma unroll
-    for (int k = 0; k < BP; ++k) a[k] -= wc * g[k] * wsh[k];
-    ok = sweep_inverse<T, BP>(a, colbuf, lane) && ok;
+  for (int d = 0; d < D; ++d) load(d, d);
+  bool ok = true;
+  for (int t0 = 0; t0 < n2; t0 += D) {
 #pragma unroll
-    for (int k = 0; k < BP; ++k) g[k] = -a[k];
-    if (dir == 0) {
-      if (lane < BP) {
-        T* dst = Gl + (((size_t)s * n2 + r) * BP + lane) * BP;
+    for (int d = 0; d < D; ++d) {
+      const int t = t0 + d;
+      if (t < n2) {  // uniform
+        const int r = dir == 0 ? t : n2 - 1 - t;
+        const double whl = rl[d], whr = rr[d], wvd = rd[d], wvu = ru[d];
+        load(d, t + D);
+        const T dd = act ? (T)(whl + whr + wvd + wvu) : (T)1;
+        const T wl = (act && i > 0) ? (T)whl : (T)0;
+        const T wr = (act && i < b - 1) ? (T)whr : (T)0;
+        const T wc = (t > 0) ? (T)(dir == 0 ? wvd : wvu) : (T)0;
+        if (q == 0) {
+          wsh[i] = wc;
+          wup[i] = (T)wvd;
+        }
+        __syncthreads();
+        // row i of D_r - W G W (columns k0 .. k0+C-1)
 #pragma unroll
-        for (int k = 0; k < BP; ++k) dst[k] = g[k];
-      }
-    } else {
-      // Hr_r = Gr_r W_r: scale column k by the edge between rows r-1 and r.
-      T wup = (T)0;
-      if (lane < b) wup = (T)wv[c * (n2 + 1) + r];
-      __syncthreads();
-      if (lane < BP) wsh[lane] = wup;
-      __syncthreads();
-      if (lane < BP) {
-        T* dst = Hsw + ((size_t)s * n2 + r) * BP * BP;
+        for (int j = 0; j < C; ++j) {
+          const int k = k0 + j;
+          const T dk = (k == i) ? dd : ((k == i - 1) ? -wl : ((k == i + 1) ? -wr : (T)0));
+          a[j] = dk - wc * g[j] * wsh[k];
+        }
+        if (i == 0) {
 #pragma unroll
-        for (int k = 0; k < BP; ++k) dst[swz_index<T>(lane, k, BP)] = g[k] * wsh[k];
+          for (int j = 0; j < C; ++j) colbuf[0][k0 + j] = a[j];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int p = 0; p < BP; ++p) {
+          const int buf = p & 1;
+          const T dp = colbuf[buf][p];
+          ok = ok && (dp > (T)0) && isfinite((double)dp);
+          const T inv = (T)1 / dp;
+          // all LDS reads first, unconditionally (no read inside a divergent branch)
+          T cb[C];
+#pragma unroll
+          for (int j = 0; j < C; ++j) cb[j] = colbuf[buf][k0 + j];
+          const T aip = colbuf[buf][i];
+          const bool piv = i == p;
+          const T f = piv ? (T)0 : aip * inv;
+#pragma unroll
+          for (int j = 0; j < C; ++j) a[j] -= f * cb[j];
+          // the pivot row is scaled, not updated (no cancellation)
+          if (piv) {
+#pragma unroll
+            for (int j = 0; j < C; ++j) a[j] = cb[j] * inv;
+          }
+          if (q == p / C) a[p % C] = piv ? -inv : f;
+          if (p + 1 < BP) {
+            if (i == p + 1) {
+#pragma unroll
+              for (int j = 0; j < C; ++j) colbuf[buf ^ 1][k0 + j] = a[j];
+            }
+            __syncthreads();
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < C; ++j) g[j] = -a[j];
+        if (dir == 0) {
+          T* dst = Gl + (((size_t)s * n2 + r) * BP + i) * BP + k0;
+#pragma unroll
+          for (int j = 0; j < C; ++j) dst[j] = g[j];
+        } else {
+          T* dst = Hsw + ((size_t)s * n2 + r) * BP * BP;
+#pragma unroll
+          for (int j = 0; j < C; ++j) dst[swz_index<T>(i, k0 + j, BP)] = g[j] * wup[k0 + j];
+        }
+        __syncthreads();
       }
     }
-    __syncthreads();
   }
   if (!ok && lane == 0) { status[0] = 2; status[1] = s; }
 }

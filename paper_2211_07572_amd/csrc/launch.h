@@ -29,9 +29,12 @@ enum { GEMM_LOWER_C = 1, GEMM_A_LOWER = 2, GEMM_B_LOWER = 4 };
 // C = beta*C + alpha * op(A) op(B) for every item; op(A)(i,k) = A[i*lda+k]
 // (ak=false) or A[k*lda+i] (ak=true); op(B)(k,j) = B[k*ldb+j] (bn=false) or
 // B[j*ldb+k] (bn=true).
+// force_tile (64 or 128, FP32 only) overrides the tile choice.
 template <typename T>
 void plan_gemm(Plan& plan, bool ak, bool bn, const std::vector<GemmItem>& items, T alpha, T beta,
-               int flags);
+               int flags, int force_tile = 0);
+// Record the FP32 tile width to use for products of n x n blocks.
+void set_gemm_tile(int n, int tile);
 
 // Cholesky factorization with carried inverse of independent pivot blocks.
 template <typename T>

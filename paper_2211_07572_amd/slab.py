@@ -96,6 +96,8 @@ def load_library(path: str = LIB_PATH):
     L.slab_batch_query.argtypes = [vp, i32, ctypes.POINTER(i64)]
     L.slab_batch_free.argtypes = [vp]
     L.slab_release_cache.argtypes = []
+    L.slab_autotune.argtypes = [ctypes.POINTER(slab_problem), ctypes.POINTER(slab_options), i32, vp,
+                                ctypes.POINTER(i32), ctypes.POINTER(dp)]
     for name in header_functions():
         if name != "slab_last_error":
             getattr(L, name).restype = ctypes.c_int
@@ -186,7 +188,11 @@ def slab_factor(kappa, n2: int, n1: int, b: int, h: float | None = None, precisi
     info = slab_solve_info()
     _check(L.slab_factor(ctypes.byref(prob), ctypes.byref(opts), _stream_ptr(stream),
                          ctypes.byref(out), ctypes.byref(info)))
-    return SlabHandle(out, n2, n1, b, h, precision)
+    handle = SlabHandle(out, n2, n1, b, h, precision)
+    if b == 0:  # width chosen by the autotuner
+        handle.b = handle.query(3)
+        handle.m = n1 // (handle.b + 1)
+    return handle
 
 
 def _solve(fn, handle: SlabHandle, f, out=None, stream=None, check=True):
@@ -348,7 +354,11 @@ class SlabBatch:
         out = ctypes.c_void_p()
         _check(load_library().slab_batch_handle(self.ptr, i, ctypes.byref(out)))
         n2, n1, b, h = self.dims[i]
-        return SlabHandle(out, n2, n1, b, h, self.precision, owned=False)
+        hd = SlabHandle(out, n2, n1, b, h, self.precision, owned=False)
+        if b == 0:
+            hd.b = hd.query(3)
+            hd.m = n1 // (hd.b + 1)
+        return hd
 
     def query(self, what: int) -> int:
         v = ctypes.c_int64()
@@ -430,3 +440,20 @@ def slab_solve_batch(batch: SlabBatch, fs, outs=None, stream=None, check=True):
 def release_cache():
     """Return the library's cached, unused device memory to HIP."""
     _check(load_library().slab_release_cache())
+
+
+def slab_autotune(kappa, n2: int, n1: int, h: float | None = None, precision: int = SLAB_FP64,
+                  tol: float = 1e-10, max_iter: int = 10, odd_even: bool = False, nrhs: int = 1,
+                  stream=None):
+    """Slab width chosen by measurement for this grid; returns (b, seconds per
+    candidate b in (3, 7, 15, 31, 63), None where not tried)."""
+    L = load_library()
+    if h is None:
+        h = 1.0 / (n2 + 1)
+    prob = slab_problem(n1, n2, 0, float(h), _dev_f64(kappa, "kappa"))
+    opts = slab_options(precision, float(tol), int(max_iter), SLAB_ODD_EVEN if odd_even else 0)
+    b = ctypes.c_int32()
+    times = (ctypes.c_double * 5)()
+    _check(L.slab_autotune(ctypes.byref(prob), ctypes.byref(opts), int(nrhs), _stream_ptr(stream),
+                           ctypes.byref(b), times))
+    return b.value, {w: (t if t >= 0 else None) for w, t in zip((3, 7, 15, 31, 63), times)}

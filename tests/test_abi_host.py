@@ -34,7 +34,9 @@ def test_every_header_symbol_exported(lib):
     (16, 64, 7, 0.1, S.SLAB_OK),
     (16, 63, 7, 0.1, S.SLAB_E_INVALID),   # n1 not a multiple of b+1
     (0, 64, 7, 0.1, S.SLAB_E_INVALID),    # empty interface
-    (16, 64, 0, 0.1, S.SLAB_E_INVALID),   # b < 1
+    (16, 64, -1, 0.1, S.SLAB_E_INVALID),  # b < 0
+    (16, 64, 0, 0.1, S.SLAB_OK),          # b = 0: chosen by the autotuner
+    (16, 66, 0, 0.1, S.SLAB_E_INVALID),   # b = 0 needs n1 % 4 == 0
     (16, 128, 127, 0.1, S.SLAB_E_INVALID),  # b > 63
     (16, 64, 7, 0.0, S.SLAB_E_INVALID),   # h <= 0
     (16, 64, 7, float("nan"), S.SLAB_E_INVALID),
@@ -77,3 +79,24 @@ def test_null_handles(lib):
     arr = (ctypes.c_double * 1)()
     assert lib.slab_residual(None, ctypes.c_void_p(8), ctypes.c_void_p(8), 1, 1, arr, None) == S.SLAB_E_INVALID
     assert lib.slab_index_maps(10, 4, 3, None, None, None, None, None, None) == S.SLAB_E_INVALID
+
+
+def test_autotune_rejects_before_device_work(lib):
+    b = ctypes.c_int32(-7)
+    prob = S.slab_problem(66, 16, 0, 0.1, ctypes.c_void_p(1))
+    assert lib.slab_autotune(ctypes.byref(prob), None, 1, None, ctypes.byref(b), None) == S.SLAB_E_INVALID
+    prob = S.slab_problem(64, 16, 0, 0.1, ctypes.c_void_p(1))
+    assert lib.slab_autotune(ctypes.byref(prob), None, 0, None, ctypes.byref(b), None) == S.SLAB_E_INVALID
+    assert lib.slab_autotune(None, None, 1, None, ctypes.byref(b), None) == S.SLAB_E_INVALID
+    assert b.value == -7
+
+
+def test_batch_rejects_before_device_work(lib):
+    out = ctypes.c_void_p(5)
+    probs = (S.slab_problem * 2)(S.slab_problem(64, 16, 7, 0.1, ctypes.c_void_p(1)),
+                                 S.slab_problem(63, 16, 7, 0.1, ctypes.c_void_p(1)))
+    assert lib.slab_factor_batch(probs, 2, None, None, ctypes.byref(out), None) == S.SLAB_E_INVALID
+    assert out.value is None
+    assert b"problem 1" in lib.slab_last_error()
+    assert lib.slab_factor_batch(probs, 0, None, None, ctypes.byref(out), None) == S.SLAB_E_INVALID
+    assert lib.slab_batch_free(None) == S.SLAB_OK

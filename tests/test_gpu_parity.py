@@ -44,6 +44,8 @@ CASES = [
     (5, 4, 3),
     (1, 8, 1),
     (64, 64, 7),
+    (40, 128, 63),
+    (70, 96, 47),
 ]
 # odd-even order: odd m and a deeper level tree on top of the cases above
 CASES_OE = CASES + [(40, 52, 3), (64, 256, 7)]
@@ -341,3 +343,36 @@ def test_batch_reports_failing_problem():
         S.slab_factor_batch([_dev(k) for k in kaps], [d[:3] for d in dims])
     assert ei.value.status == S.SLAB_E_INVALID
     assert "problem 1" in str(ei.value)
+
+
+# ------------------------------------------------------------------- autotuner
+
+def test_autotune_width_is_fastest_measured_and_used():
+    n2, n1 = 96, 256
+    kap = G.kappa_lognormal(n2, n1, 90)
+    b, times = S.slab_autotune(_dev(kap), n2, n1, precision=S.SLAB_MIXED, odd_even=True)
+    measured = {w: t for w, t in times.items() if t is not None}
+    assert b in measured and measured[b] == min(measured.values())
+    assert all(n1 % (w + 1) == 0 for w in measured)
+    h = S.slab_factor(_dev(kap), n2, n1, 0, precision=S.SLAB_MIXED, odd_even=True)
+    assert h.b == b
+    f = G.rhs_uniform(n2, n1, 2, 91)
+    u = S.slab_solve(h, _dev(f)).cpu().numpy()
+    assert O.relres(O.make_problem(kap, n2, n1, b), u, f).max() <= 1e-10
+    h.free()
+
+
+def test_batch_with_autotuned_widths():
+    dims = [(40, 64, 0, 1), (64, 96, 7, 2), (33, 128, 0, 3)]
+    kaps, fs = _batch_inputs(dims, 95)
+    bt = S.slab_factor_batch([_dev(k) for k in kaps], [d[:3] for d in dims],
+                             precision=S.SLAB_MIXED)
+    us = S.slab_solve_batch(bt, [_dev(f) for f in fs])
+    for i, (n2, n1, b, nr) in enumerate(dims):
+        bi = bt.handle(i).b
+        assert bi > 0 and n1 % (bi + 1) == 0
+        if b:
+            assert bi == b
+        rr = O.relres(O.make_problem(kaps[i], n2, n1, bi), us[i].cpu().numpy(), fs[i])
+        assert rr.max() <= 1e-10, (i, rr)
+    bt.free()
