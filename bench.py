@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--order", choices=["odd_even", "sweep"], default="odd_even",
                     help="stage two: odd-even elimination order or the sweep of Alg. 1")
     ap.add_argument("--skip-other", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 2 GiB device copy (scales the HBM counters)")
     ap.add_argument("--autotune", action="store_true",
                     help="also report the slab width the autotuner picks for the grid")
     ap.add_argument("--skip-cpu", action="store_true")
@@ -129,6 +131,83 @@ def block_factor_flops(w: G.Workload, odd_even: bool) -> float:
         total += max(NR - 1, 0) * 2.0 * n ** 3
         s *= 2
     return total
+
+
+def block_products(w: G.Workload, odd_even: bool, elem: int = 4):
+    """Launches of the block products of stage two (the GEMM kernel): total
+    algorithmic flops, total algorithmic HBM bytes and the number of launches.
+    Per item (n x n blocks): a product with a lower-triangular factor
+    (L^-1 C: n^3 flops; reads n^2/2 + n^2, writes n^2), a symmetric update
+    (D -= U^T U, lower half: n^3 flops; reads n^2 + n^2/2, writes n^2/2) and a
+    full product (-U^T V: 2 n^3 flops; reads 2 n^2, writes n^2)."""
+    n, m = w.n2, w.m
+    n2, n3 = float(n) ** 2, float(n) ** 3
+    tri = (n3, 2.5 * n2 * elem)
+    sym = (n3, 2.0 * n2 * elem)
+    full = (2 * n3, 3.0 * n2 * elem)
+    fl = by = 0.0
+    launches = 0
+
+    def add(kind, count):
+        nonlocal fl, by, launches
+        if count > 0:
+            fl += kind[0] * count
+            by += kind[1] * count
+            launches += 1
+    if not odd_even:
+        for j in range(m):
+            add(sym, 1 if j > 0 else 0)
+            add(tri, 1 if j < m - 1 else 0)
+        return fl, by, launches
+    s = 1
+    while m // s >= 1:
+        k = m // s
+        E, NR = (k + 1) // 2, k // 2
+        add(tri, E - 1)
+        add(tri, NR)
+        add(sym, E - 1)
+        add(sym, NR)
+        add(full, NR - 1)
+        s *= 2
+    return fl, by, launches
+
+
+def kernel_source_digest() -> str:
+    import hashlib
+    src = os.path.join(ROOT, "paper_2211_07572_amd", "csrc", "k_dense.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(name: str):
+    """HBM bytes per launch from a committed counter summary, or None when the
+    kernel source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if "=" in line and line.strip().startswith("- "):
+            k, v = line.strip()[2:].split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_sha256_16") != kernel_source_digest():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration():
+    """A plain device copy of known size, for scaling the FETCH_SIZE and
+    WRITE_SIZE counters: 3 copies of 2 GiB (float64)."""
+    import torch
+    a = torch.ones(1 << 28, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": a.numel() * 8, "copy_bytes_written": b.numel() * 8,
+                      "copies": 3}))
 
 
 def run_gpu(w: G.Workload, precision: int, steps: int, warmup: int, kappa, f, odd_even: bool):
@@ -219,6 +298,9 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     import torch
     from paper_2211_07572_amd import slab as S
     S.load_library()
@@ -262,15 +344,28 @@ def main():
         "refine_passes": iters32,
         "phase_ms": {k: v / 1e3 for k, v in ph.items()},
     }
-    # roofline of the Schur propagation kernel (one launch per factor), timed by
-    # HIP events recorded on the launch stream around that launch only
+    # roofline of the dominant kernel: the block products of stage two (k_gemm,
+    # FP32 MFMA), timed by HIP events recorded on the factor's stream around
+    # each of its launches (summed); achieved = algorithmic flops / time
+    fl_bp, by_bp, n_bp = block_products(w, oe)
+    t_bp = ph["block_products"] / 1e6
+    traffic = measured_traffic("traffic_k_gemm_block_products_2048x4096_b31.md")
+    result["roofline"] = {"kernel": "k_gemm<float> (block products of stage two)",
+                          "bound": "mfma", "achieved": fl_bp / t_bp / 1e12,
+                          "peak": PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
+                          "frac": fl_bp / t_bp / 1e12 / PEAK_TFLOPS["f32"],
+                          "traffic": traffic,
+                          "algorithmic_bytes_per_launch": by_bp / n_bp,
+                          "flops_per_launch": fl_bp / n_bp, "launches": n_bp,
+                          "avg_launch_ms": t_bp / n_bp * 1e3}
+    # the Schur propagation (one launch per factor) beside it
     t_schur = ph["schur"] / 1e6
     fl = schur_flops(w)
     dt = "f64" if args.precision == "mixed" else "f32"
-    result["roofline"] = {"kernel": f"k_schur<{'double' if dt == 'f64' else 'float'},32>",
-                          "bound": "mfma", "achieved": fl / t_schur / 1e12,
-                          "peak": PEAK_TFLOPS[dt], "unit": "TFLOP/s",
-                          "frac": fl / t_schur / 1e12 / PEAK_TFLOPS[dt], "traffic": None}
+    result["roofline_schur"] = {"kernel": f"k_schur<{'double' if dt == 'f64' else 'float'},32>",
+                                "bound": "mfma", "achieved": fl / t_schur / 1e12,
+                                "peak": PEAK_TFLOPS[dt], "unit": "TFLOP/s",
+                                "frac": fl / t_schur / 1e12 / PEAK_TFLOPS[dt]}
     tb = ph["block_factor"] / 1e6
     result["block_factor_tflops"] = block_factor_flops(w, oe) / tb / 1e12
 

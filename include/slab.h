@@ -197,9 +197,10 @@ int slab_export_reduced(slab_handle h, int32_t which, int32_t j, double* out, vo
 
 /* Sizes and timings of a handle: what = 0 m, 1 n1, 2 n2, 3 b, 4 precision,
    5 device bytes held, 10+p elapsed microseconds of factor phase p of the last
-   factorization (0 weights and slab factors, 1 boundary columns of the slab
-   inverses, 2 Schur propagation, 3 assembly of T, 4 block factorization of T),
-   measured with HIP events on the factor's stream. */
+   factorization (0 slab factors, 1 boundary columns of the slab inverses,
+   2 Schur propagation, 3 assembly of T, 4 block factorization of T, 5 the
+   block products inside 4: the sum over their launches), measured with HIP
+   events on the factor's stream. */
 int slab_query(slab_handle h, int32_t what, int64_t* value);
 
 /* Slab width for the grid of *prob (prob->b is ignored), chosen by measurement.

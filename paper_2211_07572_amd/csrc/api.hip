@@ -398,7 +398,7 @@ int factor_group(const std::vector<slab_handle>& hs, const std::vector<const sla
   const size_t cnt = hs.size();
   fail.assign(cnt, 0);
   blk.assign(cnt, -1);
-  for (int i = 0; i < 5; ++i) ph[i] = 0;
+  for (int i = 0; i < 6; ++i) ph[i] = 0;
   {
     Layout L;
     for (size_t i = 0; i < cnt; ++i) persistent_layout<T, TR>(hs[i], L);
@@ -476,14 +476,17 @@ int factor_group(const std::vector<slab_handle>& hs, const std::vector<const sla
     }
     Plan p;
     plan_stage1<T, TR>(p, cd, ev + 1);
+    p.timer = std::make_shared<Plan::Timer>();
     plan_stage2<TR>(p, s2, hs[lo]->odd_even != 0);
     SLAB_HIP_CHECK(hipEventRecord(ev[0], st));
     SLAB_TRY(run_plan(plan_mem, p, st));
     SLAB_HIP_CHECK(hipEventRecord(ev[5], st));
     SLAB_TRY(read_status(lo, hi));
     // phases: slab factor, boundary columns, Schur propagation, assembly of T,
-    // block factorization (summed over chunks)
+    // block factorization (summed over chunks); 5: the block products inside
+    // the block factorization
     for (int i = 0; i < 5; ++i) ph[i] += elapsed_us(ev[i], ev[i + 1]);
+    ph[5] += (long long)(p.timer->total_ms() * 1000.0);
     SLAB_HIP_CHECK(hipStreamSynchronize(st));
     plan_mem.release(block);
     for (size_t i = lo; i < hi; ++i) {
@@ -1075,7 +1078,7 @@ int slab_batch_query(slab_batch bt, int32_t what, int64_t* value) {
     *value = tot;
     return SLAB_OK;
   }
-  if (what >= 10 && what < 15) { *value = bt->phase_us[what - 10]; return SLAB_OK; }
+  if (what >= 10 && what < 16) { *value = bt->phase_us[what - 10]; return SLAB_OK; }
   set_error("unknown query");
   return SLAB_E_INVALID;
 }
@@ -1166,7 +1169,7 @@ int slab_query(slab_handle h, int32_t what, int64_t* value) {
     case 4: *value = h->precision; return SLAB_OK;
     case 5: *value = (int64_t)h->mem.bytes; return SLAB_OK;
     default:
-      if (what >= 10 && what < 15) { *value = h->phase_us[what - 10]; return SLAB_OK; }
+      if (what >= 10 && what < 16) { *value = h->phase_us[what - 10]; return SLAB_OK; }
   }
   set_error("unknown query");
   return SLAB_E_INVALID;

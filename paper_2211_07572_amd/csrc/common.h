@@ -67,6 +67,14 @@ template <> __host__ __device__ __forceinline__ int acc_elem<float>(int r16) { r
 template <> __host__ __device__ __forceinline__ int acc_group<double>(int r16) { return r16 & 3; }
 template <> __host__ __device__ __forceinline__ int acc_elem<double>(int r16) { return r16 >> 2; }
 
+// Global-memory views of pointers.  Pointers read from descriptor tables are
+// generic to the compiler, which then emits flat memory instructions; those
+// share the LDS wait counter, so every wait for an LDS read would also wait
+// for all prefetches in flight.  Kernels convert descriptor pointers once with
+// gp() and work with g_t<T>* (global address space) from there on.
+template <class T> using g_t = __attribute__((address_space(1))) T;
+template <class T> __device__ __forceinline__ g_t<T>* gp(T* p) { return (g_t<T>*)p; }
+
 // Padded slab-block order: BP in {16, 32, 64} >= b.
 inline int padded_block(int b) { return b <= 16 ? 16 : (b <= 32 ? 32 : 64); }
 

@@ -16,6 +16,7 @@
 
 #include <cstring>
 #include <functional>
+#include <memory>
 #include <vector>
 
 namespace slab {
@@ -59,7 +60,7 @@ struct ProbDev {
 // One pivot block of the block factorization.
 struct FactorItem {
   void* S;        // n x n, lower triangle; overwritten by L
-  void* Li;       // n x n, receives L^-1
+  void* Li;       // n x n, receives L^-1 (L L^T = S)
   double* S64;    // optional FP64 copy of S before the factorization
   int* status;
   int n;
@@ -127,7 +128,7 @@ struct Stage2Prob {
   void* Td;
   void* To;
   void* Linv;
-  void* Z;
+  void* Z;        // m-1 blocks: Z_j (Alg. 1) or V_e (odd-even)
   double* S64;
   int* status;
 };
@@ -162,6 +163,25 @@ class Plan {
   // A recorded launch: receives the device base of the uploaded tables.
   typedef std::function<int(const char* dev, hipStream_t st)> Step;
   void step(Step s) { steps_.push_back(std::move(s)); }
+
+  // Optional timing of one class of launches (the block products of stage
+  // two): when set, those launches record an event pair around themselves.
+  struct Timer {
+    std::vector<hipEvent_t> ev;
+    ~Timer() {
+      for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+    // summed milliseconds of the recorded pairs (after a synchronization)
+    double total_ms() const {
+      double t = 0.0;
+      for (size_t i = 0; i + 1 < ev.size(); i += 2) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) == hipSuccess) t += ms;
+      }
+      return t;
+    }
+  };
+  std::shared_ptr<Timer> timer;
 
   size_t bytes() const { return host_.size(); }
   const char* host() const { return host_.data(); }

@@ -45,9 +45,9 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmItem* __restrict__ items
   __shared__ T Bs[2][TK][TN + 4];
   const int itm = group_item(offs, count, blockIdx.x);
   const long long bx = blockIdx.x - offs[itm];
-  const T* __restrict__ A = (const T*)items[itm].A;
-  const T* __restrict__ B = (const T*)items[itm].B;
-  T* C = (T*)items[itm].C;
+  const g_t<const T>* __restrict__ A = gp((const T*)items[itm].A);
+  const g_t<const T>* __restrict__ B = gp((const T*)items[itm].B);
+  g_t<T>* C = gp((T*)items[itm].C);
   const int M = items[itm].M, N = items[itm].N, K = items[itm].K;
   const long long lda = items[itm].lda, ldb = items[itm].ldb, ldc = items[itm].ldc;
   int ti, tj;
@@ -86,7 +86,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmItem* __restrict__ items
       const long long gi = i0 + row, gk = k0 + kk;
       if (VECOK) {
         const bool in = gi < M && gk < kmax;
-        ra[q] = in ? *(const vt*)(!AK ? A + gi * lda + gk : A + gk * lda + gi) : vt(0);
+        ra[q] = in ? *(const g_t<const vt>*)(!AK ? A + gi * lda + gk : A + gk * lda + gi) : vt(0);
         if (in) {  // partial vectors at the edges
 #pragma unroll
           for (int e = 0; e < VEC; ++e)
@@ -109,7 +109,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmItem* __restrict__ items
       const long long gj = j0 + col, gk = k0 + kk;
       if (VECOK) {
         const bool in = gj < N && gk < kmax;
-        rb[q] = in ? *(const vt*)(!BN ? B + gk * ldb + gj : B + gj * ldb + gk) : vt(0);
+        rb[q] = in ? *(const g_t<const vt>*)(!BN ? B + gk * ldb + gj : B + gj * ldb + gk) : vt(0);
         if (in) {
 #pragma unroll
           for (int e = 0; e < VEC; ++e)
@@ -262,7 +262,16 @@ void plan_gemm(Plan& plan, bool ak, bool bn, const std::vector<GemmItem>& items,
   long long tot;
   const size_t oi = plan.add_vec(items), oo = plan.add_offsets(c, &tot);
   const int count = (int)items.size();
+  const std::shared_ptr<Plan::Timer> tm = plan.timer;
   plan.step([=](const char* dev, hipStream_t st) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (tm) {
+      SLAB_HIP_CHECK(hipEventCreate(&e0));
+      SLAB_HIP_CHECK(hipEventCreate(&e1));
+      tm->ev.push_back(e0);
+      tm->ev.push_back(e1);
+      SLAB_HIP_CHECK(hipEventRecord(e0, st));
+    }
     if (tile == 128)
       gemm_tile<T, 128, 16>(ak, bn, vecok, (unsigned)tot, dev_at<GemmItem>(dev, oi),
                             dev_at<int>(dev, oo), count, alpha, beta, flags, st);
@@ -270,6 +279,7 @@ void plan_gemm(Plan& plan, bool ak, bool bn, const std::vector<GemmItem>& items,
       gemm_tile<T, 64, 32>(ak, bn, vecok, (unsigned)tot, dev_at<GemmItem>(dev, oi),
                            dev_at<int>(dev, oo), count, alpha, beta, flags, st);
     SLAB_LAUNCH_CHECK();
+    if (tm) SLAB_HIP_CHECK(hipEventRecord(e1, st));
     return SLAB_OK;
   });
 }
@@ -297,9 +307,9 @@ __global__ __launch_bounds__(256) void k_panel(const FactorItem* __restrict__ it
   typedef typename acc4<T>::type V4;
   const int itm = group_item(offs, count, blockIdx.x);
   const int bx = blockIdx.x - offs[itm];
-  T* __restrict__ S = (T*)items[itm].S;
-  T* __restrict__ Lv = (T*)items[itm].Li;
-  int* __restrict__ status = items[itm].status;
+  g_t<T>* __restrict__ S = gp((T*)items[itm].S);
+  g_t<T>* __restrict__ Lv = gp((T*)items[itm].Li);
+  g_t<int>* __restrict__ status = gp(items[itm].status);
   const int n = items[itm].n, blk = items[itm].blk;
   const int nrow_wg = (n - k0 - min(64, n - k0) + 63) / 64;
   __shared__ T E[64][65];   // L_kk^-1 after the elimination
@@ -450,8 +460,8 @@ __global__ __launch_bounds__(256) void k_rank64(const FactorItem* __restrict__ i
   typedef typename acc4<T>::type V4;
   const int itm = group_item(offs, count, blockIdx.x);
   const int bx = blockIdx.x - offs[itm];
-  T* __restrict__ S = (T*)items[itm].S;
-  T* __restrict__ Lv = (T*)items[itm].Li;
+  g_t<T>* __restrict__ S = gp((T*)items[itm].S);
+  g_t<T>* __restrict__ Lv = gp((T*)items[itm].Li);
   const int n = items[itm].n;
   const int nb = min(64, n - k0);
   const long long ntr = (n - k0 - nb + 63) / 64;
@@ -464,7 +474,7 @@ __global__ __launch_bounds__(256) void k_rank64(const FactorItem* __restrict__ i
   const int wm = wave >> 1, wn = wave & 1;
   const long long base = (long long)k0 + nb;
   long long r0, c0;
-  T* C;
+  g_t<T>* C;
   bool trail = bx < ntrail;
   if (trail) {
     const long long t = bx;
@@ -548,7 +558,7 @@ __global__ void k_identity(const FactorItem* __restrict__ items, const int* __re
                            int count) {
   const int itm = group_item(offs, count, blockIdx.x);
   const long long nwg = offs[itm + 1] - offs[itm];
-  T* __restrict__ X = (T*)items[itm].Li;
+  g_t<T>* __restrict__ X = gp((T*)items[itm].Li);
   const int n = items[itm].n;
   const long long tot = (long long)n * n;
   for (long long e = (blockIdx.x - offs[itm]) * (long long)blockDim.x + threadIdx.x; e < tot;
@@ -563,8 +573,8 @@ __global__ void k_sym_to_f64(const FactorItem* __restrict__ items, const int* __
                              int count) {
   const int itm = group_item(offs, count, blockIdx.x);
   const long long nwg = offs[itm + 1] - offs[itm];
-  const T* __restrict__ S = (const T*)items[itm].S;
-  double* __restrict__ out = items[itm].S64;
+  const g_t<const T>* __restrict__ S = gp((const T*)items[itm].S);
+  g_t<double>* __restrict__ out = gp(items[itm].S64);
   const int n = items[itm].n;
   const long long tot = (long long)n * n;
   for (long long e = (blockIdx.x - offs[itm]) * (long long)blockDim.x + threadIdx.x; e < tot;
@@ -726,85 +736,122 @@ template void plan_stage2<double>(Plan&, const std::vector<Stage2Prob>&, bool);
 // Each lane loads 16 contiguous bytes of M and of x per step, which feed
 // VEC consecutive MFMA k-steps (k permuted consistently in A and B).
 // ---------------------------------------------------------------------------
-constexpr int BMV_WAVES = 16;
-
-
-
-template <typename T, bool TR, bool LOWER>
-__global__ __launch_bounds__(1024) void k_bmv(const BmvItem* __restrict__ items,
-                                             const int* __restrict__ offs, int count, T alpha,
-                                             T beta) {
-  // item: one product; workgroup: 16 rows x 16 columns of it.  xin may alias y.
+// Block-vector products y = beta xin + alpha op(M) x (nrhs <= 16 columns per
+// workgroup column group) of the reduced solve.  These stream n x n blocks
+// from HBM once per product, so the kernel is laid out for bandwidth: a
+// workgroup owns 64 output rows and walks k in chunks; each chunk of op(M)
+// (64 rows x TK) is fetched with 16-byte loads along the block's contiguous
+// dimension (k for M, i for M^T: 256-byte runs), parked in LDS, and consumed
+// by 16x16x4 MFMA tiles (one per wave) while the next chunk is in flight.
+// ---------------------------------------------------------------------------
+template <typename T, bool TR, bool LOWER, bool VECOK>
+__global__ __launch_bounds__(256) void k_bmv(const BmvItem* __restrict__ items,
+                                            const int* __restrict__ offs, int count, T alpha,
+                                            T beta) {
+  typedef typename acc4<T>::type V4;
+  constexpr int VEC = 16 / sizeof(T);
+  constexpr int TM = 64;                      // output rows per workgroup
+  constexpr int TK = 256 / sizeof(T);         // k per chunk: 64 (FP32), 32 (FP64)
+  constexpr int NVA = TM * TK / VEC / 256;    // vectors of op(M) per thread and chunk
+  static_assert(NVA * VEC * 256 == TM * TK && 16 * TK == VEC * 256, "bmv tile");
+  typedef T vt __attribute__((ext_vector_type(VEC)));
+  __shared__ T As[2][TK][TM + 4];
+  __shared__ T Bs[2][TK][16 + 4];
   const int itm = group_item(offs, count, blockIdx.x);
   const int bx = blockIdx.x - offs[itm];
   const int n = items[itm].n, nrhs = items[itm].nrhs;
-  const int nrt = (n + 15) / 16;
+  const int nrt = (n + TM - 1) / TM;
   const int rt = bx % nrt, cg = bx / nrt;
-  const T* __restrict__ M = (const T*)items[itm].M;
-  const T* __restrict__ x = (const T*)items[itm].x + (long long)cg * 16 * n;
-  const T* xin = (const T*)items[itm].xin;
+  const g_t<const T>* __restrict__ M = gp((const T*)items[itm].M);
+  const g_t<const T>* __restrict__ x = gp((const T*)items[itm].x) + (long long)cg * 16 * n;
+  const g_t<const T>* xin = gp((const T*)items[itm].xin);
   if (xin) xin += (long long)cg * 16 * n;
-  T* y = (T*)items[itm].y + (long long)cg * 16 * n;
+  g_t<T>* y = gp((T*)items[itm].y) + (long long)cg * 16 * n;
   const int nc = min(16, nrhs - 16 * cg);
-  typedef typename acc4<T>::type V4;
-  constexpr int VEC = 16 / sizeof(T);   // elements per 16-byte load
-  constexpr int KS = 4 * VEC;           // k covered by one load per lane
-  __shared__ T red[BMV_WAVES][16][17];
-  const int row0 = rt * 16;
+  const int row0 = rt * TM;
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int g = lane >> 4, nn = lane & 15;
+  // op(M)(i, k) is zero for k > i (M lower) or k < i (M^T of a lower M)
   int klo = 0, khi = n;
   if (LOWER) {
-    if (!TR) khi = min(n, row0 + 16);      // M(i,k) = 0 for k > i
-    else klo = row0;                       // M(i,k) = 0 for k < i
+    if (!TR) khi = min(n, row0 + TM);
+    else klo = (row0 / TK) * TK;
   }
-  // split [klo, khi) over the waves in whole KS chunks
-  const int nch = (khi - klo + KS - 1) / KS;
-  const int per = (nch + BMV_WAVES - 1) / BMV_WAVES;
-  const int c_begin = wave * per, c_end = min(nch, c_begin + per);
-  const int row = row0 + nn;
-  const bool rowok = row < n;
-  const bool colok = nn < nc;
-  V4 acc = V4{0, 0, 0, 0};
-#pragma unroll 8
-  for (int ch = c_begin; ch < c_end; ++ch) {
-    const int kb = klo + ch * KS + VEC * g;   // this lane's first k of the chunk
-    T av[VEC], bv[VEC];
-    if (!TR && rowok && kb + VEC <= n && ((((size_t)row * n + kb) * sizeof(T)) & 15) == 0) {
-      typedef T vt __attribute__((ext_vector_type(VEC)));
-      const vt v = *(const vt*)(M + (size_t)row * n + kb);
+  vt ra[NVA], rb;
+  auto load = [&](int k0) __attribute__((always_inline)) {
 #pragma unroll
-      for (int t = 0; t < VEC; ++t) av[t] = v[t];
-    } else {
+    for (int q = 0; q < NVA; ++q) {
+      const int v = tid + 256 * q;
+      int row, kk;
+      if (!TR) { row = v / (TK / VEC); kk = (v % (TK / VEC)) * VEC; }
+      else { kk = v / (TM / VEC); row = (v % (TM / VEC)) * VEC; }
+      const long long gi = row0 + row, gk = k0 + kk;
+      if (VECOK) {
+        const bool in = gi < n && gk < khi;
+        ra[q] = in ? *(const g_t<const vt>*)(!TR ? M + gi * n + gk : M + gk * n + gi) : vt(0);
+      } else {
 #pragma unroll
-      for (int t = 0; t < VEC; ++t) {
-        const int k = kb + t;
-        av[t] = (rowok && k < n) ? (TR ? M[(size_t)k * n + row] : M[(size_t)row * n + k]) : (T)0;
+        for (int e = 0; e < VEC; ++e) {
+          const long long ii = !TR ? gi : gi + e, kq = !TR ? gk + e : gk;
+          ra[q][e] = (ii < n && kq < khi) ? M[!TR ? ii * n + kq : kq * n + ii] : (T)0;
+        }
       }
     }
+    {
+      const int c = tid / (TK / VEC), kk = (tid % (TK / VEC)) * VEC;
+      const long long gk = k0 + kk;
+      if (VECOK) {
+        rb = (c < nc && gk < khi) ? *(const g_t<const vt>*)(x + (long long)c * n + gk) : vt(0);
+      } else {
 #pragma unroll
-    for (int t = 0; t < VEC; ++t) {
-      const int k = kb + t;
-      bv[t] = (colok && k < n) ? x[(size_t)nn * n + k] : (T)0;
+        for (int e = 0; e < VEC; ++e)
+          rb[e] = (c < nc && gk + e < khi) ? x[(long long)c * n + gk + e] : (T)0;
+      }
     }
+  };
+  auto park = [&](int buf) __attribute__((always_inline)) {
 #pragma unroll
-    for (int t = 0; t < VEC; ++t) acc = mfma16(av[t], bv[t], acc);
+    for (int q = 0; q < NVA; ++q) {
+      const int v = tid + 256 * q;
+      if (!TR) {
+        const int row = v / (TK / VEC), kk = (v % (TK / VEC)) * VEC;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) As[buf][kk + e][row] = ra[q][e];
+      } else {
+        const int kk = v / (TM / VEC), row = (v % (TM / VEC)) * VEC;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) As[buf][kk][row + e] = ra[q][e];
+      }
+    }
+    const int c = tid / (TK / VEC), kk = (tid % (TK / VEC)) * VEC;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) Bs[buf][kk + e][c] = rb[e];
+  };
+  V4 acc = V4{0, 0, 0, 0};
+  if (klo < khi) {
+    load(klo);
+    park(0);
+    __syncthreads();
+    int it = 0;
+    for (int k0 = klo; k0 < khi; k0 += TK, ++it) {
+      const int cur = it & 1;
+      const bool more = k0 + TK < khi;
+      if (more) load(k0 + TK);
+#pragma unroll
+      for (int ks = 0; ks < TK / 4; ++ks)
+        acc = mfma16(As[cur][4 * ks + g][16 * wave + nn], Bs[cur][4 * ks + g][nn], acc);
+      if (more) park(cur ^ 1);
+      __syncthreads();
+    }
   }
-  // acc[i]: row 16 blockIdx + acc_row(g, i), column nn; reduce the waves
 #pragma unroll
-  for (int i = 0; i < 4; ++i) red[wave][acc_row<T>(g, i)][nn] = acc[i];
-  __syncthreads();
-  if (tid < 256) {
-    const int rr = tid >> 4, c = tid & 15;
-    const int r = row0 + rr;
-    if (r < n && c < nc) {
-      T sum = (T)0;
-#pragma unroll
-      for (int w = 0; w < BMV_WAVES; ++w) sum += red[w][rr][c];
-      T v = alpha * sum;
-      if (xin) v += beta * xin[(size_t)c * n + r];
-      y[(size_t)c * n + r] = v;
+  for (int i = 0; i < 4; ++i) {
+    const int r = row0 + 16 * wave + acc_row<T>(g, i);
+    if (r < n && nn < nc) {
+      T v = alpha * acc[i];
+      if (xin) v += beta * xin[(long long)nn * n + r];
+      y[(long long)nn * n + r] = v;
     }
   }
 }
@@ -814,16 +861,28 @@ void plan_gemv(Plan& plan, bool tr, bool lower, const std::vector<BmvItem>& item
                T beta) {
   if (items.empty()) return;
   std::vector<int> c;
-  for (const BmvItem& b : items) c.push_back(((b.n + 15) / 16) * ((b.nrhs + 15) / 16));
+  bool vecok = true;
+  const uintptr_t al = 16;
+  for (const BmvItem& b : items) {
+    c.push_back(((b.n + 63) / 64) * ((b.nrhs + 15) / 16));
+    vecok = vecok && b.n % (int)(16 / sizeof(T)) == 0 && ((uintptr_t)b.M % al) == 0 &&
+            ((uintptr_t)b.x % al) == 0;
+  }
   long long tot;
   const size_t oi = plan.add_vec(items), oo = plan.add_offsets(c, &tot);
   const int count = (int)items.size();
   plan.step([=](const char* dev, hipStream_t st) {
     const BmvItem* it = dev_at<BmvItem>(dev, oi);
     const int* of = dev_at<int>(dev, oo);
-#define SLAB_BMV_CASE(TRV, LOV)                                                            \
-  hipLaunchKernelGGL((k_bmv<T, TRV, LOV>), dim3((unsigned)tot), dim3(64 * BMV_WAVES), 0, st, \
-                     it, of, count, alpha, beta)
+#define SLAB_BMV_CASE(TRV, LOV)                                                                 \
+  do {                                                                                          \
+    if (vecok)                                                                                  \
+      hipLaunchKernelGGL((k_bmv<T, TRV, LOV, true>), dim3((unsigned)tot), dim3(256), 0, st, it, \
+                         of, count, alpha, beta);                                               \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_bmv<T, TRV, LOV, false>), dim3((unsigned)tot), dim3(256), 0, st,    \
+                         it, of, count, alpha, beta);                                           \
+  } while (0)
     if (!tr && !lower) SLAB_BMV_CASE(false, false);
     else if (!tr && lower) SLAB_BMV_CASE(false, true);
     else if (tr && !lower) SLAB_BMV_CASE(true, false);

@@ -41,11 +41,11 @@ __global__ __launch_bounds__(256) void k_sweep(const SolveDev* __restrict__ P,
   // descriptor fields copied to locals (the lambdas below capture locals only)
   const int n2 = P[itm].n2, b = P[itm].b, nrhs = P[itm].nrhs;
   const long long ld = P[itm].ld, ldo = P[itm].ldo;
-  const double* __restrict__ wh = P[itm].wh;
-  const double* __restrict__ wv = P[itm].wv;
-  const double* __restrict__ rhs = P[itm].rhs;
-  double* __restrict__ out_g = P[itm].out;
-  T* __restrict__ xbuf = (T*)P[itm].xb;
+  const g_t<const double>* __restrict__ wh = gp(P[itm].wh);
+  const g_t<const double>* __restrict__ wv = gp(P[itm].wv);
+  const g_t<const double>* __restrict__ rhs = gp(P[itm].rhs);
+  g_t<double>* __restrict__ out_g = gp(P[itm].out);
+  g_t<T>* __restrict__ xbuf = gp((T*)P[itm].xb);
   const int tid = threadIdx.x;
   const int i = tid % BP, cl = tid / BP;
   const int c = (bx / m) * NC + cl;
@@ -53,8 +53,8 @@ __global__ __launch_bounds__(256) void k_sweep(const SolveDev* __restrict__ P,
   const bool act = i < b;
   const long long c0 = (long long)s * (b + 1);
   const long long ci = c0 + (act ? i : 0);
-  const T* Gl = (const T*)P[itm].Gl + (size_t)s * n2 * BP * BP;
-  T* zbuf = (T*)P[itm].zbuf + (size_t)s * nrhs * n2 * BP;
+  const g_t<const T>* Gl = gp((const T*)P[itm].Gl) + (size_t)s * n2 * BP * BP;
+  g_t<T>* zbuf = gp((T*)P[itm].zbuf) + (size_t)s * nrhs * n2 * BP;
   const bool acc_out = MODE == 1 && P[itm].accumulate;
 
   // register ring: RAW loaded operands of the next D row steps (no arithmetic on
@@ -79,7 +79,7 @@ __global__ __launch_bounds__(256) void k_sweep(const SolveDev* __restrict__ P,
   auto load_fwd = [&](int d, int r) __attribute__((always_inline)) {
     const int gr = TRANS ? r : r - 1;
     if (gr >= 0) {
-      const T* G = Gl + (size_t)gr * BP * BP;
+      const g_t<const T>* G = Gl + (size_t)gr * BP * BP;
 #pragma unroll
       for (int e = 0; e < GPT; ++e) rg[d][e] = G[tid + 256 * e];
     }
@@ -91,7 +91,7 @@ __global__ __launch_bounds__(256) void k_sweep(const SolveDev* __restrict__ P,
   };
   // backward step r: G = Gl_r, w = W_{r+1}, z = z_r (+ old outputs when accumulating)
   auto load_bwd = [&](int d, int r) __attribute__((always_inline)) {
-    const T* G = Gl + (size_t)r * BP * BP;
+    const g_t<const T>* G = Gl + (size_t)r * BP * BP;
 #pragma unroll
     for (int e = 0; e < GPT; ++e) rg[d][e] = G[tid + 256 * e];
     rw[d] = load_w(r + 1);
@@ -218,9 +218,9 @@ template <typename T, typename TR>
 __global__ void k_coupling(const SolveDev* __restrict__ P, const int* __restrict__ offs,
                            int count) {
   SLAB_ITEM_LOOP(e, tot) {
-    const double* __restrict__ wh = d.wh;
-    const TR* __restrict__ uo = (const TR*)d.ft;
-    T* __restrict__ xb = (T*)d.xb;
+    const g_t<const double>* __restrict__ wh = gp(d.wh);
+    const g_t<const TR>* __restrict__ uo = gp((const TR*)d.ft);
+    g_t<T>* __restrict__ xb = gp((T*)d.xb);
     const long long r = e % n2;
     const long long c = (e / n2) % nrhs;
     const long long s = e / ((long long)n2 * nrhs);
@@ -242,8 +242,8 @@ __global__ void k_interface_out(const SolveDev* __restrict__ P, const int* __res
     const long long r = e % n2;
     const long long c = (e / n2) % nrhs;
     const long long j = e / ((long long)n2 * nrhs);
-    double* o = d.out + c * d.ldo + (j * (b + 1) + b) * n2 + r;
-    const double v = (double)((const TR*)d.ft)[e];
+    g_t<double>* o = gp(d.out) + c * d.ldo + (j * (b + 1) + b) * n2 + r;
+    const double v = (double)gp((const TR*)d.ft)[e];
     *o = d.accumulate ? *o + v : v;
   }
 }
@@ -253,15 +253,15 @@ template <typename T, typename TR>
 __global__ void k_reduced_rhs(const SolveDev* __restrict__ P, const int* __restrict__ offs,
                               int count) {
   SLAB_ITEM_LOOP(e, tot) {
-    const T* __restrict__ xb = (const T*)d.xb;
+    const g_t<const T>* __restrict__ xb = gp((const T*)d.xb);
     const long long r = e % n2;
     const long long c = (e / n2) % nrhs;
     const long long j = e / ((long long)n2 * nrhs);
     const long long cj = j * (b + 1) + b;
-    double v = d.rhs[c * d.ld + cj * n2 + r];
+    double v = gp(d.rhs)[c * d.ld + cj * n2 + r];
     v += (double)xb[((j * 2 + 1) * nrhs + c) * n2 + r];
     if (j + 1 < m) v += (double)xb[(((j + 1) * 2 + 0) * nrhs + c) * n2 + r];
-    ((TR*)d.ft)[e] = (TR)v;
+    gp((TR*)d.ft)[e] = (TR)v;
   }
 }
 #undef SLAB_ITEM_LOOP
@@ -477,12 +477,12 @@ __global__ __launch_bounds__(256) void k_residual(const SolveDev* __restrict__ P
   const int chunks = res_chunks(n1, n2);
   const int c = bx / chunks, blk = bx % chunks;
   const long long ld = P[itm].ldf;
-  const double* __restrict__ wh = P[itm].wh;
-  const double* __restrict__ wv = P[itm].wv;
+  const g_t<const double>* __restrict__ wh = gp(P[itm].wh);
+  const g_t<const double>* __restrict__ wv = gp(P[itm].wv);
   const long long N = (long long)n1 * n2;
-  const double* fc = P[itm].f + c * ld;
-  const double* uc = P[itm].u + c * ld;
-  double* r = P[itm].r;
+  const g_t<const double>* fc = gp(P[itm].f) + c * ld;
+  const g_t<const double>* uc = gp(P[itm].u) + c * ld;
+  g_t<double>* r = gp(P[itm].r);
   double sr = 0.0, sf = 0.0;
   for (long long p = blk * 256LL + threadIdx.x; p < N; p += (long long)chunks * 256) {
     const long long col = p / n2, row = p % n2;
@@ -511,7 +511,7 @@ __global__ __launch_bounds__(256) void k_residual(const SolveDev* __restrict__ P
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    double* partial = P[itm].partial;
+    g_t<double>* partial = gp(P[itm].partial);
     partial[((long long)c * chunks + blk) * 2 + 0] = red[0][0];
     partial[((long long)c * chunks + blk) * 2 + 1] = red[1][0];
   }
@@ -523,14 +523,14 @@ __global__ void k_norms(const SolveDev* __restrict__ P, const int* __restrict__ 
   const int nrhs = P[itm].nrhs;
   if (c >= nrhs) return;
   const int chunks = res_chunks(P[itm].n1, P[itm].n2);
-  const double* __restrict__ partial = P[itm].partial;
+  const g_t<const double>* __restrict__ partial = gp((const double*)P[itm].partial);
   double sr = 0.0, sf = 0.0;
   for (int k = 0; k < chunks; ++k) {
     sr += partial[((long long)c * chunks + k) * 2 + 0];
     sf += partial[((long long)c * chunks + k) * 2 + 1];
   }
-  P[itm].norms[2 * c + 0] = sr;
-  P[itm].norms[2 * c + 1] = sf;
+  gp(P[itm].norms)[2 * c + 0] = sr;
+  gp(P[itm].norms)[2 * c + 1] = sf;
 }
 
 // r = f - A u and the norms of every problem (r of problem i: nrhs x n1 n2,

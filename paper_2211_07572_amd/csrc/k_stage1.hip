@@ -19,8 +19,8 @@ __global__ void k_coef(const ProbDev* __restrict__ P, const int* __restrict__ of
   const ProbDev& d = P[it];
   const long long nwg = offs[it + 1] - offs[it];
   const long long tot = (long long)(d.n1 + 2) * (d.n2 + 2);
-  const double* coef = d.coef;
-  double* kappa = d.kappa;
+  const g_t<const double>* coef = gp(d.coef);
+  g_t<double>* kappa = gp(d.kappa);
   bool bad = false;
   for (long long i = (blockIdx.x - offs[it]) * (long long)blockDim.x + threadIdx.x; i < tot;
        i += nwg * blockDim.x) {
@@ -29,7 +29,7 @@ __global__ void k_coef(const ProbDev* __restrict__ P, const int* __restrict__ of
     if (!(k > 0.0) || !isfinite(k)) bad = true;
     kappa[i] = k;
   }
-  if (bad) d.status[0] = 1;
+  if (bad) gp(d.status)[0] = 1;
 }
 
 // Edge weights w = (kappa_p + kappa_q) / (2 h^2) of the 5-point stencil.
@@ -44,9 +44,9 @@ __global__ void k_weights(const ProbDev* __restrict__ P, const int* __restrict__
   const long long nv = (long long)n1 * (n2 + 1);
   const long long ld = n2 + 2;
   const double hh = d.h * d.h;
-  const double* kappa = d.kappa;
-  double* wh = d.wh;
-  double* wv = d.wv;
+  const g_t<const double>* kappa = gp((const double*)d.kappa);
+  g_t<double>* wh = gp(d.wh);
+  g_t<double>* wv = gp(d.wv);
   for (long long i = (blockIdx.x - offs[it]) * (long long)blockDim.x + threadIdx.x; i < nh + nv;
        i += nwg * blockDim.x) {
     if (i < nh) {
@@ -105,9 +105,9 @@ int launch_maps(int n1, int n2, int b, int32_t* ck, int32_t* sc, int32_t* lc, in
 // interior, b-fastest local order), padded to BP with identity rows.
 // ---------------------------------------------------------------------------
 template <typename T, int BP>
-__device__ __forceinline__ void build_D_row(T (&a)[BP], const double* __restrict__ wh,
-                                            const double* __restrict__ wv, int n2, int b, int c0,
-                                            int r, int lane) {
+__device__ __forceinline__ void build_D_row(T (&a)[BP], const g_t<const double>* __restrict__ wh,
+                                            const g_t<const double>* __restrict__ wv, int n2, int b,
+                                            int c0, int r, int lane) {
   const bool act = lane < b;
   double d = 1.0, wl = 0.0, wr = 0.0;
   if (act) {
@@ -175,12 +175,12 @@ __global__ __launch_bounds__(64) void k_slab_factor(const ProbDev* __restrict__ 
   constexpr int D = 4;         // weight prefetch depth (row steps)
   const int it = group_item(offs, count, blockIdx.x);
   const int bx = blockIdx.x - offs[it];
-  const double* __restrict__ wh = P[it].wh;
-  const double* __restrict__ wv = P[it].wv;
+  const g_t<const double>* __restrict__ wh = gp((const double*)P[it].wh);
+  const g_t<const double>* __restrict__ wv = gp((const double*)P[it].wv);
   const int n2 = P[it].n2, b = P[it].b;
-  T* __restrict__ Gl = (T*)P[it].Gl;
-  T* __restrict__ Hsw = (T*)P[it].Hsw;
-  int* __restrict__ status = P[it].status;
+  g_t<T>* __restrict__ Gl = gp((T*)P[it].Gl);
+  g_t<T>* __restrict__ Hsw = gp((T*)P[it].Hsw);
+  g_t<int>* __restrict__ status = gp(P[it].status);
   const int s = bx >> 1, dir = bx & 1;
   const int lane = threadIdx.x;
   const int i = lane % BP, q = lane / BP;
@@ -267,11 +267,11 @@ __global__ __launch_bounds__(64) void k_slab_factor(const ProbDev* __restrict__ 
 #pragma unroll
         for (int j = 0; j < C; ++j) g[j] = -a[j];
         if (dir == 0) {
-          T* dst = Gl + (((size_t)s * n2 + r) * BP + i) * BP + k0;
+          g_t<T>* dst = Gl + (((size_t)s * n2 + r) * BP + i) * BP + k0;
 #pragma unroll
           for (int j = 0; j < C; ++j) dst[j] = g[j];
         } else {
-          T* dst = Hsw + ((size_t)s * n2 + r) * BP * BP;
+          g_t<T>* dst = Hsw + ((size_t)s * n2 + r) * BP * BP;
 #pragma unroll
           for (int j = 0; j < C; ++j) dst[swz_index<T>(i, k0 + j, BP)] = g[j] * wup[k0 + j];
         }
@@ -296,13 +296,13 @@ __global__ __launch_bounds__(256) void k_sigma(const ProbDev* __restrict__ P,
                                                const int* __restrict__ offs, int count) {
   const int it = group_item(offs, count, blockIdx.x);
   const int bx = blockIdx.x - offs[it];
-  const double* __restrict__ wh = P[it].wh;
-  const double* __restrict__ wv = P[it].wv;
+  const g_t<const double>* __restrict__ wh = gp((const double*)P[it].wh);
+  const g_t<const double>* __restrict__ wv = gp((const double*)P[it].wv);
   const int n2 = P[it].n2, b = P[it].b, m = P[it].m;
-  const T* __restrict__ Gl = (const T*)P[it].Gl;
-  const T* __restrict__ Hsw = (const T*)P[it].Hsw;
-  T* __restrict__ sig = (T*)P[it].sig;
-  int* __restrict__ status = P[it].status;
+  const g_t<const T>* __restrict__ Gl = gp((const T*)P[it].Gl);
+  const g_t<const T>* __restrict__ Hsw = gp((const T*)P[it].Hsw);
+  g_t<T>* __restrict__ sig = gp((T*)P[it].sig);
+  g_t<int>* __restrict__ status = gp(P[it].status);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const long long idx = (long long)bx * 4 + wave;
   const bool valid = idx < (long long)m * n2;
@@ -322,7 +322,7 @@ __global__ __launch_bounds__(256) void k_sigma(const ProbDev* __restrict__ P,
   if (lane < BP) wsh[lane] = wt;
   __syncthreads();
   if (rho > 0 && lane < BP) {
-    const T* G = Gl + (((size_t)s * n2 + rho - 1) * BP + lane) * BP;
+    const g_t<const T>* G = Gl + (((size_t)s * n2 + rho - 1) * BP + lane) * BP;
 #pragma unroll
     for (int k = 0; k < BP; ++k) a[k] -= wt * G[k] * wsh[k];
   }
@@ -330,7 +330,7 @@ __global__ __launch_bounds__(256) void k_sigma(const ProbDev* __restrict__ P,
   if (rho < n2 - 1 && lane < BP) {
     T wb = (T)0;
     if (lane < b) wb = (T)wv[c * (n2 + 1) + rho + 1];
-    const T* H = Hsw + ((size_t)s * n2 + rho + 1) * BP * BP;
+    const g_t<const T>* H = Hsw + ((size_t)s * n2 + rho + 1) * BP * BP;
 #pragma unroll
     for (int k = 0; k < BP; ++k) a[k] -= wb * H[swz_index<T>(lane, k, BP)];
   }
@@ -345,7 +345,7 @@ __global__ __launch_bounds__(256) void k_sigma(const ProbDev* __restrict__ P,
     }
     const double wL = wh[(long long)c0 * n2 + rho];
     const double wR = wh[(long long)(c0 + b) * n2 + rho];
-    T* dst = sig + ((size_t)s * n2 + rho) * 2 * BP;
+    g_t<T>* dst = sig + ((size_t)s * n2 + rho) * 2 * BP;
     dst[lane] = (T)(wL * (double)left);
     dst[BP + lane] = (T)(wR * (double)right);
   }
@@ -373,6 +373,8 @@ __global__ __launch_bounds__(256) void k_schur(const ProbDev* __restrict__ P,
                                                const int* __restrict__ offs, int count) {
   typedef typename acc4<T>::type V4;
   constexpr int NM = BP / 16, NK = BP / 4;
+  // (generic pointers on purpose: with global-space pointers the compiler
+  // interleaves per-load waits with the MFMA chain and the kernel is slower)
   const int it = group_item(offs, count, blockIdx.x);
   const int bx = blockIdx.x - offs[it];
   const double* __restrict__ wh = P[it].wh;
@@ -475,10 +477,11 @@ __global__ __launch_bounds__(256) void k_schur(const ProbDev* __restrict__ P,
 // T64 pointers are given.
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ __forceinline__ double diag_value(const double* __restrict__ wh,
-                                             const double* __restrict__ wv, int n2, int b, int m,
-                                             int j, const T* __restrict__ PRR,
-                                             const T* __restrict__ PLL, int R, int P) {
+__device__ __forceinline__ double diag_value(const g_t<const double>* __restrict__ wh,
+                                             const g_t<const double>* __restrict__ wv, int n2,
+                                             int b, int m, int j,
+                                             const g_t<const T>* __restrict__ PRR,
+                                             const g_t<const T>* __restrict__ PLL, int R, int P) {
   const long long cj = (long long)j * (b + 1) + b;
   double a = 0.0;
   if (R == P)
@@ -498,17 +501,17 @@ __global__ __launch_bounds__(256) void k_assemble(const ProbDev* __restrict__ P,
   __shared__ double tile[32][33];
   const int it = group_item(offs, count, blockIdx.x);
   const int bx = blockIdx.x - offs[it];
-  const double* __restrict__ wh = P[it].wh;
-  const double* __restrict__ wv = P[it].wv;
+  const g_t<const double>* __restrict__ wh = gp((const double*)P[it].wh);
+  const g_t<const double>* __restrict__ wv = gp((const double*)P[it].wv);
   const int n2 = P[it].n2, b = P[it].b, m = P[it].m;
-  const T* __restrict__ PRR = (const T*)P[it].PRR;
-  const T* __restrict__ PLL = (const T*)P[it].PLL;
-  const T* __restrict__ PLR = (const T*)P[it].PLR;
-  const T* __restrict__ PRL = (const T*)P[it].PRL;
-  TO* __restrict__ Tdiag = (TO*)P[it].Td;
-  TO* __restrict__ Toff = (TO*)P[it].To;
-  double* __restrict__ Tdiag64 = P[it].T64;
-  double* __restrict__ Toff64 = P[it].O64;
+  const g_t<const T>* __restrict__ PRR = gp((const T*)P[it].PRR);
+  const g_t<const T>* __restrict__ PLL = gp((const T*)P[it].PLL);
+  const g_t<const T>* __restrict__ PLR = gp((const T*)P[it].PLR);
+  const g_t<const T>* __restrict__ PRL = gp((const T*)P[it].PRL);
+  g_t<TO>* __restrict__ Tdiag = gp((TO*)P[it].Td);
+  g_t<TO>* __restrict__ Toff = gp((TO*)P[it].To);
+  g_t<double>* __restrict__ Tdiag64 = gp(P[it].T64);
+  g_t<double>* __restrict__ Toff64 = gp(P[it].O64);
   // workgroup bx: tile (ti, tj) of block j, kind off (0: T_jj, 1: T_{j,j+1})
   const int ntl = (n2 + 31) / 32;
   const int per = ntl * ntl;

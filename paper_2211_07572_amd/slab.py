@@ -159,7 +159,8 @@ class SlabHandle:
         return v.value
 
     def phase_us(self) -> dict:
-        names = ["slab_factor", "boundary_columns", "schur", "assemble", "block_factor"]
+        names = ["slab_factor", "boundary_columns", "schur", "assemble", "block_factor",
+                 "block_products"]
         return {n: self.query(10 + i) for i, n in enumerate(names)}
 
 
@@ -366,7 +367,8 @@ class SlabBatch:
         return v.value
 
     def phase_us(self) -> dict:
-        names = ["slab_factor", "boundary_columns", "schur", "assemble", "block_factor"]
+        names = ["slab_factor", "boundary_columns", "schur", "assemble", "block_factor",
+                 "block_products"]
         return {n: self.query(10 + i) for i, n in enumerate(names)}
 
     def free(self):
