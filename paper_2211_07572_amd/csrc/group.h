@@ -32,6 +32,16 @@ __device__ __forceinline__ int group_item(const int* __restrict__ offs, int coun
   return lo;
 }
 
+// Workgroups are handed to the eight XCDs round-robin by blockIdx.x, and each
+// XCD has an L2 of its own.  This renumbering gives XCD x the contiguous range
+// [x*G/8, (x+1)*G/8) of virtual indices (G = gridDim.x; a tail of G % 8
+// workgroups keeps its index), so that workgroups running side by side on one
+// XCD take neighbouring tiles and share their operand panels in its L2.
+__device__ __forceinline__ int xcd_linear(int bx, int G) {
+  const int per = G >> 3;
+  return bx < (per << 3) ? (bx & 7) * per + (bx >> 3) : bx;
+}
+
 // ---- descriptors ----------------------------------------------------------------
 
 // One problem of stage one (edge weights, slab factors, Schur pieces, assembly).

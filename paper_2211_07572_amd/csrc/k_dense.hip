@@ -18,8 +18,12 @@
 namespace slab {
 
 // ---------------------------------------------------------------------------
-// Tiled MFMA GEMM: C = beta*C + alpha * op(A) op(B) for gridDim.z independent
-// products (operands sa, sb, sc elements apart).
+// Tiled MFMA GEMM: C = beta*C + alpha * op(A) op(B) for a group of independent
+// products (one GemmItem each, grouped launch).
+// Tiles are numbered per XCD (xcd_linear) and, inside a product, in bands of
+// eight tile rows walked column by column, so that the workgroups resident on
+// one XCD at a time cover a near-square block of C and read each A and B panel
+// once into that XCD's L2.
 // TILE x TILE output tile per workgroup, four waves of (TILE/2)^2, k chunks of
 // TK.  The next chunk is loaded into registers (16-byte vector loads when the
 // leading dimensions allow) while the current one is multiplied out of LDS;
@@ -43,8 +47,10 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmItem* __restrict__ items
   typedef T vt __attribute__((ext_vector_type(VEC)));
   __shared__ T As[2][TK][TM + 4];
   __shared__ T Bs[2][TK][TN + 4];
-  const int itm = group_item(offs, count, blockIdx.x);
-  const long long bx = blockIdx.x - offs[itm];
+  // products with a lower-triangular A keep the plain order (measured faster)
+  const int vb = (flags & GEMM_A_LOWER) ? (int)blockIdx.x : xcd_linear(blockIdx.x, gridDim.x);
+  const int itm = group_item(offs, count, vb);
+  const long long bx = vb - offs[itm];
   const g_t<const T>* __restrict__ A = gp((const T*)items[itm].A);
   const g_t<const T>* __restrict__ B = gp((const T*)items[itm].B);
   g_t<T>* C = gp((T*)items[itm].C);
@@ -60,11 +66,18 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmItem* __restrict__ items
     tj = (int)(t - (long long)r * (r + 1) / 2);
   } else {
     const int tm = (M + TM - 1) / TM, tn = (N + TN - 1) / TN;
-    // with A lower triangular the last tile rows carry the longest k ranges:
-    // hand them out first
-    ti = (int)(bx / tn);
-    if (flags & GEMM_A_LOWER) ti = tm - 1 - ti;
-    tj = (int)(bx % tn);
+    if (flags & GEMM_A_LOWER) {
+      // the last tile rows carry the longest k ranges: hand them out first
+      ti = tm - 1 - (int)(bx / tn);
+      tj = (int)(bx % tn);
+    } else {
+      constexpr int BAND = 8;
+      const int band = (int)(bx / (BAND * tn));
+      const int pos = (int)(bx - (long long)band * BAND * tn);
+      const int rows = min(BAND, tm - band * BAND);
+      ti = band * BAND + pos % rows;
+      tj = pos / rows;
+    }
   }
   const int i0 = ti * TM, j0 = tj * TN;
   const int tid = threadIdx.x;
@@ -85,13 +98,10 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmItem* __restrict__ items
       else { kk = v / (TM / VEC); row = (v % (TM / VEC)) * VEC; }
       const long long gi = i0 + row, gk = k0 + kk;
       if (VECOK) {
-        const bool in = gi < M && gk < kmax;
-        ra[q] = in ? *(const g_t<const vt>*)(!AK ? A + gi * lda + gk : A + gk * lda + gi) : vt(0);
-        if (in) {  // partial vectors at the edges
-#pragma unroll
-          for (int e = 0; e < VEC; ++e)
-            if (!AK ? (gk + e >= kmax) : (gi + e >= M)) ra[q][e] = (T)0;
-        }
+        // nothing here may touch the loaded value (that would wait for the
+        // load): elements outside the operand are zeroed in park()
+        if (gi < M && gk < kmax)
+          ra[q] = *(const g_t<const vt>*)(!AK ? A + gi * lda + gk : A + gk * lda + gi);
       } else {
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
@@ -108,13 +118,8 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmItem* __restrict__ items
       else { col = v / (TK / VEC); kk = (v % (TK / VEC)) * VEC; }
       const long long gj = j0 + col, gk = k0 + kk;
       if (VECOK) {
-        const bool in = gj < N && gk < kmax;
-        rb[q] = in ? *(const g_t<const vt>*)(!BN ? B + gk * ldb + gj : B + gj * ldb + gk) : vt(0);
-        if (in) {
-#pragma unroll
-          for (int e = 0; e < VEC; ++e)
-            if (!BN ? (gj + e >= N) : (gk + e >= kmax)) rb[q][e] = (T)0;
-        }
+        if (gj < N && gk < kmax)
+          rb[q] = *(const g_t<const vt>*)(!BN ? B + gk * ldb + gj : B + gj * ldb + gk);
       } else {
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
@@ -124,27 +129,37 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmItem* __restrict__ items
       }
     }
   };
-  auto park = [&](int buf) __attribute__((always_inline)) {
+  // store the chunk loaded for k0 into LDS buffer buf; with vector loads the
+  // elements outside op(A) / op(B) (also those of a skipped load) become zero
+  auto park = [&](int buf, int k0) __attribute__((always_inline)) {
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
       const int v = tid + 256 * q;
       if (!AK) {
         const int row = v / (TK / VEC), kk = (v % (TK / VEC)) * VEC;
+        const bool rin = i0 + row < M;
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) As[buf][kk + e][row] = ra[q][e];
+        for (int e = 0; e < VEC; ++e)
+          As[buf][kk + e][row] = (!VECOK || (rin && k0 + kk + e < kmax)) ? ra[q][e] : (T)0;
       } else {
         const int kk = v / (TM / VEC), row = (v % (TM / VEC)) * VEC;
+        const bool kin = k0 + kk < kmax;
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) As[buf][kk][row + e] = ra[q][e];
+        for (int e = 0; e < VEC; ++e)
+          As[buf][kk][row + e] = (!VECOK || (kin && i0 + row + e < M)) ? ra[q][e] : (T)0;
       }
       if (!BN) {
         const int kk = v / (TN / VEC), col = (v % (TN / VEC)) * VEC;
+        const bool kin = k0 + kk < kmax;
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) Bs[buf][kk][col + e] = rb[q][e];
+        for (int e = 0; e < VEC; ++e)
+          Bs[buf][kk][col + e] = (!VECOK || (kin && j0 + col + e < N)) ? rb[q][e] : (T)0;
       } else {
         const int col = v / (TK / VEC), kk = (v % (TK / VEC)) * VEC;
+        const bool cin = j0 + col < N;
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) Bs[buf][kk + e][col] = rb[q][e];
+        for (int e = 0; e < VEC; ++e)
+          Bs[buf][kk + e][col] = (!VECOK || (cin && k0 + kk + e < kmax)) ? rb[q][e] : (T)0;
       }
     }
   };
@@ -155,30 +170,34 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmItem* __restrict__ items
 #pragma unroll
     for (int b = 0; b < FN; ++b) acc[a][b] = V4{0, 0, 0, 0};
 
+  auto multiply = [&](int cur) __attribute__((always_inline)) {
+#pragma unroll
+    for (int ks = 0; ks < TK / 4; ++ks) {
+      T av[FM], bv[FN];
+#pragma unroll
+      for (int mt = 0; mt < FM; ++mt) av[mt] = As[cur][4 * ks + g][wm * (TM / 2) + 16 * mt + nn];
+#pragma unroll
+      for (int nt = 0; nt < FN; ++nt) bv[nt] = Bs[cur][4 * ks + g][wn * (TN / 2) + 16 * nt + nn];
+#pragma unroll
+      for (int mt = 0; mt < FM; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < FN; ++nt) acc[mt][nt] = mfma16(av[mt], bv[nt], acc[mt][nt]);
+    }
+  };
   if (kmin < kmax) {
     load(kmin);
-    park(0);
+    park(0, kmin);
     __syncthreads();
-    int it = 0;
-    for (int k0 = kmin; k0 < kmax; k0 += TK, ++it) {
-      const int cur = it & 1;
-      const bool more = k0 + TK < kmax;
-      if (more) load(k0 + TK);
-#pragma unroll
-      for (int ks = 0; ks < TK / 4; ++ks) {
-        T av[FM], bv[FN];
-#pragma unroll
-        for (int mt = 0; mt < FM; ++mt) av[mt] = As[cur][4 * ks + g][wm * (TM / 2) + 16 * mt + nn];
-#pragma unroll
-        for (int nt = 0; nt < FN; ++nt) bv[nt] = Bs[cur][4 * ks + g][wn * (TN / 2) + 16 * nt + nn];
-#pragma unroll
-        for (int mt = 0; mt < FM; ++mt)
-#pragma unroll
-          for (int nt = 0; nt < FN; ++nt) acc[mt][nt] = mfma16(av[mt], bv[nt], acc[mt][nt]);
-      }
-      if (more) park(cur ^ 1);
+    // the last chunk is peeled off, so that every pass through the loop
+    // stores what it loaded and no load is outstanding at the loop head
+    int cur = 0, k0 = kmin;
+    for (; k0 + TK < kmax; k0 += TK, cur ^= 1) {
+      load(k0 + TK);
+      multiply(cur);
+      park(cur ^ 1, k0 + TK);
       __syncthreads();
     }
+    multiply(cur);
   }
 #pragma unroll
   for (int mt = 0; mt < FM; ++mt)
@@ -318,6 +337,10 @@ __global__ __launch_bounds__(256) void k_panel(const FactorItem* __restrict__ it
   __shared__ T colbuf[2][64];
   const int nb = min(64, n - k0);
   const int tid = threadIdx.x;
+  const bool rows = bx < nrow_wg;
+  const long long r0 = (long long)k0 + nb + (long long)bx * 64;  // rows case
+  const long long c0 = (long long)(bx - nrow_wg) * 64;            // columns case
+  const long long ncols = (long long)k0 + nb;
   // thread (row i, column quarter q) keeps 16 entries of the working matrix in registers
   const int i = tid & 63, q = tid >> 6;
   T a[16];
@@ -327,6 +350,19 @@ __global__ __launch_bounds__(256) void k_panel(const FactorItem* __restrict__ it
     T v = (i == col) ? (T)1 : (T)0;
     if (i < nb && col < nb) v = S[(long long)(k0 + max(i, col)) * n + k0 + min(i, col)];
     a[c] = v;
+  }
+  // the operand tile (rows case: rows r0.. of the panel columns; columns
+  // case: the panel rows of the carried inverse) is fetched into registers
+  // after the diagonal block, so that waiting for the block leaves these
+  // loads in flight, and stored to LDS after the elimination below
+  // (the loads are unconditional, from clamped indices: a load skipped on
+  // some lanes would make the wait for the diagonal block wait for all)
+  T tb[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int e = tid + 256 * u, hi = e >> 6, lo = min(e & 63, nb - 1);
+    if (rows) tb[u] = S[min(r0 + hi, (long long)n - 1) * n + k0 + lo];
+    else tb[u] = Lv[(long long)(k0 + min(hi, nb - 1)) * n + min(c0 + (e & 63), ncols - 1)];
   }
   if (i == 0) {
 #pragma unroll
@@ -395,20 +431,12 @@ __global__ __launch_bounds__(256) void k_panel(const FactorItem* __restrict__ it
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = V4{0, 0, 0, 0};
-  const bool rows = bx < nrow_wg;
-  const long long r0 = (long long)k0 + nb + (long long)bx * 64;  // rows case
-  const long long c0 = (long long)(bx - nrow_wg) * 64;            // columns case
-  const long long ncols = (long long)k0 + nb;
-  if (rows) {
-    for (int e = tid; e < 64 * 64; e += 256) {
-      const int rr = e >> 6, t = e & 63;
-      Bt[rr][t] = (r0 + rr < n && t < nb) ? S[(r0 + rr) * n + k0 + t] : (T)0;
-    }
-  } else {
-    for (int e = tid; e < 64 * 64; e += 256) {
-      const int t = e >> 6, cc = e & 63;
-      Bt[t][cc] = (t < nb && c0 + cc < ncols) ? Lv[(long long)(k0 + t) * n + c0 + cc] : (T)0;
-    }
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int e = tid + 256 * u, hi = e >> 6, lo = e & 63;
+    // rows case Bt[rr][t], columns case Bt[t][cc]; zero outside the operand
+    const bool in = rows ? (r0 + hi < n && lo < nb) : (hi < nb && c0 + lo < ncols);
+    Bt[hi][lo] = in ? tb[u] : (T)0;
   }
   __syncthreads();
 #pragma unroll 4
@@ -492,23 +520,6 @@ __global__ __launch_bounds__(256) void k_rank64(const FactorItem* __restrict__ i
     C = Lv;
   }
   const long long cmax = trail ? n : base;
-  // A: L rows r0.., panel columns
-  for (int e = tid; e < 64 * 64; e += 256) {
-    const int rr = e >> 6, k = e & 63;
-    As[rr][k] = (r0 + rr < n && k < nb) ? S[(r0 + rr) * n + k0 + k] : (T)0;
-  }
-  // B: trailing -> L rows c0.. (B(k, j) = L[j][k]); carried -> X_k rows (B(k, c) = X[k0+k][c])
-  if (trail) {
-    for (int e = tid; e < 64 * 64; e += 256) {
-      const int cc = e >> 6, k = e & 63;
-      Bs[cc][k] = (c0 + cc < n && k < nb) ? S[(c0 + cc) * n + k0 + k] : (T)0;
-    }
-  } else {
-    for (int e = tid; e < 64 * 64; e += 256) {
-      const int k = e >> 6, cc = e & 63;
-      Bs[cc][k] = (k < nb && c0 + cc < cmax) ? Lv[(long long)(k0 + k) * n + c0 + cc] : (T)0;
-    }
-  }
   // C is loaded up front; the 64 products are summed first and subtracted once
   // (adding them one by one into the larger C would lose accuracy in FP32)
   T cin[2][2][4];
@@ -522,6 +533,25 @@ __global__ __launch_bounds__(256) void k_rank64(const FactorItem* __restrict__ i
         const long long col = c0 + wn * 32 + 16 * nt + nn;
         cin[mt][nt][i] = (row < n && col < cmax) ? C[row * n + col] : (T)0;
       }
+  // all operand loads are issued before the first LDS store, so that their
+  // latencies overlap
+  // A: L rows r0.., panel columns
+  // B: trailing -> L rows c0.. (B(k, j) = L[j][k]); carried -> X_k rows (B(k, c) = X[k0+k][c])
+  T ta[16], tb[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int e = tid + 256 * u, hi = e >> 6, lo = e & 63;
+    ta[u] = (r0 + hi < n && lo < nb) ? S[(r0 + hi) * n + k0 + lo] : (T)0;
+    if (trail) tb[u] = (c0 + hi < n && lo < nb) ? S[(c0 + hi) * n + k0 + lo] : (T)0;
+    else tb[u] = (hi < nb && c0 + lo < cmax) ? Lv[(long long)(k0 + hi) * n + c0 + lo] : (T)0;
+  }
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int e = tid + 256 * u, hi = e >> 6, lo = e & 63;
+    As[hi][lo] = ta[u];
+    if (trail) Bs[hi][lo] = tb[u];
+    else Bs[lo][hi] = tb[u];
+  }
   V4 acc[2][2];
 #pragma unroll
   for (int mt = 0; mt < 2; ++mt)
