@@ -72,6 +72,20 @@ template <> __host__ __device__ __forceinline__ int acc_elem<double>(int r16) { 
 // share the LDS wait counter, so every wait for an LDS read would also wait
 // for all prefetches in flight.  Kernels convert descriptor pointers once with
 // gp() and work with g_t<T>* (global address space) from there on.
+// Reciprocal for pivots on the critical path of sequential eliminations: the
+// hardware estimate refined by Newton steps r <- r + r (1 - x r) (two for
+// FP64, one for FP32), a few dependent instructions instead of the IEEE
+// division sequence; the result is within about one ulp of 1/x.
+__device__ __forceinline__ double fast_recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+  return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ float fast_recip(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  return __builtin_fmaf(r, __builtin_fmaf(-x, r, 1.0f), r);
+}
+
 template <class T> using g_t = __attribute__((address_space(1))) T;
 template <class T> __device__ __forceinline__ g_t<T>* gp(T* p) { return (g_t<T>*)p; }
 

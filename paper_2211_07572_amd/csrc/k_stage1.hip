@@ -172,7 +172,8 @@ __global__ __launch_bounds__(64) void k_slab_factor(const ProbDev* __restrict__ 
                                                     const int* __restrict__ offs, int count) {
   constexpr int R = 64 / BP;   // lanes per row
   constexpr int C = BP / R;    // columns per lane
-  constexpr int D = 4;         // weight prefetch depth (row steps)
+  constexpr int D = 1;         // weight prefetch depth (row steps): one row step
+                               // (an elimination) outlasts a memory latency
   const int it = group_item(offs, count, blockIdx.x);
   const int bx = blockIdx.x - offs[it];
   const g_t<const double>* __restrict__ wh = gp((const double*)P[it].wh);
@@ -195,13 +196,15 @@ __global__ __launch_bounds__(64) void k_slab_factor(const ProbDev* __restrict__ 
   for (int j = 0; j < C; ++j) g[j] = (T)0;
   // raw edge weights of row r: wh left/right of the node, wv below/above
   double rl[D], rr[D], rd[D], ru[D];
+  // unconditional loads from clamped rows (a load skipped on some path makes
+  // the compiler wait for every outstanding load); masked where used
   auto load = [&](int d, int t) __attribute__((always_inline)) {
-    const int r = dir == 0 ? t : n2 - 1 - t;
-    const bool ld = act && t < n2;
-    rl[d] = ld ? wh[c * n2 + r] : 0.0;
-    rr[d] = ld ? wh[(c + 1) * n2 + r] : 0.0;
-    rd[d] = ld ? wv[c * (n2 + 1) + r] : 0.0;
-    ru[d] = ld ? wv[c * (n2 + 1) + r + 1] : 0.0;
+    const int tc = min(t, n2 - 1);
+    const int r = dir == 0 ? tc : n2 - 1 - tc;
+    rl[d] = wh[c * n2 + r];
+    rr[d] = wh[(c + 1) * n2 + r];
+    rd[d] = wv[c * (n2 + 1) + r];
+    ru[d] = wv[c * (n2 + 1) + r + 1];
   };
 #pragma unroll
   for (int d = 0; d < D; ++d) load(d, d);
@@ -217,10 +220,10 @@ __global__ __launch_bounds__(64) void k_slab_factor(const ProbDev* __restrict__ 
         const T dd = act ? (T)(whl + whr + wvd + wvu) : (T)1;
         const T wl = (act && i > 0) ? (T)whl : (T)0;
         const T wr = (act && i < b - 1) ? (T)whr : (T)0;
-        const T wc = (t > 0) ? (T)(dir == 0 ? wvd : wvu) : (T)0;
+        const T wc = (act && t > 0) ? (T)(dir == 0 ? wvd : wvu) : (T)0;
         if (q == 0) {
           wsh[i] = wc;
-          wup[i] = (T)wvd;
+          wup[i] = act ? (T)wvd : (T)0;
         }
         __syncthreads();
         // row i of D_r - W G W (columns k0 .. k0+C-1)
@@ -240,7 +243,7 @@ __global__ __launch_bounds__(64) void k_slab_factor(const ProbDev* __restrict__ 
           const int buf = p & 1;
           const T dp = colbuf[buf][p];
           ok = ok && (dp > (T)0) && isfinite((double)dp);
-          const T inv = (T)1 / dp;
+          const T inv = fast_recip(dp);
           // all LDS reads first, unconditionally (no read inside a divergent branch)
           T cb[C];
 #pragma unroll
