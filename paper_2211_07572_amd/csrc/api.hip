@@ -227,6 +227,11 @@ struct Workspace {
   double* r = nullptr;
   double* norms = nullptr;
   double* partial = nullptr;
+  // refined reduced solve (mixed precision): FP64 right-hand side, solution
+  // and residual of the reduced system
+  double* g64 = nullptr;
+  double* u64 = nullptr;
+  double* r64 = nullptr;
 };
 
 struct slab_handle_s {
@@ -313,6 +318,11 @@ void workspace_layout(slab_handle h, int nrhs, Layout& L) {
   L.add(&w.r, nrhs * N * sizeof(double));
   L.add(&w.norms, 2 * nrhs * sizeof(double));
   L.add(&w.partial, residual_partial_count(h->n1, h->n2, nrhs) * sizeof(double));
+  if (h->precision == SLAB_MIXED) {
+    L.add(&w.g64, m * nrhs * n * sizeof(double));
+    L.add(&w.u64, m * nrhs * n * sizeof(double));
+    L.add(&w.r64, m * nrhs * n * sizeof(double));
+  }
 }
 
 int ensure_workspaces(const std::vector<std::pair<slab_handle, int>>& need, Owner& mem) {
@@ -363,11 +373,13 @@ void persistent_layout(slab_handle h, Layout& L) {
   L.add(&h->Linv, m * nsq * e2);
   L.add(&h->Z, (m > 1 ? m - 1 : 1) * nsq * e2);
   if (h->odd_even) L.add(&h->Td, m * nsq * e2);
-  if (h->flags & SLAB_KEEP_REDUCED) {
+  // FP64 reduced blocks: exported on request, and always kept in mixed
+  // precision, where the reduced solve is refined against them
+  if ((h->flags & SLAB_KEEP_REDUCED) || h->precision == SLAB_MIXED) {
     L.add(&h->T64, m * nsq * sizeof(double));
     L.add(&h->O64, (m > 1 ? m - 1 : 1) * nsq * sizeof(double));
-    L.add(&h->S64, m * nsq * sizeof(double));
   }
+  if (h->flags & SLAB_KEEP_REDUCED) L.add(&h->S64, m * nsq * sizeof(double));
 }
 
 // Memory a handle needs only while it is factored (Schur pieces, propagators,
@@ -566,8 +578,14 @@ void plan_pass(Plan& p, const std::vector<SolveJob>& jobs, bool first, bool tran
     d.f = j.f; d.u = j.u; d.r = h->ws.r; d.ldf = j.ld; d.norms = h->ws.norms;
     d.partial = h->ws.partial;
     ReducedDev& r = red[i];
+    std::memset(&r, 0, sizeof(r));
     r.n = h->n2; r.m = h->m; r.nrhs = j.nrhs; r.Linv = h->Linv; r.Z = h->Z; r.Td = h->Td;
     r.ft = h->ws.ft; r.yt = h->ws.yt; r.tt = h->ws.tt;
+    if (h->precision == SLAB_MIXED) {
+      r.T64 = h->T64; r.O64 = h->O64;
+      r.g64 = h->ws.g64; r.u64 = h->ws.u64; r.r64 = h->ws.r64;
+      d.g64 = h->ws.g64; d.uo64 = h->ws.u64;
+    }
   }
   plan_solve_pass<T, TR>(p, sd, red, trans, jobs[0].h->odd_even != 0);
   // the transposed residual equals A^T u = A u (A is symmetric)

@@ -118,6 +118,10 @@ struct SolveDev {
   long long ldf;   // f and u leading dimension
   double* norms;
   double* partial;
+  // refined reduced solve (FP64 reduced right-hand side out, FP64 interface
+  // values in); null when the reduced system is solved in one go
+  double* g64;
+  const double* uo64;
 };
 
 // Reduced system of one problem in a solve pass (block factors from stage two
@@ -130,6 +134,14 @@ struct ReducedDev {
   void* ft;         // in: f~, out: the interface values
   void* yt;
   void* tt;         // nrhs x n temporary
+  // refinement against the FP64 reduced matrix (null T64: none): diagonal
+  // blocks T64[j], couplings O64[j] = T_{j,j+1}; FP64 right-hand side g64,
+  // solution u64 and residual r64, all [j][c][r]
+  const double* T64;
+  const double* O64;
+  double* g64;
+  double* u64;
+  double* r64;
 };
 
 // Stage two of one problem (see plan_stage2).

@@ -220,13 +220,15 @@ __global__ void k_coupling(const SolveDev* __restrict__ P, const int* __restrict
   SLAB_ITEM_LOOP(e, tot) {
     const g_t<const double>* __restrict__ wh = gp(d.wh);
     const g_t<const TR>* __restrict__ uo = gp((const TR*)d.ft);
+    const g_t<const double>* __restrict__ u64 = gp(d.uo64);
+    auto uval = [&](long long i) -> double { return u64 ? u64[i] : (double)uo[i]; };
     g_t<T>* __restrict__ xb = gp((T*)d.xb);
     const long long r = e % n2;
     const long long c = (e / n2) % nrhs;
     const long long s = e / ((long long)n2 * nrhs);
     const long long c0 = s * (b + 1);
-    const double right = wh[(c0 + b) * n2 + r] * (double)uo[(s * nrhs + c) * n2 + r];
-    double left = s > 0 ? wh[c0 * n2 + r] * (double)uo[((s - 1) * nrhs + c) * n2 + r] : 0.0;
+    const double right = wh[(c0 + b) * n2 + r] * uval((s * nrhs + c) * n2 + r);
+    double left = s > 0 ? wh[c0 * n2 + r] * uval(((s - 1) * nrhs + c) * n2 + r) : 0.0;
     if (b == 1) left += right;
     xb[((s * 2 + 0) * nrhs + c) * n2 + r] = (T)left;
     xb[((s * 2 + 1) * nrhs + c) * n2 + r] = (T)right;
@@ -243,12 +245,13 @@ __global__ void k_interface_out(const SolveDev* __restrict__ P, const int* __res
     const long long c = (e / n2) % nrhs;
     const long long j = e / ((long long)n2 * nrhs);
     g_t<double>* o = gp(d.out) + c * d.ldo + (j * (b + 1) + b) * n2 + r;
-    const double v = (double)gp((const TR*)d.ft)[e];
+    const double v = d.uo64 ? gp(d.uo64)[e] : (double)gp((const TR*)d.ft)[e];
     *o = d.accumulate ? *o + v : v;
   }
 }
 
-// f~_j = f_o(j) + xb[j][right] + xb[j+1][left]   (FP64 sum, stored in TR)
+// f~_j = f_o(j) + xb[j][right] + xb[j+1][left]   (FP64 sum, stored in TR, and
+// in FP64 too when the reduced solve is refined)
 template <typename T, typename TR>
 __global__ void k_reduced_rhs(const SolveDev* __restrict__ P, const int* __restrict__ offs,
                               int count) {
@@ -262,6 +265,7 @@ __global__ void k_reduced_rhs(const SolveDev* __restrict__ P, const int* __restr
     v += (double)xb[((j * 2 + 1) * nrhs + c) * n2 + r];
     if (j + 1 < m) v += (double)xb[(((j + 1) * 2 + 0) * nrhs + c) * n2 + r];
     gp((TR*)d.ft)[e] = (TR)v;
+    if (d.g64) gp(d.g64)[e] = v;
   }
 }
 #undef SLAB_ITEM_LOOP
@@ -394,6 +398,85 @@ static void plan_sweep(Plan& plan, const std::vector<SolveDev>& probs, size_t pd
   });
 }
 
+// Elementwise steps of the refined reduced solve, m * nrhs * n entries per
+// problem in its own workgroups of a grouped launch:
+//   MODE 0: u64 = x      MODE 1: u64 += x      (x = the TR solve in ft)
+//   MODE 2: ft = (TR) r64
+template <typename TR, int MODE>
+__global__ void k_red_step(const ReducedDev* __restrict__ R, const int* __restrict__ offs,
+                           int count) {
+  const int itm = group_item(offs, count, blockIdx.x);
+  const long long nwg = offs[itm + 1] - offs[itm];
+  const ReducedDev& d = R[itm];
+  const long long tot = (long long)d.m * d.nrhs * d.n;
+  g_t<TR>* __restrict__ ft = gp((TR*)d.ft);
+  g_t<double>* __restrict__ u64 = gp(d.u64);
+  const g_t<const double>* __restrict__ r64 = gp((const double*)d.r64);
+  for (long long e = (blockIdx.x - offs[itm]) * (long long)blockDim.x + threadIdx.x; e < tot;
+       e += nwg * blockDim.x) {
+    if (MODE == 0) u64[e] = (double)ft[e];
+    else if (MODE == 1) u64[e] += (double)ft[e];
+    else ft[e] = (TR)r64[e];
+  }
+}
+
+// Reduced solve refined against the FP64 reduced matrix (mixed precision):
+// u = T~^-1 f~ with the TR factorization, then `steps` times
+//   r = f~ - T u  (FP64, T block tridiagonal from T64 / O64),  u += T~^-1 r.
+// Each step multiplies the error by about the relative accuracy of the TR
+// factorization, so the interface values reach FP64 accuracy without
+// repeating the slab sweeps.  The result is left in u64.
+template <typename TR>
+static void plan_reduced_refined(Plan& plan, const std::vector<ReducedDev>& R, bool odd_even,
+                                 int steps) {
+  std::vector<int> cw;
+  for (const ReducedDev& r : R) cw.push_back((int)item_wgs((long long)r.m * r.nrhs * r.n));
+  long long tw;
+  const size_t ow = plan.add_offsets(cw, &tw), orr = plan.add_vec(R);
+  const int count = (int)R.size();
+  auto elementwise = [&](int mode) {
+    plan.step([=](const char* dev, hipStream_t st) {
+      const ReducedDev* P = dev_at<ReducedDev>(dev, orr);
+      const int* of = dev_at<int>(dev, ow);
+      if (mode == 0) hipLaunchKernelGGL((k_red_step<TR, 0>), dim3((unsigned)tw), dim3(256), 0, st, P, of, count);
+      else if (mode == 1) hipLaunchKernelGGL((k_red_step<TR, 1>), dim3((unsigned)tw), dim3(256), 0, st, P, of, count);
+      else hipLaunchKernelGGL((k_red_step<TR, 2>), dim3((unsigned)tw), dim3(256), 0, st, P, of, count);
+      SLAB_LAUNCH_CHECK();
+      return SLAB_OK;
+    });
+  };
+  auto item = [](const void* M, const void* x, const void* xin, void* y, int n, int nrhs) {
+    BmvItem b;
+    b.M = M; b.x = x; b.xin = xin; b.y = y; b.n = n; b.nrhs = nrhs;
+    return b;
+  };
+  plan_reduced<TR>(plan, R, odd_even);
+  elementwise(0);
+  for (int it = 0; it < steps; ++it) {
+    // r_j = g_j - T_jj u_j - T_{j,j+1} u_{j+1} - T_{j-1,j}^T u_{j-1}
+    std::vector<BmvItem> dg, up, lo;
+    for (const ReducedDev& r : R) {
+      const long long nsq = (long long)r.n * r.n, vs = (long long)r.nrhs * r.n;
+      for (int j = 0; j < r.m; ++j) {
+        dg.push_back(item(r.T64 + j * nsq, r.u64 + j * vs, r.g64 + j * vs, r.r64 + j * vs, r.n,
+                          r.nrhs));
+        if (j + 1 < r.m)
+          up.push_back(item(r.O64 + j * nsq, r.u64 + (j + 1) * vs, r.r64 + j * vs,
+                            r.r64 + j * vs, r.n, r.nrhs));
+        if (j >= 1)
+          lo.push_back(item(r.O64 + (j - 1) * nsq, r.u64 + (j - 1) * vs, r.r64 + j * vs,
+                            r.r64 + j * vs, r.n, r.nrhs));
+      }
+    }
+    plan_gemv<double>(plan, false, false, dg, -1.0, 1.0);
+    plan_gemv<double>(plan, false, false, up, -1.0, 1.0);
+    plan_gemv<double>(plan, true, false, lo, -1.0, 1.0);
+    elementwise(2);
+    plan_reduced<TR>(plan, R, odd_even);
+    elementwise(1);
+  }
+}
+
 template <typename T, typename TR>
 void plan_solve_pass(Plan& plan, const std::vector<SolveDev>& probs,
                      const std::vector<ReducedDev>& red, bool trans, bool odd_even) {
@@ -429,8 +512,9 @@ void plan_solve_pass(Plan& plan, const std::vector<SolveDev>& probs,
     SLAB_LAUNCH_CHECK();
     return SLAB_OK;
   });
-  // (ii) the reduced system
-  plan_reduced<TR>(plan, red, odd_even);
+  // (ii) the reduced system (refined in FP64 when the FP64 blocks are given)
+  if (!red.empty() && red[0].T64) plan_reduced_refined<TR>(plan, red, odd_even, REDUCED_REFINE_STEPS);
+  else plan_reduced<TR>(plan, red, odd_even);
   // (iii) interior back substitution, and the interface values
   plan.step([=](const char* dev, hipStream_t st) {
     hipLaunchKernelGGL((k_coupling<T, TR>), dim3((unsigned)tw), dim3(256), 0, st,

@@ -11,6 +11,11 @@
 
 namespace slab {
 
+// Refinement steps of the mixed-precision reduced solve (FP64 residual of the
+// reduced system, FP32 correction): three take the FP32 solve's relative error
+// of about 1e-4..1e-3 below 1e-11 on the interface values.
+constexpr int REDUCED_REFINE_STEPS = 3;
+
 // ---- stage one --------------------------------------------------------------
 // Coefficient copy (or exp of theta) with positivity check, then edge weights.
 void plan_coef_weights(Plan& plan, const std::vector<ProbDev>& probs);

@@ -113,6 +113,10 @@ def test_fp32_refinement(order, n2, n1, b, precision):
     assert rr.max() <= 1e-10, rr
     assert h.last_info.max_relres <= 1e-10
     assert 1 <= h.last_info.iterations <= 6
+    if precision == S.SLAB_MIXED:
+        # the reduced solve is refined against the FP64 reduced matrix, so the
+        # FP64 slab solves need no second pass
+        assert h.last_info.iterations == 1
     # FP32 slab work with an FP64 sum gives T to about 1e-6; FP64 slab work gives
     # T to FP64 accuracy (the block factorization itself runs in FP32 in both)
     fac = O.factor(prob, order=order)
