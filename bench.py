@@ -172,10 +172,20 @@ def block_products(w: G.Workload, odd_even: bool, elem: int = 4):
     return fl, by, launches
 
 
-def kernel_source_digest() -> str:
+def kernel_source_digest(text: str | None = None) -> str:
+    """Digest of the block-product GEMM's source: the k_gemm kernel and its
+    launch code in k_dense.hip (from its header comment to the explicit
+    instantiations of plan_gemm), plus the shared headers it includes."""
     import hashlib
-    src = os.path.join(ROOT, "paper_2211_07572_amd", "csrc", "k_dense.hip")
-    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    csrc = os.path.join(ROOT, "paper_2211_07572_amd", "csrc")
+    if text is None:
+        text = open(os.path.join(csrc, "k_dense.hip")).read()
+    a = text.index("// Tiled MFMA GEMM")
+    b = text.index("template void plan_gemm<double>")
+    h = hashlib.sha256(text[a:b].encode())
+    for hdr in ("common.h", "group.h"):
+        h.update(open(os.path.join(csrc, hdr), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(name: str):

@@ -309,38 +309,31 @@ template void plan_gemm<double>(Plan&, bool, bool, const std::vector<GemmItem>&,
 
 // ---------------------------------------------------------------------------
 // Panel of the right-looking factorization of a pivot block S (n x n), grouped
-// over independent pivot blocks (items).
-// Every workgroup first inverts the Cholesky factor of the 64x64 diagonal
-// block [k0, k0+nb): Gaussian elimination without pivoting on [S_kk | I],
-// kept in one array (U on and above the diagonal, the unit lower L~^-1 below
-// it), gives S_kk = L~ U with U = D L~^T, hence L_kk^-1 = D^-1/2 L~^-1.  The
-// working matrix lives in registers (thread = row x 16-column quarter); each
-// elimination step exchanges only the pivot row and column through LDS, with
-// one barrier per step.  Then, on 16x16x4 MFMA tiles, it either
+// over independent pivot blocks (items), in two launches.
+// k_panel_diag (one workgroup per item) inverts the Cholesky factor of the
+// 64x64 diagonal block [k0, k0+nb): Gaussian elimination without pivoting on
+// [S_kk | I], kept in one array (U on and above the diagonal, the unit lower
+// L~^-1 below it), gives S_kk = L~ U with U = D L~^T, hence
+// L_kk^-1 = D^-1/2 L~^-1.  The working matrix lives in registers (thread = row
+// x 16-column quarter); each elimination step exchanges only the pivot row and
+// column through LDS, with one barrier per step.  L_kk^-1 overwrites the lower
+// triangle of S_kk (L_kk itself is never needed again).
+// k_panel then, on 16x16x4 MFMA tiles, either
 //   * computes 64 rows of L below the block:       L_ik = S_ik L_kk^-T, or
 //   * advances 64 columns of the carried inverse:  X_k = L_kk^-1 X_k.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_panel(const FactorItem* __restrict__ items,
-                                               const int* __restrict__ offs, int count, int k0) {
-  typedef typename acc4<T>::type V4;
-  const int itm = group_item(offs, count, blockIdx.x);
-  const int bx = blockIdx.x - offs[itm];
+__global__ __launch_bounds__(256) void k_panel_diag(const FactorItem* __restrict__ items,
+                                                    int count, int k0) {
+  const int itm = blockIdx.x;
   g_t<T>* __restrict__ S = gp((T*)items[itm].S);
-  g_t<T>* __restrict__ Lv = gp((T*)items[itm].Li);
   g_t<int>* __restrict__ status = gp(items[itm].status);
   const int n = items[itm].n, blk = items[itm].blk;
-  const int nrow_wg = (n - k0 - min(64, n - k0) + 63) / 64;
-  __shared__ T E[64][65];   // L_kk^-1 after the elimination
-  __shared__ T Bt[64][65];  // operand tile
+  if (k0 >= n) return;  // uniform: this item has no panel at k0
   __shared__ T rowbuf[2][64];
   __shared__ T colbuf[2][64];
   const int nb = min(64, n - k0);
   const int tid = threadIdx.x;
-  const bool rows = bx < nrow_wg;
-  const long long r0 = (long long)k0 + nb + (long long)bx * 64;  // rows case
-  const long long c0 = (long long)(bx - nrow_wg) * 64;            // columns case
-  const long long ncols = (long long)k0 + nb;
   // thread (row i, column quarter q) keeps 16 entries of the working matrix in registers
   const int i = tid & 63, q = tid >> 6;
   T a[16];
@@ -350,19 +343,6 @@ __global__ __launch_bounds__(256) void k_panel(const FactorItem* __restrict__ it
     T v = (i == col) ? (T)1 : (T)0;
     if (i < nb && col < nb) v = S[(long long)(k0 + max(i, col)) * n + k0 + min(i, col)];
     a[c] = v;
-  }
-  // the operand tile (rows case: rows r0.. of the panel columns; columns
-  // case: the panel rows of the carried inverse) is fetched into registers
-  // after the diagonal block, so that waiting for the block leaves these
-  // loads in flight, and stored to LDS after the elimination below
-  // (the loads are unconditional, from clamped indices: a load skipped on
-  // some lanes would make the wait for the diagonal block wait for all)
-  T tb[16];
-#pragma unroll
-  for (int u = 0; u < 16; ++u) {
-    const int e = tid + 256 * u, hi = e >> 6, lo = min(e & 63, nb - 1);
-    if (rows) tb[u] = S[min(r0 + hi, (long long)n - 1) * n + k0 + lo];
-    else tb[u] = Lv[(long long)(k0 + min(hi, nb - 1)) * n + min(c0 + (e & 63), ncols - 1)];
   }
   if (i == 0) {
 #pragma unroll
@@ -378,7 +358,7 @@ __global__ __launch_bounds__(256) void k_panel(const FactorItem* __restrict__ it
       const int p = 16 * pb + pp;
       if (p >= nb) break;
       const int buf = p & 1;
-      const T ipiv = (T)1 / rowbuf[buf][p];
+      const T ipiv = fast_recip(rowbuf[buf][p]);
       T rp[16];
 #pragma unroll
       for (int c = 0; c < 16; ++c) rp[c] = rowbuf[buf][16 * q + c];
@@ -413,13 +393,52 @@ __global__ __launch_bounds__(256) void k_panel(const FactorItem* __restrict__ it
     colbuf[0][i] = (T)1 / sqrt(d);
   }
   __syncthreads();
-  {
+  if (i < nb) {
     const T rs = colbuf[0][i];
+    g_t<T>* row = S + (long long)(k0 + i) * n + k0;
 #pragma unroll
     for (int c = 0; c < 16; ++c) {
       const int col = 16 * q + c;
-      E[i][col] = (col < i) ? a[c] * rs : ((col == i) ? rs : (T)0);
+      if (col <= i) row[col] = (col < i) ? a[c] * rs : rs;
     }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_panel(const FactorItem* __restrict__ items,
+                                               const int* __restrict__ offs, int count, int k0) {
+  typedef typename acc4<T>::type V4;
+  const int itm = group_item(offs, count, blockIdx.x);
+  const int bx = blockIdx.x - offs[itm];
+  g_t<T>* __restrict__ S = gp((T*)items[itm].S);
+  g_t<T>* __restrict__ Lv = gp((T*)items[itm].Li);
+  const int n = items[itm].n;
+  const int nrow_wg = (n - k0 - min(64, n - k0) + 63) / 64;
+  __shared__ T E[64][65];   // L_kk^-1 (from the lower triangle of S_kk)
+  __shared__ T Bt[64][65];  // operand tile
+  const int nb = min(64, n - k0);
+  const int tid = threadIdx.x;
+  const bool rows = bx < nrow_wg;
+  const long long r0 = (long long)k0 + nb + (long long)bx * 64;  // rows case
+  const long long c0 = (long long)(bx - nrow_wg) * 64;            // columns case
+  const long long ncols = (long long)k0 + nb;
+  // every load is issued before the first LDS store (unconditional, from
+  // clamped indices; values outside the operands are zeroed when stored)
+  T te[16], tb[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int e = tid + 256 * u, hi = e >> 6, lo = e & 63;
+    te[u] = S[(long long)(k0 + min(hi, nb - 1)) * n + k0 + min(lo, nb - 1)];
+    if (rows) tb[u] = S[min(r0 + hi, (long long)n - 1) * n + k0 + min(lo, nb - 1)];
+    else tb[u] = Lv[(long long)(k0 + min(hi, nb - 1)) * n + min(c0 + lo, ncols - 1)];
+  }
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int e = tid + 256 * u, hi = e >> 6, lo = e & 63;
+    E[hi][lo] = (hi < nb && lo <= hi) ? te[u] : (T)0;
+    // rows case Bt[rr][t], columns case Bt[t][cc]; zero outside the operand
+    const bool in = rows ? (r0 + hi < n && lo < nb) : (hi < nb && c0 + lo < ncols);
+    Bt[hi][lo] = in ? tb[u] : (T)0;
   }
   __syncthreads();
 
@@ -431,14 +450,6 @@ __global__ __launch_bounds__(256) void k_panel(const FactorItem* __restrict__ it
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = V4{0, 0, 0, 0};
-#pragma unroll
-  for (int u = 0; u < 16; ++u) {
-    const int e = tid + 256 * u, hi = e >> 6, lo = e & 63;
-    // rows case Bt[rr][t], columns case Bt[t][cc]; zero outside the operand
-    const bool in = rows ? (r0 + hi < n && lo < nb) : (hi < nb && c0 + lo < ncols);
-    Bt[hi][lo] = in ? tb[u] : (T)0;
-  }
-  __syncthreads();
 #pragma unroll 4
   for (int ks = 0; ks < 16; ++ks) {
     const int k = 4 * ks + g;
@@ -666,6 +677,9 @@ void plan_factor_blocks(Plan& plan, std::vector<FactorItem> items) {
     long long tp, trk;
     const size_t op = plan.add_offsets(cp, &tp), orr = plan.add_offsets(cr, &trk);
     plan.step([=](const char* dev, hipStream_t st) {
+      hipLaunchKernelGGL((k_panel_diag<T>), dim3((unsigned)live), dim3(256), 0, st,
+                         dev_at<FactorItem>(dev, oi), live, k0);
+      SLAB_LAUNCH_CHECK();
       hipLaunchKernelGGL((k_panel<T>), dim3((unsigned)tp), dim3(256), 0, st,
                          dev_at<FactorItem>(dev, oi), dev_at<int>(dev, op), live, k0);
       SLAB_LAUNCH_CHECK();
