@@ -170,18 +170,33 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmItem* __restrict__ items
 #pragma unroll
     for (int b = 0; b < FN; ++b) acc[a][b] = V4{0, 0, 0, 0};
 
+  // the fragments of k-step ks+1 are read from LDS while the MFMAs of ks run
   auto multiply = [&](int cur) __attribute__((always_inline)) {
+    T av[2][FM], bv[2][FN];
+    auto frag = [&](int ks, int f) __attribute__((always_inline)) {
+#pragma unroll
+      for (int mt = 0; mt < FM; ++mt) av[f][mt] = As[cur][4 * ks + g][wm * (TM / 2) + 16 * mt + nn];
+#pragma unroll
+      for (int nt = 0; nt < FN; ++nt) bv[f][nt] = Bs[cur][4 * ks + g][wn * (TN / 2) + 16 * nt + nn];
+    };
+    frag(0, 0);
 #pragma unroll
     for (int ks = 0; ks < TK / 4; ++ks) {
-      T av[FM], bv[FN];
-#pragma unroll
-      for (int mt = 0; mt < FM; ++mt) av[mt] = As[cur][4 * ks + g][wm * (TM / 2) + 16 * mt + nn];
-#pragma unroll
-      for (int nt = 0; nt < FN; ++nt) bv[nt] = Bs[cur][4 * ks + g][wn * (TN / 2) + 16 * nt + nn];
+      if (ks + 1 < TK / 4) frag(ks + 1, (ks + 1) & 1);
 #pragma unroll
       for (int mt = 0; mt < FM; ++mt)
 #pragma unroll
-        for (int nt = 0; nt < FN; ++nt) acc[mt][nt] = mfma16(av[mt], bv[nt], acc[mt][nt]);
+        for (int nt = 0; nt < FN; ++nt)
+          acc[mt][nt] = mfma16(av[ks & 1][mt], bv[ks & 1][nt], acc[mt][nt]);
+    }
+    // schedule: reads of step 0, then the next step's reads in the middle of
+    // each step's MFMAs (while half of them are still to issue)
+    __builtin_amdgcn_sched_group_barrier(0x100, (FM + FN) / 2, 0);
+#pragma unroll
+    for (int ks = 0; ks < TK / 4; ++ks) {
+      __builtin_amdgcn_sched_group_barrier(0x008, FM * FN / 2, 0);
+      if (ks + 1 < TK / 4) __builtin_amdgcn_sched_group_barrier(0x100, (FM + FN) / 2, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, FM * FN / 2, 0);
     }
   };
   if (kmin < kmax) {
