@@ -86,6 +86,16 @@ __device__ __forceinline__ float fast_recip(float x) {
   return __builtin_fmaf(r, __builtin_fmaf(-x, r, 1.0f), r);
 }
 
+// v if c else 0, by masking the bits (keeps a select on a just-loaded value
+// out of divergent control flow, where the compiler would wait for every
+// outstanding load)
+__device__ __forceinline__ float keep_if(bool c, float v) {
+  return __builtin_bit_cast(float, __builtin_bit_cast(int, v) & -(int)c);
+}
+__device__ __forceinline__ double keep_if(bool c, double v) {
+  return __builtin_bit_cast(double, __builtin_bit_cast(long long, v) & -(long long)c);
+}
+
 template <class T> using g_t = __attribute__((address_space(1))) T;
 template <class T> __device__ __forceinline__ g_t<T>* gp(T* p) { return (g_t<T>*)p; }
 

@@ -837,73 +837,95 @@ __global__ __launch_bounds__(256) void k_bmv(const BmvItem* __restrict__ items,
     if (!TR) khi = min(n, row0 + TM);
     else klo = (row0 / TK) * TK;
   }
-  vt ra[NVA], rb;
-  auto load = [&](int k0) __attribute__((always_inline)) {
+  // Chunks of op(M) and x are loaded D chunks ahead into a register ring.
+  // Every load is unconditional, from indices clamped into the arrays (a load
+  // skipped on some path would make the compiler wait for all outstanding
+  // loads); values outside the operands are zeroed when parked in LDS, and the
+  // chunk loop runs to a multiple of D (extra chunks are all zero).
+  constexpr int D = VECOK ? 3 : 1;
+  vt ra[D][NVA], rb[D];
+  auto load = [&](int d, int k0) __attribute__((always_inline)) {
 #pragma unroll
     for (int q = 0; q < NVA; ++q) {
       const int v = tid + 256 * q;
       int row, kk;
       if (!TR) { row = v / (TK / VEC); kk = (v % (TK / VEC)) * VEC; }
       else { kk = v / (TM / VEC); row = (v % (TM / VEC)) * VEC; }
-      const long long gi = row0 + row, gk = k0 + kk;
       if (VECOK) {
-        const bool in = gi < n && gk < khi;
-        ra[q] = in ? *(const g_t<const vt>*)(!TR ? M + gi * n + gk : M + gk * n + gi) : vt(0);
+        // n % VEC == 0 here: the clamped vector stays inside its row
+        const long long gi = !TR ? min(row0 + row, n - 1) : min(row0 + row, n - VEC);
+        const long long gk = !TR ? min(k0 + kk, n - VEC) : min(k0 + kk, n - 1);
+        ra[d][q] = *(const g_t<const vt>*)(!TR ? M + gi * n + gk : M + gk * n + gi);
       } else {
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
-          const long long ii = !TR ? gi : gi + e, kq = !TR ? gk + e : gk;
-          ra[q][e] = (ii < n && kq < khi) ? M[!TR ? ii * n + kq : kq * n + ii] : (T)0;
+          const long long ii = !TR ? row0 + row : row0 + row + e, kq = !TR ? k0 + kk + e : k0 + kk;
+          ra[d][q][e] = (ii < n && kq < khi) ? M[!TR ? ii * n + kq : kq * n + ii] : (T)0;
         }
       }
     }
     {
       const int c = tid / (TK / VEC), kk = (tid % (TK / VEC)) * VEC;
-      const long long gk = k0 + kk;
       if (VECOK) {
-        rb = (c < nc && gk < khi) ? *(const g_t<const vt>*)(x + (long long)c * n + gk) : vt(0);
+        rb[d] = *(const g_t<const vt>*)(x + (long long)min(c, nc - 1) * n + min(k0 + kk, n - VEC));
       } else {
+        const long long gk = k0 + kk;
 #pragma unroll
         for (int e = 0; e < VEC; ++e)
-          rb[e] = (c < nc && gk + e < khi) ? x[(long long)c * n + gk + e] : (T)0;
+          rb[d][e] = (c < nc && gk + e < khi) ? x[(long long)c * n + gk + e] : (T)0;
       }
     }
   };
-  auto park = [&](int buf) __attribute__((always_inline)) {
+  auto park = [&](int d, int buf, int k0) __attribute__((always_inline)) {
 #pragma unroll
     for (int q = 0; q < NVA; ++q) {
       const int v = tid + 256 * q;
       if (!TR) {
         const int row = v / (TK / VEC), kk = (v % (TK / VEC)) * VEC;
+        const bool rin = row0 + row < n;
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) As[buf][kk + e][row] = ra[q][e];
+        for (int e = 0; e < VEC; ++e)
+          As[buf][kk + e][row] = VECOK ? keep_if(rin && k0 + kk + e < khi, ra[d][q][e]) : ra[d][q][e];
       } else {
         const int kk = v / (TM / VEC), row = (v % (TM / VEC)) * VEC;
+        const bool kin = k0 + kk < khi;
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) As[buf][kk][row + e] = ra[q][e];
+        for (int e = 0; e < VEC; ++e)
+          As[buf][kk][row + e] = VECOK ? keep_if(kin && row0 + row + e < n, ra[d][q][e]) : ra[d][q][e];
       }
     }
     const int c = tid / (TK / VEC), kk = (tid % (TK / VEC)) * VEC;
 #pragma unroll
-    for (int e = 0; e < VEC; ++e) Bs[buf][kk + e][c] = rb[e];
+    for (int e = 0; e < VEC; ++e)
+      Bs[buf][kk + e][c] = VECOK ? keep_if(c < nc && k0 + kk + e < khi, rb[d][e]) : rb[d][e];
   };
-  V4 acc = V4{0, 0, 0, 0};
+  // two accumulators: the chunk's MFMAs form two interleaved dependency chains
+  V4 acc2[2] = {V4{0, 0, 0, 0}, V4{0, 0, 0, 0}};
   if (klo < khi) {
-    load(klo);
-    park(0);
-    __syncthreads();
-    int it = 0;
-    for (int k0 = klo; k0 < khi; k0 += TK, ++it) {
-      const int cur = it & 1;
-      const bool more = k0 + TK < khi;
-      if (more) load(k0 + TK);
+    const int nsteps = ((khi - klo + TK - 1) / TK + D - 1) / D * D;
 #pragma unroll
-      for (int ks = 0; ks < TK / 4; ++ks)
-        acc = mfma16(As[cur][4 * ks + g][16 * wave + nn], Bs[cur][4 * ks + g][nn], acc);
-      if (more) park(cur ^ 1);
-      __syncthreads();
+    for (int d = 0; d < D; ++d) load(d, klo + d * TK);
+    // nothing from before the loop in flight at its head, so the compiler's
+    // wait counts inside follow the loop's own load order
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    for (int c0 = 0; c0 < nsteps; c0 += D) {
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const int ch = c0 + d, cur = ch & 1;
+        park(d, cur, klo + ch * TK);
+        load(d, klo + (ch + D) * TK);
+        __syncthreads();
+        // (chunks past the end are zero: their products add nothing)
+#pragma unroll
+        for (int ks = 0; ks < TK / 4; ++ks)
+          acc2[ks & 1] = mfma16(As[cur][4 * ks + g][16 * wave + nn], Bs[cur][4 * ks + g][nn],
+                                acc2[ks & 1]);
+      }
     }
   }
+  V4 acc;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) acc[i] = acc2[0][i] + acc2[1][i];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int r = row0 + 16 * wave + acc_row<T>(g, i);

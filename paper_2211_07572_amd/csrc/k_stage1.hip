@@ -250,14 +250,13 @@ __global__ __launch_bounds__(64) void k_slab_factor(const ProbDev* __restrict__ 
           for (int j = 0; j < C; ++j) cb[j] = colbuf[buf][k0 + j];
           const T aip = colbuf[buf][i];
           const bool piv = i == p;
-          const T f = piv ? (T)0 : aip * inv;
+          const T f = aip * inv;
+          // other rows: a -= f cb; the pivot row is scaled, not updated (no
+          // cancellation): a = inv cb.  One select per row, not per element.
+          const T t = piv ? inv : -f;
+          const T keep = piv ? (T)0 : (T)1;
 #pragma unroll
-          for (int j = 0; j < C; ++j) a[j] -= f * cb[j];
-          // the pivot row is scaled, not updated (no cancellation)
-          if (piv) {
-#pragma unroll
-            for (int j = 0; j < C; ++j) a[j] = cb[j] * inv;
-          }
+          for (int j = 0; j < C; ++j) a[j] = fma(t, cb[j], a[j] * keep);
           if (q == p / C) a[p % C] = piv ? -inv : f;
           if (p + 1 < BP) {
             if (i == p + 1) {
