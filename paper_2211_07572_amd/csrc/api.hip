@@ -169,14 +169,18 @@ struct Layout {
     parts.push_back({(void**)p, n});
     total += (std::max<size_t>(n, 1) + 255) & ~size_t(255);
   }
-  int commit(Owner& o, void** block) {
-    void* base = nullptr;
-    SLAB_TRY(o.alloc(&base, total));
+  // assign the parts consecutively from base (a block of at least total bytes)
+  void place(void* base) {
     char* c = (char*)base;
     for (auto& pr : parts) {
       *pr.first = c;
       c += (std::max<size_t>(pr.second, 1) + 255) & ~size_t(255);
     }
+  }
+  int commit(Owner& o, void** block) {
+    void* base = nullptr;
+    SLAB_TRY(o.alloc(&base, total));
+    place(base);
     if (block) *block = base;
     return SLAB_OK;
   }
@@ -458,11 +462,15 @@ int factor_group(const std::vector<slab_handle>& hs, const std::vector<const sla
   int dev = 0;
   SLAB_HIP_CHECK(hipGetDevice(&dev));
   const size_t budget = std::max<size_t>((free_b + Pool::get().cached(dev)) / 2, (size_t)1 << 30);
-  size_t lo = 0;
-  while (lo < cnt) {
+  // chunks first; one block of the largest chunk's size serves them all (the
+  // caching allocator then meets every later factorization of the same set)
+  std::vector<FactorTemps> tmp(cnt);
+  std::vector<std::pair<size_t, size_t>> chunks;
+  std::vector<Layout> layouts;
+  size_t block_bytes = 0;
+  for (size_t lo = 0; lo < cnt;) {
     size_t hi = lo;
     Layout L;
-    std::vector<FactorTemps> tmp(cnt);
     while (hi < cnt) {
       Layout L1 = L;
       temp_layout<T, TR>(hs[hi], tmp[hi], L1);
@@ -470,8 +478,16 @@ int factor_group(const std::vector<slab_handle>& hs, const std::vector<const sla
       L = L1;
       ++hi;
     }
-    void* block = nullptr;
-    SLAB_TRY(L.commit(plan_mem, &block));
+    chunks.push_back({lo, hi});
+    block_bytes = std::max(block_bytes, L.total);
+    layouts.push_back(L);
+    lo = hi;
+  }
+  void* block = nullptr;
+  SLAB_TRY(plan_mem.alloc(&block, block_bytes));
+  for (size_t ci = 0; ci < chunks.size(); ++ci) {
+    const size_t lo = chunks[ci].first, hi = chunks[ci].second;
+    layouts[ci].place(block);
     std::vector<ProbDev> cd;
     std::vector<Stage2Prob> s2;
     for (size_t i = lo; i < hi; ++i) {
@@ -500,15 +516,14 @@ int factor_group(const std::vector<slab_handle>& hs, const std::vector<const sla
     for (int i = 0; i < 5; ++i) ph[i] += elapsed_us(ev[i], ev[i + 1]);
     ph[5] += (long long)(p.timer->total_ms() * 1000.0);
     SLAB_HIP_CHECK(hipStreamSynchronize(st));
-    plan_mem.release(block);
     for (size_t i = lo; i < hi; ++i) {
       if (hs_status[4 * i] != 0) {
         fail[i] = hs_status[4 * i];
         blk[i] = hs_status[4 * i + 1];
       }
     }
-    lo = hi;
   }
+  plan_mem.release(block);
   return SLAB_OK;
 }
 
