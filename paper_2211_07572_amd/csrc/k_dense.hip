@@ -814,7 +814,11 @@ __global__ __launch_bounds__(256) void k_bmv(const BmvItem* __restrict__ items,
   constexpr int NVA = TM * TK / VEC / 256;    // vectors of op(M) per thread and chunk
   static_assert(NVA * VEC * 256 == TM * TK && 16 * TK == VEC * 256, "bmv tile");
   typedef T vt __attribute__((ext_vector_type(VEC)));
-  __shared__ T As[2][TK][TM + 4];
+  // op(M) chunk in LDS: [k][row] for M^T (loaded along rows), [row][k] for M
+  // (loaded along k), so that both are parked with 16-byte stores; the MFMA A
+  // fragments read either layout without bank conflicts
+  constexpr int AS0 = TR ? TK : TM, AS1 = TR ? TM + 4 : TK + 4;
+  __shared__ __attribute__((aligned(16))) T As[2][AS0][AS1];
   __shared__ T Bs[2][TK][16 + 4];
   const int itm = group_item(offs, count, blockIdx.x);
   const int bx = blockIdx.x - offs[itm];
@@ -883,9 +887,11 @@ __global__ __launch_bounds__(256) void k_bmv(const BmvItem* __restrict__ items,
       if (!TR) {
         const int row = v / (TK / VEC), kk = (v % (TK / VEC)) * VEC;
         const bool rin = row0 + row < n;
+        vt w;
 #pragma unroll
         for (int e = 0; e < VEC; ++e)
-          As[buf][kk + e][row] = VECOK ? keep_if(rin && k0 + kk + e < khi, ra[d][q][e]) : ra[d][q][e];
+          w[e] = VECOK ? keep_if(rin && k0 + kk + e < khi, ra[d][q][e]) : ra[d][q][e];
+        *(vt*)&As[buf][row][kk] = w;
       } else {
         const int kk = v / (TM / VEC), row = (v % (TM / VEC)) * VEC;
         const bool kin = k0 + kk < khi;
@@ -918,7 +924,9 @@ __global__ __launch_bounds__(256) void k_bmv(const BmvItem* __restrict__ items,
         // (chunks past the end are zero: their products add nothing)
 #pragma unroll
         for (int ks = 0; ks < TK / 4; ++ks)
-          acc2[ks & 1] = mfma16(As[cur][4 * ks + g][16 * wave + nn], Bs[cur][4 * ks + g][nn],
+          acc2[ks & 1] = mfma16(TR ? As[cur][4 * ks + g][16 * wave + nn]
+                                   : As[cur][16 * wave + nn][4 * ks + g],
+                                Bs[cur][4 * ks + g][nn],
                                 acc2[ks & 1]);
       }
     }
