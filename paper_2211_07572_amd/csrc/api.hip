@@ -236,6 +236,7 @@ struct Workspace {
   double* g64 = nullptr;
   double* u64 = nullptr;
   double* r64 = nullptr;
+  void* bpart = nullptr;  // partial products of k-split block-vector products
 };
 
 struct slab_handle_s {
@@ -322,6 +323,7 @@ void workspace_layout(slab_handle h, int nrhs, Layout& L) {
   L.add(&w.r, nrhs * N * sizeof(double));
   L.add(&w.norms, 2 * nrhs * sizeof(double));
   L.add(&w.partial, residual_partial_count(h->n1, h->n2, nrhs) * sizeof(double));
+  L.add(&w.bpart, BMV_PART_SLOTS * bmv_part_elems(h->n2, nrhs) * e2);
   if (h->precision == SLAB_MIXED) {
     L.add(&w.g64, m * nrhs * n * sizeof(double));
     L.add(&w.u64, m * nrhs * n * sizeof(double));
@@ -595,7 +597,7 @@ void plan_pass(Plan& p, const std::vector<SolveJob>& jobs, bool first, bool tran
     ReducedDev& r = red[i];
     std::memset(&r, 0, sizeof(r));
     r.n = h->n2; r.m = h->m; r.nrhs = j.nrhs; r.Linv = h->Linv; r.Z = h->Z; r.Td = h->Td;
-    r.ft = h->ws.ft; r.yt = h->ws.yt; r.tt = h->ws.tt;
+    r.ft = h->ws.ft; r.yt = h->ws.yt; r.tt = h->ws.tt; r.part = h->ws.bpart;
     if (h->precision == SLAB_MIXED) {
       r.T64 = h->T64; r.O64 = h->O64;
       r.g64 = h->ws.g64; r.u64 = h->ws.u64; r.r64 = h->ws.r64;

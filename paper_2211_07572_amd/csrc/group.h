@@ -94,7 +94,18 @@ struct BmvItem {
   void* y;
   int n;
   int nrhs;
+  // scratch for a product split over k (BMV_SPLIT_MAX partial results of
+  // 16*ceil(nrhs/16) columns of n), or null: the product is not split
+  void* part;
 };
+
+// Most k-splits of a small block-vector launch; scratch per item in elements.
+constexpr int BMV_SPLIT_MAX = 8;
+// Items of one problem in one launch that get a scratch (more: not split).
+constexpr int BMV_PART_SLOTS = 4;
+inline long long bmv_part_elems(int n, int nrhs) {
+  return (long long)BMV_SPLIT_MAX * 16 * ((nrhs + 15) / 16) * n;
+}
 
 // One problem of a solve pass (slab sweeps, reduced right-hand side,
 // coupling, interface output, residual).
@@ -134,6 +145,7 @@ struct ReducedDev {
   void* ft;         // in: f~, out: the interface values
   void* yt;
   void* tt;         // nrhs x n temporary
+  void* part;       // BMV_PART_SLOTS partial-product scratches (bmv_part_elems each)
   // refinement against the FP64 reduced matrix (null T64: none): diagonal
   // blocks T64[j], couplings O64[j] = T_{j,j+1}; FP64 right-hand side g64,
   // solution u64 and residual r64, all [j][c][r]

@@ -806,7 +806,7 @@ template void plan_stage2<double>(Plan&, const std::vector<Stage2Prob>&, bool);
 template <typename T, bool TR, bool LOWER, bool VECOK>
 __global__ __launch_bounds__(256) void k_bmv(const BmvItem* __restrict__ items,
                                             const int* __restrict__ offs, int count, T alpha,
-                                            T beta) {
+                                            T beta, int nsplit) {
   typedef typename acc4<T>::type V4;
   constexpr int VEC = 16 / sizeof(T);
   constexpr int TM = 64;                      // output rows per workgroup
@@ -823,8 +823,8 @@ __global__ __launch_bounds__(256) void k_bmv(const BmvItem* __restrict__ items,
   const int itm = group_item(offs, count, blockIdx.x);
   const int bx = blockIdx.x - offs[itm];
   const int n = items[itm].n, nrhs = items[itm].nrhs;
-  const int nrt = (n + TM - 1) / TM;
-  const int rt = bx % nrt, cg = bx / nrt;
+  const int nrt = (n + TM - 1) / TM, ncg = (nrhs + 15) / 16;
+  const int rt = bx % nrt, cg = (bx / nrt) % ncg, sk = bx / (nrt * ncg);
   const g_t<const T>* __restrict__ M = gp((const T*)items[itm].M);
   const g_t<const T>* __restrict__ x = gp((const T*)items[itm].x) + (long long)cg * 16 * n;
   const g_t<const T>* xin = gp((const T*)items[itm].xin);
@@ -840,6 +840,12 @@ __global__ __launch_bounds__(256) void k_bmv(const BmvItem* __restrict__ items,
   if (LOWER) {
     if (!TR) khi = min(n, row0 + TM);
     else klo = (row0 / TK) * TK;
+  }
+  if (nsplit > 1) {  // this workgroup's share of the chunks of [klo, khi)
+    const int per = ((khi - klo + TK - 1) / TK + nsplit - 1) / nsplit;
+    const int lo2 = klo + sk * per * TK;
+    khi = min(khi, lo2 + per * TK);
+    klo = lo2;
   }
   // Chunks of op(M) and x are loaded D chunks ahead into a register ring.
   // Every load is unconditional, from indices clamped into the arrays (a load
@@ -934,6 +940,15 @@ __global__ __launch_bounds__(256) void k_bmv(const BmvItem* __restrict__ items,
   V4 acc;
 #pragma unroll
   for (int i = 0; i < 4; ++i) acc[i] = acc2[0][i] + acc2[1][i];
+  if (nsplit > 1) {  // partial result; k_bmv_sum adds the splits up
+    g_t<T>* part = gp((T*)items[itm].part) + ((long long)sk * 16 * ncg + 16 * cg) * n;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = row0 + 16 * wave + acc_row<T>(g, i);
+      if (r < n && nn < nc) part[(long long)nn * n + r] = alpha * acc[i];
+    }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int r = row0 + 16 * wave + acc_row<T>(g, i);
@@ -945,21 +960,56 @@ __global__ __launch_bounds__(256) void k_bmv(const BmvItem* __restrict__ items,
   }
 }
 
+// y = beta xin + (sum of the nsplit partial products), column c of n at c*n.
+template <typename T>
+__global__ void k_bmv_sum(const BmvItem* __restrict__ items, const int* __restrict__ offs,
+                          int count, T beta, int nsplit) {
+  const int itm = group_item(offs, count, blockIdx.x);
+  const long long nwg = offs[itm + 1] - offs[itm];
+  const int n = items[itm].n, nrhs = items[itm].nrhs, ncg = (nrhs + 15) / 16;
+  const g_t<const T>* __restrict__ part = gp((const T*)items[itm].part);
+  const g_t<const T>* xin = gp((const T*)items[itm].xin);
+  g_t<T>* y = gp((T*)items[itm].y);
+  const long long tot = (long long)nrhs * n, stride = (long long)16 * ncg * n;
+  for (long long e = (blockIdx.x - offs[itm]) * (long long)blockDim.x + threadIdx.x; e < tot;
+       e += nwg * blockDim.x) {
+    T v = xin ? beta * xin[e] : (T)0;
+    for (int k = 0; k < nsplit; ++k) v += part[k * stride + e];
+    y[e] = v;
+  }
+}
+
 template <typename T>
 void plan_gemv(Plan& plan, bool tr, bool lower, const std::vector<BmvItem>& items, T alpha,
                T beta) {
   if (items.empty()) return;
-  std::vector<int> c;
-  bool vecok = true;
+  bool vecok = true, can_split = true;
   const uintptr_t al = 16;
+  long long base = 0;
   for (const BmvItem& b : items) {
-    c.push_back(((b.n + 63) / 64) * ((b.nrhs + 15) / 16));
+    base += ((b.n + 63) / 64) * ((b.nrhs + 15) / 16);
     vecok = vecok && b.n % (int)(16 / sizeof(T)) == 0 && ((uintptr_t)b.M % al) == 0 &&
             ((uintptr_t)b.x % al) == 0;
+    can_split = can_split && b.part != nullptr && b.n >= 512;
   }
+  // a launch of few workgroups is bound by one workgroup's walk over k: split
+  // k so that the chip holds about 512 workgroups, then add the partial sums
+  int nsplit = 1;
+  if (can_split)
+    while (nsplit < BMV_SPLIT_MAX && base * nsplit * 2 <= 512) nsplit *= 2;
+  std::vector<int> c;
+  for (const BmvItem& b : items) c.push_back(((b.n + 63) / 64) * ((b.nrhs + 15) / 16) * nsplit);
   long long tot;
   const size_t oi = plan.add_vec(items), oo = plan.add_offsets(c, &tot);
   const int count = (int)items.size();
+  size_t os = 0;
+  long long ts = 0;
+  if (nsplit > 1) {
+    std::vector<int> cs;
+    for (const BmvItem& b : items)
+      cs.push_back((int)std::min<long long>(((long long)b.nrhs * b.n + 255) / 256, 256));
+    os = plan.add_offsets(cs, &ts);
+  }
   plan.step([=](const char* dev, hipStream_t st) {
     const BmvItem* it = dev_at<BmvItem>(dev, oi);
     const int* of = dev_at<int>(dev, oo);
@@ -967,10 +1017,10 @@ void plan_gemv(Plan& plan, bool tr, bool lower, const std::vector<BmvItem>& item
   do {                                                                                          \
     if (vecok)                                                                                  \
       hipLaunchKernelGGL((k_bmv<T, TRV, LOV, true>), dim3((unsigned)tot), dim3(256), 0, st, it, \
-                         of, count, alpha, beta);                                               \
+                         of, count, alpha, beta, nsplit);                                       \
     else                                                                                        \
       hipLaunchKernelGGL((k_bmv<T, TRV, LOV, false>), dim3((unsigned)tot), dim3(256), 0, st,    \
-                         it, of, count, alpha, beta);                                           \
+                         it, of, count, alpha, beta, nsplit);                                   \
   } while (0)
     if (!tr && !lower) SLAB_BMV_CASE(false, false);
     else if (!tr && lower) SLAB_BMV_CASE(false, true);
@@ -978,9 +1028,15 @@ void plan_gemv(Plan& plan, bool tr, bool lower, const std::vector<BmvItem>& item
     else SLAB_BMV_CASE(true, true);
 #undef SLAB_BMV_CASE
     SLAB_LAUNCH_CHECK();
+    if (nsplit > 1) {
+      hipLaunchKernelGGL((k_bmv_sum<T>), dim3((unsigned)ts), dim3(256), 0, st, it,
+                         dev_at<int>(dev, os), count, beta, nsplit);
+      SLAB_LAUNCH_CHECK();
+    }
     return SLAB_OK;
   });
 }
+
 template void plan_gemv<float>(Plan&, bool, bool, const std::vector<BmvItem>&, float, float);
 template void plan_gemv<double>(Plan&, bool, bool, const std::vector<BmvItem>&, double, double);
 

@@ -279,10 +279,16 @@ static void plan_reduced(Plan& plan, const std::vector<ReducedDev>& R, bool odd_
   auto at = [](const void* base, long long j, long long stride) {
     return (void*)((TR*)base + j * stride);
   };
-  auto item = [](const void* M, const void* x, const void* xin, void* y, int n, int nrhs) {
+  auto item = [](const void* M, const void* x, const void* xin, void* y, int n, int nrhs,
+                 void* part = nullptr) {
     BmvItem b;
-    b.M = M; b.x = x; b.xin = xin; b.y = y; b.n = n; b.nrhs = nrhs;
+    b.M = M; b.x = x; b.xin = xin; b.y = y; b.n = n; b.nrhs = nrhs; b.part = part;
     return b;
+  };
+  // scratch slot s of a problem for a product split over k (see plan_gemv)
+  auto part = [](const ReducedDev& r, int s) -> void* {
+    if (!r.part || s >= BMV_PART_SLOTS) return nullptr;
+    return (TR*)r.part + s * bmv_part_elems(r.n, r.nrhs);
   };
   int mmax = 0;
   for (const ReducedDev& r : R) mmax = std::max(mmax, r.m);
@@ -297,10 +303,11 @@ static void plan_reduced(Plan& plan, const std::vector<ReducedDev>& R, bool odd_
         const void* src = at(r.ft, j, vs);
         if (j > 0) {
           a.push_back(item(at(r.Z, j - 1, nsq), at(r.yt, j - 1, vs), at(r.ft, j, vs), r.tt, r.n,
-                           r.nrhs));
+                           r.nrhs, part(r, 0)));
           src = r.tt;
         }
-        bb.push_back(item(at(r.Linv, j, nsq), src, nullptr, at(r.yt, j, vs), r.n, r.nrhs));
+        bb.push_back(item(at(r.Linv, j, nsq), src, nullptr, at(r.yt, j, vs), r.n, r.nrhs,
+                          part(r, 1)));
       }
       plan_gemv<TR>(plan, true, false, a, (TR)-1, (TR)1);
       plan_gemv<TR>(plan, false, true, bb, (TR)1, (TR)0);
@@ -313,10 +320,11 @@ static void plan_reduced(Plan& plan, const std::vector<ReducedDev>& R, bool odd_
         const void* src = at(r.yt, j, vs);
         if (j < r.m - 1) {
           a.push_back(item(at(r.Z, j, nsq), at(r.ft, j + 1, vs), at(r.yt, j, vs), r.tt, r.n,
-                           r.nrhs));
+                           r.nrhs, part(r, 0)));
           src = r.tt;
         }
-        bb.push_back(item(at(r.Linv, j, nsq), src, nullptr, at(r.ft, j, vs), r.n, r.nrhs));
+        bb.push_back(item(at(r.Linv, j, nsq), src, nullptr, at(r.ft, j, vs), r.n, r.nrhs,
+                          part(r, 1)));
       }
       plan_gemv<TR>(plan, false, false, a, (TR)-1, (TR)1);
       plan_gemv<TR>(plan, true, true, bb, (TR)1, (TR)0);
@@ -342,22 +350,22 @@ static void plan_reduced(Plan& plan, const std::vector<ReducedDev>& R, bool odd_
           const long long e = (2 * q + 1) * s - 1;
           if (pass == 0) {
             a.push_back(item(at(r.Linv, e, nsq), at(r.ft, e, vs), nullptr, at(r.yt, e, vs), r.n,
-                             r.nrhs));
+                             r.nrhs, part(r, q)));
             if (q < NR)
               bb.push_back(item(at(r.Z, e, nsq), at(r.yt, e, vs), at(r.ft, e + s, vs),
-                                at(r.ft, e + s, vs), r.n, r.nrhs));
+                                at(r.ft, e + s, vs), r.n, r.nrhs, part(r, q)));
             if (q >= 1)
               cc.push_back(item(at(r.Td, e, nsq), at(r.yt, e, vs), at(r.ft, e - s, vs),
-                                at(r.ft, e - s, vs), r.n, r.nrhs));
+                                at(r.ft, e - s, vs), r.n, r.nrhs, part(r, q - 1)));
           } else {
             if (q < NR)
               a.push_back(item(at(r.Z, e, nsq), at(r.ft, e + s, vs), at(r.yt, e, vs),
-                               at(r.yt, e, vs), r.n, r.nrhs));
+                               at(r.yt, e, vs), r.n, r.nrhs, part(r, q)));
             if (q >= 1)
               bb.push_back(item(at(r.Td, e, nsq), at(r.ft, e - s, vs), at(r.yt, e, vs),
-                                at(r.yt, e, vs), r.n, r.nrhs));
+                                at(r.yt, e, vs), r.n, r.nrhs, part(r, q - 1)));
             cc.push_back(item(at(r.Linv, e, nsq), at(r.yt, e, vs), nullptr, at(r.ft, e, vs), r.n,
-                              r.nrhs));
+                              r.nrhs, part(r, q)));
           }
         }
       }
@@ -447,7 +455,7 @@ static void plan_reduced_refined(Plan& plan, const std::vector<ReducedDev>& R, b
   };
   auto item = [](const void* M, const void* x, const void* xin, void* y, int n, int nrhs) {
     BmvItem b;
-    b.M = M; b.x = x; b.xin = xin; b.y = y; b.n = n; b.nrhs = nrhs;
+    b.M = M; b.x = x; b.xin = xin; b.y = y; b.n = n; b.nrhs = nrhs; b.part = nullptr;
     return b;
   };
   plan_reduced<TR>(plan, R, odd_even);
