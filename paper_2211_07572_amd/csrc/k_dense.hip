@@ -34,7 +34,7 @@ namespace slab {
 // tile index over the lower triangle); GEMM_A_LOWER / GEMM_B_LOWER skip the
 // k ranges where op(A) / op(B) is known to be zero (lower-triangular factors).
 // ---------------------------------------------------------------------------
-template <typename T, int TILE, int TK, bool AK, bool BN, bool VECOK>
+template <typename T, int TILE, int TK, bool AK, bool BN, bool VECOK, bool CPRE = false>
 __global__ __launch_bounds__(256) void k_gemm(const GemmItem* __restrict__ items,
                                               const int* __restrict__ offs, int count, T alpha,
                                               T beta, int flags) {
@@ -199,6 +199,21 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmItem* __restrict__ items
       __builtin_amdgcn_sched_group_barrier(0x008, FM * FN / 2, 0);
     }
   };
+  // CPRE: the C tile (beta != 0) is loaded now, from clamped indices, so that
+  // its latency hides behind the k loop instead of following it
+  T cpre[CPRE ? FM : 1][CPRE ? FN : 1][4];
+  if (CPRE) {
+#pragma unroll
+    for (int mt = 0; mt < FM; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < FN; ++nt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const long long gi = min((long long)i0 + wm * (TM / 2) + 16 * mt + acc_row<T>(g, i), (long long)M - 1);
+          const long long gj = min((long long)j0 + wn * (TN / 2) + 16 * nt + nn, (long long)N - 1);
+          cpre[mt][nt][i] = C[gi * ldc + gj];
+        }
+  }
   if (kmin < kmax) {
     load(kmin);
     park(0, kmin);
@@ -224,23 +239,24 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmItem* __restrict__ items
         const long long gj = j0 + wn * (TN / 2) + 16 * nt + nn;
         if (gi < M && gj < N) {
           T v = alpha * acc[mt][nt][i];
-          if (beta != (T)0) v += beta * C[gi * ldc + gj];
+          if (CPRE) v += beta * cpre[CPRE ? mt : 0][CPRE ? nt : 0][i];
+          else if (beta != (T)0) v += beta * C[gi * ldc + gj];
           C[gi * ldc + gj] = v;
         }
       }
 }
 
-template <typename T, int TILE, int TK>
+template <typename T, int TILE, int TK, bool CPRE = false>
 static void gemm_tile(bool ak, bool bn, bool vecok, unsigned grid, const GemmItem* items,
                       const int* offs, int count, T alpha, T beta, int flags, hipStream_t st) {
 #define SLAB_GEMM_CASE(AKV, BNV)                                                                   \
   do {                                                                                             \
     if (vecok)                                                                                     \
-      hipLaunchKernelGGL((k_gemm<T, TILE, TK, AKV, BNV, true>), dim3(grid), dim3(256), 0, st,      \
-                         items, offs, count, alpha, beta, flags);                                  \
+      hipLaunchKernelGGL((k_gemm<T, TILE, TK, AKV, BNV, true, CPRE>), dim3(grid), dim3(256), 0,   \
+                         st, items, offs, count, alpha, beta, flags);                              \
     else                                                                                           \
-      hipLaunchKernelGGL((k_gemm<T, TILE, TK, AKV, BNV, false>), dim3(grid), dim3(256), 0, st,     \
-                         items, offs, count, alpha, beta, flags);                                  \
+      hipLaunchKernelGGL((k_gemm<T, TILE, TK, AKV, BNV, false, CPRE>), dim3(grid), dim3(256), 0,  \
+                         st, items, offs, count, alpha, beta, flags);                              \
   } while (0)
   if (!ak && !bn) SLAB_GEMM_CASE(false, false);
   else if (!ak && bn) SLAB_GEMM_CASE(false, true);
@@ -281,6 +297,7 @@ void plan_gemm(Plan& plan, bool ak, bool bn, const std::vector<GemmItem>& items,
   }
   if (flags & GEMM_LOWER_C) area /= 2;
   int tile = (sizeof(T) == 4 && area >= 1024LL * 128 * 128) ? 128 : 64;
+  const bool cpre = (flags & GEMM_C_PREFETCH) != 0;
   if (sizeof(T) == 4) {
     bool same_n = true;
     for (const GemmItem& g : items) same_n = same_n && g.M == items[0].M && g.N == items[0].M;
@@ -288,6 +305,7 @@ void plan_gemm(Plan& plan, bool ak, bool bn, const std::vector<GemmItem>& items,
     if (tuned) tile = tuned;
     if (force_tile) tile = force_tile;
   }
+  if (cpre) tile = 64;
   std::vector<int> c;
   for (const GemmItem& g : items) {
     const long long tm = (g.M + tile - 1) / tile, tn = (g.N + tile - 1) / tile;
@@ -306,7 +324,10 @@ void plan_gemm(Plan& plan, bool ak, bool bn, const std::vector<GemmItem>& items,
       tm->ev.push_back(e1);
       SLAB_HIP_CHECK(hipEventRecord(e0, st));
     }
-    if (tile == 128)
+    if (cpre)
+      gemm_tile<T, 64, 32, true>(ak, bn, vecok, (unsigned)tot, dev_at<GemmItem>(dev, oi),
+                                 dev_at<int>(dev, oo), count, alpha, beta, flags, st);
+    else if (tile == 128)
       gemm_tile<T, 128, 16>(ak, bn, vecok, (unsigned)tot, dev_at<GemmItem>(dev, oi),
                             dev_at<int>(dev, oo), count, alpha, beta, flags, st);
     else
@@ -501,12 +522,16 @@ __global__ __launch_bounds__(256) void k_panel(const FactorItem* __restrict__ it
 }
 
 // ---------------------------------------------------------------------------
-// Update after panel [k0, k0+nb) of the factorization of one pivot block:
-//   trailing  S_ij -= L_i L_j^T     (lower 64x64 tiles of rows/cols >= k0+nb)
-//   carried   X_ic -= L_i X_k,c     (rows >= k0+nb, columns < k0+nb)
-// with L_i = S[i, k0:k0+nb] (just computed by the panel) and X_k the panel's
-// rows of the carried inverse.  One launch covers both tile kinds; every
-// workgroup issues all its loads (A, B and the C tile) before the first MFMA.
+// The factorization advances in 128-column panels made of two 64-column
+// sub-panels.  After the first sub-panel [k0, k0+64) this kernel applies its
+// update to what the second sub-panel [k0+64, k0+128) needs:
+//   trailing  S_ij -= L_i L_j^T     (rows i >= k0+64, columns j in [k0+64, k0+128))
+//   carried   X_ic -= L_i X_k,c     (rows i in [k0+64, k0+128), columns c < k0+64)
+// with L_i = S[i, k0:k0+64] (just computed by the panel) and X_k the panel's
+// rows of the carried inverse.  The rest of both updates, for both sub-panels
+// at once, is two 128-deep GEMMs (see plan_factor_blocks).  One launch covers
+// both tile kinds; every workgroup issues all its loads (A, B and the C tile)
+// before the first MFMA.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_rank64(const FactorItem* __restrict__ items,
@@ -518,8 +543,7 @@ __global__ __launch_bounds__(256) void k_rank64(const FactorItem* __restrict__ i
   g_t<T>* __restrict__ Lv = gp((T*)items[itm].Li);
   const int n = items[itm].n;
   const int nb = min(64, n - k0);
-  const long long ntr = (n - k0 - nb + 63) / 64;
-  const int ntrail = (int)(ntr * (ntr + 1) / 2);
+  const int ntrail = (n - k0 - nb + 63) / 64;  // row tiles of the one column tile
   __shared__ T As[64][65];  // As[row][k]
   __shared__ T Bs[64][65];  // Bs[col][k]
   const int tid = threadIdx.x;
@@ -531,18 +555,12 @@ __global__ __launch_bounds__(256) void k_rank64(const FactorItem* __restrict__ i
   g_t<T>* C;
   bool trail = bx < ntrail;
   if (trail) {
-    const long long t = bx;
-    int r = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
-    while ((long long)(r + 1) * (r + 2) / 2 <= t) ++r;
-    while ((long long)r * (r + 1) / 2 > t) --r;
-    r0 = base + 64LL * r;
-    c0 = base + 64LL * (t - (long long)r * (r + 1) / 2);
+    r0 = base + 64LL * bx;
+    c0 = base;
     C = S;
   } else {
-    const long long t = bx - ntrail;
-    const long long ncb = (base + 63) / 64;
-    r0 = base + 64LL * (t / ncb);
-    c0 = 64LL * (t % ncb);
+    r0 = base;
+    c0 = 64LL * (bx - ntrail);
     C = Lv;
   }
   const long long cmax = trail ? n : base;
@@ -678,19 +696,24 @@ void plan_factor_blocks(Plan& plan, std::vector<FactorItem> items) {
       return SLAB_OK;
     });
   }
-  // panels of 64 columns; at step k0 the items with n > k0 form a prefix
-  for (int k0 = 0; k0 < items[0].n; k0 += 64) {
-    int live = 0;
-    while (live < count && items[live].n > k0) ++live;
-    std::vector<int> cp, cr;
+  // 128-column panels; at each step the items with n beyond the step form a
+  // prefix (items are sorted by n).  The update GEMMs are not block products
+  // of the elimination: they stay out of the plan's product timer.
+  const std::shared_ptr<Plan::Timer> timer = plan.timer;
+  plan.timer.reset();
+  auto live_beyond = [&](int k) {
+    int l = 0;
+    while (l < count && items[l].n > k) ++l;
+    return l;
+  };
+  auto panel = [&](int k0, int live) {
+    std::vector<int> cp;
     for (int i = 0; i < live; ++i) {
       const int n = items[i].n, nb = std::min(64, n - k0), nrow = n - k0 - nb;
-      const long long tr = (nrow + 63) / 64;
       cp.push_back((nrow + 63) / 64 + (k0 + nb + 63) / 64);
-      cr.push_back(nrow > 0 ? (int)(tr * (tr + 1) / 2 + tr * ((k0 + nb + 63) / 64)) : 0);
     }
-    long long tp, trk;
-    const size_t op = plan.add_offsets(cp, &tp), orr = plan.add_offsets(cr, &trk);
+    long long tp;
+    const size_t op = plan.add_offsets(cp, &tp);
     plan.step([=](const char* dev, hipStream_t st) {
       hipLaunchKernelGGL((k_panel_diag<T>), dim3((unsigned)live), dim3(256), 0, st,
                          dev_at<FactorItem>(dev, oi), live, k0);
@@ -698,14 +721,51 @@ void plan_factor_blocks(Plan& plan, std::vector<FactorItem> items) {
       hipLaunchKernelGGL((k_panel<T>), dim3((unsigned)tp), dim3(256), 0, st,
                          dev_at<FactorItem>(dev, oi), dev_at<int>(dev, op), live, k0);
       SLAB_LAUNCH_CHECK();
-      if (trk > 0) {
-        hipLaunchKernelGGL((k_rank64<T>), dim3((unsigned)trk), dim3(256), 0, st,
-                           dev_at<FactorItem>(dev, oi), dev_at<int>(dev, orr), live, k0);
-        SLAB_LAUNCH_CHECK();
-      }
       return SLAB_OK;
     });
+  };
+  for (int K0 = 0; K0 < items[0].n; K0 += 128) {
+    panel(K0, live_beyond(K0));
+    const int live2 = live_beyond(K0 + 64);
+    if (live2 == 0) continue;
+    {
+      std::vector<int> cr;
+      for (int i = 0; i < live2; ++i) {
+        const int n = items[i].n, base = K0 + 64;
+        cr.push_back((n - base + 63) / 64 + (base + 63) / 64);
+      }
+      long long trk;
+      const size_t orr = plan.add_offsets(cr, &trk);
+      plan.step([=](const char* dev, hipStream_t st) {
+        hipLaunchKernelGGL((k_rank64<T>), dim3((unsigned)trk), dim3(256), 0, st,
+                           dev_at<FactorItem>(dev, oi), dev_at<int>(dev, orr), live2, K0);
+        SLAB_LAUNCH_CHECK();
+        return SLAB_OK;
+      });
+    }
+    panel(K0 + 64, live2);
+    // both sub-panels' updates of everything beyond the panel, 128 deep:
+    //   S_22 -= L_21 L_21^T (lower tiles),  X_2c -= L_21 X_1c  (c < K0+128)
+    const int live3 = live_beyond(K0 + 128);
+    std::vector<GemmItem> tr, ca;
+    for (int i = 0; i < live3; ++i) {
+      const FactorItem& f = items[i];
+      const long long n = f.n, K2 = K0 + 128;
+      T* S = (T*)f.S;
+      T* X = (T*)f.Li;
+      GemmItem a;
+      a.A = S + K2 * n + K0; a.B = S + K2 * n + K0; a.C = S + K2 * n + K2;
+      a.M = a.N = (int)(n - K2); a.K = 128; a.lda = a.ldb = a.ldc = (int)n;
+      tr.push_back(a);
+      GemmItem c;
+      c.A = S + K2 * n + K0; c.B = X + (long long)K0 * n; c.C = X + K2 * n;
+      c.M = (int)(n - K2); c.N = (int)K2; c.K = 128; c.lda = c.ldb = c.ldc = (int)n;
+      ca.push_back(c);
+    }
+    plan_gemm<T>(plan, false, true, tr, (T)-1, (T)1, GEMM_LOWER_C | GEMM_C_PREFETCH);
+    plan_gemm<T>(plan, false, false, ca, (T)-1, (T)1, GEMM_C_PREFETCH);
   }
+  plan.timer = timer;
 }
 
 template <typename T>

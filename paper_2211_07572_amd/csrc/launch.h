@@ -29,7 +29,9 @@ int launch_maps(int n1, int n2, int b, int32_t* ck, int32_t* sc, int32_t* lc, in
                 int64_t* po, hipStream_t st);
 
 // ---- dense kernels ------------------------------------------------------------
-enum { GEMM_LOWER_C = 1, GEMM_A_LOWER = 2, GEMM_B_LOWER = 4 };
+enum { GEMM_LOWER_C = 1, GEMM_A_LOWER = 2, GEMM_B_LOWER = 4,
+       // load the C tile before the k loop (short k, beta != 0): 64-wide tiles
+       GEMM_C_PREFETCH = 8 };
 
 // C = beta*C + alpha * op(A) op(B) for every item; op(A)(i,k) = A[i*lda+k]
 // (ak=false) or A[k*lda+i] (ak=true); op(B)(k,j) = B[k*ldb+j] (bn=false) or
