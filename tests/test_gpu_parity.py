@@ -46,6 +46,7 @@ CASES = [
     (64, 64, 7),
     (40, 128, 63),
     (70, 96, 47),
+    (300, 48, 15),  # pivot blocks over two 128-column panels (GEMM updates at two depths)
 ]
 # odd-even order: odd m and a deeper level tree on top of the cases above
 CASES_OE = CASES + [(40, 52, 3), (64, 256, 7)]
