@@ -47,8 +47,8 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmItem* __restrict__ items
   typedef T vt __attribute__((ext_vector_type(VEC)));
   __shared__ T As[2][TK][TM + 4];
   __shared__ T Bs[2][TK][TN + 4];
-  // products with a lower-triangular A keep the plain order (measured faster)
-  const int vb = (flags & GEMM_A_LOWER) ? (int)blockIdx.x : xcd_linear(blockIdx.x, gridDim.x);
+  // (products with a lower-triangular A keep the row order inside an XCD range)
+  const int vb = xcd_linear(blockIdx.x, gridDim.x);
   const int itm = group_item(offs, count, vb);
   const long long bx = vb - offs[itm];
   const g_t<const T>* __restrict__ A = gp((const T*)items[itm].A);
