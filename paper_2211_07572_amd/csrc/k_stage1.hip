@@ -167,10 +167,16 @@ __device__ __forceinline__ bool sweep_inverse(T (&a)[BP], T (*colbuf)[BP], int l
 // D steps ahead into a register ring and used raw, so no load latency sits on
 // the row-to-row chain.
 // ---------------------------------------------------------------------------
-template <typename T, int BP>
-__global__ __launch_bounds__(64) void k_slab_factor(const ProbDev* __restrict__ P,
+#ifndef SLAB_FACTOR_THREADS
+#define SLAB_FACTOR_THREADS 256
+#endif
+#ifndef SLAB_FACTOR_PB
+#define SLAB_FACTOR_PB 2
+#endif
+template <typename T, int BP, int NT = SLAB_FACTOR_THREADS, int PB = SLAB_FACTOR_PB>
+__global__ __launch_bounds__(NT) void k_slab_factor(const ProbDev* __restrict__ P,
                                                     const int* __restrict__ offs, int count) {
-  constexpr int R = 64 / BP;   // lanes per row
+  constexpr int R = NT / BP;   // lanes per row
   constexpr int C = BP / R;    // columns per lane
   constexpr int D = 1;         // weight prefetch depth (row steps): one row step
                                // (an elimination) outlasts a memory latency
@@ -188,14 +194,17 @@ __global__ __launch_bounds__(64) void k_slab_factor(const ProbDev* __restrict__ 
   const int k0 = q * C;                    // first column of this lane
   const bool act = i < b;
   const long long c = (long long)s * (b + 1) + (act ? i : 0);
-  __shared__ T colbuf[2][BP];
-  __shared__ T wsh[BP];   // W of the coupling to the previous row, by column
-  __shared__ T wup[BP];   // W_r by column (Hr_r = Gr_r W_r)
+  static_assert((BP / PB) % 2 == 0 && BP % PB == 0, "an even number of pivot blocks");
+  // rows of the current pivot block; double-buffered, and with an even number
+  // of blocks per row step the next step's first block never overwrites a
+  // buffer still being read
+  __shared__ T colbuf[2][PB][BP];
   T g[C], a[C];
 #pragma unroll
   for (int j = 0; j < C; ++j) g[j] = (T)0;
-  // raw edge weights of row r: wh left/right of the node, wv below/above
-  double rl[D], rr[D], rd[D], ru[D];
+  // raw edge weights of row r: wh left/right of the node, wv below/above; and
+  // wv below/above the nodes of this lane's columns k0 .. k0+C-1
+  double rl[D], rr[D], rd[D], ru[D], cd[D][C], cu[D][C];
   // unconditional loads from clamped rows (a load skipped on some path makes
   // the compiler wait for every outstanding load); masked where used
   auto load = [&](int d, int t) __attribute__((always_inline)) {
@@ -205,6 +214,12 @@ __global__ __launch_bounds__(64) void k_slab_factor(const ProbDev* __restrict__ 
     rr[d] = wh[(c + 1) * n2 + r];
     rd[d] = wv[c * (n2 + 1) + r];
     ru[d] = wv[c * (n2 + 1) + r + 1];
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const long long ck = (long long)s * (b + 1) + min(k0 + j, b - 1);
+      cd[d][j] = wv[ck * (n2 + 1) + r];
+      cu[d][j] = wv[ck * (n2 + 1) + r + 1];
+    }
   };
 #pragma unroll
   for (int d = 0; d < D; ++d) load(d, d);
@@ -216,52 +231,109 @@ __global__ __launch_bounds__(64) void k_slab_factor(const ProbDev* __restrict__ 
       if (t < n2) {  // uniform
         const int r = dir == 0 ? t : n2 - 1 - t;
         const double whl = rl[d], whr = rr[d], wvd = rd[d], wvu = ru[d];
+        // W of the coupling to the previous row step and W_r, at this lane's columns
+        T wk[C], wup[C];
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+          const bool ak = k0 + j < b;
+          wk[j] = (ak && t > 0) ? (T)(dir == 0 ? cd[d][j] : cu[d][j]) : (T)0;
+          wup[j] = ak ? (T)cd[d][j] : (T)0;
+        }
         load(d, t + D);
         const T dd = act ? (T)(whl + whr + wvd + wvu) : (T)1;
         const T wl = (act && i > 0) ? (T)whl : (T)0;
         const T wr = (act && i < b - 1) ? (T)whr : (T)0;
         const T wc = (act && t > 0) ? (T)(dir == 0 ? wvd : wvu) : (T)0;
-        if (q == 0) {
-          wsh[i] = wc;
-          wup[i] = act ? (T)wvd : (T)0;
-        }
-        __syncthreads();
         // row i of D_r - W G W (columns k0 .. k0+C-1)
 #pragma unroll
         for (int j = 0; j < C; ++j) {
           const int k = k0 + j;
           const T dk = (k == i) ? dd : ((k == i - 1) ? -wl : ((k == i + 1) ? -wr : (T)0));
-          a[j] = dk - wc * g[j] * wsh[k];
+          a[j] = dk - wc * g[j] * wk[j];
         }
-        if (i == 0) {
+        if (i < PB) {
 #pragma unroll
-          for (int j = 0; j < C; ++j) colbuf[0][k0 + j] = a[j];
+          for (int j = 0; j < C; ++j) colbuf[0][i][k0 + j] = a[j];
         }
         __syncthreads();
+        // block sweeps over pivots p0 .. p0+PB-1 (rows published in colbuf)
 #pragma unroll
-        for (int p = 0; p < BP; ++p) {
-          const int buf = p & 1;
-          const T dp = colbuf[buf][p];
-          ok = ok && (dp > (T)0) && isfinite((double)dp);
-          const T inv = fast_recip(dp);
+        for (int p0 = 0; p0 < BP; p0 += PB) {
+          const int buf = (p0 / PB) & 1;
           // all LDS reads first, unconditionally (no read inside a divergent branch)
-          T cb[C];
+          T h[PB][PB], mpk[PB][C], mip[PB];
 #pragma unroll
-          for (int j = 0; j < C; ++j) cb[j] = colbuf[buf][k0 + j];
-          const T aip = colbuf[buf][i];
-          const bool piv = i == p;
-          const T f = aip * inv;
-          // other rows: a -= f cb; the pivot row is scaled, not updated (no
-          // cancellation): a = inv cb.  One select per row, not per element.
-          const T t = piv ? inv : -f;
+          for (int u = 0; u < PB; ++u) {
+#pragma unroll
+            for (int v = 0; v < PB; ++v) h[u][v] = colbuf[buf][u][p0 + v];
+#pragma unroll
+            for (int j = 0; j < C; ++j) mpk[u][j] = colbuf[buf][u][k0 + j];
+            mip[u] = colbuf[buf][u][i];  // = entry (i, p0+u) by symmetry
+          }
+          // h := -(pivot block)^{-1}: the sweep over its own PB pivots, in
+          // registers (2 x 2: adjugate over the determinant; the leading
+          // entry and the determinant positive <=> both pivots positive)
+          if constexpr (PB == 2) {
+            const T h00 = h[0][0], h01 = h[0][1], h11 = h[1][1];
+            const T det = fma(h00, h11, -(h01 * h01));
+            ok = ok && (h00 > (T)0) && (det > (T)0) && isfinite((double)det);
+            const T ninv = -fast_recip(det);
+            h[0][0] = h11 * ninv;
+            h[1][1] = h00 * ninv;
+            h[0][1] = h[1][0] = -h01 * ninv;
+          } else {
+#pragma unroll
+          for (int pp = 0; pp < PB; ++pp) {
+            const T dp = h[pp][pp];
+            ok = ok && (dp > (T)0) && isfinite((double)dp);
+            const T inv = fast_recip(dp);
+#pragma unroll
+            for (int u = 0; u < PB; ++u) {
+              if (u == pp) continue;
+              const T f = h[u][pp] * inv;
+#pragma unroll
+              for (int v = 0; v < PB; ++v)
+                if (v != pp) h[u][v] = fma(-f, h[pp][v], h[u][v]);
+              h[u][pp] = f;
+            }
+#pragma unroll
+            for (int v = 0; v < PB; ++v)
+              if (v != pp) h[pp][v] *= inv;
+            h[pp][pp] = -inv;
+          }
+          }
+          // row multipliers: other rows -c = (row i, pivot columns) * h; a pivot
+          // row pr takes row pr of h, and keeps nothing of its old values.  In
+          // both cases the new entries in the pivot columns are -t.
+          const int pr = i - p0;
+          const bool piv = pr >= 0 && pr < PB;
+          T tv[PB];
+#pragma unroll
+          for (int v = 0; v < PB; ++v) {
+            T cv = (T)0;
+#pragma unroll
+            for (int u = 0; u < PB; ++u) cv = fma(mip[u], h[u][v], cv);
+            T hv = h[0][v];
+#pragma unroll
+            for (int u = 1; u < PB; ++u) hv = (pr == u) ? h[u][v] : hv;
+            tv[v] = piv ? -hv : cv;
+          }
           const T keep = piv ? (T)0 : (T)1;
 #pragma unroll
-          for (int j = 0; j < C; ++j) a[j] = fma(t, cb[j], a[j] * keep);
-          if (q == p / C) a[p % C] = piv ? -inv : f;
-          if (p + 1 < BP) {
-            if (i == p + 1) {
+          for (int j = 0; j < C; ++j) {
+            T acc = a[j] * keep;
 #pragma unroll
-              for (int j = 0; j < C; ++j) colbuf[buf ^ 1][k0 + j] = a[j];
+            for (int v = 0; v < PB; ++v) acc = fma(tv[v], mpk[v][j], acc);
+            a[j] = acc;
+          }
+#pragma unroll
+          for (int v = 0; v < PB; ++v)
+            if (q == (p0 + v) / C) a[(p0 + v) % C] = -tv[v];
+          if (p0 + PB < BP) {
+            const int nr = i - (p0 + PB);
+            if (nr >= 0 && nr < PB) {
+#pragma unroll
+              for (int j = 0; j < C; ++j) colbuf[buf ^ 1][nr][k0 + j] = a[j];
             }
             __syncthreads();
           }
@@ -275,9 +347,8 @@ __global__ __launch_bounds__(64) void k_slab_factor(const ProbDev* __restrict__ 
         } else {
           g_t<T>* dst = Hsw + ((size_t)s * n2 + r) * BP * BP;
 #pragma unroll
-          for (int j = 0; j < C; ++j) dst[swz_index<T>(i, k0 + j, BP)] = g[j] * wup[k0 + j];
+          for (int j = 0; j < C; ++j) dst[swz_index<T>(i, k0 + j, BP)] = g[j] * wup[j];
         }
-        __syncthreads();
       }
     }
   }
@@ -600,7 +671,7 @@ static void plan_stage1_bp(Plan& plan, const std::vector<ProbDev>& probs, int ph
   if (phase == 0) {
     counts([](const ProbDev& d) { return 2LL * d.m; });
     plan.step([=](const char* dev, hipStream_t st) {
-      hipLaunchKernelGGL((k_slab_factor<T, BP>), dim3((unsigned)tot), dim3(64), 0, st,
+      hipLaunchKernelGGL((k_slab_factor<T, BP>), dim3((unsigned)tot), dim3(SLAB_FACTOR_THREADS), 0, st,
                          dev_at<ProbDev>(dev, pd), dev_at<int>(dev, off), count);
       SLAB_LAUNCH_CHECK();
       if (ev) SLAB_HIP_CHECK(hipEventRecord(ev, st));
