@@ -123,34 +123,6 @@ __device__ __forceinline__ void build_D_row(T (&a)[BP], const g_t<const double>*
   }
 }
 
-// Symmetric sweep operator over all pivots: on return a (row `lane`) holds
-// row `lane` of -M^{-1}.  Row-per-lane; the pivot column is exchanged through
-// LDS (by symmetry it equals the pivot row).  Returns false on a pivot that is
-// not positive and finite.
-template <typename T, int BP>
-__device__ __forceinline__ bool sweep_inverse(T (&a)[BP], T (*colbuf)[BP], int lane) {
-  bool ok = true;
-#pragma unroll
-  for (int p = 0; p < BP; ++p) {
-    if (lane < BP) colbuf[p & 1][lane] = a[p];
-    __syncthreads();
-    const T d = colbuf[p & 1][p];
-    ok = ok && (d > (T)0) && isfinite((double)d);
-    const T inv = (T)1 / d;
-    if (lane == p) {
-#pragma unroll
-      for (int k = 0; k < BP; ++k) a[k] = colbuf[p & 1][k] * inv;
-      a[p] = -inv;
-    } else {
-      const T f = a[p] * inv;
-#pragma unroll
-      for (int k = 0; k < BP; ++k) a[k] -= f * colbuf[p & 1][k];
-      a[p] = f;
-    }
-  }
-  return ok;
-}
-
 // ---------------------------------------------------------------------------
 // Slab factorization (Alg. 3 first loop), block-tridiagonal form of the banded
 // slab matrix A_{2s,2s}: diagonal blocks D_r, couplings A_{r,r-1} = -W_r with
@@ -362,11 +334,23 @@ __global__ __launch_bounds__(NT) void k_slab_factor(const ProbDev* __restrict__ 
 // interface s), pre-scaled by the interface edge weights:
 //   sig[s][rho][0] = wL_rho Sigma_rho[:, 0],  sig[s][rho][1] = wR_rho Sigma_rho[:, b-1].
 // These start the downward propagation (Sec. 3.1, eq. (T11_detailed)).
-// Four waves per block, one (slab, rho) per wave.
+// BP lanes per (slab, rho), lane = row; Gauss-Jordan elimination of the matrix
+// augmented with the two unit columns, touching at pivot p only the columns
+// right of p and the two right-hand sides (the inverse itself is not formed).
+// The pivot row goes through LDS with wave-level ordering only: the problems
+// of a wave never wait for another wave.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <typename T, int BP>
 __global__ __launch_bounds__(256) void k_sigma(const ProbDev* __restrict__ P,
                                                const int* __restrict__ offs, int count) {
+  constexpr int PPW = 64 / BP;  // problems per wave
+  constexpr int RW = BP + 3;    // published pivot row: columns, pivot, two right-hand sides
   const int it = group_item(offs, count, blockIdx.x);
   const int bx = blockIdx.x - offs[it];
   const g_t<const double>* __restrict__ wh = gp((const double*)P[it].wh);
@@ -377,52 +361,63 @@ __global__ __launch_bounds__(256) void k_sigma(const ProbDev* __restrict__ P,
   g_t<T>* __restrict__ sig = gp((T*)P[it].sig);
   g_t<int>* __restrict__ status = gp(P[it].status);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const long long idx = (long long)bx * 4 + wave;
+  const int h = lane / BP, i = lane % BP;
+  const long long idx = ((long long)bx * 4 + wave) * PPW + h;
   const bool valid = idx < (long long)m * n2;
   const int s = valid ? (int)(idx / n2) : 0;
   const int rho = valid ? (int)(idx % n2) : 0;
   const int c0 = s * (b + 1);
-  const long long c = c0 + (lane < b ? lane : 0);
-  __shared__ T colbuf_all[4][2][BP];
-  __shared__ T wsh_all[4][BP];
-  T (*colbuf)[BP] = colbuf_all[wave];
-  T* wsh = wsh_all[wave];
+  const long long c = c0 + (i < b ? i : 0);
+  __shared__ T pivrow[4][PPW][2][RW];
+  __shared__ T wsh[4][PPW][BP];
   T a[BP];
-  build_D_row<T, BP>(a, wh, wv, n2, b, c0, rho, lane);
-  // top coupling: W_rho Gl_{rho-1} W_rho
-  T wt = (T)0;
-  if (rho > 0 && lane < b) wt = (T)wv[c * (n2 + 1) + rho];
-  if (lane < BP) wsh[lane] = wt;
-  __syncthreads();
-  if (rho > 0 && lane < BP) {
-    const g_t<const T>* G = Gl + (((size_t)s * n2 + rho - 1) * BP + lane) * BP;
+  build_D_row<T, BP>(a, wh, wv, n2, b, c0, rho, i);
+  // top coupling W_rho Gl_{rho-1} W_rho (column weights through LDS), bottom
+  // coupling W_{rho+1} Hr_{rho+1} (Hr already carries the column scaling);
+  // loads from clamped rows, masked by the weights
+  const T wt = (rho > 0 && i < b) ? (T)wv[c * (n2 + 1) + rho] : (T)0;
+  const T wb = (rho < n2 - 1 && i < b) ? (T)wv[c * (n2 + 1) + rho + 1] : (T)0;
+  wsh[wave][h][i] = wt;
+  wave_lds_sync();
+  {
+    const g_t<const T>* G = Gl + (((size_t)s * n2 + max(rho - 1, 0)) * BP + i) * BP;
+    const g_t<const T>* H = Hsw + ((size_t)s * n2 + min(rho + 1, n2 - 1)) * BP * BP;
 #pragma unroll
-    for (int k = 0; k < BP; ++k) a[k] -= wt * G[k] * wsh[k];
+    for (int k = 0; k < BP; ++k) a[k] -= wt * G[k] * wsh[wave][h][k] + wb * H[swz_index<T>(i, k, BP)];
   }
-  // bottom coupling: W_{rho+1} Hr_{rho+1} (Hr already carries the column scaling)
-  if (rho < n2 - 1 && lane < BP) {
-    T wb = (T)0;
-    if (lane < b) wb = (T)wv[c * (n2 + 1) + rho + 1];
-    const g_t<const T>* H = Hsw + ((size_t)s * n2 + rho + 1) * BP * BP;
+  T rl = (i == 0) ? (T)1 : (T)0, rr = (i == b - 1) ? (T)1 : (T)0;
+  bool ok = true;
 #pragma unroll
-    for (int k = 0; k < BP; ++k) a[k] -= wb * H[swz_index<T>(lane, k, BP)];
-  }
-  __syncthreads();
-  bool ok = sweep_inverse<T, BP>(a, colbuf, lane);
-  if (valid && lane < BP) {
-    T left = (T)0, right = (T)0;
+  for (int p = 0; p < BP; ++p) {
+    T* pr = pivrow[wave][h][p & 1];
+    if (i == p) {
 #pragma unroll
-    for (int k = 0; k < BP; ++k) {
-      if (k == 0) left = -a[k];
-      if (k == b - 1) right = -a[k];
+      for (int k = p; k < BP; ++k) pr[k] = a[k];
+      pr[BP + 1] = rl;
+      pr[BP + 2] = rr;
     }
+    wave_lds_sync();
+    const T d = pr[p];
+    ok = ok && (d > (T)0) && isfinite((double)d);
+    const T inv = fast_recip(d);
+    const bool piv = i == p;
+    // other rows: x -= f x_p with f = a[p] / d; the pivot row is scaled (no
+    // cancellation): x = inv x_p
+    const T t = piv ? inv : -(a[p] * inv);
+    const T keep = piv ? (T)0 : (T)1;
+#pragma unroll
+    for (int k = p + 1; k < BP; ++k) a[k] = fma(t, pr[k], a[k] * keep);
+    rl = fma(t, pr[BP + 1], rl * keep);
+    rr = fma(t, pr[BP + 2], rr * keep);
+  }
+  if (valid) {
     const double wL = wh[(long long)c0 * n2 + rho];
     const double wR = wh[(long long)(c0 + b) * n2 + rho];
     g_t<T>* dst = sig + ((size_t)s * n2 + rho) * 2 * BP;
-    dst[lane] = (T)(wL * (double)left);
-    dst[BP + lane] = (T)(wR * (double)right);
+    dst[i] = (T)(wL * (double)rl);
+    dst[BP + i] = (T)(wR * (double)rr);
   }
-  if (valid && !ok && lane == 0) { status[0] = 2; status[1] = s; }
+  if (valid && !ok && i == 0) { status[0] = 2; status[1] = s; }
 }
 
 // ---------------------------------------------------------------------------
@@ -678,7 +673,7 @@ static void plan_stage1_bp(Plan& plan, const std::vector<ProbDev>& probs, int ph
       return SLAB_OK;
     });
   } else if (phase == 1) {
-    counts([](const ProbDev& d) { return ceil_div((long long)d.m * d.n2, 4); });
+    counts([](const ProbDev& d) { return ceil_div((long long)d.m * d.n2, 4LL * (64 / BP)); });
     plan.step([=](const char* dev, hipStream_t st) {
       hipLaunchKernelGGL((k_sigma<T, BP>), dim3((unsigned)tot), dim3(256), 0, st,
                          dev_at<ProbDev>(dev, pd), dev_at<int>(dev, off), count);
