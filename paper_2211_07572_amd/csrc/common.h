@@ -116,6 +116,19 @@ __host__ __device__ __forceinline__ int swz_index(int row, int col, int BP) {
   return (mt * NK + ks) * 64 + 16 * g + n;
 }
 
+// LDS exchange between the lanes of one wave: a wave's LDS operations are
+// performed in order, so only the compiler has to keep them in order.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+// Workgroup barrier, or the wave-level ordering when the workgroup is one wave.
+template <int NT> __device__ __forceinline__ void group_sync() {
+  if constexpr (NT == 64) wave_lds_sync();
+  else __syncthreads();
+}
+
 inline unsigned int ceil_div(long long a, long long b) { return (unsigned int)((a + b - 1) / b); }
 
 }  // namespace slab

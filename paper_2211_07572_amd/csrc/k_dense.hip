@@ -351,8 +351,8 @@ template void plan_gemm<double>(Plan&, bool, bool, const std::vector<GemmItem>&,
 // [S_kk | I], kept in one array (U on and above the diagonal, the unit lower
 // L~^-1 below it), gives S_kk = L~ U with U = D L~^T, hence
 // L_kk^-1 = D^-1/2 L~^-1.  The working matrix lives in registers (thread = row
-// x 16-column quarter); each elimination step exchanges only the pivot row and
-// column through LDS, with one barrier per step.  L_kk^-1 overwrites the lower
+// x 16-column quarter); each step eliminates two pivots and exchanges only the
+// two pivot rows and columns through LDS, with one barrier per step.  L_kk^-1 overwrites the lower
 // triangle of S_kk (L_kk itself is never needed again).
 // k_panel then, on 16x16x4 MFMA tiles, either
 //   * computes 64 rows of L below the block:       L_ik = S_ik L_kk^-T, or
@@ -366,11 +366,13 @@ __global__ __launch_bounds__(256) void k_panel_diag(const FactorItem* __restrict
   g_t<int>* __restrict__ status = gp(items[itm].status);
   const int n = items[itm].n, blk = items[itm].blk;
   if (k0 >= n) return;  // uniform: this item has no panel at k0
-  __shared__ T rowbuf[2][64];
-  __shared__ T colbuf[2][64];
+  __shared__ T rowbuf[2][2][64];  // the two pivot rows of a step
+  __shared__ T colbuf[2][2][64];  // the two pivot columns of a step
   const int nb = min(64, n - k0);
   const int tid = threadIdx.x;
-  // thread (row i, column quarter q) keeps 16 entries of the working matrix in registers
+  // thread (row i, column quarter q) keeps 16 entries of the working matrix in
+  // registers; rows and columns beyond nb are the identity (their pivots are
+  // eliminated as no-ops)
   const int i = tid & 63, q = tid >> 6;
   T a[16];
 #pragma unroll
@@ -380,37 +382,71 @@ __global__ __launch_bounds__(256) void k_panel_diag(const FactorItem* __restrict
     if (i < nb && col < nb) v = S[(long long)(k0 + max(i, col)) * n + k0 + min(i, col)];
     a[c] = v;
   }
-  if (i == 0) {
+  if (i < 2) {
 #pragma unroll
-    for (int c = 0; c < 16; ++c) rowbuf[0][16 * q + c] = a[c];
+    for (int c = 0; c < 16; ++c) rowbuf[0][i][16 * q + c] = a[c];
   }
-  if (q == 0) colbuf[0][i] = a[0];
+  if (q == 0) {
+    colbuf[0][0][i] = a[0];
+    colbuf[0][1][i] = a[1];
+  }
   __syncthreads();
-  // pivot p = 16 pb + pp: the register index pp is a compile-time constant and
-  // the owner of column p is the wave q == pb (uniform branches only)
+  // two pivots p, p+1 per step (one barrier): with the pivot block
+  // M = [d0 e; e2 d11] (rows p, p+1 at columns p, p+1), a row i > p+1 takes
+  // (h0, h1) = (a_ip, a_i,p+1) M^-1, i.e. both eliminations at once:
+  //   a_i -= h0 a_p + h1 a_p+1,  a_ip = -h0,  a_i,p+1 = -h1;
+  // row p+1 takes the first elimination only (g = e2 / d0):
+  //   a_p+1 -= g a_p,  a_p+1,p = -g.
+  // p = 16 pb + pp: the register index pp is a compile-time constant and the
+  // owner of columns p, p+1 is the wave q == pb (uniform branches only)
   for (int pb = 0; pb < 4; ++pb) {
 #pragma unroll
-    for (int pp = 0; pp < 16; ++pp) {
+    for (int pp = 0; pp < 16; pp += 2) {
       const int p = 16 * pb + pp;
       if (p >= nb) break;
-      const int buf = p & 1;
-      const T ipiv = fast_recip(rowbuf[buf][p]);
-      T rp[16];
+      const int buf = (p >> 1) & 1;
+      const T d0 = rowbuf[buf][0][p], e = rowbuf[buf][0][p + 1];
+      const T e2 = rowbuf[buf][1][p], d11 = rowbuf[buf][1][p + 1];
+      const T ai0 = colbuf[buf][0][i], ai1 = colbuf[buf][1][i];
+      T r0[16], r1[16];
 #pragma unroll
-      for (int c = 0; c < 16; ++c) rp[c] = rowbuf[buf][16 * q + c];
-      const T f = (i > p) ? colbuf[buf][i] * ipiv : (T)0;  // f = 0 keeps rows <= p
+      for (int c = 0; c < 16; ++c) {
+        r0[c] = rowbuf[buf][0][16 * q + c];
+        r1[c] = rowbuf[buf][1][16 * q + c];
+      }
+      const T rdet = fast_recip(fma(d0, d11, -(e * e2)));
+      const T h0 = fma(ai0, d11, -(ai1 * e2)) * rdet;
+      const T h1 = fma(ai1, d0, -(ai0 * e)) * rdet;
+      const T gg = e2 * fast_recip(d0);
+      const bool below = i > p + 1, next = i == p + 1;
+      const T t0 = below ? h0 : (next ? gg : (T)0);
+      const T t1 = below ? h1 : (T)0;
 #pragma unroll
-      for (int c = 0; c < 16; ++c) a[c] -= f * rp[c];
-      if (q == pb && i > p) a[pp] = -f;
-      if (p + 1 < nb) {  // publish the next pivot row and pivot column
-        if (i == p + 1) {
-#pragma unroll
-          for (int c = 0; c < 16; ++c) rowbuf[buf ^ 1][16 * q + c] = a[c];
+      for (int c = 0; c < 16; ++c) a[c] = fma(-t0, r0[c], fma(-t1, r1[c], a[c]));
+      if (q == pb) {
+        if (below) {
+          a[pp] = -h0;
+          a[pp + 1] = -h1;
+        } else if (next) {
+          a[pp] = -gg;
         }
-        if (pp < 15) {
-          if (q == pb) colbuf[buf ^ 1][i] = a[(pp + 1) & 15];
+      }
+      if (p + 2 < nb) {  // publish the next two pivot rows and columns
+        const int nr = i - (p + 2);
+        if (nr >= 0 && nr < 2) {
+#pragma unroll
+          for (int c = 0; c < 16; ++c) rowbuf[buf ^ 1][nr][16 * q + c] = a[c];
+        }
+        if (pp < 14) {
+          if (q == pb) {
+            colbuf[buf ^ 1][0][i] = a[(pp + 2) & 15];
+            colbuf[buf ^ 1][1][i] = a[(pp + 3) & 15];
+          }
         } else {
-          if (q == pb + 1) colbuf[buf ^ 1][i] = a[0];
+          if (q == pb + 1) {
+            colbuf[buf ^ 1][0][i] = a[0];
+            colbuf[buf ^ 1][1][i] = a[1];
+          }
         }
       }
       __syncthreads();
@@ -426,11 +462,11 @@ __global__ __launch_bounds__(256) void k_panel_diag(const FactorItem* __restrict
       status[0] = 3;
       status[1] = blk;
     }
-    colbuf[0][i] = (T)1 / sqrt(d);
+    colbuf[0][0][i] = (T)1 / sqrt(d);
   }
   __syncthreads();
   if (i < nb) {
-    const T rs = colbuf[0][i];
+    const T rs = colbuf[0][0][i];
     g_t<T>* row = S + (long long)(k0 + i) * n + k0;
 #pragma unroll
     for (int c = 0; c < 16; ++c) {

@@ -227,7 +227,7 @@ __global__ __launch_bounds__(NT) void k_slab_factor(const ProbDev* __restrict__ 
 #pragma unroll
           for (int j = 0; j < C; ++j) colbuf[0][i][k0 + j] = a[j];
         }
-        __syncthreads();
+        group_sync<NT>();
         // block sweeps over pivots p0 .. p0+PB-1 (rows published in colbuf)
 #pragma unroll
         for (int p0 = 0; p0 < BP; p0 += PB) {
@@ -307,7 +307,7 @@ __global__ __launch_bounds__(NT) void k_slab_factor(const ProbDev* __restrict__ 
 #pragma unroll
               for (int j = 0; j < C; ++j) colbuf[buf ^ 1][nr][k0 + j] = a[j];
             }
-            __syncthreads();
+            group_sync<NT>();
           }
         }
 #pragma unroll
@@ -340,12 +340,6 @@ __global__ __launch_bounds__(NT) void k_slab_factor(const ProbDev* __restrict__ 
 // The pivot row goes through LDS with wave-level ordering only: the problems
 // of a wave never wait for another wave.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 template <typename T, int BP>
 __global__ __launch_bounds__(256) void k_sigma(const ProbDev* __restrict__ P,
                                                const int* __restrict__ offs, int count) {
