@@ -358,8 +358,11 @@ template void plan_gemm<double>(Plan&, bool, bool, const std::vector<GemmItem>&,
 //   * computes 64 rows of L below the block:       L_ik = S_ik L_kk^-T, or
 //   * advances 64 columns of the carried inverse:  X_k = L_kk^-1 X_k.
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256) void k_panel_diag(const FactorItem* __restrict__ items,
+#ifndef PANEL_DIAG_THREADS
+#define PANEL_DIAG_THREADS 512
+#endif
+template <typename T, int NT = PANEL_DIAG_THREADS>
+__global__ __launch_bounds__(NT) void k_panel_diag(const FactorItem* __restrict__ items,
                                                     int count, int k0) {
   const int itm = blockIdx.x;
   g_t<T>* __restrict__ S = gp((T*)items[itm].S);
@@ -370,21 +373,22 @@ __global__ __launch_bounds__(256) void k_panel_diag(const FactorItem* __restrict
   __shared__ T colbuf[2][2][64];  // the two pivot columns of a step
   const int nb = min(64, n - k0);
   const int tid = threadIdx.x;
-  // thread (row i, column quarter q) keeps 16 entries of the working matrix in
+  // thread (row i, column group q) keeps CQ entries of the working matrix in
   // registers; rows and columns beyond nb are the identity (their pivots are
   // eliminated as no-ops)
+  constexpr int NQ = NT / 64, CQ = 64 / NQ;  // column groups, columns per group
   const int i = tid & 63, q = tid >> 6;
-  T a[16];
+  T a[CQ];
 #pragma unroll
-  for (int c = 0; c < 16; ++c) {
-    const int col = 16 * q + c;
+  for (int c = 0; c < CQ; ++c) {
+    const int col = CQ * q + c;
     T v = (i == col) ? (T)1 : (T)0;
     if (i < nb && col < nb) v = S[(long long)(k0 + max(i, col)) * n + k0 + min(i, col)];
     a[c] = v;
   }
   if (i < 2) {
 #pragma unroll
-    for (int c = 0; c < 16; ++c) rowbuf[0][i][16 * q + c] = a[c];
+    for (int c = 0; c < CQ; ++c) rowbuf[0][i][CQ * q + c] = a[c];
   }
   if (q == 0) {
     colbuf[0][0][i] = a[0];
@@ -397,22 +401,22 @@ __global__ __launch_bounds__(256) void k_panel_diag(const FactorItem* __restrict
   //   a_i -= h0 a_p + h1 a_p+1,  a_ip = -h0,  a_i,p+1 = -h1;
   // row p+1 takes the first elimination only (g = e2 / d0):
   //   a_p+1 -= g a_p,  a_p+1,p = -g.
-  // p = 16 pb + pp: the register index pp is a compile-time constant and the
+  // p = CQ pb + pp: the register index pp is a compile-time constant and the
   // owner of columns p, p+1 is the wave q == pb (uniform branches only)
-  for (int pb = 0; pb < 4; ++pb) {
+  for (int pb = 0; pb < NQ; ++pb) {
 #pragma unroll
-    for (int pp = 0; pp < 16; pp += 2) {
-      const int p = 16 * pb + pp;
+    for (int pp = 0; pp < CQ; pp += 2) {
+      const int p = CQ * pb + pp;
       if (p >= nb) break;
       const int buf = (p >> 1) & 1;
       const T d0 = rowbuf[buf][0][p], e = rowbuf[buf][0][p + 1];
       const T e2 = rowbuf[buf][1][p], d11 = rowbuf[buf][1][p + 1];
       const T ai0 = colbuf[buf][0][i], ai1 = colbuf[buf][1][i];
-      T r0[16], r1[16];
+      T r0[CQ], r1[CQ];
 #pragma unroll
-      for (int c = 0; c < 16; ++c) {
-        r0[c] = rowbuf[buf][0][16 * q + c];
-        r1[c] = rowbuf[buf][1][16 * q + c];
+      for (int c = 0; c < CQ; ++c) {
+        r0[c] = rowbuf[buf][0][CQ * q + c];
+        r1[c] = rowbuf[buf][1][CQ * q + c];
       }
       const T rdet = fast_recip(fma(d0, d11, -(e * e2)));
       const T h0 = fma(ai0, d11, -(ai1 * e2)) * rdet;
@@ -422,7 +426,7 @@ __global__ __launch_bounds__(256) void k_panel_diag(const FactorItem* __restrict
       const T t0 = below ? h0 : (next ? gg : (T)0);
       const T t1 = below ? h1 : (T)0;
 #pragma unroll
-      for (int c = 0; c < 16; ++c) a[c] = fma(-t0, r0[c], fma(-t1, r1[c], a[c]));
+      for (int c = 0; c < CQ; ++c) a[c] = fma(-t0, r0[c], fma(-t1, r1[c], a[c]));
       if (q == pb) {
         if (below) {
           a[pp] = -h0;
@@ -435,12 +439,12 @@ __global__ __launch_bounds__(256) void k_panel_diag(const FactorItem* __restrict
         const int nr = i - (p + 2);
         if (nr >= 0 && nr < 2) {
 #pragma unroll
-          for (int c = 0; c < 16; ++c) rowbuf[buf ^ 1][nr][16 * q + c] = a[c];
+          for (int c = 0; c < CQ; ++c) rowbuf[buf ^ 1][nr][CQ * q + c] = a[c];
         }
-        if (pp < 14) {
+        if (pp < CQ - 2) {
           if (q == pb) {
-            colbuf[buf ^ 1][0][i] = a[(pp + 2) & 15];
-            colbuf[buf ^ 1][1][i] = a[(pp + 3) & 15];
+            colbuf[buf ^ 1][0][i] = a[(pp + 2) % CQ];
+            colbuf[buf ^ 1][1][i] = a[(pp + 3) % CQ];
           }
         } else {
           if (q == pb + 1) {
@@ -453,11 +457,11 @@ __global__ __launch_bounds__(256) void k_panel_diag(const FactorItem* __restrict
     }
   }
   // diagonal of U is D; L_kk^-1 = D^-1/2 L~^-1
-  if (q == (i >> 4)) {
+  if (q == i / CQ) {
     T d = (T)1;
 #pragma unroll
-    for (int c = 0; c < 16; ++c)
-      if (c == (i & 15)) d = a[c];
+    for (int c = 0; c < CQ; ++c)
+      if (c == i % CQ) d = a[c];
     if (i < nb && (!(d > (T)0) || !isfinite((double)d))) {
       status[0] = 3;
       status[1] = blk;
@@ -469,8 +473,8 @@ __global__ __launch_bounds__(256) void k_panel_diag(const FactorItem* __restrict
     const T rs = colbuf[0][0][i];
     g_t<T>* row = S + (long long)(k0 + i) * n + k0;
 #pragma unroll
-    for (int c = 0; c < 16; ++c) {
-      const int col = 16 * q + c;
+    for (int c = 0; c < CQ; ++c) {
+      const int col = CQ * q + c;
       if (col <= i) row[col] = (col < i) ? a[c] * rs : rs;
     }
   }
@@ -751,7 +755,7 @@ void plan_factor_blocks(Plan& plan, std::vector<FactorItem> items) {
     long long tp;
     const size_t op = plan.add_offsets(cp, &tp);
     plan.step([=](const char* dev, hipStream_t st) {
-      hipLaunchKernelGGL((k_panel_diag<T>), dim3((unsigned)live), dim3(256), 0, st,
+      hipLaunchKernelGGL((k_panel_diag<T>), dim3((unsigned)live), dim3(PANEL_DIAG_THREADS), 0, st,
                          dev_at<FactorItem>(dev, oi), live, k0);
       SLAB_LAUNCH_CHECK();
       hipLaunchKernelGGL((k_panel<T>), dim3((unsigned)tp), dim3(256), 0, st,
