@@ -534,87 +534,120 @@ __global__ __launch_bounds__(256) void k_schur(const ProbDev* __restrict__ P,
 //   T_jj     = A_oo(j) - PRR[j] - PLL[j+1]      (symmetric; full block written)
 //   T_{j,j+1} = -PLR[j+1] (lower part), -PRL[j+1]^T (upper part)
 // A_oo(j): diagonal of the interface column, -w on the vertical edges.
-// 32x32 tiles; upper tiles read the transposed source tile through LDS.
-// Outputs in the precision TO of the block factorization, and in FP64 when the
-// T64 pointers are given.
+// 64x64 tiles, 16 entries per thread.  The pieces hold lower triangles only:
+// a tile at or below the diagonal reads its own entries, a tile at or above it
+// reads the mirrored source tile and transposes it through LDS.  Every load is
+// unconditional, from clamped indices, and masked where it is used (a skipped
+// load makes the compiler wait for all outstanding ones); the A_oo entries of
+// the tile's rows go through LDS.  Outputs in the precision TO of the block
+// factorization, and in FP64 when the T64 pointers are given.
 // ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ double diag_value(const g_t<const double>* __restrict__ wh,
-                                             const g_t<const double>* __restrict__ wv, int n2,
-                                             int b, int m, int j,
-                                             const g_t<const T>* __restrict__ PRR,
-                                             const g_t<const T>* __restrict__ PLL, int R, int P) {
-  const long long cj = (long long)j * (b + 1) + b;
-  double a = 0.0;
-  if (R == P)
-    a = wh[cj * n2 + R] + wh[(cj + 1) * n2 + R] + wv[cj * (n2 + 1) + R] + wv[cj * (n2 + 1) + R + 1];
-  else if (R == P + 1)
-    a = -wv[cj * (n2 + 1) + R];
+template <typename T, typename TO, bool OFF>
+__device__ __forceinline__ void assemble_tile(const ProbDev& pd, int j, int ti, int tj,
+                                              double (*tile)[65], double* aoo_d,
+                                              double* aoo_s) {
+  const g_t<const double>* __restrict__ wh = gp((const double*)pd.wh);
+  const g_t<const double>* __restrict__ wv = gp((const double*)pd.wv);
+  const int n2 = pd.n2, b = pd.b, m = pd.m;
+  const g_t<const T>* __restrict__ PRR = gp((const T*)pd.PRR);
+  const g_t<const T>* __restrict__ PLL = gp((const T*)pd.PLL);
+  const g_t<const T>* __restrict__ PLR = gp((const T*)pd.PLR);
+  const g_t<const T>* __restrict__ PRL = gp((const T*)pd.PRL);
+  g_t<TO>* __restrict__ Tout = gp((TO*)(OFF ? pd.To : pd.Td));
+  g_t<double>* __restrict__ Tout64 = gp(OFF ? pd.O64 : pd.T64);
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   const size_t nsq = (size_t)n2 * n2;
-  const size_t off = (size_t)R * n2 + P;
-  double v = a - (double)PRR[(size_t)j * nsq + off];
-  if (j + 1 < m) v -= (double)PLL[(size_t)(j + 1) * nsq + off];
-  return v;
+  const bool lastj = j + 1 >= m;
+  // T_jj: -PRR[j] - PLL[j+1] (+ A_oo);  T_{j,j+1}: -PLR[j+1] (lower), -PRL[j+1]^T (upper)
+  const g_t<const T>* __restrict__ src0 = OFF ? PLR + (size_t)(j + 1) * nsq : PRR + (size_t)j * nsq;
+  const g_t<const T>* __restrict__ src0m = OFF ? PRL + (size_t)(j + 1) * nsq : src0;
+  const g_t<const T>* __restrict__ src1 = PLL + (size_t)min(j + 1, m - 1) * nsq;
+  const bool direct = ti >= tj, mirrored = ti <= tj;  // uniform
+  // A_oo entries of rows ti*64 + tx (diagonal tiles and the tiles just below
+  // them), and A_oo(rho, rho-1) of this thread's column (the superdiagonal of
+  // the mirrored part)
+  double aoo_c = 0.0;
+  if (!OFF) {
+    const long long cj = (long long)j * (b + 1) + b;
+    const int R = min(ti * 64 + tx, n2 - 1), C = min(tj * 64 + tx, n2 - 1);
+    aoo_d[tx] = wh[cj * n2 + R] + wh[(cj + 1) * n2 + R] + wv[cj * (n2 + 1) + R] +
+                wv[cj * (n2 + 1) + R + 1];
+    aoo_s[tx] = -wv[cj * (n2 + 1) + R];
+    aoo_c = -wv[cj * (n2 + 1) + C];
+  }
+  T q0[16], q1[16];
+  if (mirrored) {  // source tile (tj, ti), transposed through LDS
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int R = min(tj * 64 + ty + 4 * k, n2 - 1), Pc = min(ti * 64 + tx, n2 - 1);
+      const size_t o = (size_t)R * n2 + Pc;
+      q0[k] = src0m[o];
+      if (!OFF) q1[k] = src1[o];
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int R = tj * 64 + ty + 4 * k, Pc = ti * 64 + tx;
+      double v = -(double)q0[k];
+      if (!OFF) v -= lastj ? 0.0 : (double)q1[k];
+      tile[ty + 4 * k][tx] = (R < n2 && Pc < n2 && R >= Pc) ? v : 0.0;
+    }
+  }
+  T d0[16], d1[16];
+  if (direct) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int r = min(ti * 64 + ty + 4 * k, n2 - 1), rho = min(tj * 64 + tx, n2 - 1);
+      const size_t o = (size_t)r * n2 + rho;
+      d0[k] = src0[o];
+      if (!OFF) d1[k] = src1[o];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int yy = ty + 4 * k;
+    const int r = ti * 64 + yy, rho = tj * 64 + tx;
+    double v = 0.0;
+    if (r >= rho) {
+      if (direct) {
+        v = -(double)d0[k];
+        if (!OFF) {
+          v -= lastj ? 0.0 : (double)d1[k];
+          if (r == rho) v += aoo_d[yy];
+          if (r == rho + 1) v += aoo_s[yy];
+        }
+      }
+    } else if (mirrored) {
+      v = tile[tx][yy];  // source (rho, r)
+      if (!OFF && rho == r + 1) v += aoo_c;
+    }
+    if (r < n2 && rho < n2) {
+      const size_t o = (size_t)j * nsq + (size_t)r * n2 + rho;
+      Tout[o] = (TO)v;
+      if (Tout64) Tout64[o] = v;
+    }
+  }
 }
 
 template <typename T, typename TO>
 __global__ __launch_bounds__(256) void k_assemble(const ProbDev* __restrict__ P,
                                                   const int* __restrict__ offs, int count) {
-  __shared__ double tile[32][33];
+  __shared__ double tile[64][65];
+  __shared__ double aoo_d[64], aoo_s[64];  // A_oo(r, r) and A_oo(r, r-1) of the tile's rows
   const int it = group_item(offs, count, blockIdx.x);
   const int bx = blockIdx.x - offs[it];
-  const g_t<const double>* __restrict__ wh = gp((const double*)P[it].wh);
-  const g_t<const double>* __restrict__ wv = gp((const double*)P[it].wv);
-  const int n2 = P[it].n2, b = P[it].b, m = P[it].m;
-  const g_t<const T>* __restrict__ PRR = gp((const T*)P[it].PRR);
-  const g_t<const T>* __restrict__ PLL = gp((const T*)P[it].PLL);
-  const g_t<const T>* __restrict__ PLR = gp((const T*)P[it].PLR);
-  const g_t<const T>* __restrict__ PRL = gp((const T*)P[it].PRL);
-  g_t<TO>* __restrict__ Tdiag = gp((TO*)P[it].Td);
-  g_t<TO>* __restrict__ Toff = gp((TO*)P[it].To);
-  g_t<double>* __restrict__ Tdiag64 = gp(P[it].T64);
-  g_t<double>* __restrict__ Toff64 = gp(P[it].O64);
+  const int n2 = P[it].n2, m = P[it].m;
   // workgroup bx: tile (ti, tj) of block j, kind off (0: T_jj, 1: T_{j,j+1})
-  const int ntl = (n2 + 31) / 32;
+  const int ntl = (n2 + 63) / 64;
   const int per = ntl * ntl;
   const int j = (bx / per) % m;
   const bool off = bx / (per * m) == 1;
-  if (off && j >= m - 1) return;
   const int ti = (bx % per) / ntl, tj = (bx % per) % ntl;
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-  const size_t nsq = (size_t)n2 * n2;
-  const int s = j + 1;
-  // transposed source tile (rows from tj range, cols from ti range) for r < rho
-  if (ti <= tj) {
-    for (int yy = ty; yy < 32; yy += 8) {
-      const int R = tj * 32 + yy, P = ti * 32 + tx;  // source (R, P), R >= P needed
-      double v = 0.0;
-      if (R < n2 && P < n2 && R >= P) {
-        if (!off) v = diag_value<T>(wh, wv, n2, b, m, j, PRR, PLL, R, P);
-        else v = -(double)PRL[(size_t)s * nsq + (size_t)R * n2 + P];
-      }
-      tile[yy][tx] = v;
-    }
-  }
-  __syncthreads();
-  for (int yy = ty; yy < 32; yy += 8) {
-    const int r = ti * 32 + yy, rho = tj * 32 + tx;
-    if (r >= n2 || rho >= n2) continue;
-    double v;
-    if (r >= rho) {
-      if (!off) v = diag_value<T>(wh, wv, n2, b, m, j, PRR, PLL, r, rho);
-      else v = -(double)PLR[(size_t)s * nsq + (size_t)r * n2 + rho];
-    } else {
-      v = tile[tx][yy];  // source (rho, r)
-    }
-    const size_t o = (size_t)j * nsq + (size_t)r * n2 + rho;
-    if (!off) {
-      Tdiag[o] = (TO)v;
-      if (Tdiag64) Tdiag64[o] = v;
-    } else {
-      Toff[o] = (TO)v;
-      if (Toff64) Toff64[o] = v;
-    }
+  if (off) {
+    if (j >= m - 1) return;  // uniform
+    assemble_tile<T, TO, true>(P[it], j, ti, tj, tile, aoo_d, aoo_s);
+  } else {
+    assemble_tile<T, TO, false>(P[it], j, ti, tj, tile, aoo_d, aoo_s);
   }
 }
 
@@ -686,7 +719,7 @@ static void plan_stage1_bp(Plan& plan, const std::vector<ProbDev>& probs, int ph
     });
   } else {
     counts([](const ProbDev& d) {
-      const long long ntl = (d.n2 + 31) / 32;
+      const long long ntl = (d.n2 + 63) / 64;
       return ntl * ntl * d.m * 2;
     });
     plan.step([=](const char* dev, hipStream_t st) {
