@@ -952,7 +952,9 @@ __global__ __launch_bounds__(256) void k_bmv(const BmvItem* __restrict__ items,
   // skipped on some path would make the compiler wait for all outstanding
   // loads); values outside the operands are zeroed when parked in LDS, and the
   // chunk loop runs to a multiple of D (extra chunks are all zero).
-  constexpr int D = VECOK ? 3 : 1;
+  // (triangular operands: many row tiles walk only a few chunks, so the ring
+  // is shallower; measured faster)
+  constexpr int D = VECOK ? (LOWER ? 2 : 3) : 1;
   vt ra[D][NVA], rb[D];
   auto load = [&](int d, int k0) __attribute__((always_inline)) {
 #pragma unroll
