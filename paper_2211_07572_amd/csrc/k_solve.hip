@@ -31,8 +31,6 @@ __global__ __launch_bounds__(256) void k_sweep(const SolveDev* __restrict__ P,
   constexpr int GPT = BP * BP / 256;      // block-inverse elements loaded per thread
   constexpr int D = BP == 64 ? (sizeof(T) == 8 ? 2 : 4) : 8;  // prefetch depth (row steps)
   __shared__ T Gs[2][BP][BP + 1];
-  __shared__ T Ws[2][BP];
-  __shared__ T Ys[2][NC][BP + 1];
   __shared__ T Vs[2][NC][BP + 1];
   const int itm = group_item(offs, count, blockIdx.x);
   const int bx = blockIdx.x - offs[itm];
@@ -73,7 +71,7 @@ __global__ __launch_bounds__(256) void k_sweep(const SolveDev* __restrict__ P,
   // slot 0, lane b-1 slot 1; for b = 1 slot 0 carries both terms)
   const int xslot = (i == 0) ? 0 : ((i == b - 1) ? 1 : -1);
   auto load_w = [&](int r) __attribute__((always_inline)) -> double {
-    return (tid < BP && act && r >= 1 && r <= n2 - 1) ? wv[ci * (n2 + 1) + r] : 0.0;
+    return (act && r >= 1 && r <= n2 - 1) ? wv[ci * (n2 + 1) + r] : 0.0;
   };
   // forward step r: G = Gl_{r-1} (A x) or Gl_r (A^T x), w = W_r, y = y_r
   auto load_fwd = [&](int d, int r) __attribute__((always_inline)) {
@@ -108,49 +106,52 @@ __global__ __launch_bounds__(256) void k_sweep(const SolveDev* __restrict__ P,
       const int idx = tid + 256 * e;
       Gs[buf][idx / BP][idx % BP] = rg[d][e];
     }
-    if (tid < BP) Ws[buf][tid] = (T)rw[d];
   };
-  auto park_fwd = [&](int d, int buf) __attribute__((always_inline)) {
-    parkG(d, buf);
-    Ys[buf][cl][i] = (T)(ry[d] + (MODE == 1 ? (double)rx[d] : 0.0));
-  };
-  auto park_bwd = [&](int d, int buf) __attribute__((always_inline)) {
-    parkG(d, buf);
-    Ys[buf][cl][i] = rz[d];
+  // right-hand side of ring slot d (forward steps)
+  auto yval = [&](int d) __attribute__((always_inline)) -> T {
+    return (T)(ry[d] + (MODE == 1 ? (double)rx[d] : 0.0));
   };
 
   // ---------------- forward sweep: z_r (stored in zbuf) ----------------
+  // Vs holds the vector the step's block inverse multiplies; the thread that
+  // owns entry (i, column) forms it for the next step from its own values:
+  //   A x:    forward v = z_{r-1};                backward v = z_r + W_{r+1} x_{r+1}
+  //   A^T x:  forward v = y_r + W_r z_{r-1};      backward v = W_{r+1} x_{r+1}
+  // so a step reads only the block inverse and v from LDS.
 #pragma unroll
   for (int d = 0; d < D; ++d)
     if (d < n2) load_fwd(d, d);
-  Vs[0][cl][i] = (T)0;
+  Vs[0][cl][i] = TRANS ? yval(0) : (T)0;
   for (int r0 = 0; r0 < n2; r0 += D) {
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       const int r = r0 + d;
       if (r < n2) {  // uniform
       const int cur = r & 1;
-      park_fwd(d, cur);
+      parkG(d, cur);
+      const T y = yval(d), w = (T)rw[d];
       if (r + D < n2) load_fwd(d, r + D);
       __syncthreads();
       // dot products over k in four independent partial sums (short FMA chains)
-      T out;
+      T out, vn;
       if (!TRANS) {
         T t[4] = {(T)0, (T)0, (T)0, (T)0};
         if (r > 0) {
 #pragma unroll
           for (int k = 0; k < BP; ++k) t[k & 3] += Gs[cur][i][k] * Vs[cur][cl][k];
         }
-        out = Ys[cur][cl][i] + Ws[cur][i] * ((t[0] + t[1]) + (t[2] + t[3]));
+        out = y + w * ((t[0] + t[1]) + (t[2] + t[3]));
+        vn = out;
       } else {
         T t[4] = {(T)0, (T)0, (T)0, (T)0};
 #pragma unroll
-        for (int k = 0; k < BP; ++k)
-          t[k & 3] += Gs[cur][k][i] * (Ys[cur][cl][k] + Ws[cur][k] * Vs[cur][cl][k]);
+        for (int k = 0; k < BP; ++k) t[k & 3] += Gs[cur][k][i] * Vs[cur][cl][k];
         out = (t[0] + t[1]) + (t[2] + t[3]);
+        const int dn = (d + 1) % D;  // ring slot of the next step
+        vn = yval(dn) + (T)rw[dn] * out;
       }
       if (valid) zbuf[((size_t)c * n2 + r) * BP + i] = out;
-      Vs[cur ^ 1][cl][i] = out;
+      Vs[cur ^ 1][cl][i] = vn;
       }
     }
   }
@@ -160,7 +161,7 @@ __global__ __launch_bounds__(256) void k_sweep(const SolveDev* __restrict__ P,
 #pragma unroll
   for (int d = 0; d < D; ++d)
     if (d < n2) load_bwd(d, n2 - 1 - d);
-  Vs[0][cl][i] = (T)0;
+  Vs[0][cl][i] = TRANS ? (T)0 : rz[0];
   for (int t0 = 0; t0 < n2; t0 += D) {
 #pragma unroll
     for (int d = 0; d < D; ++d) {
@@ -168,24 +169,26 @@ __global__ __launch_bounds__(256) void k_sweep(const SolveDev* __restrict__ P,
       if (it < n2) {  // uniform
       const int r = n2 - 1 - it;
       const int cur = it & 1;
-      park_bwd(d, cur);
+      parkG(d, cur);
       const double uold = ru[d], wbl = rbl[d], wbr = rbr[d];
+      const T z = rz[d];
       if (it + D < n2) load_bwd(d, r - D);
       __syncthreads();
       T x;
+      const int dn = (d + 1) % D;  // ring slot of the next step (row r - 1)
       if (!TRANS) {
         T t[4] = {(T)0, (T)0, (T)0, (T)0};
 #pragma unroll
-        for (int k = 0; k < BP; ++k)
-          t[k & 3] += Gs[cur][i][k] * (Ys[cur][cl][k] + Ws[cur][k] * Vs[cur][cl][k]);
+        for (int k = 0; k < BP; ++k) t[k & 3] += Gs[cur][i][k] * Vs[cur][cl][k];
         x = (t[0] + t[1]) + (t[2] + t[3]);
+        Vs[cur ^ 1][cl][i] = rz[dn] + (T)rw[dn] * x;
       } else {
         T t[4] = {(T)0, (T)0, (T)0, (T)0};
 #pragma unroll
-        for (int k = 0; k < BP; ++k) t[k & 3] += Gs[cur][k][i] * (Ws[cur][k] * Vs[cur][cl][k]);
-        x = Ys[cur][cl][i] + ((t[0] + t[1]) + (t[2] + t[3]));
+        for (int k = 0; k < BP; ++k) t[k & 3] += Gs[cur][k][i] * Vs[cur][cl][k];
+        x = z + ((t[0] + t[1]) + (t[2] + t[3]));
+        Vs[cur ^ 1][cl][i] = (T)rw[dn] * x;
       }
-      Vs[cur ^ 1][cl][i] = x;
       if (valid) {
         if (MODE == 0) {
           if (i == 0) xbuf[(((size_t)s * 2 + 0) * nrhs + c) * n2 + r] = (T)(wbl * (double)x);
