@@ -163,6 +163,11 @@ __global__ __launch_bounds__(256) void k_sweep(const SolveDev* __restrict__ P,
     if (d < n2) load_bwd(d, n2 - 1 - d);
   Vs[0][cl][i] = TRANS ? (T)0 : rz[0];
   for (int t0 = 0; t0 < n2; t0 += D) {
+    // MODE 1: this thread's outputs of the D steps, stored together after them
+    // (consecutive rows of one natural-order column: each cache line is
+    // written at once instead of over D row steps)
+    T xs[D];
+    double us[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       const int it = t0 + d;
@@ -189,14 +194,21 @@ __global__ __launch_bounds__(256) void k_sweep(const SolveDev* __restrict__ P,
         x = z + ((t[0] + t[1]) + (t[2] + t[3]));
         Vs[cur ^ 1][cl][i] = (T)rw[dn] * x;
       }
-      if (valid) {
-        if (MODE == 0) {
-          if (i == 0) xbuf[(((size_t)s * 2 + 0) * nrhs + c) * n2 + r] = (T)(wbl * (double)x);
-          if (i == b - 1) xbuf[(((size_t)s * 2 + 1) * nrhs + c) * n2 + r] = (T)(wbr * (double)x);
-        } else if (act) {
-          out_g[(long long)c * ldo + ci * n2 + r] = acc_out ? uold + (double)x : (double)x;
-        }
+      if (MODE == 0 && valid) {
+        if (i == 0) xbuf[(((size_t)s * 2 + 0) * nrhs + c) * n2 + r] = (T)(wbl * (double)x);
+        if (i == b - 1) xbuf[(((size_t)s * 2 + 1) * nrhs + c) * n2 + r] = (T)(wbr * (double)x);
       }
+      xs[d] = x;
+      us[d] = uold;
+      }
+    }
+    if (MODE == 1 && valid && act) {
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const int it = t0 + d;
+        if (it < n2)
+          out_g[(long long)c * ldo + ci * n2 + (n2 - 1 - it)] =
+              acc_out ? us[d] + (double)xs[d] : (double)xs[d];
       }
     }
   }
