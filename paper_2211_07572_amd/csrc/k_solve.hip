@@ -82,9 +82,12 @@ __global__ __launch_bounds__(256) void k_sweep(const SolveDev* __restrict__ P,
       for (int e = 0; e < GPT; ++e) rg[d][e] = G[tid + 256 * e];
     }
     rw[d] = load_w(r);
-    ry[d] = (valid && act) ? rhs[(long long)c * ld + ci * n2 + r] : 0.0;
+  };
+  // right-hand side of row r (natural order) into y slot d
+  auto load_y = [&](double (&yy)[D], T (&xx)[D], int d, int r) __attribute__((always_inline)) {
+    yy[d] = (valid && act && r < n2) ? rhs[(long long)c * ld + ci * n2 + r] : 0.0;
     if (MODE == 1)
-      rx[d] = (valid && act && xslot >= 0)
+      xx[d] = (valid && act && xslot >= 0 && r < n2)
                   ? xbuf[(((size_t)s * 2 + xslot) * nrhs + c) * n2 + r] : (T)0;
   };
   // backward step r: G = Gl_r, w = W_{r+1}, z = z_r (+ old outputs when accumulating)
@@ -118,11 +121,25 @@ __global__ __launch_bounds__(256) void k_sweep(const SolveDev* __restrict__ P,
   //   A x:    forward v = z_{r-1};                backward v = z_r + W_{r+1} x_{r+1}
   //   A^T x:  forward v = y_r + W_r z_{r-1};      backward v = W_{r+1} x_{r+1}
   // so a step reads only the block inverse and v from LDS.
+  // the right-hand sides of a ring pass are loaded together one pass ahead
+  // (consecutive rows of one natural-order column: each cache line is read
+  // at once instead of over D row steps)
+  double ryn[D];
+  T rxn[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    ryn[d] = 0.0;
+    rxn[d] = (T)0;
+  }
+#pragma unroll
+  for (int d = 0; d < D; ++d) load_y(ry, rx, d, d);
 #pragma unroll
   for (int d = 0; d < D; ++d)
     if (d < n2) load_fwd(d, d);
   Vs[0][cl][i] = TRANS ? yval(0) : (T)0;
   for (int r0 = 0; r0 < n2; r0 += D) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) load_y(ryn, rxn, d, r0 + D + d);
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       const int r = r0 + d;
@@ -148,11 +165,18 @@ __global__ __launch_bounds__(256) void k_sweep(const SolveDev* __restrict__ P,
         for (int k = 0; k < BP; ++k) t[k & 3] += Gs[cur][k][i] * Vs[cur][cl][k];
         out = (t[0] + t[1]) + (t[2] + t[3]);
         const int dn = (d + 1) % D;  // ring slot of the next step
-        vn = yval(dn) + (T)rw[dn] * out;
+        // (the next pass's first right-hand side is still in the batch buffer)
+        const T yn = d + 1 < D ? yval(dn) : (T)(ryn[0] + (MODE == 1 ? (double)rxn[0] : 0.0));
+        vn = yn + (T)rw[dn] * out;
       }
       if (valid) zbuf[((size_t)c * n2 + r) * BP + i] = out;
       Vs[cur ^ 1][cl][i] = vn;
       }
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      ry[d] = ryn[d];
+      rx[d] = rxn[d];
     }
   }
   __syncthreads();
