@@ -19,10 +19,15 @@ namespace slab {
 //   natural-order output (the interface values go through k_interface_out).
 // One workgroup per (problem, slab, group of 256/BP columns); thread = (row i,
 // column).
-// Software pipeline: while row step r is computed, the block inverse, edge
-// weights and right-hand side of the next step are loaded into registers and
-// then parked in the other half of double-buffered LDS, so each step costs one
-// barrier and no exposed global-memory latency.
+// Software pipeline: while row step r is computed, the block inverses and
+// edge weights of the next D steps are in flight in a register ring and
+// parked in the other half of double-buffered LDS when their step comes (one
+// barrier per step).  The natural-order vectors are touched one ring pass at
+// a time: each thread loads its right-hand sides of the next D rows together
+// and stores its outputs of the last D rows together (consecutive rows of one
+// column share cache lines).  The vector a step multiplies is formed by the
+// thread that owns each entry, so a step reads only the block inverse and
+// that vector from LDS.
 // ---------------------------------------------------------------------------
 template <typename T, typename TU, int BP, bool TRANS, int MODE>
 __global__ __launch_bounds__(256) void k_sweep(const SolveDev* __restrict__ P,
