@@ -130,14 +130,16 @@ __device__ __forceinline__ void build_D_row(T (&a)[BP], const g_t<const double>*
 //   top-down  (dir 0):  Dl_0 = D_0,        Dl_r = D_r - W_r Gl_{r-1} W_r,    Gl_r = Dl_r^-1
 //   bottom-up (dir 1):  Dr_{n-1} = D_{n-1}, Dr_r = D_r - W_{r+1} Gr_{r+1} W_{r+1}
 // Stored: Gl_r row-major (block solves), Hr_r = Gr_r W_r in fragment-major
-// order (Schur propagation).  One wave per (slab, direction): lane = (row i,
-// column group q) holds BP/R entries of row i, R = 64/BP lanes per row.  Each
-// block is inverted in place by the symmetric sweep operator (the swept matrix
-// stays symmetric, so the pivot column needed by every row is the pivot row
-// published through LDS): one barrier per pivot, the same instructions for
-// the pivot row and the others (a select picks the scaled pivot row).  The edge weights of the next rows are loaded
-// D steps ahead into a register ring and used raw, so no load latency sits on
-// the row-to-row chain.
+// order (Schur propagation).  One four-wave workgroup per (slab, direction):
+// thread = (row i, column group q) holds BP/R entries of row i, R = 256/BP
+// threads per row.  Each block is inverted in place by the symmetric sweep
+// operator taken two pivots at a time: the 2x2 pivot block is inverted in
+// registers by every thread (adjugate over the determinant), and since the
+// swept matrix stays symmetric, the pivot columns every row needs are the
+// pivot rows published through LDS: one barrier per pivot pair, the same
+// instructions for the pivot rows and the others (selects pick the scaled
+// pivot rows).  Every thread loads the edge weights of its own row and columns
+// one row step ahead, so no load latency sits on the row-to-row chain.
 // ---------------------------------------------------------------------------
 #ifndef SLAB_FACTOR_THREADS
 #define SLAB_FACTOR_THREADS 256
