@@ -924,17 +924,27 @@ __global__ __launch_bounds__(256) void k_bmv(const BmvItem* __restrict__ items,
   const int bx = blockIdx.x - offs[itm];
   const int n = items[itm].n, nrhs = items[itm].nrhs;
   const int nrt = (n + TM - 1) / TM, ncg = (nrhs + 15) / 16;
-  const int rt = bx % nrt, cg = (bx / nrt) % ncg, sk = bx / (nrt * ncg);
+  // a triangular op(M) pairs row tile p with row tile nrt-1-p in one
+  // workgroup, so every workgroup walks nrt+1 chunks and the launch keeps its
+  // concurrency to the end
+  const int nrw = LOWER ? (nrt + 1) / 2 : nrt;
+  const int rp = bx % nrw, cg = (bx / nrw) % ncg, sk = bx / (nrw * ncg);
   const g_t<const T>* __restrict__ M = gp((const T*)items[itm].M);
   const g_t<const T>* __restrict__ x = gp((const T*)items[itm].x) + (long long)cg * 16 * n;
   const g_t<const T>* xin = gp((const T*)items[itm].xin);
   if (xin) xin += (long long)cg * 16 * n;
   g_t<T>* y = gp((T*)items[itm].y) + (long long)cg * 16 * n;
   const int nc = min(16, nrhs - 16 * cg);
-  const int row0 = rt * TM;
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int g = lane >> 4, nn = lane & 15;
+  for (int pass = 0; pass < (LOWER ? 2 : 1); ++pass) {
+  const int rt = pass == 0 ? rp : nrt - 1 - rp;
+  if (pass == 1) {
+    if (rt == rp) break;  // the middle tile of an odd count (uniform)
+    __syncthreads();      // the LDS buffers of the first tile are free again
+  }
+  const int row0 = rt * TM;
   // op(M)(i, k) is zero for k > i (M lower) or k < i (M^T of a lower M)
   int klo = 0, khi = n;
   if (LOWER) {
@@ -1049,7 +1059,7 @@ __global__ __launch_bounds__(256) void k_bmv(const BmvItem* __restrict__ items,
       const int r = row0 + 16 * wave + acc_row<T>(g, i);
       if (r < n && nn < nc) part[(long long)nn * n + r] = alpha * acc[i];
     }
-    return;
+    continue;
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
@@ -1059,6 +1069,7 @@ __global__ __launch_bounds__(256) void k_bmv(const BmvItem* __restrict__ items,
       if (xin) v += beta * xin[(long long)nn * n + r];
       y[(long long)nn * n + r] = v;
     }
+  }
   }
 }
 
@@ -1088,8 +1099,10 @@ void plan_gemv(Plan& plan, bool tr, bool lower, const std::vector<BmvItem>& item
   bool vecok = true, can_split = true;
   const uintptr_t al = 16;
   long long base = 0;
+  // (a triangular operand pairs two row tiles per workgroup, see k_bmv)
+  auto row_wgs = [&](int n) { return lower ? ((n + 63) / 64 + 1) / 2 : (n + 63) / 64; };
   for (const BmvItem& b : items) {
-    base += ((b.n + 63) / 64) * ((b.nrhs + 15) / 16);
+    base += row_wgs(b.n) * ((b.nrhs + 15) / 16);
     vecok = vecok && b.n % (int)(16 / sizeof(T)) == 0 && ((uintptr_t)b.M % al) == 0 &&
             ((uintptr_t)b.x % al) == 0;
     can_split = can_split && b.part != nullptr && b.n >= 512;
@@ -1100,7 +1113,7 @@ void plan_gemv(Plan& plan, bool tr, bool lower, const std::vector<BmvItem>& item
   if (can_split)
     while (nsplit < BMV_SPLIT_MAX && base * nsplit * 2 <= 512) nsplit *= 2;
   std::vector<int> c;
-  for (const BmvItem& b : items) c.push_back(((b.n + 63) / 64) * ((b.nrhs + 15) / 16) * nsplit);
+  for (const BmvItem& b : items) c.push_back(row_wgs(b.n) * ((b.nrhs + 15) / 16) * nsplit);
   long long tot;
   const size_t oi = plan.add_vec(items), oo = plan.add_offsets(c, &tot);
   const int count = (int)items.size();
