@@ -50,6 +50,10 @@ def parse():
     ap.add_argument("--autotune", action="store_true",
                     help="also report the slab width the autotuner picks for the grid")
     ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--skip-extra", action="store_true",
+                    help="skip the 1024x1024 and 512x512 lines")
+    ap.add_argument("--cpu-c2", action="store_true",
+                    help="also time the whole 1024x1024 job (1 RHS) on the FP64 oracle")
     ap.add_argument("--cpu-slabs", type=int, default=1)
     return ap.parse_args()
 
@@ -221,6 +225,10 @@ def copy_calibration():
 
 
 def run_gpu(w: G.Workload, precision: int, steps: int, warmup: int, kappa, f, odd_even: bool):
+    """W untimed steps, then K timed ones.  Returns the mean time per step over
+    the K steps (one interval, synchronized on both sides), the per-step times
+    (each synchronized), the last solution, and per-step solve infos and phase
+    times."""
     import torch
     from paper_2211_07572_amd import slab as S
     torch.cuda.synchronize()
@@ -241,12 +249,36 @@ def run_gpu(w: G.Workload, precision: int, steps: int, warmup: int, kappa, f, od
     torch.cuda.synchronize()
     infos.clear()
     phases.clear()
+    per_step = []
     t0 = time.perf_counter()
     for _ in range(steps):
-        u = one()
+        ts = time.perf_counter()
+        u = one()   # every call returns after its work has finished
+        per_step.append(time.perf_counter() - ts)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
-    return dt, u, infos, phases
+    return dt, per_step, u, infos, phases
+
+
+def host_cpu() -> dict:
+    """CPU model and logical core count of the host (from /proc/cpuinfo)."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count()}
+
+
+def host_relres(w: G.Workload, kappa_np, f_np, u) -> float:
+    """Max-over-columns relative residual of a GPU solution, recomputed on the
+    host by the FP64 oracle's A (Sec. 5.1 relerr_res)."""
+    from oracle import slab_oracle as O
+    prob = O.make_problem(kappa_np, w.n2, w.n1, w.b, w.h)
+    return float(O.relres(prob, u.cpu().numpy(), f_np).max())
 
 
 def cpu_baseline(w: G.Workload, kappa_np: np.ndarray, f_np: np.ndarray, slabs: int = 1) -> dict:
@@ -298,9 +330,71 @@ def cpu_baseline(w: G.Workload, kappa_np: np.ndarray, f_np: np.ndarray, slabs: i
     return {"value": w.N / total, "unit": "DOF/s", "cores": threads, "kind": "oracle",
             "sample": (f"FP64 oracle (NumPy/SciPy-LAPACK, {threads} BLAS threads) timed on "
                        f"{slabs} slab of stage one, 1 step of Alg. 1, 1 slab + 1 block of the "
-                       f"16-RHS solve ({sampled:.1f} s), scaled by m={m}: estimated "
-                       f"{total:.0f} s for the whole job"),
-            "estimated_total_s": total, "sampled_s": sampled, "setup_s": setup_s}
+                       f"16-RHS solve ({sampled:.1f} s), scaled by m={m}: an ESTIMATE of "
+                       f"{total:.0f} s for the whole job, not a measurement of it"),
+            "estimated_total_s": total, "sampled_s": sampled, "setup_s": setup_s,
+            "host_cpu": host_cpu()}
+
+
+def cpu_oracle_c2() -> dict:
+    """The whole 1024x1024 job (factor + 1-RHS solve) on the FP64 oracle,
+    measured: stage one with its independent slabs spread over a process pool
+    of one worker per core, stage two (Alg. 1, LAPACK) and the solve (Alg. 4)
+    in this process."""
+    from oracle import slab_oracle as O
+    w = G.DIFFUSION_1024
+    workers = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    prob = O.make_problem(w.kappa(), w.n2, w.n1, w.b, w.h)
+    f = w.rhs(1)
+    t0 = time.perf_counter()
+    fac = O.factor(prob, workers=workers)
+    t1 = time.perf_counter()
+    u = O.solve(fac, f)
+    t2 = time.perf_counter()
+    return {"value": w.N / (t2 - t0), "unit": "DOF/s", "cores": workers, "kind": "oracle",
+            "sample": "the whole 1024x1024 b=31 job, 1 RHS, measured (not extrapolated)",
+            "factor_s": t1 - t0, "solve_s": t2 - t1,
+            "relres": float(O.relres(prob, u, f).max()), "host_cpu": host_cpu()}
+
+
+def extra_workloads(warmup: int, steps: int) -> dict:
+    """The 1024x1024 (FP64, 1 and 64 right-hand sides; mixed, 1 RHS) and
+    512x512 (FP64 factor + solve + adjoint + gradient) workloads on the GPU,
+    median step times."""
+    import torch
+    from paper_2211_07572_amd import slab as S
+    out = {}
+    w = G.DIFFUSION_1024
+    kap = torch.as_tensor(w.kappa(), device="cuda")
+    for nrhs in (1, 64):
+        f = torch.as_tensor(w.rhs(nrhs), device="cuda").contiguous()
+        for name, prec in (("fp64", S.SLAB_FP64), ("mixed", S.SLAB_MIXED)):
+            if name == "mixed" and nrhs == 64:
+                continue
+            _, per, _, info, _ = run_gpu(w, prec, steps, warmup, kap, f, True)
+            med = float(np.median(per))
+            out[f"{w.name}_{name}_nrhs{nrhs}"] = {
+                "ms_per_step": med * 1e3, "dof_per_s": w.N / med, "nrhs": nrhs,
+                "max_relres": max(r for _, r in info), "refine_passes": max(i for i, _ in info)}
+    w = G.ADJOINT_512
+    theta = torch.as_tensor(G.grf(w.n2, w.n1, 10, w.h), device="cuda")
+    f = torch.as_tensor(w.rhs(1), device="cuda").contiguous()
+    times = []
+    for it in range(warmup + steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = S.slab_factor(theta, w.n2, w.n1, w.b, w.h, coef_log=True, odd_even=True)
+        u = S.slab_solve(h, f)
+        lam = S.slab_solve_adjoint(h, u)
+        g = S.slab_kappa_grad(h, u, lam, mode=1)
+        torch.cuda.synchronize()
+        if it >= warmup:
+            times.append(time.perf_counter() - t0)
+        h.free()
+    med = float(np.median(times))
+    out[f"{w.name}_fp64_factor_solve_adjoint_grad"] = {"ms_per_step": med * 1e3,
+                                                       "dof_per_s": w.N / med}
+    return out
 
 
 def main():
@@ -326,7 +420,7 @@ def main():
 
     prec = {"mixed": S.SLAB_MIXED, "fp32": S.SLAB_FP32_REFINE}[args.precision]
     oe = args.order == "odd_even"
-    dt32, u32, info32, ph32 = run_gpu(w, prec, args.steps, args.warmup, kappa, f, oe)
+    dt32, per32, u32, info32, ph32 = run_gpu(w, prec, args.steps, args.warmup, kappa, f, oe)
     relres32 = max(r for _, r in info32)
     iters32 = max(i for i, _ in info32)
     ph = {k: float(np.median([p[k] for p in ph32])) for k in ph32[0]}
@@ -351,6 +445,8 @@ def main():
                    "stage_two": {"odd_even": "odd-even elimination order",
                                  "sweep": "sweep of Alg. 1"}[args.order]},
         "max_relres": relres32,
+        "max_relres_host": host_relres(w, kappa_np, f_np, u32),
+        "step_ms": [t * 1e3 for t in per32],
         "refine_passes": iters32,
         "phase_ms": {k: v / 1e3 for k, v in ph.items()},
     }
@@ -379,18 +475,24 @@ def main():
     tb = ph["block_factor"] / 1e6
     result["block_factor_tflops"] = block_factor_flops(w, oe) / tb / 1e12
 
-    def form(precision, odd_even, steps, warmup):
-        dto, _, info_o, ph_o = run_gpu(w, precision, steps, warmup, kappa, f, odd_even)
+    # the compared forms run with the same warm-up and step counts as the
+    # headline (at least 1 and 3); ms_per_step is the median step
+    cw, cs = max(args.warmup, 1), max(args.steps, 3)
+
+    def form(precision, odd_even):
+        dto, per_o, _, info_o, ph_o = run_gpu(w, precision, cs, cw, kappa, f, odd_even)
         pm = {k: float(np.median([p[k] for p in ph_o])) / 1e3 for k in ph_o[0]}
-        return dto, {"value": w.N / dto, "ms_per_step": dto * 1e3,
+        med = float(np.median(per_o))
+        return med, {"value": w.N / med, "ms_per_step": med * 1e3, "mean_ms": dto * 1e3,
+                     "steps": cs, "warmup": cw,
                      "max_relres": max(r for _, r in info_o),
                      "refine_passes": max(i for i, _ in info_o), "phase_ms": pm,
                      "block_factor_tflops": block_factor_flops(w, odd_even) / (pm["block_factor"] / 1e3) / 1e12}
     if not args.skip_other:
         other = "fp32" if args.precision == "mixed" else "mixed"
-        result[f"{other}_form"] = form({"mixed": S.SLAB_MIXED, "fp32": S.SLAB_FP32_REFINE}[other], oe, 1, 1)[1]
+        result[f"{other}_form"] = form({"mixed": S.SLAB_MIXED, "fp32": S.SLAB_FP32_REFINE}[other], oe)[1]
         other_order = "sweep" if oe else "odd_even"
-        result[f"{other_order}_order"] = form(prec, not oe, 1, 1)[1]
+        result[f"{other_order}_order"] = form(prec, not oe)[1]
     if args.autotune:
         # slab width picked by the autotuner for this grid (the configuration fixes b)
         t0 = time.perf_counter()
@@ -399,11 +501,15 @@ def main():
         result["autotune"] = {"b": bt, "seconds_per_candidate": {str(k): v for k, v in times.items()},
                               "tuning_s": time.perf_counter() - t0}
     if not args.skip_fp64:
-        dt64, res64 = form(S.SLAB_FP64, oe, 1, 0)
+        dt64, res64 = form(S.SLAB_FP64, oe)
         result["fp64"] = res64
-        result["fp32_refine_speedup_vs_fp64"] = dt64 / dt32
+        result["fp32_refine_speedup_vs_fp64"] = dt64 / float(np.median(per32))
+    if not args.skip_extra:
+        result["extra_workloads"] = extra_workloads(cw, cs)
     if not args.skip_cpu:
         result["cpu_baseline"] = cpu_baseline(w, kappa_np, f_np, args.cpu_slabs)
+    if args.cpu_c2:
+        result["cpu_oracle_1024x1024"] = cpu_oracle_c2()
     print(json.dumps(result))
 
 

@@ -94,6 +94,11 @@ typedef struct {
   double tol;          /* target max-over-columns ||f - A u||_2 / ||f||_2 (e.g. 1e-10) */
   int32_t max_iter;    /* refinement iterations allowed (>= 1; FP64 uses at most this too) */
   int32_t flags;       /* SLAB_KEEP_REDUCED | SLAB_COEF_LOG | SLAB_ODD_EVEN | SLAB_GRAPH */
+  int32_t tile;        /* output tile of the FP32 block products of stage two: 64 or 128,
+                          or 0 = automatic (128 once a launch has enough tiles for four
+                          per compute unit, else 64; for a problem given with b = 0 the
+                          width the autotuner measured fastest for its block size).
+                          Ignored in FP64. */
 } slab_options;
 
 typedef struct {
@@ -196,11 +201,17 @@ int slab_residual(slab_handle h, const double* f, const double* u, int32_t nrhs,
 int slab_export_reduced(slab_handle h, int32_t which, int32_t j, double* out, void* hip_stream);
 
 /* Sizes and timings of a handle: what = 0 m, 1 n1, 2 n2, 3 b, 4 precision,
-   5 device bytes held, 10+p elapsed microseconds of factor phase p of the last
+   5 device bytes held, 6 the FP32 product tile in use (0: automatic),
+   10+p elapsed microseconds of factor phase p of the last
    factorization (0 slab factors, 1 boundary columns of the slab inverses,
    2 Schur propagation, 3 assembly of T, 4 block factorization of T, 5 the
    block products inside 4: the sum over their launches), measured with HIP
-   events on the factor's stream. */
+   events on the factor's stream; 20+k the number of kernel launches of kind k
+   issued for this handle so far (factorization and every solve pass):
+   k = 0 block products on 128-wide tiles, 1 block products on 64-wide tiles,
+   2 factorization updates with the C tile prefetched, 3 block-vector products
+   split over k (with the launch that adds the partial sums), 4 block-vector
+   products in one launch. */
 int slab_query(slab_handle h, int32_t what, int64_t* value);
 
 /* Slab width for the grid of *prob (prob->b is ignored), chosen by measurement.
@@ -213,8 +224,10 @@ int slab_query(slab_handle h, int32_t what, int64_t* value);
    [-1, 1), fixed seed) on the device from
    prob->kappa and timed.  The fastest converging width goes to *b_out and is
    cached per (n1, n2, precision, flags, nrhs) for the process.  For FP32
-   reduced systems in odd-even order the FP32 product tile (64 or 128) of
-   n2 x n2 blocks is timed and recorded first.  times (optional, host, 5
+   reduced systems in odd-even order with opts->tile = 0 the FP32 product tile
+   (64 or 128) of n2 x n2 blocks is timed first and cached per n2; it is used
+   by the candidates timed here and by factorizations of problems given with
+   b = 0 (those given with b > 0 keep the size rule).  times (optional, host, 5
    entries for b = 3, 7, 15, 31, 63) receives the seconds measured, -1 where a
    width was not tried.  slab_factor and slab_factor_batch call this for every
    problem given with b = 0. */

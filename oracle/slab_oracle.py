@@ -289,7 +289,22 @@ def interface_blocks(prob: Problem, j: int) -> tuple:
     return Tjj, Tup
 
 
-def stage_one(prob: Problem, transpose: bool = False) -> StageOne:
+_POOL_STATE = {}
+
+
+def _pool_init(prob: Problem, transpose: bool):
+    _POOL_STATE["prob"], _POOL_STATE["transpose"] = prob, transpose
+
+
+def _pool_slab(s: int):
+    """Worker of stage_one(workers > 1): factor slab s and form its pieces."""
+    prob, transpose = _POOL_STATE["prob"], _POOL_STATE["transpose"]
+    A = prob.A.T.tocsr() if transpose else prob.A
+    fac = SlabFactor(A[prob.I_e(s)][:, prob.I_e(s)], prob.b)
+    return fac, slab_contributions(prob, s, fac, transpose)
+
+
+def stage_one(prob: Problem, transpose: bool = False, workers: int = 1) -> StageOne:
     """Eliminate every slab interior and form the block-tridiagonal T (eq. (dell3)).
 
     For interface j (index set I_{2j+1}) with slab j on its left (I_{2j}) and
@@ -307,12 +322,24 @@ def stage_one(prob: Problem, transpose: bool = False) -> StageOne:
     def blk(I, J):
         return A[I][:, J]
 
-    factors = [SlabFactor(blk(prob.I_e(s), prob.I_e(s)), prob.b) for s in range(m)]
+    if workers > 1:
+        # the slabs are independent (Sec. 3.1): spread them over processes
+        import concurrent.futures as cf
+        import multiprocessing as mp
+        with cf.ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn"),
+                                    initializer=_pool_init, initargs=(prob, transpose)) as ex:
+            done = list(ex.map(_pool_slab, range(m)))
+        factors = [d[0] for d in done]
+        pieces = [d[1] for d in done]
+    else:
+        factors = [SlabFactor(blk(prob.I_e(s), prob.I_e(s)), prob.b) for s in range(m)]
+        pieces = None
     T_diag = [blk(prob.I_o(j), prob.I_o(j)).toarray() for j in range(m)]
     T_up = [blk(prob.I_o(j), prob.I_o(j + 1)).toarray() for j in range(m - 1)]
     T_lo = [blk(prob.I_o(j + 1), prob.I_o(j)).toarray() for j in range(m - 1)]
     for s in range(m):
-        for (jr, jc), C in slab_contributions(prob, s, factors[s], transpose).items():
+        C_s = pieces[s] if pieces is not None else slab_contributions(prob, s, factors[s], transpose)
+        for (jr, jc), C in C_s.items():
             if jr == jc:
                 T_diag[jr] -= C
             elif jc == jr + 1:
@@ -511,10 +538,12 @@ class Factorization:
     transpose: bool = False
 
 
-def factor(prob: Problem, transpose: bool = False, order: str = "sweep") -> Factorization:
+def factor(prob: Problem, transpose: bool = False, order: str = "sweep",
+           workers: int = 1) -> Factorization:
     """Alg. 3: slab factorizations, reduced blocks T (formed densely), then
-    stage two by Alg. 1 (order="sweep") or in odd-even order (order="odd_even")."""
-    s1 = stage_one(prob, transpose)
+    stage two by Alg. 1 (order="sweep") or in odd-even order (order="odd_even").
+    workers > 1 runs the independent slabs of stage one in that many processes."""
+    s1 = stage_one(prob, transpose, workers)
     if order == "sweep":
         s2 = sweeping_build(s1)
     elif order == "odd_even":

@@ -9,6 +9,7 @@
 // replay it.
 #include "launch.h"
 
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -219,10 +220,21 @@ long long elapsed_us(hipEvent_t a, hipEvent_t b) {
 
 }  // namespace
 
+// The allocation holding the solve buffers of one or more handles (the items
+// of a batch share one); returned to its owner when the last handle using it
+// lets go.
+struct WsBlock {
+  Owner* owner = nullptr;
+  void* p = nullptr;
+  ~WsBlock() {
+    if (owner) owner->release(p);
+  }
+};
+
 struct Workspace {
   int nrhs = 0;
-  void* block = nullptr;   // allocation holding the buffers below
-  bool own_block = false;  // block belongs to this handle alone
+  std::shared_ptr<WsBlock> block;  // allocation holding the buffers below
+  long long generation = 0;        // distinct for every allocation (graph keys)
   void* zbuf = nullptr;
   void* xb = nullptr;
   void* ft = nullptr;
@@ -261,10 +273,16 @@ struct slab_handle_s {
   double* T64 = nullptr;
   double* O64 = nullptr;
   double* S64 = nullptr;
+  int tile = 0;    // forced FP32 product tile (0: size rule)
   long long phase_us[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  long long launches[LK_COUNT] = {0, 0, 0, 0, 0, 0, 0, 0};
   Owner mem;
   Workspace ws;
 };
+
+static void count_launches(slab_handle h, const Plan& p) {
+  for (int k = 0; k < LK_COUNT; ++k) h->launches[k] += p.launches[k];
+}
 
 // A solve pass captured as a HIP graph, valid for one set of arguments.
 struct GraphCache {
@@ -332,23 +350,27 @@ void workspace_layout(slab_handle h, int nrhs, Layout& L) {
 }
 
 int ensure_workspaces(const std::vector<std::pair<slab_handle, int>>& need, Owner& mem) {
+  static std::atomic<long long> generations{0};
   Layout L;
   std::vector<std::pair<slab_handle, int>> grow;
   for (const auto& q : need) {
     slab_handle h = q.first;
     if (h->ws.nrhs >= q.second) continue;
-    if (h->ws.own_block) h->mem.release(h->ws.block);
-    h->ws = Workspace();
+    h->ws = Workspace();  // the old block goes back once no handle uses it
     workspace_layout(h, q.second, L);
     grow.push_back(q);
   }
   if (grow.empty()) return SLAB_OK;
-  void* block = nullptr;
-  SLAB_TRY(L.commit(mem, &block));
+  void* base = nullptr;
+  SLAB_TRY(L.commit(mem, &base));
+  auto block = std::make_shared<WsBlock>();
+  block->owner = &mem;
+  block->p = base;
+  const long long gen = ++generations;
   for (const auto& q : grow) {
     q.first->ws.nrhs = q.second;
     q.first->ws.block = block;
-    q.first->ws.own_block = grow.size() == 1 && &mem == &q.first->mem;
+    q.first->ws.generation = gen;
   }
   return SLAB_OK;
 }
@@ -504,10 +526,15 @@ int factor_group(const std::vector<slab_handle>& hs, const std::vector<const sla
       q.Z = hs[i]->Z; q.S64 = hs[i]->S64; q.status = hs[i]->status;
       s2.push_back(q);
     }
+    // one forced product tile for the chunk when its problems agree on it
+    int tile = hs[lo]->tile;
+    for (size_t i = lo; i < hi; ++i)
+      if (hs[i]->tile != tile) tile = 0;
     Plan p;
     plan_stage1<T, TR>(p, cd, ev + 1);
     p.timer = std::make_shared<Plan::Timer>();
-    plan_stage2<TR>(p, s2, hs[lo]->odd_even != 0);
+    plan_stage2<TR>(p, s2, hs[lo]->odd_even != 0, tile);
+    for (size_t i = lo; i < hi; ++i) count_launches(hs[i], p);
     SLAB_HIP_CHECK(hipEventRecord(ev[0], st));
     SLAB_TRY(run_plan(plan_mem, p, st));
     SLAB_HIP_CHECK(hipEventRecord(ev[5], st));
@@ -551,6 +578,7 @@ slab_handle new_handle(const slab_problem* prob, const slab_options* opts, int d
   h->BP = padded_block(prob->b); h->h = prob->h;
   if (opts) { h->precision = opts->precision; h->tol = opts->tol; h->max_iter = opts->max_iter; h->flags = opts->flags; }
   h->odd_even = (h->flags & SLAB_ODD_EVEN) ? 1 : 0;
+  h->tile = opts ? opts->tile : 0;
   h->esz = h->precision == SLAB_FP32_REFINE ? 4 : 8;
   h->esz2 = h->precision == SLAB_FP64 ? 8 : 4;
   h->device = device;
@@ -650,7 +678,10 @@ int run_pass(Owner& mem, GraphCache* gc, const std::vector<SolveJob>& jobs, int 
              bool first, bool trans, hipStream_t st) {
   Plan p;
   plan_pass_dispatch(precision, p, jobs, first, trans);
+  for (const SolveJob& j : jobs) count_launches(j.h, p);
   if (!gc) return run_plan(mem, p, st);
+  // the captured launches read the jobs' vectors and workspaces: a new
+  // workspace (grown by any call on one of the handles) invalidates the graph
   std::vector<long long> key;
   key.push_back(first);
   key.push_back(trans);
@@ -660,6 +691,7 @@ int run_pass(Owner& mem, GraphCache* gc, const std::vector<SolveJob>& jobs, int 
     key.push_back((long long)(uintptr_t)j.u);
     key.push_back(j.nrhs);
     key.push_back(j.ld);
+    key.push_back(j.h->ws.generation);
   }
   if (gc->exec && gc->key == key) {
     SLAB_HIP_CHECK(hipGraphLaunch(gc->exec, st));
@@ -771,15 +803,18 @@ double model_seconds(int n1, int n2, int b, int precision, bool odd_even) {
 
 std::mutex g_tune_mu;
 std::map<std::vector<long long>, int> g_width_cache;
-std::map<int, bool> g_tile_done;
+std::map<int, int> g_tile_cache;  // FP32 product tile measured fastest per block size
+
+int cached_tile(int n) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tile_cache.find(n);
+  return it == g_tile_cache.end() ? 0 : it->second;
+}
 
 // Time the two tile widths on `count` products of n x n FP32 blocks shaped
 // like the odd-even update L^-1 C, and record the faster one.
 int tune_tile(int n, int count, hipStream_t st) {
-  {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    if (g_tile_done[n]) return SLAB_OK;
-  }
+  if (cached_tile(n)) return SLAB_OK;
   Owner tmp;
   struct Free {
     Owner& o;
@@ -821,9 +856,8 @@ int tune_tile(int n, int count, hipStream_t st) {
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  set_gemm_tile(n, best_tile);
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  g_tile_done[n] = true;
+  g_tile_cache[n] = best_tile;
   return SLAB_OK;
 }
 
@@ -837,10 +871,10 @@ int slab_autotune(const slab_problem* prob, const slab_options* opts, int32_t nr
   slab_problem p = *prob;
   p.b = 0;
   SLAB_TRY(slab_check_problem(&p, opts));
-  slab_options o = opts ? *opts : slab_options{SLAB_FP64, 1e-10, 10, 0};
+  slab_options o = opts ? *opts : slab_options{SLAB_FP64, 1e-10, 10, 0, 0};
   o.flags &= ~(SLAB_KEEP_REDUCED | SLAB_GRAPH);
   const bool odd_even = (o.flags & SLAB_ODD_EVEN) != 0;
-  const std::vector<long long> key{p.n1, p.n2, o.precision, o.flags, nrhs};
+  const std::vector<long long> key{p.n1, p.n2, o.precision, o.flags, nrhs, o.tile};
   for (int k = 0; k < 5; ++k)
     if (times) times[k] = -1.0;
   {
@@ -856,8 +890,10 @@ int slab_autotune(const slab_problem* prob, const slab_options* opts, int32_t nr
   double mbest = 1e300;
   for (int b : kWidths)
     if (p.n1 % (b + 1) == 0) mbest = std::min(mbest, model_seconds(p.n1, p.n2, b, o.precision, odd_even));
-  if (o.precision != SLAB_FP64 && odd_even && p.n2 >= 256)
+  if (o.precision != SLAB_FP64 && odd_even && p.n2 >= 256 && o.tile == 0) {
     SLAB_TRY(tune_tile(p.n2, std::min(16, std::max(1, p.n1 / 64)), st));
+    o.tile = cached_tile(p.n2);  // the candidates are timed with it
+  }
   const long long N = (long long)p.n1 * p.n2;
   Owner tmp;
   struct Free {
@@ -943,6 +979,9 @@ int slab_check_problem(const slab_problem* prob, const slab_options* opts) {
     if (opts->flags & ~(SLAB_KEEP_REDUCED | SLAB_COEF_LOG | SLAB_ODD_EVEN | SLAB_GRAPH)) {
       set_error("unknown flag"); return SLAB_E_INVALID;
     }
+    if (opts->tile != 0 && opts->tile != 64 && opts->tile != 128) {
+      set_error("tile must be 0, 64 or 128"); return SLAB_E_INVALID;
+    }
   }
   return SLAB_OK;
 }
@@ -958,12 +997,14 @@ int slab_factor(const slab_problem* prob, const slab_options* opts, void* hip_st
   if (hipGetDevice(&device) != hipSuccess) { set_error("no HIP device"); return SLAB_E_HIP; }
   hipStream_t st = (hipStream_t)hip_stream;
   slab_problem tuned = *prob;
-  if (tuned.b == 0) {
+  const bool autotuned = tuned.b == 0;
+  if (autotuned) {
     rc = slab_autotune(prob, opts, 1, hip_stream, &tuned.b, nullptr);
     if (rc) return rc;
     prob = &tuned;
   }
   slab_handle h = new_handle(prob, opts, device);
+  if (autotuned && h->tile == 0 && h->precision != SLAB_FP64) h->tile = cached_tile(h->n2);
   std::vector<slab_handle> hs{h};
   std::vector<const slab_problem*> ps{prob};
   std::vector<int> fail, blk;
@@ -1029,10 +1070,12 @@ int slab_factor_batch(const slab_problem* probs, int32_t count, const slab_optio
   int device = 0;
   if (hipGetDevice(&device) != hipSuccess) { set_error("no HIP device"); return SLAB_E_HIP; }
   std::vector<slab_problem> tuned(probs, probs + count);
+  std::vector<char> autotuned(count, 0);
   for (int i = 0; i < count; ++i) {
     if (tuned[i].b != 0) continue;
     const int rc = slab_autotune(&probs[i], opts, 1, hip_stream, &tuned[i].b, nullptr);
     if (rc) return rc;
+    autotuned[i] = 1;
   }
   probs = tuned.data();
   slab_batch bt = new slab_batch_s();
@@ -1041,7 +1084,9 @@ int slab_factor_batch(const slab_problem* probs, int32_t count, const slab_optio
   bt->flags = opts ? opts->flags : 0;
   std::vector<const slab_problem*> ps;
   for (int i = 0; i < count; ++i) {
-    bt->items.push_back(new_handle(&probs[i], opts, device));
+    slab_handle h = new_handle(&probs[i], opts, device);
+    if (autotuned[i] && h->tile == 0 && h->precision != SLAB_FP64) h->tile = cached_tile(h->n2);
+    bt->items.push_back(h);
     ps.push_back(&probs[i]);
   }
   hipStream_t st = (hipStream_t)hip_stream;
@@ -1203,8 +1248,10 @@ int slab_query(slab_handle h, int32_t what, int64_t* value) {
     case 3: *value = h->b; return SLAB_OK;
     case 4: *value = h->precision; return SLAB_OK;
     case 5: *value = (int64_t)h->mem.bytes; return SLAB_OK;
+    case 6: *value = h->tile; return SLAB_OK;
     default:
       if (what >= 10 && what < 16) { *value = h->phase_us[what - 10]; return SLAB_OK; }
+      if (what >= 20 && what < 20 + LK_COUNT) { *value = h->launches[what - 20]; return SLAB_OK; }
   }
   set_error("unknown query");
   return SLAB_E_INVALID;

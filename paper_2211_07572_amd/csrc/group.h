@@ -169,6 +169,16 @@ struct Stage2Prob {
 
 // ---- host-side plan -----------------------------------------------------------
 
+// Kinds of launches a plan counts (reported per handle by slab_query).
+enum LaunchKind {
+  LK_GEMM128 = 0,   // block products on 128-wide tiles
+  LK_GEMM64 = 1,    // block products on 64-wide tiles
+  LK_GEMM_CPRE = 2, // factorization updates with the C tile prefetched
+  LK_BMV_SPLIT = 3, // block-vector products split over k (+ the partial-sum launch)
+  LK_BMV = 4,       // block-vector products in one launch
+  LK_COUNT = 8
+};
+
 class Plan {
  public:
   // Stage `bytes` of table data; returns its offset (256-byte aligned).
@@ -216,6 +226,8 @@ class Plan {
     }
   };
   std::shared_ptr<Timer> timer;
+  // launches recorded so far, by LaunchKind
+  long long launches[LK_COUNT] = {0, 0, 0, 0, 0, 0, 0, 0};
 
   size_t bytes() const { return host_.size(); }
   const char* host() const { return host_.data(); }

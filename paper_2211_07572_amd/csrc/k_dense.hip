@@ -265,28 +265,12 @@ static void gemm_tile(bool ak, bool bn, bool vecok, unsigned grid, const GemmIte
 #undef SLAB_GEMM_CASE
 }
 
-// Tile width chosen by the autotuner for FP32 products of n x n blocks
-// (0: none recorded, use the size rule below).
-static std::mutex g_tile_mu;
-static std::map<int, int> g_tile_f32;
-
-void set_gemm_tile(int n, int tile) {
-  std::lock_guard<std::mutex> lk(g_tile_mu);
-  g_tile_f32[n] = tile;
-}
-
-static int tuned_tile(int n) {
-  std::lock_guard<std::mutex> lk(g_tile_mu);
-  auto it = g_tile_f32.find(n);
-  return it == g_tile_f32.end() ? 0 : it->second;
-}
-
 template <typename T>
 void plan_gemm(Plan& plan, bool ak, bool bn, const std::vector<GemmItem>& items, T alpha, T beta,
                int flags, int force_tile) {
   if (items.empty()) return;
   // 128-wide tiles once there are enough of them for four per compute unit,
-  // unless the autotuner recorded a choice for this block size
+  // unless the caller forces a width (FP32 only)
   long long area = 0;
   bool vecok = true;
   const uintptr_t vec = 16;
@@ -298,14 +282,9 @@ void plan_gemm(Plan& plan, bool ak, bool bn, const std::vector<GemmItem>& items,
   if (flags & GEMM_LOWER_C) area /= 2;
   int tile = (sizeof(T) == 4 && area >= 1024LL * 128 * 128) ? 128 : 64;
   const bool cpre = (flags & GEMM_C_PREFETCH) != 0;
-  if (sizeof(T) == 4) {
-    bool same_n = true;
-    for (const GemmItem& g : items) same_n = same_n && g.M == items[0].M && g.N == items[0].M;
-    const int tuned = same_n ? tuned_tile(items[0].M) : 0;
-    if (tuned) tile = tuned;
-    if (force_tile) tile = force_tile;
-  }
+  if (sizeof(T) == 4 && (force_tile == 64 || force_tile == 128)) tile = force_tile;
   if (cpre) tile = 64;
+  ++plan.launches[cpre ? LK_GEMM_CPRE : (tile == 128 ? LK_GEMM128 : LK_GEMM64)];
   std::vector<int> c;
   for (const GemmItem& g : items) {
     const long long tm = (g.M + tile - 1) / tile, tn = (g.N + tile - 1) / tile;
@@ -809,7 +788,7 @@ void plan_factor_blocks(Plan& plan, std::vector<FactorItem> items) {
 }
 
 template <typename T>
-void plan_stage2(Plan& plan, const std::vector<Stage2Prob>& probs, bool odd_even) {
+void plan_stage2(Plan& plan, const std::vector<Stage2Prob>& probs, bool odd_even, int tile) {
   auto blk = [](const Stage2Prob& p, void* base, long long j) {
     return (void*)((T*)base + j * (long long)p.n * p.n);
   };
@@ -836,9 +815,9 @@ void plan_stage2(Plan& plan, const std::vector<Stage2Prob>& probs, bool odd_even
         fi.push_back(f);
         if (j < p.m - 1) zi.push_back(sq(blk(p, p.Linv, j), blk(p, p.To, j), blk(p, p.Z, j), p.n));
       }
-      plan_gemm<T>(plan, true, false, upd, (T)-1, (T)1, GEMM_LOWER_C);
+      plan_gemm<T>(plan, true, false, upd, (T)-1, (T)1, GEMM_LOWER_C, tile);
       plan_factor_blocks<T>(plan, fi);
-      plan_gemm<T>(plan, false, false, zi, (T)1, (T)0, GEMM_A_LOWER);
+      plan_gemm<T>(plan, false, false, zi, (T)1, (T)0, GEMM_A_LOWER, tile);
     }
     return;
   }
@@ -876,15 +855,15 @@ void plan_stage2(Plan& plan, const std::vector<Stage2Prob>& probs, bool odd_even
       }
     }
     plan_factor_blocks<T>(plan, fi);
-    plan_gemm<T>(plan, false, true, gu, (T)1, (T)0, GEMM_A_LOWER);    // U_e = L^-1 C_l^T
-    plan_gemm<T>(plan, false, false, gv, (T)1, (T)0, GEMM_A_LOWER);   // V_e = L^-1 C_e
-    plan_gemm<T>(plan, true, false, gdl, (T)-1, (T)1, GEMM_LOWER_C);  // D_l -= U^T U
-    plan_gemm<T>(plan, true, false, gdr, (T)-1, (T)1, GEMM_LOWER_C);  // D_r -= V^T V
-    plan_gemm<T>(plan, true, false, gc, (T)-1, (T)0, 0);              // C_l = -U^T V
+    plan_gemm<T>(plan, false, true, gu, (T)1, (T)0, GEMM_A_LOWER, tile);    // U_e = L^-1 C_l^T
+    plan_gemm<T>(plan, false, false, gv, (T)1, (T)0, GEMM_A_LOWER, tile);   // V_e = L^-1 C_e
+    plan_gemm<T>(plan, true, false, gdl, (T)-1, (T)1, GEMM_LOWER_C, tile);  // D_l -= U^T U
+    plan_gemm<T>(plan, true, false, gdr, (T)-1, (T)1, GEMM_LOWER_C, tile);  // D_r -= V^T V
+    plan_gemm<T>(plan, true, false, gc, (T)-1, (T)0, 0, tile);              // C_l = -U^T V
   }
 }
-template void plan_stage2<float>(Plan&, const std::vector<Stage2Prob>&, bool);
-template void plan_stage2<double>(Plan&, const std::vector<Stage2Prob>&, bool);
+template void plan_stage2<float>(Plan&, const std::vector<Stage2Prob>&, bool, int);
+template void plan_stage2<double>(Plan&, const std::vector<Stage2Prob>&, bool, int);
 
 // ---------------------------------------------------------------------------
 // Block-vector product for the sweeping solve (Alg. 2):
@@ -1112,6 +1091,7 @@ void plan_gemv(Plan& plan, bool tr, bool lower, const std::vector<BmvItem>& item
   int nsplit = 1;
   if (can_split)
     while (nsplit < BMV_SPLIT_MAX && base * nsplit * 2 <= 512) nsplit *= 2;
+  ++plan.launches[nsplit > 1 ? LK_BMV_SPLIT : LK_BMV];
   std::vector<int> c;
   for (const BmvItem& b : items) c.push_back(row_wgs(b.n) * ((b.nrhs + 15) / 16) * nsplit);
   long long tot;

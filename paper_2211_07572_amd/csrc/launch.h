@@ -36,12 +36,10 @@ enum { GEMM_LOWER_C = 1, GEMM_A_LOWER = 2, GEMM_B_LOWER = 4,
 // C = beta*C + alpha * op(A) op(B) for every item; op(A)(i,k) = A[i*lda+k]
 // (ak=false) or A[k*lda+i] (ak=true); op(B)(k,j) = B[k*ldb+j] (bn=false) or
 // B[j*ldb+k] (bn=true).
-// force_tile (64 or 128, FP32 only) overrides the tile choice.
+// force_tile (64 or 128, FP32 only) overrides the size rule's tile choice.
 template <typename T>
 void plan_gemm(Plan& plan, bool ak, bool bn, const std::vector<GemmItem>& items, T alpha, T beta,
                int flags, int force_tile = 0);
-// Record the FP32 tile width to use for products of n x n blocks.
-void set_gemm_tile(int n, int tile);
 
 // Cholesky factorization with carried inverse of independent pivot blocks.
 template <typename T>
@@ -53,9 +51,10 @@ void plan_factor_blocks(Plan& plan, std::vector<FactorItem> items);
 // pivot block of interface e, Td_e = U_e = L_e^-1 C^T (coupling to the
 // neighbour before e), Z_e = V_e = L_e^-1 C_e (to the neighbour after e);
 // To holds the couplings of the last level that used them.  S64 (optional)
-// receives every pivot block before its factorization.
+// receives every pivot block before its factorization.  tile (0, 64 or 128)
+// is passed to the block products as their forced FP32 tile width.
 template <typename T>
-void plan_stage2(Plan& plan, const std::vector<Stage2Prob>& probs, bool odd_even);
+void plan_stage2(Plan& plan, const std::vector<Stage2Prob>& probs, bool odd_even, int tile);
 
 // y = beta*xin + alpha * op(M) x for every item over nrhs columns of length n
 // (column c of a block vector at c*n); op(M)(i,k) = M[i*n+k] (tr=false) or

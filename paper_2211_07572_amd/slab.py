@@ -48,7 +48,8 @@ class slab_problem(ctypes.Structure):
 
 class slab_options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("tol", ctypes.c_double),
-                ("max_iter", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("max_iter", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("tile", ctypes.c_int32)]
 
 
 class slab_solve_info(ctypes.Structure):
@@ -163,6 +164,12 @@ class SlabHandle:
                  "block_products"]
         return {n: self.query(10 + i) for i, n in enumerate(names)}
 
+    LAUNCH_KINDS = ("gemm128", "gemm64", "gemm_cprefetch", "bmv_split", "bmv")
+
+    def launches(self) -> dict:
+        """Kernel launches issued for this handle so far, by kind."""
+        return {n: self.query(20 + i) for i, n in enumerate(self.LAUNCH_KINDS)}
+
 
 def _vec_shape(t, n2, n1):
     if t.dim() == 2:
@@ -174,8 +181,10 @@ def _vec_shape(t, n2, n1):
 
 def slab_factor(kappa, n2: int, n1: int, b: int, h: float | None = None, precision: int = SLAB_FP64,
                 tol: float = 1e-10, max_iter: int = 10, keep_reduced: bool = False,
-                coef_log: bool = False, odd_even: bool = False, stream=None) -> SlabHandle:
-    """Alg. 3 on the device field kappa (or theta = log kappa), shape (n1+2, n2+2)."""
+                coef_log: bool = False, odd_even: bool = False, tile: int = 0,
+                stream=None) -> SlabHandle:
+    """Alg. 3 on the device field kappa (or theta = log kappa), shape (n1+2, n2+2).
+    tile: FP32 block-product tile (0 automatic, 64 or 128)."""
     L = load_library()
     if h is None:
         h = 1.0 / (n2 + 1)
@@ -184,7 +193,7 @@ def slab_factor(kappa, n2: int, n1: int, b: int, h: float | None = None, precisi
     prob = slab_problem(n1, n2, b, float(h), _dev_f64(kappa, "kappa"))
     flags = ((SLAB_KEEP_REDUCED if keep_reduced else 0) | (SLAB_COEF_LOG if coef_log else 0)
              | (SLAB_ODD_EVEN if odd_even else 0))
-    opts = slab_options(precision, float(tol), int(max_iter), flags)
+    opts = slab_options(precision, float(tol), int(max_iter), flags, int(tile))
     out = ctypes.c_void_p()
     info = slab_solve_info()
     _check(L.slab_factor(ctypes.byref(prob), ctypes.byref(opts), _stream_ptr(stream),
@@ -278,10 +287,10 @@ def slab_export_reduced(handle: SlabHandle, which: int, j: int, stream=None):
 
 def slab_check_problem(n2: int, n1: int, b: int, h: float, kappa_ptr: int = 1,
                        precision: int = SLAB_FP64, tol: float = 1e-10, max_iter: int = 10,
-                       flags: int = 0) -> int:
+                       flags: int = 0, tile: int = 0) -> int:
     """Host-only argument check; returns the status code (no HIP call is made)."""
     prob = slab_problem(n1, n2, b, float(h), ctypes.c_void_p(kappa_ptr))
-    opts = slab_options(precision, float(tol), int(max_iter), flags)
+    opts = slab_options(precision, float(tol), int(max_iter), flags, int(tile))
     return load_library().slab_check_problem(ctypes.byref(prob), ctypes.byref(opts))
 
 
@@ -385,7 +394,7 @@ class SlabBatch:
 
 def slab_factor_batch(kappas, dims, precision: int = SLAB_FP64, tol: float = 1e-10,
                       max_iter: int = 10, odd_even: bool = True, graph: bool = False,
-                      keep_reduced: bool = False, stream=None) -> SlabBatch:
+                      keep_reduced: bool = False, tile: int = 0, stream=None) -> SlabBatch:
     """Factor independent problems together.  kappas: CUDA float64 tensors of
     shape (n1+2, n2+2); dims: (n2, n1, b) or (n2, n1, b, h) per problem."""
     L = load_library()
@@ -403,7 +412,7 @@ def slab_factor_batch(kappas, dims, precision: int = SLAB_FP64, tol: float = 1e-
         arr[i] = slab_problem(n1, n2, b, h, _dev_f64(k, f"kappa[{i}]"))
     flags = ((SLAB_ODD_EVEN if odd_even else 0) | (SLAB_GRAPH if graph else 0)
              | (SLAB_KEEP_REDUCED if keep_reduced else 0))
-    opts = slab_options(precision, float(tol), int(max_iter), flags)
+    opts = slab_options(precision, float(tol), int(max_iter), flags, int(tile))
     infos = (slab_solve_info * len(full))()
     out = ctypes.c_void_p()
     _check(L.slab_factor_batch(arr, len(full), ctypes.byref(opts), _stream_ptr(stream),

@@ -339,6 +339,29 @@ def test_batch_graph_replays_match_eager():
     bt.free()
 
 
+def test_batch_graph_after_workspace_regrow():
+    """A call with more right-hand sides on one problem of a graph batch gives
+    that problem a new solve workspace; the next batch solve must not replay a
+    graph that still points at the old one."""
+    dims = BATCH_DIMS[:3]
+    kaps, fs = _batch_inputs(dims, 70)
+    fd = [_dev(f) for f in fs]
+    bt = S.slab_factor_batch([_dev(k) for k in kaps], [d[:3] for d in dims],
+                             precision=S.SLAB_MIXED, graph=True)
+    S.slab_solve_batch(bt, fd)
+    n2, n1, b, nr = dims[0]
+    fbig = G.rhs_uniform(n2, n1, nr + 1, 71)
+    ubig = np.zeros_like(fbig)
+    rr0 = S.slab_residual(bt.handle(0), _dev(fbig), _dev(ubig))   # grows problem 0's workspace
+    assert np.allclose(rr0, 1.0)
+    us = S.slab_solve_batch(bt, fd)
+    for i, (n2, n1, b, nr) in enumerate(dims):
+        rr = O.relres(O.make_problem(kaps[i], n2, n1, b), us[i].cpu().numpy(), fs[i])
+        assert rr.max() <= 1e-10, (i, rr)
+        assert bt.last_infos[i].max_relres <= 1e-10, i
+    bt.free()
+
+
 def test_batch_reports_failing_problem():
     dims = BATCH_DIMS[:3]
     kaps, _ = _batch_inputs(dims, 80)

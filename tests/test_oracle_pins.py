@@ -474,3 +474,78 @@ def test_odd_even_last_pivot_matches_sweep():
     assert [el.e for el in oe.levels[-1]] == [p.m - 1]
     D = oe.pivot(p.m - 1)
     assert np.abs(D - sw.S[-1]).max() <= 1e-12 * np.abs(D).max()
+
+
+# ------------------------------------------- relres and the per-interface blocks
+
+def _loop_apply(kap, n2, n1, h, u):
+    """A u by a plain loop over nodes and their four neighbours (Sec. 2.1 stencil
+    with the variable-coefficient edge weights), for u of shape (n1, n2)."""
+    out = np.zeros_like(u)
+    for c in range(n1):
+        for r in range(n2):
+            acc = 0.0
+            for dc, dr in ((-1, 0), (1, 0), (0, -1), (0, 1)):
+                cq, rq = c + dc, r + dr
+                w = (kap[c + 1, r + 1] + kap[cq + 1, rq + 1]) / (2 * h * h)
+                uq = u[cq, rq] if (0 <= cq < n1 and 0 <= rq < n2) else 0.0
+                acc += w * (u[c, r] - uq)
+            out[c, r] = acc
+    return out
+
+
+def test_relres_against_loop_residual():
+    """relerr_res of Sec. 5.1 per column: ||A u - f|| / ||f|| with A applied by
+    node loops, for columns perturbed by very different amounts (a norm taken
+    over the wrong axis, a missing square root or a swapped numerator would
+    each change the values)."""
+    n2, n1, b = 6, 8, 3
+    h = 1.0 / (n2 + 1)
+    kap = G.kappa_lognormal(n2, n1, 2, h)
+    p = O.make_problem(kap, n2, n1, b, h)
+    f = G.rhs_uniform(n2, n1, 3, 21)
+    u_exact = np.linalg.solve(p.A.toarray(), f.reshape(3, -1).T).T.reshape(f.shape)
+    rng = np.random.default_rng(5)
+    scales = [0.0, 1e-6, 1e-2]
+    u = u_exact + np.array(scales)[:, None, None] * rng.standard_normal(f.shape)
+    rr = O.relres(p, u, f)
+    for k in range(3):
+        res = _loop_apply(kap, n2, n1, h, u[k]) - f[k]
+        want = np.sqrt(np.sum(res ** 2)) / np.sqrt(np.sum(f[k] ** 2))
+        if scales[k] == 0.0:
+            assert rr[k] <= 1e-13
+        else:
+            assert abs(rr[k] - want) <= 1e-10 * want, (k, rr[k], want)
+    assert rr[1] < rr[2]
+
+
+@pytest.mark.parametrize("n2,n1,b", [(5, 16, 3), (4, 12, 2), (3, 4, 1), (6, 8, 7)])
+def test_interface_blocks_are_dense_schur_blocks(n2, n1, b):
+    """T_jj and T_{j,j+1} from the two slabs at interface j equal the blocks of
+    the dense Schur complement of all slab interiors (and those of stage_one)."""
+    p = O.make_problem(G.kappa_lognormal(n2, n1, 9), n2, n1, b)
+    A = p.A.toarray()
+    e, o = p.maps["perm_even"], p.maps["perm_odd"]
+    T_ref = A[np.ix_(o, o)] - A[np.ix_(o, e)] @ np.linalg.solve(A[np.ix_(e, e)], A[np.ix_(e, o)])
+    s1 = O.stage_one(p)
+    for j in range(p.m):
+        Tjj, Tup = O.interface_blocks(p, j)
+        sl = slice(j * n2, (j + 1) * n2)
+        assert np.abs(Tjj - T_ref[sl, sl]).max() <= 1e-13 * np.abs(T_ref).max()
+        assert np.array_equal(Tjj, s1.T_diag[j]) or np.abs(Tjj - s1.T_diag[j]).max() <= 1e-14 * np.abs(Tjj).max()
+        if j + 1 < p.m:
+            su = slice((j + 1) * n2, (j + 2) * n2)
+            assert np.abs(Tup - T_ref[sl, su]).max() <= 1e-13 * np.abs(T_ref).max()
+        else:
+            assert Tup is None
+
+
+def test_stage_one_process_pool_equals_serial():
+    """Spreading the independent slabs over processes changes nothing."""
+    n2, n1, b = 12, 24, 3
+    p = O.make_problem(G.kappa_lognormal(n2, n1, 3), n2, n1, b)
+    a, c = O.stage_one(p), O.stage_one(p, workers=2)
+    for x, y in zip(a.T_diag + a.T_up + a.T_lo, c.T_diag + c.T_up + c.T_lo):
+        assert np.array_equal(x, y)
+    f = G.rhs_uniform(n2, n1, 1, 3)
+    assert np.array_equal(O.solve(O.factor(p), f), O.solve(O.factor(p, workers=2), f))
