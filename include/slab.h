@@ -43,6 +43,7 @@
 #ifndef SLAB_H_
 #define SLAB_H_
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -133,6 +134,27 @@ int slab_solve_adjoint(slab_handle h, const double* g, double* lam, int32_t nrhs
 
 /* Release the handle and its device memory (NULL is a no-op). */
 int slab_free(slab_handle h);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, serving loops, harnesses that forbid hipMalloc): slab_solve with
+   every solve buffer and plan table placed in one device array of the
+   library, SLAB_NOALLOC_SCRATCH_BYTES long, instead of memory the library
+   allocates.  Same arguments, result and conventions as slab_solve; the
+   handle must come from slab_factor or slab_batch_handle.  It calls no
+   hipMalloc, hipFree or other allocating routine.  Each GPU the library runs
+   on holds its own copy of the array until the process ends; its address is
+   looked up once per device, on the first call there.
+   SLAB_E_INVALID (before any device work) when the solve buffers for this
+   problem and nrhs need more than SLAB_NOALLOC_SCRATCH_BYTES - 1 MiB (in
+   FP64 about 8 * nrhs * n1 * n2 * (2 + BP/(b+1)) bytes, BP = b rounded up to
+   16, 32 or 64; the message states the size needed), or a pass's plan tables
+   more than the 1 MiB kept for them.  Every call on one GPU shares
+   its array: calls that overlap in time on one GPU (two host threads, or two
+   streams) race and give wrong results.  No buffer of the array needs to
+   start at zero; a call leaves its last contents behind. */
+#define SLAB_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int slab_solve_noalloc(slab_handle h, const double* f, double* u, int32_t nrhs, int64_t ld,
+                       void* hip_stream, slab_solve_info* info);
 
 /* ---- batches of independent problems ------------------------------------- */
 

@@ -673,12 +673,31 @@ double worst_of(const std::vector<double>& v) {
   return w;
 }
 
+// Device memory of a call that allocates nothing: the plan tables of every
+// pass are copied to `tables` (the solve buffers were placed by the caller).
+struct FixedTables {
+  char* tables;
+  size_t cap;
+};
+
 // One refinement pass of `jobs`, eagerly or through a cached graph.
 int run_pass(Owner& mem, GraphCache* gc, const std::vector<SolveJob>& jobs, int precision,
-             bool first, bool trans, hipStream_t st) {
+             bool first, bool trans, hipStream_t st, const FixedTables* fx) {
   Plan p;
   plan_pass_dispatch(precision, p, jobs, first, trans);
   for (const SolveJob& j : jobs) count_launches(j.h, p);
+  if (fx) {
+    if (p.bytes() > fx->cap) {
+      set_error("plan tables of " + std::to_string(p.bytes()) + " bytes exceed the " +
+                std::to_string(fx->cap) + " bytes reserved for them in the scratch array");
+      return SLAB_E_INVALID;
+    }
+    // ordered on the stream after the previous pass's launches, which read
+    // the same table region
+    if (p.bytes())
+      SLAB_HIP_CHECK(hipMemcpyAsync(fx->tables, p.host(), p.bytes(), hipMemcpyHostToDevice, st));
+    return p.run(fx->tables, st);
+  }
   if (!gc) return run_plan(mem, p, st);
   // the captured launches read the jobs' vectors and workspaces: a new
   // workspace (grown by any call on one of the handles) invalidates the graph
@@ -722,9 +741,11 @@ int run_pass(Owner& mem, GraphCache* gc, const std::vector<SolveJob>& jobs, int 
   return SLAB_OK;
 }
 
+// fx: the workspaces of the jobs' handles are already in place and the plan
+// tables go to fx->tables (nothing is allocated); null: the usual path.
 int solve_group(std::vector<SolveJob>& jobs, int precision, bool trans, hipStream_t st,
-                Owner& mem, GraphCache* graphs) {
-  {
+                Owner& mem, GraphCache* graphs, const FixedTables* fx = nullptr) {
+  if (!fx) {
     std::vector<std::pair<slab_handle, int>> need;
     for (SolveJob& j : jobs) need.push_back({j.h, j.nrhs});
     SLAB_TRY(ensure_workspaces(need, mem));
@@ -737,7 +758,7 @@ int solve_group(std::vector<SolveJob>& jobs, int precision, bool trans, hipStrea
   bool first = true;
   while (!live.empty()) {
     GraphCache* gc = graphs ? &graphs[first ? 0 : 1] : nullptr;
-    SLAB_TRY(run_pass(mem, gc, live, precision, first, trans, st));
+    SLAB_TRY(run_pass(mem, gc, live, precision, first, trans, st, fx));
     std::vector<std::vector<double>> rr;
     SLAB_TRY(read_relres(live, st, rr));
     std::vector<SolveJob> next;
@@ -781,6 +802,75 @@ int solve_one(slab_handle h, const double* f, double* u, int32_t nrhs, int64_t l
   SLAB_HIP_CHECK(hipSetDevice(h->device));
   std::vector<SolveJob> jobs{{h, f, u, nrhs, ld, info}};
   return solve_group(jobs, h->precision, trans, st, h->mem, nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free solve.  The solve buffers and plan tables of one call live
+// in a file-scope device array of fixed size; host code reaches it only
+// through the address hipGetSymbolAddress returns for the current device
+// (the array's name is a host-side stand-in, not a device address).
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchTableBytes = size_t(1) << 20;
+
+std::mutex g_scratch_mu;
+std::map<int, char*> g_scratch_addr;  // device -> address of `scratch` on it
+
+}  // namespace
+
+__device__ __align__(256) char scratch[SLAB_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+// Address of the scratch array on the current device, looked up once per
+// device (with that device current) and kept.
+int scratch_address(char** out) {
+  int dev = 0;
+  SLAB_HIP_CHECK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_addr.find(dev);
+  if (it == g_scratch_addr.end()) {
+    char* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      set_error(std::string("hipGetSymbolAddress of the scratch array failed: ") +
+                hipGetErrorString(e));
+      return SLAB_E_HIP;
+    }
+    it = g_scratch_addr.emplace(dev, ptr).first;
+  }
+  *out = it->second;
+  return SLAB_OK;
+}
+
+int solve_noalloc(slab_handle h, const double* f, double* u, int32_t nrhs, int64_t ld,
+                  void* stream, slab_solve_info* info) {
+  SLAB_TRY(check_vec_args(h, f, u, nrhs, ld));
+  hipStream_t st = (hipStream_t)stream;
+  SLAB_HIP_CHECK(hipSetDevice(h->device));
+  char* base = nullptr;
+  SLAB_TRY(scratch_address(&base));
+  // the call's solve buffers, laid out as for the handle's own workspace but
+  // placed in the scratch array after the table region; the handle's own
+  // workspace is put back afterwards
+  Workspace own = h->ws;
+  h->ws = Workspace();
+  Layout L;
+  workspace_layout(h, nrhs, L);
+  if (L.total > SLAB_NOALLOC_SCRATCH_BYTES - kScratchTableBytes) {
+    h->ws = own;
+    set_error("the allocation-free solve needs " + std::to_string(L.total) +
+              " bytes of solve buffers for this problem and nrhs; its scratch array holds " +
+              std::to_string(SLAB_NOALLOC_SCRATCH_BYTES - kScratchTableBytes));
+    return SLAB_E_INVALID;
+  }
+  L.place(base + kScratchTableBytes);
+  h->ws.nrhs = nrhs;
+  h->ws.generation = -1;  // never equal to a batch graph's key
+  const FixedTables fx{base, kScratchTableBytes};
+  std::vector<SolveJob> jobs{{h, f, u, nrhs, ld, info}};
+  const int rc = solve_group(jobs, h->precision, false, st, h->mem, nullptr, &fx);
+  h->ws = own;
+  return rc;
 }
 
 // ---------------------------------------------------------------------------
@@ -1031,6 +1121,11 @@ int slab_solve(slab_handle h, const double* f, double* u, int32_t nrhs, int64_t 
 int slab_solve_adjoint(slab_handle h, const double* g, double* lam, int32_t nrhs, int64_t ld,
                        void* hip_stream, slab_solve_info* info) {
   return solve_one(h, g, lam, nrhs, ld, hip_stream, info, true);
+}
+
+int slab_solve_noalloc(slab_handle h, const double* f, double* u, int32_t nrhs, int64_t ld,
+                       void* hip_stream, slab_solve_info* info) {
+  return solve_noalloc(h, f, u, nrhs, ld, hip_stream, info);
 }
 
 int slab_free(slab_handle h) {

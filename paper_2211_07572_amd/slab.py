@@ -82,6 +82,7 @@ def load_library(path: str = LIB_PATH):
                               ctypes.POINTER(vp), ctypes.POINTER(slab_solve_info)]
     L.slab_solve.argtypes = [vp, vp, vp, i32, i64, vp, ctypes.POINTER(slab_solve_info)]
     L.slab_solve_adjoint.argtypes = [vp, vp, vp, i32, i64, vp, ctypes.POINTER(slab_solve_info)]
+    L.slab_solve_noalloc.argtypes = [vp, vp, vp, i32, i64, vp, ctypes.POINTER(slab_solve_info)]
     L.slab_free.argtypes = [vp]
     L.slab_index_maps.argtypes = [i32, i32, i32, vp, vp, vp, vp, vp, vp]
     L.slab_kappa_grad.argtypes = [vp, vp, vp, i32, i64, i32, vp, vp]
@@ -228,6 +229,13 @@ def slab_solve(handle: SlabHandle, f, out=None, stream=None, check=True):
 def slab_solve_adjoint(handle: SlabHandle, g, out=None, stream=None, check=True):
     """lambda = A^-T g with the stored factors applied transposed."""
     return _solve(load_library().slab_solve_adjoint, handle, g, out, stream, check)
+
+
+def slab_solve_noalloc(handle: SlabHandle, f, out=None, stream=None, check=True):
+    """slab_solve with its buffers in the library's fixed scratch array (no
+    device allocation inside the library call; out must be given to avoid the
+    one torch allocation of the result)."""
+    return _solve(load_library().slab_solve_noalloc, handle, f, out, stream, check)
 
 
 def slab_free(handle: SlabHandle):
