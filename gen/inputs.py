@@ -130,6 +130,26 @@ DIFFUSION_2048x4096 = Workload("diffusion_2048x4096_b31", 2048, 4096, 31, 16, "l
 ADJOINT_512 = Workload("adjoint_512x512_b15", 512, 512, 15, 1, "lognormal", "uniform")
 
 
+# The differentiation workload: 16 coefficient fields theta_i = log kappa_i on
+# the 512x512 grid (GRF seeds 10..25), one shared uniform load, an observation
+# made from a second field (seed SEED_KAPPA_OBS) plus 1% Gaussian noise, and
+# central differences at 32 random interior nodes.
+DIFF_THETA_SEEDS = tuple(range(10, 26))
+DIFF_NOISE_LEVEL = 0.01
+
+
+def noise_normal(n2: int, n1: int, nrhs: int, seed: int = SEED_NOISE) -> np.ndarray:
+    """Standard normal samples of the shape of a right-hand side block."""
+    return np.random.default_rng(seed).standard_normal((nrhs, n1, n2))
+
+
+def fd_nodes(n2: int, n1: int, count: int = 32, seed: int = SEED_FD_NODES) -> np.ndarray:
+    """Distinct random interior nodes as (c, r) pairs, shape (count, 2)."""
+    rng = np.random.default_rng(seed)
+    flat = rng.choice(n1 * n2, size=count, replace=False)
+    return np.stack([flat // n2, flat % n2], axis=1)
+
+
 def batch_problems(count: int = 256, seed: int = SEED_BATCH) -> list[Workload]:
     """Uneven batch: n2 in {128,...,1024}, n1 in {128,...,2048}, b in {7,15,31}, 1-16 RHS.
 

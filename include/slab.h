@@ -180,6 +180,20 @@ int slab_factor_batch(const slab_problem* probs, int32_t count, const slab_optio
 int slab_solve_batch(slab_batch bt, const double* const* f, double* const* u, const int32_t* nrhs,
                      const int64_t* ld, void* hip_stream, slab_solve_info* infos);
 
+/* A^T lambda_i = g_i for every problem of the batch with its stored factors
+   applied transposed (as slab_solve_adjoint), in the grouped launches of
+   slab_solve_batch; arguments and SLAB_GRAPH behaviour as there. */
+int slab_solve_adjoint_batch(slab_batch bt, const double* const* g, double* const* lam,
+                             const int32_t* nrhs, const int64_t* ld, void* hip_stream,
+                             slab_solve_info* infos);
+
+/* slab_kappa_grad for every problem of the batch: u[i], lam[i], grad[i] are
+   device pointers (host arrays of them), nrhs[i] and ld[i] as in
+   slab_kappa_grad, the same mode for all.  Synchronizes once at the end. */
+int slab_kappa_grad_batch(slab_batch bt, const double* const* u, const double* const* lam,
+                          const int32_t* nrhs, const int64_t* ld, int32_t mode,
+                          double* const* grad, void* hip_stream);
+
 /* Handle of problem i of the batch (owned by the batch: do not free it).
    slab_solve, slab_solve_adjoint, slab_kappa_grad, slab_residual,
    slab_export_reduced and slab_query work on it as on any handle. */

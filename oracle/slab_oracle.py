@@ -617,9 +617,9 @@ def kappa_grad(prob: Problem, u: np.ndarray, lam: np.ndarray) -> np.ndarray:
     return gk * prob.kappa
 
 
-def direct_solve(prob: Problem, f: np.ndarray) -> np.ndarray:
-    """Independent cross-check: sparse LU (SuperLU) of A in natural order."""
-    lu = spla.splu(prob.A.tocsc())
+def direct_solve(prob: Problem, f: np.ndarray, transpose: bool = False) -> np.ndarray:
+    """Independent cross-check: sparse LU (SuperLU) of A (or A^T) in natural order."""
+    lu = spla.splu((prob.A.T if transpose else prob.A).tocsc())
     F = f.reshape(-1, prob.N)
     U = np.stack([lu.solve(F[i]) for i in range(F.shape[0])])
     return U.reshape(f.shape)

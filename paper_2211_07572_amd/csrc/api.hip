@@ -308,7 +308,7 @@ struct slab_batch_s {
   int device = 0;
   long long phase_us[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   Owner mem;            // plan tables of batched factorizations and solves
-  GraphCache graphs[2]; // first pass, later passes
+  GraphCache graphs[4]; // forward first pass, later passes; adjoint first, later
 };
 
 namespace {
@@ -1207,8 +1207,12 @@ int slab_factor_batch(const slab_problem* probs, int32_t count, const slab_optio
   return SLAB_OK;
 }
 
-int slab_solve_batch(slab_batch bt, const double* const* f, double* const* u, const int32_t* nrhs,
-                     const int64_t* ld, void* hip_stream, slab_solve_info* infos) {
+}  // extern "C"
+
+namespace {
+
+int solve_batch(slab_batch bt, const double* const* f, double* const* u, const int32_t* nrhs,
+                const int64_t* ld, void* hip_stream, slab_solve_info* infos, bool trans) {
   if (!bt || !f || !u || !nrhs || !ld) { set_error("null argument"); return SLAB_E_INVALID; }
   std::vector<SolveJob> jobs;
   for (size_t i = 0; i < bt->items.size(); ++i) {
@@ -1222,7 +1226,7 @@ int slab_solve_batch(slab_batch bt, const double* const* f, double* const* u, co
   }
   SLAB_HIP_CHECK(hipSetDevice(bt->device));
   hipStream_t st = (hipStream_t)hip_stream;
-  if (!(bt->flags & SLAB_GRAPH)) return solve_group(jobs, bt->precision, false, st, bt->mem, nullptr);
+  if (!(bt->flags & SLAB_GRAPH)) return solve_group(jobs, bt->precision, trans, st, bt->mem, nullptr);
   // stream capture needs a stream other than the legacy default stream
   // (work queued on the default stream, e.g. the inputs, is finished first)
   hipStream_t cs = st;
@@ -1230,12 +1234,52 @@ int slab_solve_batch(slab_batch bt, const double* const* f, double* const* u, co
     SLAB_HIP_CHECK(hipStreamSynchronize(st));
     SLAB_HIP_CHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
   }
-  const int rc = solve_group(jobs, bt->precision, false, cs, bt->mem, bt->graphs);
+  const int rc = solve_group(jobs, bt->precision, trans, cs, bt->mem, bt->graphs + (trans ? 2 : 0));
   if (!st) {
     (void)hipStreamSynchronize(cs);
     (void)hipStreamDestroy(cs);
   }
   return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int slab_solve_batch(slab_batch bt, const double* const* f, double* const* u, const int32_t* nrhs,
+                     const int64_t* ld, void* hip_stream, slab_solve_info* infos) {
+  return solve_batch(bt, f, u, nrhs, ld, hip_stream, infos, false);
+}
+
+int slab_solve_adjoint_batch(slab_batch bt, const double* const* g, double* const* lam,
+                             const int32_t* nrhs, const int64_t* ld, void* hip_stream,
+                             slab_solve_info* infos) {
+  return solve_batch(bt, g, lam, nrhs, ld, hip_stream, infos, true);
+}
+
+int slab_kappa_grad_batch(slab_batch bt, const double* const* u, const double* const* lam,
+                          const int32_t* nrhs, const int64_t* ld, int32_t mode,
+                          double* const* grad, void* hip_stream) {
+  if (!bt || !u || !lam || !nrhs || !ld || !grad || (mode != 0 && mode != 1)) {
+    set_error("bad arguments to slab_kappa_grad_batch");
+    return SLAB_E_INVALID;
+  }
+  for (size_t i = 0; i < bt->items.size(); ++i) {
+    slab_handle h = bt->items[i];
+    if (!u[i] || !lam[i] || !grad[i] || nrhs[i] <= 0 || ld[i] < (long long)h->n1 * h->n2) {
+      set_error("bad arguments to slab_kappa_grad_batch in problem " + std::to_string(i));
+      return SLAB_E_INVALID;
+    }
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  SLAB_HIP_CHECK(hipSetDevice(bt->device));
+  for (size_t i = 0; i < bt->items.size(); ++i) {
+    slab_handle h = bt->items[i];
+    SLAB_TRY(launch_kappa_grad(h->n1, h->n2, nrhs[i], ld[i], h->h, h->kappa, u[i], lam[i], mode,
+                               grad[i], st));
+  }
+  SLAB_HIP_CHECK(hipStreamSynchronize(st));
+  return SLAB_OK;
 }
 
 int slab_batch_handle(slab_batch bt, int32_t i, slab_handle* out) {

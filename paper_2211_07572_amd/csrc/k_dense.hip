@@ -2,8 +2,9 @@
 // reduced matrix T (Alg. 1) and the dense kernels it is built from.
 //
 // T is symmetric positive definite for kappa > 0, so every S_j of Alg. 1 is
-// too.  "Compute and store S_j^-1" is realised as S_j = L_j L_j^T with the
-// explicit inverse L_j^-1 kept, and the next pivot block formed as
+// too.  Alg. 1 keeps the inverse of each S_j; here it is held as the Cholesky
+// factor S_j = L_j L_j^T with its explicit inverse L_j^-1, and the next pivot
+// block is formed as
 //   S_{j+1} = T_{j+1,j+1} - Z_j^T Z_j,   Z_j = L_j^-1 T_{j,j+1},
 // which equals T_{j+1,j+1} - T_{j+1,j} S_j^-1 T_{j,j+1} since T_{j+1,j} = T_{j,j+1}^T.
 // The factorization of each S_j is right-looking in 64-column panels; the

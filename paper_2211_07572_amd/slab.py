@@ -94,6 +94,12 @@ def load_library(path: str = LIB_PATH):
     L.slab_solve_batch.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                    ctypes.POINTER(i32), ctypes.POINTER(i64), vp,
                                    ctypes.POINTER(slab_solve_info)]
+    L.slab_solve_adjoint_batch.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                           ctypes.POINTER(i32), ctypes.POINTER(i64), vp,
+                                           ctypes.POINTER(slab_solve_info)]
+    L.slab_kappa_grad_batch.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                        ctypes.POINTER(i32), ctypes.POINTER(i64), i32,
+                                        ctypes.POINTER(vp), vp]
     L.slab_batch_handle.argtypes = [vp, i32, ctypes.POINTER(vp)]
     L.slab_batch_query.argtypes = [vp, i32, ctypes.POINTER(i64)]
     L.slab_batch_free.argtypes = [vp]
@@ -333,7 +339,60 @@ def _autograd():
     return SlabSolveFunction
 
 
+def _autograd_batch():
+    import torch
+
+    class SlabSolveBatchFunction(torch.autograd.Function):
+        """Forward: slab_factor_batch of B fields theta_i = log kappa_i (one
+        grid) + slab_solve_batch.  Backward: slab_solve_adjoint_batch for
+        lambda_i = A_i^-T dL/du_i, then slab_kappa_grad_batch for dL/dtheta_i;
+        dL/df = lambda (summed over the batch when f is shared)."""
+
+        @staticmethod
+        def forward(ctx, theta, f, n2, n1, b, h, precision, tol):
+            B = theta.shape[0]
+            thetas = [theta[i].contiguous() for i in range(B)]
+            batch = slab_factor_batch(thetas, [(n2, n1, b, h)] * B, precision=precision, tol=tol,
+                                      coef_log=True)
+            shared = f.dim() == 3
+            fs = [f.contiguous() if shared else f[i].contiguous() for i in range(B)]
+            us = slab_solve_batch(batch, fs)
+            u = torch.stack(us)
+            ctx.batch = batch
+            ctx.shared = shared
+            ctx.save_for_backward(u)
+            return u
+
+        @staticmethod
+        def backward(ctx, gu):
+            (u,) = ctx.saved_tensors
+            batch = ctx.batch
+            B = u.shape[0]
+            lams = slab_solve_adjoint_batch(batch, [gu[i].contiguous() for i in range(B)])
+            grads = slab_kappa_grad_batch(batch, [u[i] for i in range(B)], lams, mode=1)
+            lam = torch.stack(lams)
+            gf = lam.sum(0) if ctx.shared else lam
+            return torch.stack(grads), gf, None, None, None, None, None, None
+
+    return SlabSolveBatchFunction
+
+
 _fn = None
+_fn_batch = None
+
+
+def solve_theta_batch(theta, f, n2: int, n1: int, b: int, h: float | None = None,
+                      precision: int = SLAB_FP64, tol: float = 1e-10):
+    """Differentiable u_i = A(exp theta_i)^-1 f_i for a batch of B coefficient
+    fields on one grid: theta of shape (B, n1+2, n2+2); f of shape
+    (nrhs, n1, n2) (shared by every field) or (B, nrhs, n1, n2).  Returns u of
+    shape (B, nrhs, n1, n2)."""
+    global _fn_batch
+    if _fn_batch is None:
+        _fn_batch = _autograd_batch()
+    if h is None:
+        h = 1.0 / (n2 + 1)
+    return _fn_batch.apply(theta, f, n2, n1, b, h, precision, tol)
 
 
 def solve_theta(theta, f, n2: int, n1: int, b: int, h: float | None = None,
@@ -402,7 +461,8 @@ class SlabBatch:
 
 def slab_factor_batch(kappas, dims, precision: int = SLAB_FP64, tol: float = 1e-10,
                       max_iter: int = 10, odd_even: bool = True, graph: bool = False,
-                      keep_reduced: bool = False, tile: int = 0, stream=None) -> SlabBatch:
+                      keep_reduced: bool = False, tile: int = 0, coef_log: bool = False,
+                      stream=None) -> SlabBatch:
     """Factor independent problems together.  kappas: CUDA float64 tensors of
     shape (n1+2, n2+2); dims: (n2, n1, b) or (n2, n1, b, h) per problem."""
     L = load_library()
@@ -419,7 +479,7 @@ def slab_factor_batch(kappas, dims, precision: int = SLAB_FP64, tol: float = 1e-
             raise ValueError(f"kappa {i} must have shape {(n1 + 2, n2 + 2)}")
         arr[i] = slab_problem(n1, n2, b, h, _dev_f64(k, f"kappa[{i}]"))
     flags = ((SLAB_ODD_EVEN if odd_even else 0) | (SLAB_GRAPH if graph else 0)
-             | (SLAB_KEEP_REDUCED if keep_reduced else 0))
+             | (SLAB_KEEP_REDUCED if keep_reduced else 0) | (SLAB_COEF_LOG if coef_log else 0))
     opts = slab_options(precision, float(tol), int(max_iter), flags, int(tile))
     infos = (slab_solve_info * len(full))()
     out = ctypes.c_void_p()
@@ -428,11 +488,8 @@ def slab_factor_batch(kappas, dims, precision: int = SLAB_FP64, tol: float = 1e-
     return SlabBatch(out, full, precision)
 
 
-def slab_solve_batch(batch: SlabBatch, fs, outs=None, stream=None, check=True):
-    """Solve every problem of the batch: fs[i] of shape (nrhs_i, n1_i, n2_i)
-    (or (n1_i, n2_i)), CUDA float64.  Returns the list of solutions."""
+def _batch_vectors(batch: SlabBatch, fs, outs):
     import torch
-    L = load_library()
     cnt = len(batch)
     if len(fs) != cnt:
         raise ValueError("one right-hand side block per problem")
@@ -448,12 +505,46 @@ def slab_solve_batch(batch: SlabBatch, fs, outs=None, stream=None, check=True):
     up = (ctypes.c_void_p * cnt)(*[_dev_f64(t, f"u[{i}]").value for i, t in enumerate(us)])
     nr = (ctypes.c_int32 * cnt)(*[t.shape[0] for t in f3])
     ld = (ctypes.c_int64 * cnt)(*[batch.dims[i][0] * batch.dims[i][1] for i in range(cnt)])
+    return f3, us, fp, up, nr, ld
+
+
+def _solve_batch(fn, batch: SlabBatch, fs, outs, stream, check):
+    cnt = len(batch)
+    _, us, fp, up, nr, ld = _batch_vectors(batch, fs, outs)
     infos = (slab_solve_info * cnt)()
-    rc = L.slab_solve_batch(batch.ptr, fp, up, nr, ld, _stream_ptr(stream), infos)
+    rc = fn(batch.ptr, fp, up, nr, ld, _stream_ptr(stream), infos)
     batch.last_infos = list(infos)
     if check:
         _check(rc)
     return [u.view(f.shape) if f.dim() == 2 else u for u, f in zip(us, fs)]
+
+
+def slab_solve_batch(batch: SlabBatch, fs, outs=None, stream=None, check=True):
+    """Solve every problem of the batch: fs[i] of shape (nrhs_i, n1_i, n2_i)
+    (or (n1_i, n2_i)), CUDA float64.  Returns the list of solutions."""
+    return _solve_batch(load_library().slab_solve_batch, batch, fs, outs, stream, check)
+
+
+def slab_solve_adjoint_batch(batch: SlabBatch, gs, outs=None, stream=None, check=True):
+    """lambda_i = A_i^-T g_i for every problem of the batch (stored factors
+    applied transposed).  Returns the list of lambda_i."""
+    return _solve_batch(load_library().slab_solve_adjoint_batch, batch, gs, outs, stream, check)
+
+
+def slab_kappa_grad_batch(batch: SlabBatch, us, lams, mode: int = 1, stream=None):
+    """slab_kappa_grad for every problem: list of (n1_i+2, n2_i+2) gradients."""
+    import torch
+    cnt = len(batch)
+    u3, _, upp, _, nr, ld = _batch_vectors(batch, us, lams)
+    l3 = [_vec_shape(l, batch.dims[i][0], batch.dims[i][1]).contiguous()
+          for i, l in enumerate(lams)]
+    lp = (ctypes.c_void_p * cnt)(*[_dev_f64(t, f"lam[{i}]").value for i, t in enumerate(l3)])
+    grads = [torch.empty((n1 + 2, n2 + 2), dtype=torch.float64, device=u3[0].device)
+             for (n2, n1, _, _) in batch.dims]
+    gp = (ctypes.c_void_p * cnt)(*[_dev_f64(g, f"grad[{i}]").value for i, g in enumerate(grads)])
+    _check(load_library().slab_kappa_grad_batch(batch.ptr, upp, lp, nr, ld, int(mode), gp,
+                                                _stream_ptr(stream)))
+    return grads
 
 
 def release_cache():

@@ -359,6 +359,8 @@ def test_adjoint_transposes_nonsymmetric(order):
     lam = O.solve_adjoint(p, g, order=order)
     ref = spla.spsolve(p.A.T.tocsc(), g.reshape(2, -1).T).T.reshape(g.shape)
     assert np.abs(lam - ref).max() <= 1e-12 * np.abs(ref).max()
+    lam_d = O.direct_solve(p, g, transpose=True)
+    assert np.abs(lam_d - ref).max() <= 1e-12 * np.abs(ref).max()
     u = O.solve(O.factor(p, order=order), g)
     ref_u = spla.spsolve(p.A.tocsc(), g.reshape(2, -1).T).T.reshape(g.shape)
     assert np.abs(u - ref_u).max() <= 1e-12 * np.abs(ref_u).max()
