@@ -77,8 +77,8 @@ typedef struct slab_batch_s* slab_batch;
                                 positions of those left are eliminated together, so
                                 a level is one batch of independent block
                                 factorizations; without it, the sweep of Alg. 1 */
-#define SLAB_GRAPH 8         /* batched solves: capture each refinement pass of the
-                                batch as a HIP graph on first use and replay it */
+#define SLAB_GRAPH 8         /* batched solves: capture all refinement passes of the
+                                batch as one HIP graph on first use and replay it */
 
 typedef struct {
   int32_t n1;          /* interior columns (slab direction); n1 % (b+1) == 0, n1 >= 2 */
@@ -173,12 +173,31 @@ int slab_factor_batch(const slab_problem* probs, int32_t count, const slab_optio
    arrays of device pointers), nrhs[i] and ld[i] (host arrays) as in
    slab_solve.  Every refinement pass of the batch is one set of grouped
    launches; a problem drops out once its residual meets tol.  With SLAB_GRAPH
-   a pass is captured as a HIP graph the first time and replayed while the
-   arguments and the set of unfinished problems stay the same (the graph and
-   its tables live until slab_batch_free).  SLAB_E_NOCONV if any problem
-   misses tol. */
+   all max_iter passes are captured as ONE HIP graph the first time and
+   replayed while the arguments stay the same (the graph and its tables live
+   until slab_batch_free): each pass ends with a convergence test on the
+   device, later passes skip the work of problems that have met tol, and the
+   host synchronizes once.  SLAB_E_NOCONV if any problem misses tol. */
 int slab_solve_batch(slab_batch bt, const double* const* f, double* const* u, const int32_t* nrhs,
                      const int64_t* ld, void* hip_stream, slab_solve_info* infos);
+
+/* Factor every problem of the batch again from new coefficient fields kappa[i]
+   (device, same shapes and options as at slab_factor_batch) and solve
+   f[i] -> u[i] (arguments as in slab_solve_batch), as ONE HIP graph launch:
+   Alg. 3 for all problems, then max_iter passes of Alg. 4 with FP64
+   refinement, each followed by a convergence test on the device; a problem
+   that has met tol skips the work of the later passes on the device, and the
+   host synchronizes once, at the end.  The graph is captured on the first
+   call and replayed while kappa, f, u, nrhs and ld are the same pointers and
+   values (write new data into the same buffers to reuse it); it and the
+   factorization temporaries it uses live until slab_batch_free.  The batch's
+   handles then hold the new factors.  Failures are reported as by
+   slab_factor_batch (SLAB_E_INVALID for an invalid field, SLAB_E_BREAKDOWN)
+   and slab_solve_batch (SLAB_E_NOCONV); phase times (slab_batch_query) are
+   not updated. */
+int slab_batch_run(slab_batch bt, const double* const* kappa, const double* const* f,
+                   double* const* u, const int32_t* nrhs, const int64_t* ld, void* hip_stream,
+                   slab_solve_info* infos);
 
 /* A^T lambda_i = g_i for every problem of the batch with its stored factors
    applied transposed (as slab_solve_adjoint), in the grouped launches of

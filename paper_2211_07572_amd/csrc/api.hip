@@ -284,7 +284,8 @@ static void count_launches(slab_handle h, const Plan& p) {
   for (int k = 0; k < LK_COUNT; ++k) h->launches[k] += p.launches[k];
 }
 
-// A solve pass captured as a HIP graph, valid for one set of arguments.
+// Work captured as a HIP graph (all refinement passes of a batch solve, or a
+// batch's factorization and solve), valid for one set of arguments.
 struct GraphCache {
   std::vector<long long> key;
   hipGraph_t graph = nullptr;
@@ -308,7 +309,13 @@ struct slab_batch_s {
   int device = 0;
   long long phase_us[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   Owner mem;            // plan tables of batched factorizations and solves
-  GraphCache graphs[4]; // forward first pass, later passes; adjoint first, later
+  GraphCache graphs[2]; // all passes of a batch solve (forward, adjoint)
+  GraphCache run;       // factorization and solve (slab_batch_run)
+  void* run_temps = nullptr;  // factorization temporaries of the run graph
+  size_t run_temps_cap = 0;
+  // device-side refinement state per problem (graphs): int live[n], iters[n],
+  // factor status[4n]; double relres[n]
+  void* conv = nullptr;
 };
 
 namespace {
@@ -426,6 +433,95 @@ void temp_layout(slab_handle h, FactorTemps& t, Layout& L) {
   if (!h->odd_even) L.add(&t.Td, m * nsq * e2);
 }
 
+// Problem descriptors of stage one for handles whose persistent buffers are
+// in place; coefs[i] is the field read by the coefficient step.
+std::vector<ProbDev> prob_descs(const std::vector<slab_handle>& hs,
+                                const std::vector<const double*>& coefs) {
+  std::vector<ProbDev> pd(hs.size());
+  for (size_t i = 0; i < hs.size(); ++i) {
+    slab_handle h = hs[i];
+    ProbDev& d = pd[i];
+    std::memset(&d, 0, sizeof(d));
+    d.n1 = h->n1; d.n2 = h->n2; d.b = h->b; d.m = h->m; d.h = h->h;
+    d.is_log = (h->flags & SLAB_COEF_LOG) ? 1 : 0;
+    d.coef = coefs[i]; d.kappa = h->kappa; d.wh = h->wh; d.wv = h->wv;
+    d.Gl = h->Gl; d.T64 = h->T64; d.O64 = h->O64; d.status = h->status;
+  }
+  return pd;
+}
+
+// Consecutive chunks of handles whose factorization temporaries fit `budget`
+// bytes together; every chunk is laid out from the start of one block of
+// *block_bytes (the largest chunk).  tmp receives each handle's temporaries
+// once a chunk's layout is placed.
+struct Chunks {
+  std::vector<FactorTemps> tmp;
+  std::vector<std::pair<size_t, size_t>> ranges;
+  std::vector<Layout> layouts;
+  size_t block_bytes = 0;
+};
+
+template <typename T, typename TR>
+void chunk_layouts(const std::vector<slab_handle>& hs, size_t budget, Chunks& ch) {
+  const size_t cnt = hs.size();
+  ch.tmp.assign(cnt, FactorTemps());
+  for (size_t lo = 0; lo < cnt;) {
+    size_t hi = lo;
+    Layout L;
+    while (hi < cnt) {
+      Layout L1 = L;
+      temp_layout<T, TR>(hs[hi], ch.tmp[hi], L1);
+      if (hi > lo && L1.total > budget) break;
+      L = L1;
+      ++hi;
+    }
+    ch.ranges.push_back({lo, hi});
+    ch.block_bytes = std::max(ch.block_bytes, L.total);
+    ch.layouts.push_back(L);
+    lo = hi;
+  }
+}
+
+// Stage one and stage two of chunk ci, placed in `block`, recorded into p
+// (ev: optional phase events of stage one).
+template <typename T, typename TR>
+void plan_chunk(Plan& p, const std::vector<slab_handle>& hs, const std::vector<ProbDev>& pd,
+                Chunks& ch, size_t ci, void* block, const hipEvent_t* ev) {
+  const size_t lo = ch.ranges[ci].first, hi = ch.ranges[ci].second;
+  ch.layouts[ci].place(block);
+  std::vector<ProbDev> cd;
+  std::vector<Stage2Prob> s2;
+  for (size_t i = lo; i < hi; ++i) {
+    FactorTemps& t = ch.tmp[i];
+    if (hs[i]->odd_even) t.Td = hs[i]->Td;
+    ProbDev d = pd[i];
+    d.Hsw = t.Hsw; d.sig = t.sig; d.PRR = t.PRR; d.PLL = t.PLL; d.PLR = t.PLR; d.PRL = t.PRL;
+    d.Td = t.Td; d.To = t.To;
+    cd.push_back(d);
+    Stage2Prob q;
+    q.n = hs[i]->n2; q.m = hs[i]->m; q.Td = t.Td; q.To = t.To; q.Linv = hs[i]->Linv;
+    q.Z = hs[i]->Z; q.S64 = hs[i]->S64; q.status = hs[i]->status;
+    s2.push_back(q);
+  }
+  // one forced product tile for the chunk when its problems agree on it
+  int tile = hs[lo]->tile;
+  for (size_t i = lo; i < hi; ++i)
+    if (hs[i]->tile != tile) tile = 0;
+  plan_stage1<T, TR>(p, cd, ev);
+  plan_stage2<TR>(p, s2, hs[lo]->odd_even != 0, tile);
+}
+
+// Temporaries of a factorization may take half of the memory that is free or
+// cached, and at least 1 GiB.
+int temp_budget(size_t* budget) {
+  size_t free_b = 0, total_b = 0;
+  SLAB_HIP_CHECK(hipMemGetInfo(&free_b, &total_b));
+  int dev = 0;
+  SLAB_HIP_CHECK(hipGetDevice(&dev));
+  *budget = std::max<size_t>((free_b + Pool::get().cached(dev)) / 2, (size_t)1 << 30);
+  return SLAB_OK;
+}
+
 // Factor every handle of hs (sizes set) from probs[i]->kappa.  Per problem,
 // fail[i] receives 0 (ok), 1 (invalid kappa), 2 (slab breakdown) or 3 (block
 // breakdown) and blk[i] the slab / interface index; ph the group's phase times.
@@ -444,17 +540,9 @@ int factor_group(const std::vector<slab_handle>& hs, const std::vector<const sla
     for (size_t i = 0; i < cnt; ++i) persistent_layout<T, TR>(hs[i], L);
     SLAB_TRY(L.commit(plan_mem, nullptr));
   }
-  std::vector<ProbDev> pd(cnt);
-  for (size_t i = 0; i < cnt; ++i) {
-    slab_handle h = hs[i];
-    ProbDev& d = pd[i];
-    std::memset(&d, 0, sizeof(d));
-    d.n1 = h->n1; d.n2 = h->n2; d.b = h->b; d.m = h->m; d.h = h->h;
-    d.is_log = (h->flags & SLAB_COEF_LOG) ? 1 : 0;
-    d.coef = probs[i]->kappa; d.kappa = h->kappa; d.wh = h->wh; d.wv = h->wv;
-    d.Gl = h->Gl; d.T64 = h->T64; d.O64 = h->O64; d.status = h->status;
-    SLAB_HIP_CHECK(hipMemsetAsync(h->status, 0, 4 * sizeof(int), st));
-  }
+  std::vector<const double*> coefs;
+  for (size_t i = 0; i < cnt; ++i) coefs.push_back(probs[i]->kappa);
+  const std::vector<ProbDev> pd = prob_descs(hs, coefs);
   hipEvent_t ev[6];
   for (int i = 0; i < 6; ++i) SLAB_HIP_CHECK(hipEventCreate(&ev[i]));
   struct EvGuard {
@@ -478,62 +566,21 @@ int factor_group(const std::vector<slab_handle>& hs, const std::vector<const sla
   SLAB_TRY(read_status(0, cnt));
   bool any_bad = false;
   for (size_t i = 0; i < cnt; ++i)
-    if (hs_status[4 * i] == 1) { fail[i] = 1; any_bad = true; }
+    if (hs_status[4 * i + 2] == 1) { fail[i] = 1; any_bad = true; }
   if (any_bad) return SLAB_E_INVALID;
-  // temporaries of a chunk: at most half of the memory that is free or cached
-  size_t free_b = 0, total_b = 0;
-  SLAB_HIP_CHECK(hipMemGetInfo(&free_b, &total_b));
-  int dev = 0;
-  SLAB_HIP_CHECK(hipGetDevice(&dev));
-  const size_t budget = std::max<size_t>((free_b + Pool::get().cached(dev)) / 2, (size_t)1 << 30);
   // chunks first; one block of the largest chunk's size serves them all (the
   // caching allocator then meets every later factorization of the same set)
-  std::vector<FactorTemps> tmp(cnt);
-  std::vector<std::pair<size_t, size_t>> chunks;
-  std::vector<Layout> layouts;
-  size_t block_bytes = 0;
-  for (size_t lo = 0; lo < cnt;) {
-    size_t hi = lo;
-    Layout L;
-    while (hi < cnt) {
-      Layout L1 = L;
-      temp_layout<T, TR>(hs[hi], tmp[hi], L1);
-      if (hi > lo && L1.total > budget) break;
-      L = L1;
-      ++hi;
-    }
-    chunks.push_back({lo, hi});
-    block_bytes = std::max(block_bytes, L.total);
-    layouts.push_back(L);
-    lo = hi;
-  }
+  size_t budget = 0;
+  SLAB_TRY(temp_budget(&budget));
+  Chunks ch;
+  chunk_layouts<T, TR>(hs, budget, ch);
   void* block = nullptr;
-  SLAB_TRY(plan_mem.alloc(&block, block_bytes));
-  for (size_t ci = 0; ci < chunks.size(); ++ci) {
-    const size_t lo = chunks[ci].first, hi = chunks[ci].second;
-    layouts[ci].place(block);
-    std::vector<ProbDev> cd;
-    std::vector<Stage2Prob> s2;
-    for (size_t i = lo; i < hi; ++i) {
-      FactorTemps& t = tmp[i];
-      if (hs[i]->odd_even) t.Td = hs[i]->Td;
-      ProbDev d = pd[i];
-      d.Hsw = t.Hsw; d.sig = t.sig; d.PRR = t.PRR; d.PLL = t.PLL; d.PLR = t.PLR; d.PRL = t.PRL;
-      d.Td = t.Td; d.To = t.To;
-      cd.push_back(d);
-      Stage2Prob q;
-      q.n = hs[i]->n2; q.m = hs[i]->m; q.Td = t.Td; q.To = t.To; q.Linv = hs[i]->Linv;
-      q.Z = hs[i]->Z; q.S64 = hs[i]->S64; q.status = hs[i]->status;
-      s2.push_back(q);
-    }
-    // one forced product tile for the chunk when its problems agree on it
-    int tile = hs[lo]->tile;
-    for (size_t i = lo; i < hi; ++i)
-      if (hs[i]->tile != tile) tile = 0;
+  SLAB_TRY(plan_mem.alloc(&block, ch.block_bytes));
+  for (size_t ci = 0; ci < ch.ranges.size(); ++ci) {
+    const size_t lo = ch.ranges[ci].first, hi = ch.ranges[ci].second;
     Plan p;
-    plan_stage1<T, TR>(p, cd, ev + 1);
     p.timer = std::make_shared<Plan::Timer>();
-    plan_stage2<TR>(p, s2, hs[lo]->odd_even != 0, tile);
+    plan_chunk<T, TR>(p, hs, pd, ch, ci, block, ev + 1);
     for (size_t i = lo; i < hi; ++i) count_launches(hs[i], p);
     SLAB_HIP_CHECK(hipEventRecord(ev[0], st));
     SLAB_TRY(run_plan(plan_mem, p, st));
@@ -553,6 +600,33 @@ int factor_group(const std::vector<slab_handle>& hs, const std::vector<const sla
     }
   }
   plan_mem.release(block);
+  return SLAB_OK;
+}
+
+// The whole factorization of handles whose persistent buffers are in place,
+// recorded into p with no host synchronization (for graph capture): status
+// words cleared and coefficients from coefs on the device, then every chunk in
+// order, all chunks in *block (allocated from mem on first use, or when too
+// small).  Failures are left in the handles' status words.
+template <typename T, typename TR>
+int plan_factor_nosync(Plan& p, const std::vector<slab_handle>& hs,
+                       const std::vector<const double*>& coefs, Owner& mem, void** block,
+                       size_t* block_cap) {
+  const std::vector<ProbDev> pd = prob_descs(hs, coefs);
+  plan_coef_weights(p, pd);
+  size_t budget = 0;
+  SLAB_TRY(temp_budget(&budget));
+  Chunks ch;
+  chunk_layouts<T, TR>(hs, budget + *block_cap, ch);
+  if (!*block || *block_cap < ch.block_bytes) {
+    if (*block) mem.release(*block);
+    *block = nullptr;
+    *block_cap = 0;
+    SLAB_TRY(mem.alloc(block, ch.block_bytes));
+    *block_cap = ch.block_bytes;
+  }
+  for (size_t ci = 0; ci < ch.ranges.size(); ++ci) plan_chunk<T, TR>(p, hs, pd, ch, ci, *block, nullptr);
+  for (slab_handle h : hs) count_launches(h, p);
   return SLAB_OK;
 }
 
@@ -604,8 +678,11 @@ struct SolveJob {
   slab_solve_info* info;
 };
 
+// live (optional): the refinement flag of every job; the pass's work for a
+// job whose flag is 0 is skipped on the device.
 template <typename T, typename TR>
-void plan_pass(Plan& p, const std::vector<SolveJob>& jobs, bool first, bool trans) {
+void plan_pass(Plan& p, const std::vector<SolveJob>& jobs, bool first, bool trans,
+               const std::vector<const int*>* live) {
   std::vector<SolveDev> sd(jobs.size());
   std::vector<ReducedDev> red(jobs.size());
   for (size_t i = 0; i < jobs.size(); ++i) {
@@ -622,10 +699,12 @@ void plan_pass(Plan& p, const std::vector<SolveJob>& jobs, bool first, bool tran
     d.out = j.u; d.ldo = j.ld; d.accumulate = first ? 0 : 1;
     d.f = j.f; d.u = j.u; d.r = h->ws.r; d.ldf = j.ld; d.norms = h->ws.norms;
     d.partial = h->ws.partial;
+    d.live = live ? (*live)[i] : nullptr;
     ReducedDev& r = red[i];
     std::memset(&r, 0, sizeof(r));
     r.n = h->n2; r.m = h->m; r.nrhs = j.nrhs; r.Linv = h->Linv; r.Z = h->Z; r.Td = h->Td;
     r.ft = h->ws.ft; r.yt = h->ws.yt; r.tt = h->ws.tt; r.part = h->ws.bpart;
+    r.live = d.live;
     if (h->precision == SLAB_MIXED) {
       r.T64 = h->T64; r.O64 = h->O64;
       r.g64 = h->ws.g64; r.u64 = h->ws.u64; r.r64 = h->ws.r64;
@@ -638,10 +717,10 @@ void plan_pass(Plan& p, const std::vector<SolveJob>& jobs, bool first, bool tran
 }
 
 void plan_pass_dispatch(int precision, Plan& p, const std::vector<SolveJob>& jobs, bool first,
-                        bool trans) {
-  if (precision == SLAB_FP32_REFINE) plan_pass<float, float>(p, jobs, first, trans);
-  else if (precision == SLAB_MIXED) plan_pass<double, float>(p, jobs, first, trans);
-  else plan_pass<double, double>(p, jobs, first, trans);
+                        bool trans, const std::vector<const int*>* live = nullptr) {
+  if (precision == SLAB_FP32_REFINE) plan_pass<float, float>(p, jobs, first, trans, live);
+  else if (precision == SLAB_MIXED) plan_pass<double, float>(p, jobs, first, trans, live);
+  else plan_pass<double, double>(p, jobs, first, trans, live);
 }
 
 int read_relres(const std::vector<SolveJob>& jobs, hipStream_t st,
@@ -680,9 +759,10 @@ struct FixedTables {
   size_t cap;
 };
 
-// One refinement pass of `jobs`, eagerly or through a cached graph.
-int run_pass(Owner& mem, GraphCache* gc, const std::vector<SolveJob>& jobs, int precision,
-             bool first, bool trans, hipStream_t st, const FixedTables* fx) {
+// One refinement pass of `jobs`, eagerly (plan tables in the owner's table
+// buffer, or in fx's region).
+int run_pass(Owner& mem, const std::vector<SolveJob>& jobs, int precision, bool first, bool trans,
+             hipStream_t st, const FixedTables* fx) {
   Plan p;
   plan_pass_dispatch(precision, p, jobs, first, trans);
   for (const SolveJob& j : jobs) count_launches(j.h, p);
@@ -698,27 +778,84 @@ int run_pass(Owner& mem, GraphCache* gc, const std::vector<SolveJob>& jobs, int 
       SLAB_HIP_CHECK(hipMemcpyAsync(fx->tables, p.host(), p.bytes(), hipMemcpyHostToDevice, st));
     return p.run(fx->tables, st);
   }
-  if (!gc) return run_plan(mem, p, st);
-  // the captured launches read the jobs' vectors and workspaces: a new
-  // workspace (grown by any call on one of the handles) invalidates the graph
-  std::vector<long long> key;
-  key.push_back(first);
-  key.push_back(trans);
-  for (const SolveJob& j : jobs) {
-    key.push_back((long long)(uintptr_t)j.h);
-    key.push_back((long long)(uintptr_t)j.f);
-    key.push_back((long long)(uintptr_t)j.u);
-    key.push_back(j.nrhs);
-    key.push_back(j.ld);
-    key.push_back(j.h->ws.generation);
+  return run_plan(mem, p, st);
+}
+
+// Pass counts and final residuals into the jobs' infos; SLAB_E_NOCONV (with
+// a message naming the problem) if one missed its tolerance.
+int finish_jobs(std::vector<SolveJob>& jobs, const std::vector<int>& it,
+                const std::vector<double>& worst) {
+  int rc = SLAB_OK;
+  for (size_t i = 0; i < jobs.size(); ++i) {
+    if (jobs[i].info) {
+      jobs[i].info->iterations = it[i];
+      jobs[i].info->max_relres = worst[i];
+      jobs[i].info->failed_block = -1;
+    }
+    if (!(worst[i] <= jobs[i].h->tol) && rc == SLAB_OK) {
+      set_error("refinement stopped at relative residual " + std::to_string(worst[i]) +
+                " after " + std::to_string(it[i]) + " passes (tol " +
+                std::to_string(jobs[i].h->tol) + ")" +
+                (jobs.size() > 1 ? " in problem " + std::to_string(i) : std::string()));
+      rc = SLAB_E_NOCONV;
+    }
   }
+  return rc;
+}
+
+// fx: the workspaces of the jobs' handles are already in place and the plan
+// tables go to fx->tables (nothing is allocated); null: the usual path.
+// Passes run one at a time; the host reads the residuals after each one and
+// drops the problems that meet their tolerance.
+int solve_group(std::vector<SolveJob>& jobs, int precision, bool trans, hipStream_t st,
+                Owner& mem, const FixedTables* fx = nullptr) {
+  if (!fx) {
+    std::vector<std::pair<slab_handle, int>> need;
+    for (SolveJob& j : jobs) need.push_back({j.h, j.nrhs});
+    SLAB_TRY(ensure_workspaces(need, mem));
+  }
+  std::vector<int> it(jobs.size(), 0);
+  std::vector<double> worst(jobs.size(), 0.0);
+  std::vector<SolveJob> live = jobs;
+  std::vector<size_t> idx(jobs.size());
+  for (size_t i = 0; i < jobs.size(); ++i) idx[i] = i;
+  bool first = true;
+  while (!live.empty()) {
+    SLAB_TRY(run_pass(mem, live, precision, first, trans, st, fx));
+    std::vector<std::vector<double>> rr;
+    SLAB_TRY(read_relres(live, st, rr));
+    std::vector<SolveJob> next;
+    std::vector<size_t> nidx;
+    for (size_t k = 0; k < live.size(); ++k) {
+      const size_t i = idx[k];
+      ++it[i];
+      worst[i] = worst_of(rr[k]);
+      const bool done = !(worst[i] > jobs[i].h->tol) || it[i] >= jobs[i].h->max_iter;
+      if (!done) {
+        next.push_back(live[k]);
+        nidx.push_back(i);
+      }
+    }
+    live.swap(next);
+    idx.swap(nidx);
+    first = false;
+  }
+  return finish_jobs(jobs, it, worst);
+}
+
+// Launch gc's graph if it was captured for `key`; otherwise record the work
+// with build(p) (no host synchronization inside), upload its tables to a
+// buffer that lives with the graph, capture, instantiate and launch.
+int launch_graph(Owner& mem, GraphCache* gc, const std::vector<long long>& key,
+                 const std::function<int(Plan&)>& build, hipStream_t st) {
   if (gc->exec && gc->key == key) {
     SLAB_HIP_CHECK(hipGraphLaunch(gc->exec, st));
     return SLAB_OK;
   }
   SLAB_HIP_CHECK(hipStreamSynchronize(st));
   gc->clear(mem);
-  // the tables stay in place while the graph lives
+  Plan p;
+  SLAB_TRY(build(p));
   SLAB_TRY(mem.alloc(&gc->tables, std::max<size_t>(p.bytes(), 256)));
   SLAB_HIP_CHECK(hipMemcpyAsync(gc->tables, p.host(), p.bytes(), hipMemcpyHostToDevice, st));
   SLAB_HIP_CHECK(hipStreamSynchronize(st));
@@ -741,58 +878,111 @@ int run_pass(Owner& mem, GraphCache* gc, const std::vector<SolveJob>& jobs, int 
   return SLAB_OK;
 }
 
-// fx: the workspaces of the jobs' handles are already in place and the plan
-// tables go to fx->tables (nothing is allocated); null: the usual path.
-int solve_group(std::vector<SolveJob>& jobs, int precision, bool trans, hipStream_t st,
-                Owner& mem, GraphCache* graphs, const FixedTables* fx = nullptr) {
-  if (!fx) {
+// Device-side refinement state of a batch (see slab_batch_s::conv).
+struct ConvPtrs {
+  int* live;
+  int* iters;
+  int* fstat;
+  double* relres;
+};
+
+int batch_conv(slab_batch bt, ConvPtrs* c) {
+  const size_t n = bt->items.size();
+  const size_t ib = (6 * n * sizeof(int) + 255) & ~size_t(255);
+  if (!bt->conv) SLAB_TRY(bt->mem.alloc(&bt->conv, ib + n * sizeof(double)));
+  c->live = (int*)bt->conv;
+  c->iters = c->live + n;
+  c->fstat = c->iters + n;
+  c->relres = (double*)((char*)bt->conv + ib);
+  return SLAB_OK;
+}
+
+// Every refinement pass of the jobs (as many as the largest max_iter), each
+// followed by the device-side convergence test, recorded after what p holds.
+// Passes after a problem has met its tolerance skip its work on the device.
+// fstatus: copy the factorization status words too (batch runs).
+void plan_all_passes(Plan& p, const std::vector<SolveJob>& jobs, int precision, bool trans,
+                     const ConvPtrs& c, bool fstatus) {
+  int maxit = 1;
+  for (const SolveJob& j : jobs) maxit = std::max(maxit, j.h->max_iter);
+  std::vector<ConvDev> conv(jobs.size());
+  std::vector<const int*> live(jobs.size());
+  for (size_t i = 0; i < jobs.size(); ++i) {
+    slab_handle h = jobs[i].h;
+    conv[i] = ConvDev{h->ws.norms, jobs[i].nrhs, h->max_iter, h->tol, c.live + i, c.iters + i,
+                      c.relres + i, fstatus ? h->status : nullptr,
+                      fstatus ? c.fstat + 4 * i : nullptr};
+    live[i] = c.live + i;
+  }
+  for (int k = 0; k < maxit; ++k) {
+    plan_pass_dispatch(precision, p, jobs, k == 0, trans, k == 0 ? nullptr : &live);
+    plan_converge(p, conv, k == 0);
+  }
+}
+
+// Key of a graph over jobs: the captured launches read the jobs' vectors and
+// workspaces, so a new workspace (grown by any call on one of the handles)
+// invalidates it.
+std::vector<long long> jobs_key(const std::vector<SolveJob>& jobs, long long tag) {
+  std::vector<long long> key{tag};
+  for (const SolveJob& j : jobs) {
+    key.push_back((long long)(uintptr_t)j.h);
+    key.push_back((long long)(uintptr_t)j.f);
+    key.push_back((long long)(uintptr_t)j.u);
+    key.push_back(j.nrhs);
+    key.push_back(j.ld);
+    key.push_back(j.h->ws.generation);
+  }
+  return key;
+}
+
+// Read the pass counts, residuals and (optionally) factorization statuses of a
+// batch after its graph (one copy, one synchronization).
+int read_conv(slab_batch bt, hipStream_t st, std::vector<int>& it, std::vector<double>& worst,
+              std::vector<int>* fstat) {
+  const size_t n = bt->items.size();
+  const size_t ib = (6 * n * sizeof(int) + 255) & ~size_t(255);
+  std::vector<char> host(ib + n * sizeof(double));
+  SLAB_HIP_CHECK(hipMemcpyAsync(host.data(), bt->conv, host.size(), hipMemcpyDeviceToHost, st));
+  SLAB_HIP_CHECK(hipStreamSynchronize(st));
+  const int* ip = (const int*)host.data();
+  const double* dp = (const double*)(host.data() + ib);
+  it.assign(ip + n, ip + 2 * n);
+  worst.assign(dp, dp + n);
+  if (fstat) fstat->assign(ip + 2 * n, ip + 6 * n);
+  return SLAB_OK;
+}
+
+int plan_factor_nosync_dispatch(int precision, Plan& p, const std::vector<slab_handle>& hs,
+                                const std::vector<const double*>& coefs, Owner& mem,
+                                void** block, size_t* cap) {
+  if (precision == SLAB_FP32_REFINE)
+    return plan_factor_nosync<float, float>(p, hs, coefs, mem, block, cap);
+  if (precision == SLAB_MIXED) return plan_factor_nosync<double, float>(p, hs, coefs, mem, block, cap);
+  return plan_factor_nosync<double, double>(p, hs, coefs, mem, block, cap);
+}
+
+// All refinement passes of a batch solve as one graph launch (SLAB_GRAPH):
+// the convergence test runs on the device and the host synchronizes once.
+int solve_batch_graph(slab_batch bt, std::vector<SolveJob>& jobs, bool trans, hipStream_t st) {
+  {
     std::vector<std::pair<slab_handle, int>> need;
     for (SolveJob& j : jobs) need.push_back({j.h, j.nrhs});
-    SLAB_TRY(ensure_workspaces(need, mem));
+    SLAB_TRY(ensure_workspaces(need, bt->mem));
   }
-  std::vector<int> it(jobs.size(), 0);
-  std::vector<double> worst(jobs.size(), 0.0);
-  std::vector<SolveJob> live = jobs;
-  std::vector<size_t> idx(jobs.size());
-  for (size_t i = 0; i < jobs.size(); ++i) idx[i] = i;
-  bool first = true;
-  while (!live.empty()) {
-    GraphCache* gc = graphs ? &graphs[first ? 0 : 1] : nullptr;
-    SLAB_TRY(run_pass(mem, gc, live, precision, first, trans, st, fx));
-    std::vector<std::vector<double>> rr;
-    SLAB_TRY(read_relres(live, st, rr));
-    std::vector<SolveJob> next;
-    std::vector<size_t> nidx;
-    for (size_t k = 0; k < live.size(); ++k) {
-      const size_t i = idx[k];
-      ++it[i];
-      worst[i] = worst_of(rr[k]);
-      const bool done = !(worst[i] > jobs[i].h->tol) || it[i] >= jobs[i].h->max_iter;
-      if (!done) {
-        next.push_back(live[k]);
-        nidx.push_back(i);
-      }
-    }
-    live.swap(next);
-    idx.swap(nidx);
-    first = false;
-  }
-  int rc = SLAB_OK;
-  for (size_t i = 0; i < jobs.size(); ++i) {
-    if (jobs[i].info) {
-      jobs[i].info->iterations = it[i];
-      jobs[i].info->max_relres = worst[i];
-      jobs[i].info->failed_block = -1;
-    }
-    if (!(worst[i] <= jobs[i].h->tol) && rc == SLAB_OK) {
-      set_error("refinement stopped at relative residual " + std::to_string(worst[i]) +
-                " after " + std::to_string(it[i]) + " passes (tol " +
-                std::to_string(jobs[i].h->tol) + ")" +
-                (jobs.size() > 1 ? " in problem " + std::to_string(i) : std::string()));
-      rc = SLAB_E_NOCONV;
-    }
-  }
-  return rc;
+  ConvPtrs c;
+  SLAB_TRY(batch_conv(bt, &c));
+  auto build = [&](Plan& p) {
+    plan_all_passes(p, jobs, bt->precision, trans, c, false);
+    for (const SolveJob& j : jobs) count_launches(j.h, p);
+    return SLAB_OK;
+  };
+  SLAB_TRY(launch_graph(bt->mem, &bt->graphs[trans ? 1 : 0], jobs_key(jobs, trans ? 1 : 0),
+                        build, st));
+  std::vector<int> it;
+  std::vector<double> worst;
+  SLAB_TRY(read_conv(bt, st, it, worst, nullptr));
+  return finish_jobs(jobs, it, worst);
 }
 
 int solve_one(slab_handle h, const double* f, double* u, int32_t nrhs, int64_t ld, void* stream,
@@ -801,7 +991,7 @@ int solve_one(slab_handle h, const double* f, double* u, int32_t nrhs, int64_t l
   hipStream_t st = (hipStream_t)stream;
   SLAB_HIP_CHECK(hipSetDevice(h->device));
   std::vector<SolveJob> jobs{{h, f, u, nrhs, ld, info}};
-  return solve_group(jobs, h->precision, trans, st, h->mem, nullptr);
+  return solve_group(jobs, h->precision, trans, st, h->mem);
 }
 
 // ---------------------------------------------------------------------------
@@ -868,7 +1058,7 @@ int solve_noalloc(slab_handle h, const double* f, double* u, int32_t nrhs, int64
   h->ws.generation = -1;  // never equal to a batch graph's key
   const FixedTables fx{base, kScratchTableBytes};
   std::vector<SolveJob> jobs{{h, f, u, nrhs, ld, info}};
-  const int rc = solve_group(jobs, h->precision, false, st, h->mem, nullptr, &fx);
+  const int rc = solve_group(jobs, h->precision, false, st, h->mem, &fx);
   h->ws = own;
   return rc;
 }
@@ -1143,6 +1333,7 @@ int slab_batch_free(slab_batch bt) {
   (void)hipSetDevice(bt->device);
   (void)hipDeviceSynchronize();
   for (GraphCache& g : bt->graphs) g.clear(bt->mem);
+  bt->run.clear(bt->mem);
   for (slab_handle h : bt->items) delete_handle(h);
   bt->mem.release_all();
   delete bt;
@@ -1226,7 +1417,7 @@ int solve_batch(slab_batch bt, const double* const* f, double* const* u, const i
   }
   SLAB_HIP_CHECK(hipSetDevice(bt->device));
   hipStream_t st = (hipStream_t)hip_stream;
-  if (!(bt->flags & SLAB_GRAPH)) return solve_group(jobs, bt->precision, trans, st, bt->mem, nullptr);
+  if (!(bt->flags & SLAB_GRAPH)) return solve_group(jobs, bt->precision, trans, st, bt->mem);
   // stream capture needs a stream other than the legacy default stream
   // (work queued on the default stream, e.g. the inputs, is finished first)
   hipStream_t cs = st;
@@ -1234,7 +1425,7 @@ int solve_batch(slab_batch bt, const double* const* f, double* const* u, const i
     SLAB_HIP_CHECK(hipStreamSynchronize(st));
     SLAB_HIP_CHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
   }
-  const int rc = solve_group(jobs, bt->precision, trans, cs, bt->mem, bt->graphs + (trans ? 2 : 0));
+  const int rc = solve_batch_graph(bt, jobs, trans, cs);
   if (!st) {
     (void)hipStreamSynchronize(cs);
     (void)hipStreamDestroy(cs);
@@ -1255,6 +1446,75 @@ int slab_solve_adjoint_batch(slab_batch bt, const double* const* g, double* cons
                              const int32_t* nrhs, const int64_t* ld, void* hip_stream,
                              slab_solve_info* infos) {
   return solve_batch(bt, g, lam, nrhs, ld, hip_stream, infos, true);
+}
+
+int slab_batch_run(slab_batch bt, const double* const* kappa, const double* const* f,
+                   double* const* u, const int32_t* nrhs, const int64_t* ld, void* hip_stream,
+                   slab_solve_info* infos) {
+  if (!bt || !kappa || !f || !u || !nrhs || !ld) { set_error("null argument"); return SLAB_E_INVALID; }
+  std::vector<SolveJob> jobs;
+  std::vector<const double*> coefs;
+  for (size_t i = 0; i < bt->items.size(); ++i) {
+    const int rc = check_vec_args(bt->items[i], f[i], u[i], nrhs[i], ld[i]);
+    if (rc || !kappa[i]) {
+      set_error("problem " + std::to_string(i) + ": " +
+                (rc ? g_last_error : std::string("null coefficient pointer")));
+      return SLAB_E_INVALID;
+    }
+    if (infos) { infos[i].iterations = 0; infos[i].max_relres = 0.0; infos[i].failed_block = -1; }
+    jobs.push_back({bt->items[i], f[i], u[i], nrhs[i], (long long)ld[i],
+                    infos ? &infos[i] : nullptr});
+    coefs.push_back(kappa[i]);
+  }
+  SLAB_HIP_CHECK(hipSetDevice(bt->device));
+  hipStream_t st = (hipStream_t)hip_stream;
+  // stream capture needs a stream other than the legacy default stream
+  hipStream_t cs = st;
+  if (!cs) {
+    SLAB_HIP_CHECK(hipStreamSynchronize(st));
+    SLAB_HIP_CHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  }
+  auto body = [&]() -> int {
+    {
+      std::vector<std::pair<slab_handle, int>> need;
+      for (SolveJob& j : jobs) need.push_back({j.h, j.nrhs});
+      SLAB_TRY(ensure_workspaces(need, bt->mem));
+    }
+    ConvPtrs c;
+    SLAB_TRY(batch_conv(bt, &c));
+    std::vector<long long> key = jobs_key(jobs, 2);
+    for (const double* k : coefs) key.push_back((long long)(uintptr_t)k);
+    auto build = [&](Plan& p) {
+      SLAB_TRY(plan_factor_nosync_dispatch(bt->precision, p, bt->items, coefs, bt->mem,
+                                           &bt->run_temps, &bt->run_temps_cap));
+      plan_all_passes(p, jobs, bt->precision, false, c, true);
+      for (const SolveJob& j : jobs) count_launches(j.h, p);
+      return SLAB_OK;
+    };
+    SLAB_TRY(launch_graph(bt->mem, &bt->run, key, build, cs));
+    std::vector<int> it, fstat;
+    std::vector<double> worst;
+    SLAB_TRY(read_conv(bt, cs, it, worst, &fstat));
+    // an invalid field first (the factorization of such a field breaks down too)
+    for (size_t i = 0; i < jobs.size(); ++i) {
+      if (fstat[4 * i + 2] == 0) continue;
+      set_error("problem " + std::to_string(i) + ": " + fail_message(1, -1));
+      return SLAB_E_INVALID;
+    }
+    for (size_t i = 0; i < jobs.size(); ++i) {
+      if (fstat[4 * i] == 0) continue;
+      if (infos) infos[i].failed_block = fstat[4 * i + 1];
+      set_error("problem " + std::to_string(i) + ": " + fail_message(fstat[4 * i], fstat[4 * i + 1]));
+      return SLAB_E_BREAKDOWN;
+    }
+    return finish_jobs(jobs, it, worst);
+  };
+  const int rc = body();
+  if (!st) {
+    (void)hipStreamSynchronize(cs);
+    (void)hipStreamDestroy(cs);
+  }
+  return rc;
 }
 
 int slab_kappa_grad_batch(slab_batch bt, const double* const* u, const double* const* lam,

@@ -42,6 +42,14 @@ __device__ __forceinline__ int xcd_linear(int bx, int G) {
   return bx < (per << 3) ? (bx & 7) * per + (bx >> 3) : bx;
 }
 
+// Refinement passes issued ahead of their convergence test (a graph of a fixed
+// number of passes) carry a per-problem flag: once a problem's residual has
+// met its tolerance (k_converge writes 0), every workgroup of its later
+// passes returns at once.  A null flag means the work always runs.
+__device__ __forceinline__ bool item_done(const int* live) {
+  return live != nullptr && *live == 0;
+}
+
 // ---- descriptors ----------------------------------------------------------------
 
 // One problem of stage one (edge weights, slab factors, Schur pieces, assembly).
@@ -97,6 +105,7 @@ struct BmvItem {
   // scratch for a product split over k (BMV_SPLIT_MAX partial results of
   // 16*ceil(nrhs/16) columns of n), or null: the product is not split
   void* part;
+  const int* live;  // refinement flag of the problem (see item_done), or null
 };
 
 // Most k-splits of a small block-vector launch; scratch per item in elements.
@@ -133,6 +142,20 @@ struct SolveDev {
   // values in); null when the reduced system is solved in one go
   double* g64;
   const double* uo64;
+  const int* live;  // refinement flag of the problem (see item_done), or null
+};
+
+// Convergence test of one problem after a refinement pass (k_converge).
+struct ConvDev {
+  const double* norms;  // per column: sum r^2, sum f^2
+  int nrhs;
+  int max_iter;
+  double tol;
+  int* live;      // out: 1 while another pass is needed
+  int* iters;     // passes done
+  double* relres; // max over columns of ||r|| / ||f|| after the last pass
+  const int* fstatus;  // optional: the problem's four factorization status
+  int* fstatus_out;    // words, copied beside the counts on the first pass
 };
 
 // Reduced system of one problem in a solve pass (block factors from stage two
@@ -154,6 +177,7 @@ struct ReducedDev {
   double* g64;
   double* u64;
   double* r64;
+  const int* live;  // refinement flag of the problem (see item_done), or null
 };
 
 // Stage two of one problem (see plan_stage2).

@@ -901,6 +901,7 @@ __global__ __launch_bounds__(256) void k_bmv(const BmvItem* __restrict__ items,
   __shared__ __attribute__((aligned(16))) T As[2][AS0][AS1];
   __shared__ T Bs[2][TK][16 + 4];
   const int itm = group_item(offs, count, blockIdx.x);
+  if (item_done(items[itm].live)) return;
   const int bx = blockIdx.x - offs[itm];
   const int n = items[itm].n, nrhs = items[itm].nrhs;
   const int nrt = (n + TM - 1) / TM, ncg = (nrhs + 15) / 16;
@@ -1058,6 +1059,7 @@ template <typename T>
 __global__ void k_bmv_sum(const BmvItem* __restrict__ items, const int* __restrict__ offs,
                           int count, T beta, int nsplit) {
   const int itm = group_item(offs, count, blockIdx.x);
+  if (item_done(items[itm].live)) return;
   const long long nwg = offs[itm + 1] - offs[itm];
   const int n = items[itm].n, nrhs = items[itm].nrhs, ncg = (nrhs + 15) / 16;
   const g_t<const T>* __restrict__ part = gp((const T*)items[itm].part);

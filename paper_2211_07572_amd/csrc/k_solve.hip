@@ -38,6 +38,7 @@ __global__ __launch_bounds__(256) void k_sweep(const SolveDev* __restrict__ P,
   __shared__ T Gs[2][BP][BP + 1];
   __shared__ T Vs[2][NC][BP + 1];
   const int itm = group_item(offs, count, blockIdx.x);
+  if (item_done(P[itm].live)) return;
   const int bx = blockIdx.x - offs[itm];
   const int m = P[itm].m;
   const int s = bx % m;
@@ -253,6 +254,7 @@ __global__ __launch_bounds__(256) void k_sweep(const SolveDev* __restrict__ P,
   const int itm = group_item(offs, count, blockIdx.x);                                \
   const long long nwg_ = offs[itm + 1] - offs[itm];                                   \
   const SolveDev& d = P[itm];                                                         \
+  if (item_done(d.live)) return;                                                      \
   const int n2 = d.n2, b = d.b, m = d.m, nrhs = d.nrhs;                               \
   const long long tot = (long long)m * nrhs * n2;                                     \
   for (long long e = (blockIdx.x - offs[itm]) * (long long)blockDim.x + threadIdx.x; \
@@ -323,10 +325,13 @@ static void plan_reduced(Plan& plan, const std::vector<ReducedDev>& R, bool odd_
   auto at = [](const void* base, long long j, long long stride) {
     return (void*)((TR*)base + j * stride);
   };
-  auto item = [](const void* M, const void* x, const void* xin, void* y, int n, int nrhs,
-                 void* part = nullptr) {
+  // every product of a problem carries its refinement flag
+  const int* live_flag = nullptr;
+  auto item = [&live_flag](const void* M, const void* x, const void* xin, void* y, int n,
+                           int nrhs, void* part = nullptr) {
     BmvItem b;
     b.M = M; b.x = x; b.xin = xin; b.y = y; b.n = n; b.nrhs = nrhs; b.part = part;
+    b.live = live_flag;
     return b;
   };
   // scratch slot s of a problem for a product split over k (see plan_gemv)
@@ -343,6 +348,7 @@ static void plan_reduced(Plan& plan, const std::vector<ReducedDev>& R, bool odd_
       std::vector<BmvItem> a, bb;
       for (const ReducedDev& r : R) {
         if (j >= r.m) continue;
+        live_flag = r.live;
         const long long nsq = (long long)r.n * r.n, vs = (long long)r.nrhs * r.n;
         const void* src = at(r.ft, j, vs);
         if (j > 0) {
@@ -360,6 +366,7 @@ static void plan_reduced(Plan& plan, const std::vector<ReducedDev>& R, bool odd_
       std::vector<BmvItem> a, bb;
       for (const ReducedDev& r : R) {
         if (j >= r.m) continue;
+        live_flag = r.live;
         const long long nsq = (long long)r.n * r.n, vs = (long long)r.nrhs * r.n;
         const void* src = at(r.yt, j, vs);
         if (j < r.m - 1) {
@@ -388,6 +395,7 @@ static void plan_reduced(Plan& plan, const std::vector<ReducedDev>& R, bool odd_
       for (const ReducedDev& r : R) {
         const int k = (int)(r.m / s);
         if (k < 1) continue;
+        live_flag = r.live;
         const int E = (k + 1) / 2, NR = k / 2;
         const long long nsq = (long long)r.n * r.n, vs = (long long)r.nrhs * r.n;
         for (int q = 0; q < E; ++q) {
@@ -460,6 +468,7 @@ __global__ void k_red_step(const ReducedDev* __restrict__ R, const int* __restri
   const int itm = group_item(offs, count, blockIdx.x);
   const long long nwg = offs[itm + 1] - offs[itm];
   const ReducedDev& d = R[itm];
+  if (item_done(d.live)) return;
   const long long tot = (long long)d.m * d.nrhs * d.n;
   g_t<TR>* __restrict__ ft = gp((TR*)d.ft);
   g_t<double>* __restrict__ u64 = gp(d.u64);
@@ -497,9 +506,12 @@ static void plan_reduced_refined(Plan& plan, const std::vector<ReducedDev>& R, b
       return SLAB_OK;
     });
   };
-  auto item = [](const void* M, const void* x, const void* xin, void* y, int n, int nrhs) {
+  const int* live_flag = nullptr;
+  auto item = [&live_flag](const void* M, const void* x, const void* xin, void* y, int n,
+                           int nrhs) {
     BmvItem b;
     b.M = M; b.x = x; b.xin = xin; b.y = y; b.n = n; b.nrhs = nrhs; b.part = nullptr;
+    b.live = live_flag;
     return b;
   };
   plan_reduced<TR>(plan, R, odd_even);
@@ -509,6 +521,7 @@ static void plan_reduced_refined(Plan& plan, const std::vector<ReducedDev>& R, b
     std::vector<BmvItem> dg, up, lo;
     for (const ReducedDev& r : R) {
       const long long nsq = (long long)r.n * r.n, vs = (long long)r.nrhs * r.n;
+      live_flag = r.live;
       for (int j = 0; j < r.m; ++j) {
         dg.push_back(item(r.T64 + j * nsq, r.u64 + j * vs, r.g64 + j * vs, r.r64 + j * vs, r.n,
                           r.nrhs));
@@ -611,6 +624,7 @@ __global__ __launch_bounds__(256) void k_residual(const SolveDev* __restrict__ P
                                                   const int* __restrict__ offs, int count) {
   __shared__ double red[2][256];
   const int itm = group_item(offs, count, blockIdx.x);
+  if (item_done(P[itm].live)) return;
   const int bx = blockIdx.x - offs[itm];
   const int n1 = P[itm].n1, n2 = P[itm].n2;
   const int chunks = res_chunks(n1, n2);
@@ -660,7 +674,7 @@ __global__ void k_norms(const SolveDev* __restrict__ P, const int* __restrict__ 
   const int itm = group_item(offs, count, blockIdx.x);
   const int c = (blockIdx.x - offs[itm]) * blockDim.x + threadIdx.x;
   const int nrhs = P[itm].nrhs;
-  if (c >= nrhs) return;
+  if (c >= nrhs || item_done(P[itm].live)) return;
   const int chunks = res_chunks(P[itm].n1, P[itm].n2);
   const g_t<const double>* __restrict__ partial = gp((const double*)P[itm].partial);
   double sr = 0.0, sf = 0.0;
@@ -691,6 +705,52 @@ void plan_residual(Plan& plan, const std::vector<SolveDev>& probs) {
     SLAB_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_norms, dim3((unsigned)t2), dim3(64), 0, st, dev_at<SolveDev>(dev, pd),
                        dev_at<int>(dev, o2), count);
+    SLAB_LAUNCH_CHECK();
+    return SLAB_OK;
+  });
+}
+
+// ---------------------------------------------------------------------------
+// Convergence test on the device, for passes issued without a host
+// synchronization in between: after the residual norms of a pass, the pass
+// count and the max-over-columns relative residual of every live problem are
+// updated, and the problem stays live while relres > tol and passes remain
+// (a non-finite residual stops it, like the host test).  One thread per
+// problem.
+// ---------------------------------------------------------------------------
+__global__ void k_converge(const ConvDev* __restrict__ C, int count, int first) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const ConvDev& c = C[i];
+  if (first) {
+    *c.iters = 0;
+    if (c.fstatus)
+      for (int k = 0; k < 4; ++k) c.fstatus_out[k] = c.fstatus[k];
+  } else if (*c.live == 0) {
+    return;
+  }
+  double worst = 0.0;
+  bool finite = true;
+  for (int k = 0; k < c.nrhs; ++k) {
+    const double rn = sqrt(c.norms[2 * k]), fn = sqrt(c.norms[2 * k + 1]);
+    const double v = fn > 0.0 ? rn / fn : rn;
+    if (!isfinite(v)) finite = false;
+    else worst = fmax(worst, v);
+  }
+  if (!finite) worst = NAN;
+  const int it = *c.iters + 1;
+  *c.iters = it;
+  *c.relres = worst;
+  *c.live = (worst > c.tol && it < c.max_iter) ? 1 : 0;
+}
+
+void plan_converge(Plan& plan, const std::vector<ConvDev>& conv, bool first) {
+  if (conv.empty()) return;
+  const size_t pc = plan.add_vec(conv);
+  const int count = (int)conv.size();
+  plan.step([=](const char* dev, hipStream_t st) {
+    hipLaunchKernelGGL(k_converge, dim3((unsigned)((count + 63) / 64)), dim3(64), 0, st,
+                       dev_at<ConvDev>(dev, pc), count, first ? 1 : 0);
     SLAB_LAUNCH_CHECK();
     return SLAB_OK;
   });

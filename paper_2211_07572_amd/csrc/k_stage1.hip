@@ -8,9 +8,17 @@
 
 namespace slab {
 
+// The four status words of every problem cleared (a kernel rather than a
+// memset, so that a captured graph holds no memset node).
+__global__ void k_status_clear(const ProbDev* __restrict__ P, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < 4 * count) gp(P[i >> 2].status)[i & 3] = 0;
+}
+
 // ---------------------------------------------------------------------------
 // Coefficient field: copy (or exponentiate theta) and check positivity.
-// status[0] is set to 1 when some kappa is not > 0 or not finite.
+// status[2] is set to 1 when some kappa is not > 0 or not finite (status[0..1]
+// record a breakdown of the factorization).
 // Grouped: each problem owns a fixed number of workgroups and strides over
 // its (n1+2)(n2+2) nodes with them.
 // ---------------------------------------------------------------------------
@@ -29,7 +37,7 @@ __global__ void k_coef(const ProbDev* __restrict__ P, const int* __restrict__ of
     if (!(k > 0.0) || !isfinite(k)) bad = true;
     kappa[i] = k;
   }
-  if (bad) gp(d.status)[0] = 1;
+  if (bad) gp(d.status)[2] = 1;
 }
 
 // Edge weights w = (kappa_p + kappa_q) / (2 h^2) of the 5-point stencil.
@@ -669,6 +677,9 @@ void plan_coef_weights(Plan& plan, const std::vector<ProbDev>& probs) {
   const size_t oc = plan.add_offsets(cc, &tc), ow = plan.add_offsets(cw, &tw);
   const int count = (int)probs.size();
   plan.step([=](const char* dev, hipStream_t st) {
+    hipLaunchKernelGGL(k_status_clear, dim3((unsigned)((4 * count + 255) / 256)), dim3(256), 0,
+                       st, dev_at<ProbDev>(dev, pd), count);
+    SLAB_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_coef, dim3((unsigned)tc), dim3(256), 0, st, dev_at<ProbDev>(dev, pd),
                        dev_at<int>(dev, oc), count);
     SLAB_LAUNCH_CHECK();

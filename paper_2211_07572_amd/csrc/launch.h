@@ -17,7 +17,8 @@ namespace slab {
 constexpr int REDUCED_REFINE_STEPS = 3;
 
 // ---- stage one --------------------------------------------------------------
-// Coefficient copy (or exp of theta) with positivity check, then edge weights.
+// Status words cleared, coefficient copy (or exp of theta) with positivity
+// check, then edge weights.
 void plan_coef_weights(Plan& plan, const std::vector<ProbDev>& probs);
 // Slab factors, boundary columns, Schur propagation and assembly of T for a
 // group of problems (one launch per phase and padded block order).  T: slab
@@ -75,6 +76,9 @@ void plan_solve_pass(Plan& plan, const std::vector<SolveDev>& probs,
 // r = f - A u and per-column sums of r^2 and f^2 (FP64) for every problem.
 void plan_residual(Plan& plan, const std::vector<SolveDev>& probs);
 size_t residual_partial_count(int n1, int n2, int nrhs);
+// Device-side convergence test of every problem after a pass (see ConvDev);
+// first: the first pass (resets the pass counts).
+void plan_converge(Plan& plan, const std::vector<ConvDev>& conv, bool first);
 
 int launch_kappa_grad(int n1, int n2, int nrhs, long long ld, double h, const double* kappa,
                       const double* u, const double* lam, int mode, double* grad, hipStream_t st);

@@ -100,6 +100,9 @@ def load_library(path: str = LIB_PATH):
     L.slab_kappa_grad_batch.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                         ctypes.POINTER(i32), ctypes.POINTER(i64), i32,
                                         ctypes.POINTER(vp), vp]
+    L.slab_batch_run.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                 ctypes.POINTER(i32), ctypes.POINTER(i64), vp,
+                                 ctypes.POINTER(slab_solve_info)]
     L.slab_batch_handle.argtypes = [vp, i32, ctypes.POINTER(vp)]
     L.slab_batch_query.argtypes = [vp, i32, ctypes.POINTER(i64)]
     L.slab_batch_free.argtypes = [vp]
@@ -529,6 +532,28 @@ def slab_solve_adjoint_batch(batch: SlabBatch, gs, outs=None, stream=None, check
     """lambda_i = A_i^-T g_i for every problem of the batch (stored factors
     applied transposed).  Returns the list of lambda_i."""
     return _solve_batch(load_library().slab_solve_adjoint_batch, batch, gs, outs, stream, check)
+
+
+def slab_batch_run(batch: SlabBatch, kappas, fs, outs=None, stream=None, check=True):
+    """Factor every problem again from kappas[i] (CUDA float64, shape
+    (n1_i+2, n2_i+2)) and solve fs[i], as one HIP graph launch (captured on
+    the first call, replayed while the tensors are the same).  Returns the
+    list of solutions."""
+    cnt = len(batch)
+    if len(kappas) != cnt:
+        raise ValueError("one coefficient field per problem")
+    for i, k in enumerate(kappas):
+        n2, n1 = batch.dims[i][0], batch.dims[i][1]
+        if tuple(k.shape) != (n1 + 2, n2 + 2):
+            raise ValueError(f"kappa {i} must have shape {(n1 + 2, n2 + 2)}")
+    kp = (ctypes.c_void_p * cnt)(*[_dev_f64(k, f"kappa[{i}]").value for i, k in enumerate(kappas)])
+    _, us, fp, up, nr, ld = _batch_vectors(batch, fs, outs)
+    infos = (slab_solve_info * cnt)()
+    rc = load_library().slab_batch_run(batch.ptr, kp, fp, up, nr, ld, _stream_ptr(stream), infos)
+    batch.last_infos = list(infos)
+    if check:
+        _check(rc)
+    return [u.view(f.shape) if f.dim() == 2 else u for u, f in zip(us, fs)]
 
 
 def slab_kappa_grad_batch(batch: SlabBatch, us, lams, mode: int = 1, stream=None):
