@@ -58,8 +58,6 @@ def parse():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-extra", action="store_true",
                     help="skip the 1024x1024 and 512x512 lines")
-    ap.add_argument("--cpu-c2", action="store_true",
-                    help="also time the whole 1024x1024 job (1 RHS) on the FP64 oracle")
     ap.add_argument("--cpu-slabs", type=int, default=1)
     return ap.parse_args()
 
@@ -292,16 +290,33 @@ def run_gpu(w: G.Workload, precision: int, steps: int, warmup: int, kappa, f, od
 
 
 def host_cpu() -> dict:
-    """CPU model and logical core count of the host (from /proc/cpuinfo)."""
-    model = "unknown"
+    """CPU model, logical CPUs and cores of the host (lscpu, else /proc/cpuinfo)."""
+    info = {"model": "unknown", "logical_cpus": os.cpu_count()}
     try:
-        for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                model = line.split(":", 1)[1].strip()
-                break
-    except OSError:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            k, v = k.strip(), v.strip()
+            if k == "Model name":
+                info["model"] = v
+            elif k == "Socket(s)":
+                info["sockets"] = int(v)
+            elif k == "Core(s) per socket":
+                info["cores_per_socket"] = int(v)
+            elif k == "Thread(s) per core":
+                info["threads_per_core"] = int(v)
+    except (OSError, ValueError, subprocess.SubprocessError):
         pass
-    return {"model": model, "logical_cpus": os.cpu_count()}
+    if info["model"] == "unknown":
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.startswith("model name"):
+                    info["model"] = line.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            pass
+    return info
 
 
 def host_relres(w: G.Workload, kappa_np, f_np, u) -> float:
@@ -367,25 +382,34 @@ def cpu_baseline(w: G.Workload, kappa_np: np.ndarray, f_np: np.ndarray, slabs: i
             "host_cpu": host_cpu()}
 
 
-def cpu_oracle_c2() -> dict:
-    """The whole 1024x1024 job (factor + 1-RHS solve) on the FP64 oracle,
+def cpu_oracle_whole(w: G.Workload, workers: int, one_core: bool = False) -> dict:
+    """The whole job of workload w (factor + 1-RHS solve) on the FP64 oracle,
     measured: stage one with its independent slabs spread over a process pool
-    of one worker per core, stage two (Alg. 1, LAPACK) and the solve (Alg. 4)
-    in this process."""
+    of `workers` processes (one BLAS thread each), stage two (Alg. 1, LAPACK)
+    and the solve (Alg. 4) in this process; one_core: everything on one
+    thread (one BLAS thread, no pool)."""
     from oracle import slab_oracle as O
-    w = G.DIFFUSION_1024
-    workers = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     prob = O.make_problem(w.kappa(), w.n2, w.n1, w.b, w.h)
     f = w.rhs(1)
-    t0 = time.perf_counter()
-    fac = O.factor(prob, workers=workers)
-    t1 = time.perf_counter()
-    u = O.solve(fac, f)
-    t2 = time.perf_counter()
-    return {"value": w.N / (t2 - t0), "unit": "DOF/s", "cores": workers, "kind": "oracle",
-            "sample": "the whole 1024x1024 b=31 job, 1 RHS, measured (not extrapolated)",
+
+    def run():
+        t0 = time.perf_counter()
+        fac = O.factor(prob, workers=workers)
+        t1 = time.perf_counter()
+        u = O.solve(fac, f)
+        t2 = time.perf_counter()
+        return t0, t1, t2, u
+    if one_core:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(1):
+            t0, t1, t2, u = run()
+    else:
+        t0, t1, t2, u = run()
+    return {"value": w.N / (t2 - t0), "unit": "DOF/s", "kind": "oracle",
+            "cores": 1 if one_core else workers,
+            "sample": f"the whole {w.name} job, 1 RHS, measured (not extrapolated)",
             "factor_s": t1 - t0, "solve_s": t2 - t1,
-            "relres": float(O.relres(prob, u, f).max()), "host_cpu": host_cpu()}
+            "relres": float(O.relres(prob, u, f).max())}
 
 
 def extra_workloads(warmup: int, steps: int) -> dict:
@@ -562,8 +586,14 @@ def main():
     if not args.skip_cpu:
         log("cpu baseline")
         result["cpu_baseline"] = cpu_baseline(w, kappa_np, f_np, args.cpu_slabs)
-    if args.cpu_c2:
-        result["cpu_oracle_1024x1024"] = cpu_oracle_c2()
+        workers = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        log("oracle: whole 64x64 job (1 core, all cores) and whole 1024x1024 job")
+        result["cpu_oracle_whole_jobs"] = {
+            "host_cpu": host_cpu(),
+            "poisson_64x64_b7_1core": cpu_oracle_whole(G.POISSON_64, 1, one_core=True),
+            f"poisson_64x64_b7_{workers}workers": cpu_oracle_whole(G.POISSON_64, workers),
+            f"diffusion_1024x1024_b31_{workers}workers": cpu_oracle_whole(G.DIFFUSION_1024, workers),
+        }
     print(json.dumps(result))
 
 

@@ -293,6 +293,14 @@ _POOL_STATE = {}
 
 
 def _pool_init(prob: Problem, transpose: bool):
+    # one BLAS thread per worker process: the workers already fill the cores
+    # (multithreaded BLAS pools in every worker oversubscribe them and have
+    # stalled the pool)
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except ImportError:
+        pass
     _POOL_STATE["prob"], _POOL_STATE["transpose"] = prob, transpose
 
 
