@@ -391,8 +391,32 @@ int ensure_workspace(slab_handle h, int nrhs) {
 // ---------------------------------------------------------------------------
 struct FactorTemps {
   void *Hsw = nullptr, *sig = nullptr, *PRR = nullptr, *PLL = nullptr, *PLR = nullptr,
-       *PRL = nullptr, *Td = nullptr, *To = nullptr;
+       *PRL = nullptr, *Td = nullptr, *To = nullptr, *fchk = nullptr;
+  int* fredo = nullptr;
 };
+
+// Segments of the slab recursion's chains (k_slab_factor): chains of n2 row
+// steps are cut into segments of about `seg` = 512 steps once there are at
+// least two (at 2048 x 4096, b = 31: 9.7 ms unsegmented, 8.1 ms with 512,
+// 10.2 ms with 256, 14.5 ms with 128: the redundant warm-up work, not the
+// chain, bounds the shorter segments),
+// each segment after the first warming up over `warm` = 7 (b+1) steps (the
+// influence of the start shrinks by about exp(-2 pi/(b+1)) per step, so by
+// ~1e-19 over the warm-up).  The environment variables SLAB_FACTOR_SEG
+// (segment length, 0: no segments) and SLAB_FACTOR_WARM (warm-up steps)
+// override both, for measurements and tests.
+void slab_segments(int n2, int b, int* nseg, int* seg, int* warm) {
+  const char* es = getenv("SLAB_FACTOR_SEG");
+  const char* ew = getenv("SLAB_FACTOR_WARM");
+  const int seg_len = es ? atoi(es) : 512;
+  *warm = ew ? std::max(1, atoi(ew)) : 7 * (b + 1);
+  *seg = seg_len > 0 ? seg_len : n2;
+  *nseg = seg_len > 0 ? std::max(1, n2 / seg_len) : 1;
+  if (*nseg < 2) {
+    *nseg = 1;
+    *seg = n2;
+  }
+}
 
 // Memory a handle keeps after the factorization.
 template <typename T, typename TR>
@@ -425,6 +449,10 @@ void temp_layout(slab_handle h, FactorTemps& t, Layout& L) {
   const size_t nsq = n * n;
   L.add(&t.Hsw, m * n * BP * BP * e);
   L.add(&t.sig, m * n * 2 * BP * e);
+  int nseg, seg, warm;
+  slab_segments(h->n2, h->b, &nseg, &seg, &warm);
+  L.add(&t.fchk, nseg > 1 ? m * 2 * nseg * BP * BP * e : 0);
+  L.add(&t.fredo, m * 2 * sizeof(int));
   L.add(&t.PRR, m * nsq * e);
   L.add(&t.PLL, m * nsq * e);
   L.add(&t.PLR, m * nsq * e);
@@ -446,6 +474,7 @@ std::vector<ProbDev> prob_descs(const std::vector<slab_handle>& hs,
     d.is_log = (h->flags & SLAB_COEF_LOG) ? 1 : 0;
     d.coef = coefs[i]; d.kappa = h->kappa; d.wh = h->wh; d.wv = h->wv;
     d.Gl = h->Gl; d.T64 = h->T64; d.O64 = h->O64; d.status = h->status;
+    slab_segments(h->n2, h->b, &d.fnseg, &d.fseg, &d.fwarm);
   }
   return pd;
 }
@@ -496,7 +525,7 @@ void plan_chunk(Plan& p, const std::vector<slab_handle>& hs, const std::vector<P
     if (hs[i]->odd_even) t.Td = hs[i]->Td;
     ProbDev d = pd[i];
     d.Hsw = t.Hsw; d.sig = t.sig; d.PRR = t.PRR; d.PLL = t.PLL; d.PLR = t.PLR; d.PRL = t.PRL;
-    d.Td = t.Td; d.To = t.To;
+    d.Td = t.Td; d.To = t.To; d.fchk = t.fchk; d.fredo = t.fredo;
     cd.push_back(d);
     Stage2Prob q;
     q.n = hs[i]->n2; q.m = hs[i]->m; q.Td = t.Td; q.To = t.To; q.Linv = hs[i]->Linv;

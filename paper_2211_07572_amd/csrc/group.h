@@ -73,6 +73,15 @@ struct ProbDev {
   double* T64;         // optional FP64 copies
   double* O64;
   int* status;
+  // segmented slab recursion (k_slab_factor): the n2 row steps of a chain are
+  // cut into fnseg segments of fseg steps; a segment after the first starts
+  // fwarm steps early from a zero inverse and stores only its own rows, plus
+  // its warm-up's last block into fchk ([slab][dir][segment][BP][BP]) for the
+  // check against the previous segment; fredo[slab*2+dir] = 1 marks a chain
+  // whose warm-up did not converge (recomputed in one piece)
+  int fnseg, fseg, fwarm;
+  void* fchk;
+  int* fredo;
 };
 
 // One pivot block of the block factorization.

@@ -149,6 +149,19 @@ __device__ __forceinline__ void build_D_row(T (&a)[BP], const g_t<const double>*
 // pivot rows).  Every thread loads the edge weights of its own row and columns
 // one row step ahead, so no load latency sits on the row-to-row chain.
 // ---------------------------------------------------------------------------
+//
+// Segments.  The recursion forgets where it started: a change of Gl_{r-1}
+// reaches Gl_r through Gl_r W_r (.) W_r Gl_r, which shrinks it by about
+// exp(-2 pi / (b+1)) per row for this operator (the decay of the slowest
+// mode across a strip of b+1 columns).  So the n2 row steps of a chain are
+// cut into segments that run in parallel: a segment after the first starts
+// fwarm steps before its first row from a zero inverse (the recursion of a
+// slab cut off there), and stores only its own rows.  Its warm-up's last
+// block goes to fchk; k_factor_check compares it with the block the previous
+// segment stored for that row, and a chain whose warm-up has not converged
+// there is recomputed in one piece by the redo launch (redo = 1: one
+// workgroup per chain, only for marked chains).
+// ---------------------------------------------------------------------------
 #ifndef SLAB_FACTOR_THREADS
 #define SLAB_FACTOR_THREADS 256
 #endif
@@ -157,7 +170,8 @@ __device__ __forceinline__ void build_D_row(T (&a)[BP], const g_t<const double>*
 #endif
 template <typename T, int BP, int NT = SLAB_FACTOR_THREADS, int PB = SLAB_FACTOR_PB>
 __global__ __launch_bounds__(NT) void k_slab_factor(const ProbDev* __restrict__ P,
-                                                    const int* __restrict__ offs, int count) {
+                                                    const int* __restrict__ offs, int count,
+                                                    int redo) {
   constexpr int R = NT / BP;   // lanes per row
   constexpr int C = BP / R;    // columns per lane
   constexpr int D = 1;         // weight prefetch depth (row steps): one row step
@@ -170,7 +184,18 @@ __global__ __launch_bounds__(NT) void k_slab_factor(const ProbDev* __restrict__ 
   g_t<T>* __restrict__ Gl = gp((T*)P[it].Gl);
   g_t<T>* __restrict__ Hsw = gp((T*)P[it].Hsw);
   g_t<int>* __restrict__ status = gp(P[it].status);
-  const int s = bx >> 1, dir = bx & 1;
+  const int nseg = redo ? 1 : P[it].fnseg;
+  const int seg = bx % nseg, sd = bx / nseg;
+  const int s = sd >> 1, dir = sd & 1;
+  g_t<int>* __restrict__ fredo = gp(P[it].fredo);
+  if (redo && fredo[sd] == 0) return;   // uniform: this chain's segments agreed
+  if (!redo && seg == 0 && threadIdx.x == 0) fredo[sd] = 0;
+  // steps [t_lo, t_hi) are stored; the chain starts at t_start
+  const int t_lo = seg * P[it].fseg;
+  const int t_hi = seg == nseg - 1 ? n2 : t_lo + P[it].fseg;
+  const int t_start = seg == 0 ? 0 : max(0, t_lo - P[it].fwarm);
+  g_t<T>* __restrict__ fchk =
+      seg > 0 ? gp((T*)P[it].fchk) + ((size_t)sd * nseg + seg) * BP * BP : nullptr;
   const int lane = threadIdx.x;
   const int i = lane % BP, q = lane / BP;
   const int k0 = q * C;                    // first column of this lane
@@ -204,13 +229,13 @@ __global__ __launch_bounds__(NT) void k_slab_factor(const ProbDev* __restrict__ 
     }
   };
 #pragma unroll
-  for (int d = 0; d < D; ++d) load(d, d);
+  for (int d = 0; d < D; ++d) load(d, t_start + d);
   bool ok = true;
-  for (int t0 = 0; t0 < n2; t0 += D) {
+  for (int t0 = t_start; t0 < t_hi; t0 += D) {
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       const int t = t0 + d;
-      if (t < n2) {  // uniform
+      if (t < t_hi) {  // uniform
         const int r = dir == 0 ? t : n2 - 1 - t;
         const double whl = rl[d], whr = rr[d], wvd = rd[d], wvu = ru[d];
         // W of the coupling to the previous row step and W_r, at this lane's columns
@@ -322,19 +347,65 @@ __global__ __launch_bounds__(NT) void k_slab_factor(const ProbDev* __restrict__ 
         }
 #pragma unroll
         for (int j = 0; j < C; ++j) g[j] = -a[j];
-        if (dir == 0) {
-          g_t<T>* dst = Gl + (((size_t)s * n2 + r) * BP + i) * BP + k0;
+        // own rows go to Gl / Hsw; the warm-up's last row to the check block
+        if (t >= t_lo || t == t_lo - 1) {  // uniform
+          const bool own = t >= t_lo;
+          if (dir == 0) {
+            g_t<T>* dst = own ? Gl + (((size_t)s * n2 + r) * BP + i) * BP + k0
+                              : fchk + (size_t)i * BP + k0;
 #pragma unroll
-          for (int j = 0; j < C; ++j) dst[j] = g[j];
-        } else {
-          g_t<T>* dst = Hsw + ((size_t)s * n2 + r) * BP * BP;
+            for (int j = 0; j < C; ++j) dst[j] = g[j];
+          } else {
+            g_t<T>* dst = own ? Hsw + ((size_t)s * n2 + r) * BP * BP : fchk;
 #pragma unroll
-          for (int j = 0; j < C; ++j) dst[swz_index<T>(i, k0 + j, BP)] = g[j] * wup[j];
+            for (int j = 0; j < C; ++j) dst[swz_index<T>(i, k0 + j, BP)] = g[j] * wup[j];
+          }
         }
       }
     }
   }
   if (!ok && lane == 0) { status[0] = 2; status[1] = s; }
+}
+
+// Warm-up check of the segmented slab recursion: for every segment after the
+// first, the block its warm-up reached at the row before its first one is
+// compared with the block the previous segment stored for that row; a
+// relative difference above tol (or a non-finite one) marks the chain for the
+// redo launch.  One workgroup per (slab, direction, segment > 0).
+template <typename T, int BP>
+__global__ __launch_bounds__(256) void k_factor_check(const ProbDev* __restrict__ P,
+                                                      const int* __restrict__ offs, int count,
+                                                      double tol) {
+  __shared__ double red[2][256];
+  const int it = group_item(offs, count, blockIdx.x);
+  const int bx = blockIdx.x - offs[it];
+  const int nseg = P[it].fnseg, n2 = P[it].n2;
+  const int seg = 1 + bx % (nseg - 1), sd = bx / (nseg - 1);
+  const int s = sd >> 1, dir = sd & 1;
+  const int t = seg * P[it].fseg - 1;
+  const int r = dir == 0 ? t : n2 - 1 - t;
+  const g_t<const T>* ref = dir == 0 ? gp((const T*)P[it].Gl) + ((size_t)s * n2 + r) * BP * BP
+                                     : gp((const T*)P[it].Hsw) + ((size_t)s * n2 + r) * BP * BP;
+  const g_t<const T>* chk = gp((const T*)P[it].fchk) + ((size_t)sd * nseg + seg) * BP * BP;
+  double dmax = 0.0, rmax = 0.0;
+  for (int e = threadIdx.x; e < BP * BP; e += 256) {
+    const double a = (double)ref[e], c = (double)chk[e];
+    const double d = fabs(a - c);
+    dmax = (d > dmax || d != d) ? d : dmax;   // a NaN difference is kept
+    rmax = fmax(rmax, fabs(a));
+  }
+  red[0][threadIdx.x] = dmax;
+  red[1][threadIdx.x] = rmax;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      const double x = red[0][threadIdx.x + off];
+      red[0][threadIdx.x] = (x > red[0][threadIdx.x] || x != x) ? x : red[0][threadIdx.x];
+      red[1][threadIdx.x] = fmax(red[1][threadIdx.x], red[1][threadIdx.x + off]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && !(red[0][0] <= tol * red[1][0])) gp(P[it].fredo)[sd] = 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -704,11 +775,31 @@ static void plan_stage1_bp(Plan& plan, const std::vector<ProbDev>& probs, int ph
     off = plan.add_offsets(c, &tot);
   };
   if (phase == 0) {
+    // segments of every chain, then the warm-up check and the redo of the
+    // chains it marks (its workgroups of unmarked chains return at once)
+    counts([](const ProbDev& d) { return 2LL * d.m * d.fnseg; });
+    const size_t o_seg = off;
+    const long long t_seg = tot;
+    counts([](const ProbDev& d) { return 2LL * d.m * (d.fnseg - 1); });
+    const size_t o_chk = off;
+    const long long t_chk = tot;
     counts([](const ProbDev& d) { return 2LL * d.m; });
+    const size_t o_redo = off;
+    const long long t_redo = tot;
+    // a converged warm-up differs from the full chain by rounding only
+    const double tol = sizeof(T) == 8 ? 1e-13 : 1e-5;
     plan.step([=](const char* dev, hipStream_t st) {
-      hipLaunchKernelGGL((k_slab_factor<T, BP>), dim3((unsigned)tot), dim3(SLAB_FACTOR_THREADS), 0, st,
-                         dev_at<ProbDev>(dev, pd), dev_at<int>(dev, off), count);
+      hipLaunchKernelGGL((k_slab_factor<T, BP>), dim3((unsigned)t_seg), dim3(SLAB_FACTOR_THREADS), 0, st,
+                         dev_at<ProbDev>(dev, pd), dev_at<int>(dev, o_seg), count, 0);
       SLAB_LAUNCH_CHECK();
+      if (t_chk > 0) {
+        hipLaunchKernelGGL((k_factor_check<T, BP>), dim3((unsigned)t_chk), dim3(256), 0, st,
+                           dev_at<ProbDev>(dev, pd), dev_at<int>(dev, o_chk), count, tol);
+        SLAB_LAUNCH_CHECK();
+        hipLaunchKernelGGL((k_slab_factor<T, BP>), dim3((unsigned)t_redo), dim3(SLAB_FACTOR_THREADS), 0, st,
+                           dev_at<ProbDev>(dev, pd), dev_at<int>(dev, o_redo), count, 1);
+        SLAB_LAUNCH_CHECK();
+      }
       if (ev) SLAB_HIP_CHECK(hipEventRecord(ev, st));
       return SLAB_OK;
     });

@@ -404,3 +404,34 @@ def test_batch_with_autotuned_widths():
         rr = O.relres(O.make_problem(kaps[i], n2, n1, bi), us[i].cpu().numpy(), fs[i])
         assert rr.max() <= 1e-10, (i, rr)
     bt.free()
+
+
+# ------------------------------------------------- segmented slab recursion
+
+SEG_CASES = [(130, 128, 7), (300, 48, 15), (200, 96, 31), (97, 64, 3)]
+
+
+@pytest.mark.parametrize("warm", [None, "1"])
+@pytest.mark.parametrize("n2,n1,b", SEG_CASES)
+def test_segmented_slab_factor(monkeypatch, n2, n1, b, warm):
+    """The slab recursion cut into segments of 32 row steps that start early
+    from a zero inverse (warm-up of 7 (b+1) steps): T, the pivot blocks and u
+    equal the oracle's to 1e-12.  With a one-step warm-up the segments cannot
+    agree with their predecessors, so every segmented chain must be caught by
+    the check and recomputed in one piece; the results are still exact."""
+    monkeypatch.setenv("SLAB_FACTOR_SEG", "32")
+    if warm:
+        monkeypatch.setenv("SLAB_FACTOR_WARM", warm)
+    kap = G.kappa_lognormal(n2, n1, 7)
+    prob = O.make_problem(kap, n2, n1, b)
+    fac = O.factor(prob, order="odd_even")
+    h = S.slab_factor(_dev(kap), n2, n1, b, keep_reduced=True, odd_even=True)
+    for j in range(prob.m):
+        assert _rel_fro(S.slab_export_reduced(h, 0, j).cpu().numpy(), fac.s1.T_diag[j]) <= 1e-12
+        assert _rel_fro(S.slab_export_reduced(h, 2, j).cpu().numpy(), fac.s2.pivot(j)) <= 1e-12
+    for j in range(prob.m - 1):
+        assert _rel_fro(S.slab_export_reduced(h, 1, j).cpu().numpy(), fac.s1.T_up[j]) <= 1e-12
+    f = G.rhs_uniform(n2, n1, 2, 9)
+    u = S.slab_solve(h, _dev(f)).cpu().numpy()
+    assert _col_rel(u, O.solve(fac, f)).max() <= 1e-12
+    h.free()
