@@ -436,6 +436,30 @@ def extra_workloads(warmup: int, steps: int) -> dict:
     return out
 
 
+def sketch_workload(w: G.Workload, kappa, warmup: int, steps: int) -> dict:
+    """Matrix-free products with the reduced matrix, Y = T Omega, for s = 6b
+    Gaussian test vectors on grid w (mixed precision: FP64 slab sweeps), the
+    product the paper's randomized sketches of T are formed from.  One step is
+    one slab_apply_reduced call on a factored handle (factorization untimed)."""
+    import torch
+    from paper_2211_07572_amd import slab as S
+    s = 6 * w.b
+    h = S.slab_factor(kappa, w.n2, w.n1, w.b, w.h, precision=S.SLAB_MIXED, odd_even=True)
+    x = torch.as_tensor(G.gaussian_test_vectors(w.m, s, w.n2), device="cuda")
+    times = []
+    for it in range(warmup + steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S.slab_apply_reduced(h, x)      # synchronizes at its end
+        if it >= warmup:
+            times.append(time.perf_counter() - t0)
+    h.free()
+    med = float(np.median(times))
+    return {"ms_per_step": med * 1e3, "test_vectors": s, "vectors_per_s": s / med,
+            "slab_factor_reads_GBps": 2.0 * w.m * w.n2 * 32 * 32 * 8 / med / 1e9,
+            "steps": steps, "warmup": warmup}
+
+
 def differentiation_batch(warmup: int, steps: int) -> dict:
     """The 512x512 differentiation workload (b = 15): 16 fields theta_i = log
     kappa_i factored together (FP64, odd-even order), the shared load solved,
@@ -581,6 +605,8 @@ def main():
     if not args.skip_extra:
         log("extra workloads: 1024x1024, 512x512 batch of 16")
         result["extra_workloads"] = extra_workloads(cw, cs)
+        log("extra workload: sketch of T")
+        result["extra_workloads"][f"{w.name}_sketch_T_6b"] = sketch_workload(w, kappa, cw, cs)
         log("extra workload: batch of 256")
         result["extra_workloads"]["batch256_uneven"] = run_batch(cw, cs)
     if not args.skip_cpu:

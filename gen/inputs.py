@@ -39,6 +39,7 @@ SEED_RHS = 100
 SEED_NOISE = 200
 SEED_FD_NODES = 300
 SEED_BATCH = 400
+SEED_SKETCH = 500
 
 
 def default_h(n2: int) -> float:
@@ -141,6 +142,12 @@ DIFF_NOISE_LEVEL = 0.01
 def noise_normal(n2: int, n1: int, nrhs: int, seed: int = SEED_NOISE) -> np.ndarray:
     """Standard normal samples of the shape of a right-hand side block."""
     return np.random.default_rng(seed).standard_normal((nrhs, n1, n2))
+
+
+def gaussian_test_vectors(m: int, ncols: int, n2: int, seed: int = SEED_SKETCH) -> np.ndarray:
+    """ncols standard normal interface vectors, shape (m, ncols, n2): block j
+    of column k is interface j's part (the test vectors of a sketch of T)."""
+    return np.random.default_rng(seed).standard_normal((m, ncols, n2))
 
 
 def fd_nodes(n2: int, n1: int, count: int = 32, seed: int = SEED_FD_NODES) -> np.ndarray:

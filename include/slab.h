@@ -248,6 +248,18 @@ int slab_kappa_grad(slab_handle h, const double* u, const double* lam, int32_t n
 int slab_residual(slab_handle h, const double* f, const double* u, int32_t nrhs, int64_t ld,
                   double* relres, void* hip_stream);
 
+/* Matrix-free product with the reduced matrix of a factored problem,
+   y = T x = A_oo x - A_oe A_ee^-1 A_eo x (Sec. 3.1, eq. (T11_detailed)), for
+   ncols interface vectors: the operation the paper's randomized sketches of T
+   are formed from (Alg. 3, Sec. 3.3: T applied to Gaussian test vectors
+   through the slab solves, never formed).  x and y are device FP64 arrays of
+   m * ncols * n2 entries, block j of column k at (j * ncols + k) * n2 (rows r
+   fastest), owned by the caller and not overlapping.  A_ee^-1 is applied with
+   the stored slab factors (two slab sweeps per slab, FP64 except in
+   SLAB_FP32_REFINE, where they are FP32); A_oo and A_eo come from the edge
+   weights.  Uses the handle's solve workspace (grown for ncols columns). */
+int slab_apply_reduced(slab_handle h, const double* x, double* y, int32_t ncols, void* hip_stream);
+
 /* Export a reduced block as FP64 n2 x n2 row-major into device memory out:
    which = 0: T_jj, 1: T_{j,j+1} (j < m-1), 2: the pivot block of interface j
    before its factorization (S_j of Alg. 1, or with SLAB_ODD_EVEN the block of

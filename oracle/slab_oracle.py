@@ -584,6 +584,23 @@ def solve_adjoint(prob: Problem, g: np.ndarray, fac_T: Factorization | None = No
     return solve(fac_T, g)
 
 
+def apply_T(prob: Problem, x: np.ndarray) -> np.ndarray:
+    """T x = A_oo x - A_oe A_ee^-1 A_eo x, the Schur complement of A onto the
+    interface unknowns (Sec. 3.1, eq. (T11_detailed)) applied without forming
+    it: the product the randomized sketches of T are built from (Alg. 3,
+    Sec. 3.3), here for given test vectors.  x and the result have shape
+    (m, ncols, n2): block j of column k is interface j's part.  A_ee (all
+    slab interiors together) is factored by a sparse LU."""
+    m, n2 = prob.m, prob.n2
+    Io = np.concatenate([prob.I_o(j) for j in range(m)])
+    Ie = np.concatenate([prob.I_e(s) for s in range(m)])
+    A = prob.A
+    X = np.ascontiguousarray(x.transpose(0, 2, 1).reshape(m * n2, -1))
+    lu = spla.splu(A[Ie][:, Ie].tocsc())
+    Y = A[Io][:, Io] @ X - A[Io][:, Ie] @ lu.solve(np.asarray(A[Ie][:, Io] @ X))
+    return np.ascontiguousarray(Y.reshape(m, n2, -1).transpose(0, 2, 1))
+
+
 def interface_values(u: np.ndarray, prob: Problem) -> np.ndarray:
     """Restriction of a full solution (nrhs, n1, n2) to I_1, I_3, ... -> (nrhs, m, n2)."""
     flat = u.reshape(-1, prob.N)

@@ -1653,6 +1653,33 @@ int slab_residual(slab_handle h, const double* f, const double* u, int32_t nrhs,
   return SLAB_OK;
 }
 
+int slab_apply_reduced(slab_handle h, const double* x, double* y, int32_t ncols,
+                       void* hip_stream) {
+  if (!h || !x || !y || ncols < 1) { set_error("bad arguments to slab_apply_reduced"); return SLAB_E_INVALID; }
+  const long long span = (long long)h->m * ncols * h->n2 * 8;
+  if ((const char*)x < (const char*)y + span && (const char*)y < (const char*)x + span) {
+    set_error("x and y overlap");
+    return SLAB_E_INVALID;
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  SLAB_HIP_CHECK(hipSetDevice(h->device));
+  SLAB_TRY(ensure_workspace(h, ncols));
+  SolveDev d;
+  std::memset(&d, 0, sizeof(d));
+  const long long N = (long long)h->n1 * h->n2;
+  d.n1 = h->n1; d.n2 = h->n2; d.b = h->b; d.m = h->m; d.nrhs = ncols;
+  d.wh = h->wh; d.wv = h->wv; d.Gl = h->Gl;
+  d.zbuf = h->ws.zbuf; d.xb = h->ws.xb; d.ft = h->ws.ft;
+  d.rhs = h->ws.r; d.ld = N; d.r = h->ws.r; d.u = x; d.g64 = y;
+  Plan p;
+  if (h->precision == SLAB_FP32_REFINE) plan_reduced_apply<float, float>(p, {d});
+  else if (h->precision == SLAB_MIXED) plan_reduced_apply<double, float>(p, {d});
+  else plan_reduced_apply<double, double>(p, {d});
+  SLAB_TRY(run_plan(h->mem, p, st));
+  SLAB_HIP_CHECK(hipStreamSynchronize(st));
+  return SLAB_OK;
+}
+
 int slab_export_reduced(slab_handle h, int32_t which, int32_t j, double* out, void* hip_stream) {
   if (!h || !out) { set_error("null argument"); return SLAB_E_INVALID; }
   if (!(h->flags & SLAB_KEEP_REDUCED)) { set_error("factor without SLAB_KEEP_REDUCED"); return SLAB_E_INVALID; }

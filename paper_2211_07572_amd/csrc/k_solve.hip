@@ -547,7 +547,8 @@ static void plan_reduced_refined(Plan& plan, const std::vector<ReducedDev>& R, b
 
 template <typename T, typename TR>
 void plan_solve_pass(Plan& plan, const std::vector<SolveDev>& probs,
-                     const std::vector<ReducedDev>& red, bool trans, bool odd_even) {
+                     const std::vector<ReducedDev>& red, bool trans, bool odd_even,
+                     bool rhs_only) {
   if (probs.empty()) return;
   // problems split by padded block order for the sweeps
   std::vector<SolveDev> cls[3];
@@ -580,6 +581,7 @@ void plan_solve_pass(Plan& plan, const std::vector<SolveDev>& probs,
     SLAB_LAUNCH_CHECK();
     return SLAB_OK;
   });
+  if (rhs_only) return;
   // (ii) the reduced system (refined in FP64 when the FP64 blocks are given)
   if (!red.empty() && red[0].T64) plan_reduced_refined<TR>(plan, red, odd_even, REDUCED_REFINE_STEPS);
   else plan_reduced<TR>(plan, red, odd_even);
@@ -599,11 +601,80 @@ void plan_solve_pass(Plan& plan, const std::vector<SolveDev>& probs,
   });
 }
 template void plan_solve_pass<float, float>(Plan&, const std::vector<SolveDev>&,
-                                            const std::vector<ReducedDev>&, bool, bool);
+                                            const std::vector<ReducedDev>&, bool, bool, bool);
 template void plan_solve_pass<double, double>(Plan&, const std::vector<SolveDev>&,
-                                              const std::vector<ReducedDev>&, bool, bool);
+                                              const std::vector<ReducedDev>&, bool, bool, bool);
 template void plan_solve_pass<double, float>(Plan&, const std::vector<SolveDev>&,
-                                             const std::vector<ReducedDev>&, bool, bool);
+                                             const std::vector<ReducedDev>&, bool, bool, bool);
+
+// ---------------------------------------------------------------------------
+// Matrix-free product with the reduced matrix, T x = A_oo x - A_oe A_ee^-1 A_eo x
+// (eq. (T11_detailed); the operation the paper's randomized sketches of T are
+// built from, Sec. 3.3), for nrhs interface vectors x ([j][c][r], the layout of
+// the reduced vectors): k_apply_rhs writes the load f = (A_eo x on the slab
+// nodes next to an interface, A_oo x on the interface nodes, zero elsewhere)
+// in natural order into d.r; the reduced right-hand side of f (slab sweeps +
+// k_reduced_rhs) is then f_o - A_oe A_ee^-1 f_e = T x, which k_reduced_rhs
+// writes to d.g64 in FP64.
+// ---------------------------------------------------------------------------
+__global__ void k_apply_rhs(const SolveDev* __restrict__ P, const int* __restrict__ offs,
+                            int count) {
+  const int itm = group_item(offs, count, blockIdx.x);
+  const long long nwg = offs[itm + 1] - offs[itm];
+  const SolveDev& d = P[itm];
+  const int n1 = d.n1, n2 = d.n2, b = d.b, m = d.m, nrhs = d.nrhs;
+  const long long N = (long long)n1 * n2;
+  const g_t<const double>* __restrict__ wh = gp(d.wh);
+  const g_t<const double>* __restrict__ wv = gp(d.wv);
+  const g_t<const double>* __restrict__ x = gp(d.u);
+  g_t<double>* __restrict__ f = gp(d.r);
+  auto xv = [&](long long j, long long c, long long r) -> double {
+    return (j >= 0 && j < m) ? x[(j * nrhs + c) * n2 + r] : 0.0;
+  };
+  for (long long e = (blockIdx.x - offs[itm]) * (long long)blockDim.x + threadIdx.x;
+       e < (long long)nrhs * N; e += nwg * blockDim.x) {
+    const long long c = e / N, p = e % N;
+    const long long col = p / n2, r = p % n2;
+    const long long k = col % (b + 1), s = col / (b + 1);
+    double v = 0.0;
+    if (k == b) {
+      // interface node of interface s: its row of A_oo (vertical edges within
+      // the interface column; horizontal edges lead to slab nodes)
+      const double wl = wh[col * n2 + r], wr = wh[(col + 1) * n2 + r];
+      const double wd = wv[col * (n2 + 1) + r], wu = wv[col * (n2 + 1) + r + 1];
+      v = (wl + wr + wd + wu) * xv(s, c, r);
+      if (r > 0) v -= wd * xv(s, c, r - 1);
+      if (r < n2 - 1) v -= wu * xv(s, c, r + 1);
+    } else {
+      // slab node: -w to the interface on its left (interface s-1) at k = 0
+      // and on its right (interface s) at k = b-1
+      if (k == 0) v -= wh[col * n2 + r] * xv(s - 1, c, r);
+      if (k == b - 1) v -= wh[(col + 1) * n2 + r] * xv(s, c, r);
+    }
+    f[c * N + p] = v;
+  }
+}
+
+template <typename T, typename TR>
+void plan_reduced_apply(Plan& plan, const std::vector<SolveDev>& probs) {
+  if (probs.empty()) return;
+  std::vector<int> cw;
+  for (const SolveDev& d : probs)
+    cw.push_back((int)item_wgs((long long)d.nrhs * d.n1 * d.n2));
+  long long tw;
+  const size_t ow = plan.add_offsets(cw, &tw), pd = plan.add_vec(probs);
+  const int count = (int)probs.size();
+  plan.step([=](const char* dev, hipStream_t st) {
+    hipLaunchKernelGGL(k_apply_rhs, dim3((unsigned)tw), dim3(256), 0, st,
+                       dev_at<SolveDev>(dev, pd), dev_at<int>(dev, ow), count);
+    SLAB_LAUNCH_CHECK();
+    return SLAB_OK;
+  });
+  plan_solve_pass<T, TR>(plan, probs, {}, false, false, true);
+}
+template void plan_reduced_apply<float, float>(Plan&, const std::vector<SolveDev>&);
+template void plan_reduced_apply<double, double>(Plan&, const std::vector<SolveDev>&);
+template void plan_reduced_apply<double, float>(Plan&, const std::vector<SolveDev>&);
 
 // ---------------------------------------------------------------------------
 // Residual r = f - A u (FP64) with per-column partial sums of r^2 and f^2.

@@ -69,9 +69,17 @@ void plan_gemv(Plan& plan, bool tr, bool lower, const std::vector<BmvItem>& item
 // One pass of Alg. 4 for every problem: slab sweeps in T (the slab factors'
 // type), the reduced system in TR (the block factorization's type); rhs (FP64)
 // -> out (FP64), written or added (SolveDev::accumulate).
+// rhs_only: stop after the reduced right-hand side (step (i)).
 template <typename T, typename TR>
 void plan_solve_pass(Plan& plan, const std::vector<SolveDev>& probs,
-                     const std::vector<ReducedDev>& red, bool trans, bool odd_even);
+                     const std::vector<ReducedDev>& red, bool trans, bool odd_even,
+                     bool rhs_only = false);
+
+// y = T x for nrhs interface vectors (matrix-free, through the slab sweeps):
+// x in d.u and y in d.g64, both [j][c][r]; d.r receives the load built from x
+// (nrhs x n1 n2, FP64), the solve workspace as for a pass.
+template <typename T, typename TR>
+void plan_reduced_apply(Plan& plan, const std::vector<SolveDev>& probs);
 
 // r = f - A u and per-column sums of r^2 and f^2 (FP64) for every problem.
 void plan_residual(Plan& plan, const std::vector<SolveDev>& probs);

@@ -88,6 +88,7 @@ def load_library(path: str = LIB_PATH):
     L.slab_kappa_grad.argtypes = [vp, vp, vp, i32, i64, i32, vp, vp]
     L.slab_residual.argtypes = [vp, vp, vp, i32, i64, ctypes.POINTER(dp), vp]
     L.slab_export_reduced.argtypes = [vp, i32, i32, vp, vp]
+    L.slab_apply_reduced.argtypes = [vp, vp, vp, i32, vp]
     L.slab_query.argtypes = [vp, i32, ctypes.POINTER(i64)]
     L.slab_factor_batch.argtypes = [ctypes.POINTER(slab_problem), i32, ctypes.POINTER(slab_options),
                                     vp, ctypes.POINTER(vp), ctypes.POINTER(slab_solve_info)]
@@ -290,6 +291,19 @@ def slab_residual(handle: SlabHandle, f, u, stream=None) -> list[float]:
                                         f3.shape[0], handle.n1 * handle.n2, arr,
                                         _stream_ptr(stream)))
     return list(arr)
+
+
+def slab_apply_reduced(handle: SlabHandle, x, stream=None):
+    """y = T x (matrix-free, through the stored slab factors) for interface
+    vectors x of shape (m, ncols, n2), CUDA float64; returns y of that shape."""
+    import torch
+    if x.dim() != 3 or x.shape[0] != handle.m or x.shape[2] != handle.n2:
+        raise ValueError(f"x must have shape ({handle.m}, ncols, {handle.n2})")
+    xc = x.contiguous()
+    y = torch.empty_like(xc)
+    _check(load_library().slab_apply_reduced(handle.ptr, _dev_f64(xc, "x"), _dev_f64(y, "y"),
+                                             xc.shape[1], _stream_ptr(stream)))
+    return y
 
 
 def slab_export_reduced(handle: SlabHandle, which: int, j: int, stream=None):

@@ -551,3 +551,38 @@ def test_stage_one_process_pool_equals_serial():
         assert np.array_equal(x, y)
     f = G.rhs_uniform(n2, n1, 1, 3)
     assert np.array_equal(O.solve(O.factor(p), f), O.solve(O.factor(p, workers=2), f))
+
+
+# ------------------------------------------------------------ matrix-free T
+
+@pytest.mark.parametrize("n2,n1,b", [(5, 8, 3), (7, 12, 2), (4, 6, 1), (6, 4, 3)])
+def test_apply_T_equals_dense_schur_complement(n2, n1, b):
+    """apply_T against the Schur complement of the dense A onto the interface
+    unknowns, formed by numpy.linalg.solve (brute force)."""
+    p = O.make_problem(G.kappa_lognormal(n2, n1, 13), n2, n1, b)
+    A = p.A.toarray()
+    Io = np.concatenate([p.I_o(j) for j in range(p.m)])
+    Ie = np.concatenate([p.I_e(s) for s in range(p.m)])
+    Tdense = A[np.ix_(Io, Io)] - A[np.ix_(Io, Ie)] @ np.linalg.solve(A[np.ix_(Ie, Ie)], A[np.ix_(Ie, Io)])
+    x = G.gaussian_test_vectors(p.m, 3, n2, 1)
+    y = O.apply_T(p, x)
+    X = x.transpose(0, 2, 1).reshape(p.m * n2, 3)
+    ref = (Tdense @ X).reshape(p.m, n2, 3).transpose(0, 2, 1)
+    assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_apply_T_equals_assembled_blocks():
+    """apply_T against the block-tridiagonal product with stage_one's blocks
+    (eqs. (T11)-(T35)) on a larger grid."""
+    n2, n1, b = 24, 40, 7
+    p = O.make_problem(G.kappa_lognormal(n2, n1, 14), n2, n1, b)
+    s1 = O.stage_one(p)
+    x = G.gaussian_test_vectors(p.m, 4, n2, 2)
+    y = O.apply_T(p, x)
+    ref = np.zeros_like(x)
+    for j in range(p.m):
+        ref[j] += (s1.T_diag[j] @ x[j].T).T
+        if j + 1 < p.m:
+            ref[j] += (s1.T_up[j] @ x[j + 1].T).T
+            ref[j + 1] += (s1.T_lo[j] @ x[j].T).T
+    assert np.abs(y - ref).max() <= 1e-12 * np.abs(ref).max()
