@@ -144,6 +144,16 @@ def noise_normal(n2: int, n1: int, nrhs: int, seed: int = SEED_NOISE) -> np.ndar
     return np.random.default_rng(seed).standard_normal((nrhs, n1, n2))
 
 
+def helmholtz_shift(n2: int, n1: int, ppw: float, h: float | None = None) -> np.ndarray:
+    """Diagonal term c = -k^2 of the constant-coefficient Helmholtz operator
+    -Laplace u - k^2 u with k chosen for `ppw` grid points per wavelength
+    (k h = 2 pi / ppw), on the (n1, n2) interior nodes."""
+    if h is None:
+        h = default_h(n2)
+    k = 2.0 * np.pi / (ppw * h)
+    return np.full((n1, n2), -k * k)
+
+
 def gaussian_test_vectors(m: int, ncols: int, n2: int, seed: int = SEED_SKETCH) -> np.ndarray:
     """ncols standard normal interface vectors, shape (m, ncols, n2): block j
     of column k is interface j's part (the test vectors of a sketch of T)."""

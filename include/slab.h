@@ -88,6 +88,13 @@ typedef struct {
   double h;            /* grid spacing, > 0 */
   const double* kappa; /* device, (n1+2)*(n2+2) FP64, r fastest; > 0 and finite
                           (or theta = log kappa, finite, with SLAB_COEF_LOG) */
+  const double* shift; /* device, n1*n2 FP64 (node (c, r) at c*n2 + r), finite, or NULL:
+                          a diagonal term c_p added to A, (A u)_p += c_p u_p.  With
+                          c = -k^2 b(x) it is the Helmholtz term of eq. (var_helm)
+                          (wavenumber k; the paper writes kappa for it).  The factor
+                          kernels are those of a positive definite A: a shift that
+                          makes A indefinite is reported as SLAB_E_BREAKDOWN.  Read
+                          during slab_factor (and again by slab_batch_run). */
 } slab_problem;
 
 typedef struct {
@@ -112,7 +119,7 @@ typedef struct {
    Returns SLAB_OK or SLAB_E_INVALID. */
 int slab_check_problem(const slab_problem* prob, const slab_options* opts);
 
-/* Alg. 3 (factor).  prob->kappa is read during the call only.  On success
+/* Alg. 3 (factor).  prob->kappa and prob->shift are read during the call only.  On success
    *out receives a new handle.  SLAB_E_INVALID for bad sizes or a coefficient
    that is not positive and finite; SLAB_E_BREAKDOWN if a pivot block is not
    positive definite (its interface index is in info->failed_block when info is

@@ -176,12 +176,22 @@ class Problem:
         return self.A[I][:, J]
 
 
-def make_problem(kappa, n2: int, n1: int, b: int, h: float | None = None) -> Problem:
+def make_problem(kappa, n2: int, n1: int, b: int, h: float | None = None,
+                 shift: np.ndarray | None = None) -> Problem:
+    """shift: optional diagonal term c on the interior nodes, shape (n1, n2):
+    (A u)_p gains c_p u_p.  The Helmholtz operator of eq. (var_helm),
+    -Laplace u - k^2 b(x) u (the paper calls the wavenumber kappa), is kappa = 1
+    with c = -k^2 b(x); every factorization here pivots (banded and dense
+    LAPACK LU), so indefinite shifts are handled."""
     if h is None:
         h = 1.0 / (n2 + 1)
     maps = index_maps(n2, n1, b)
     wh, wv = edge_weights(kappa, n2, n1, h)
     A = assemble_A(wh, wv, n2, n1)
+    if shift is not None:
+        c = np.asarray(shift, dtype=np.float64)
+        assert c.shape == (n1, n2)
+        A = (A + sp.diags(c.reshape(-1))).tocsr()
     return Problem(n2, n1, b, float(h), np.asarray(kappa, dtype=np.float64), maps, wh, wv, A)
 
 

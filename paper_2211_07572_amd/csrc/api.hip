@@ -265,6 +265,8 @@ struct slab_handle_s {
   double* kappa = nullptr;
   double* wh = nullptr;
   double* wv = nullptr;
+  const double* shift_src = nullptr;  // caller's diagonal term (read at factor time)
+  double* shift = nullptr;            // its copy, or one zero
   int* status = nullptr;
   void* Gl = nullptr;
   void* Linv = nullptr;
@@ -427,6 +429,7 @@ void persistent_layout(slab_handle h, Layout& L) {
   L.add(&h->kappa, ncoef * sizeof(double));
   L.add(&h->wh, (size_t)(h->n1 + 1) * n * sizeof(double));
   L.add(&h->wv, (size_t)h->n1 * (n + 1) * sizeof(double));
+  L.add(&h->shift, (h->shift_src ? (size_t)h->n1 * n : 1) * sizeof(double));
   L.add(&h->status, 4 * sizeof(int));
   L.add(&h->Gl, m * n * BP * BP * e);
   L.add(&h->Linv, m * nsq * e2);
@@ -474,6 +477,7 @@ std::vector<ProbDev> prob_descs(const std::vector<slab_handle>& hs,
     d.is_log = (h->flags & SLAB_COEF_LOG) ? 1 : 0;
     d.coef = coefs[i]; d.kappa = h->kappa; d.wh = h->wh; d.wv = h->wv;
     d.Gl = h->Gl; d.T64 = h->T64; d.O64 = h->O64; d.status = h->status;
+    d.shift_src = h->shift_src; d.shift = h->shift; d.shift_stride = h->shift_src ? 1 : 0;
     slab_segments(h->n2, h->b, &d.fnseg, &d.fseg, &d.fwarm);
   }
   return pd;
@@ -670,7 +674,9 @@ int factor_dispatch(int precision, const std::vector<slab_handle>& hs,
 }
 
 std::string fail_message(int code, int blk) {
-  if (code == 1) return "coefficient field has a value that is not positive and finite";
+  if (code == 1)
+    return "coefficient field has a value that is not positive and finite (or the diagonal "
+           "term one that is not finite)";
   if (code == 2) return "slab factorization breakdown in slab " + std::to_string(blk);
   return "block factorization breakdown at interface " + std::to_string(blk);
 }
@@ -678,7 +684,7 @@ std::string fail_message(int code, int blk) {
 slab_handle new_handle(const slab_problem* prob, const slab_options* opts, int device) {
   slab_handle h = new slab_handle_s();
   h->n1 = prob->n1; h->n2 = prob->n2; h->b = prob->b; h->m = prob->n1 / (prob->b + 1);
-  h->BP = padded_block(prob->b); h->h = prob->h;
+  h->BP = padded_block(prob->b); h->h = prob->h; h->shift_src = prob->shift;
   if (opts) { h->precision = opts->precision; h->tol = opts->tol; h->max_iter = opts->max_iter; h->flags = opts->flags; }
   h->odd_even = (h->flags & SLAB_ODD_EVEN) ? 1 : 0;
   h->tile = opts ? opts->tile : 0;
@@ -721,6 +727,7 @@ void plan_pass(Plan& p, const std::vector<SolveJob>& jobs, bool first, bool tran
     std::memset(&d, 0, sizeof(d));
     d.n1 = h->n1; d.n2 = h->n2; d.b = h->b; d.m = h->m; d.nrhs = j.nrhs;
     d.wh = h->wh; d.wv = h->wv; d.Gl = h->Gl;
+    d.shift = h->shift; d.shift_stride = h->shift_src ? 1 : 0;
     d.zbuf = h->ws.zbuf; d.xb = h->ws.xb; d.ft = h->ws.ft;
     const long long N = (long long)h->n1 * h->n2;
     d.rhs = first ? j.f : h->ws.r;
@@ -1642,6 +1649,7 @@ int slab_residual(slab_handle h, const double* f, const double* u, int32_t nrhs,
   std::memset(&d, 0, sizeof(d));
   d.n1 = h->n1; d.n2 = h->n2; d.b = h->b; d.m = h->m; d.nrhs = nrhs;
   d.wh = h->wh; d.wv = h->wv; d.f = f; d.u = u; d.r = nullptr; d.ldf = ld;
+  d.shift = h->shift; d.shift_stride = h->shift_src ? 1 : 0;
   d.norms = h->ws.norms; d.partial = h->ws.partial;
   Plan p;
   plan_residual(p, std::vector<SolveDev>{d});
@@ -1669,6 +1677,7 @@ int slab_apply_reduced(slab_handle h, const double* x, double* y, int32_t ncols,
   const long long N = (long long)h->n1 * h->n2;
   d.n1 = h->n1; d.n2 = h->n2; d.b = h->b; d.m = h->m; d.nrhs = ncols;
   d.wh = h->wh; d.wv = h->wv; d.Gl = h->Gl;
+  d.shift = h->shift; d.shift_stride = h->shift_src ? 1 : 0;
   d.zbuf = h->ws.zbuf; d.xb = h->ws.xb; d.ft = h->ws.ft;
   d.rhs = h->ws.r; d.ld = N; d.r = h->ws.r; d.u = x; d.g64 = y;
   Plan p;

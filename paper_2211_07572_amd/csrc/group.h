@@ -61,6 +61,12 @@ struct ProbDev {
   double* kappa;       // working copy
   double* wh;
   double* wv;
+  // diagonal term c_p of the operator (the Helmholtz term of eq. (var_helm)):
+  // shift_src is the caller's n1 x n2 field or null; shift the working copy
+  // (n1 x n2 entries with shift_stride 1, or one zero with stride 0)
+  const double* shift_src;
+  double* shift;
+  long long shift_stride;
   void* Gl;
   void* Hsw;
   void* sig;
@@ -134,6 +140,8 @@ struct SolveDev {
   long long ldo;   // out leading dimension
   const double* wh;
   const double* wv;
+  const double* shift;       // diagonal term c_p (see ProbDev), index p * shift_stride
+  long long shift_stride;
   const void* Gl;
   void* zbuf;
   void* xb;

@@ -642,7 +642,7 @@ __global__ void k_apply_rhs(const SolveDev* __restrict__ P, const int* __restric
       // the interface column; horizontal edges lead to slab nodes)
       const double wl = wh[col * n2 + r], wr = wh[(col + 1) * n2 + r];
       const double wd = wv[col * (n2 + 1) + r], wu = wv[col * (n2 + 1) + r + 1];
-      v = (wl + wr + wd + wu) * xv(s, c, r);
+      v = (wl + wr + wd + wu + gp(d.shift)[p * d.shift_stride]) * xv(s, c, r);
       if (r > 0) v -= wd * xv(s, c, r - 1);
       if (r < n2 - 1) v -= wu * xv(s, c, r + 1);
     } else {
@@ -703,6 +703,8 @@ __global__ __launch_bounds__(256) void k_residual(const SolveDev* __restrict__ P
   const long long ld = P[itm].ldf;
   const g_t<const double>* __restrict__ wh = gp(P[itm].wh);
   const g_t<const double>* __restrict__ wv = gp(P[itm].wv);
+  const g_t<const double>* __restrict__ sh = gp(P[itm].shift);
+  const long long ss = P[itm].shift_stride;
   const long long N = (long long)n1 * n2;
   const g_t<const double>* fc = gp(P[itm].f) + c * ld;
   const g_t<const double>* uc = gp(P[itm].u) + c * ld;
@@ -713,7 +715,7 @@ __global__ __launch_bounds__(256) void k_residual(const SolveDev* __restrict__ P
     const double w_l = wh[col * n2 + row], w_r = wh[(col + 1) * n2 + row];
     const double w_d = wv[col * (n2 + 1) + row], w_u = wv[col * (n2 + 1) + row + 1];
     const double up = uc[p];
-    double au = (w_l + w_r + w_d + w_u) * up;
+    double au = (w_l + w_r + w_d + w_u + sh[p * ss]) * up;
     if (col > 0) au -= w_l * uc[p - n2];
     if (col < n1 - 1) au -= w_r * uc[p + n2];
     if (row > 0) au -= w_d * uc[p - 1];

@@ -40,6 +40,25 @@ __global__ void k_coef(const ProbDev* __restrict__ P, const int* __restrict__ of
   if (bad) gp(d.status)[2] = 1;
 }
 
+// Diagonal term of the operator: the caller's field copied (status[2] = 1 for
+// a value that is not finite), or the single zero a problem without one
+// points at.
+__global__ void k_shift(const ProbDev* __restrict__ P, const int* __restrict__ offs, int count) {
+  const int it = group_item(offs, count, blockIdx.x);
+  const ProbDev& d = P[it];
+  const long long nwg = offs[it + 1] - offs[it];
+  const long long tot = d.shift_src ? (long long)d.n1 * d.n2 : 1;
+  g_t<double>* sh = gp(d.shift);
+  bool bad = false;
+  for (long long i = (blockIdx.x - offs[it]) * (long long)blockDim.x + threadIdx.x; i < tot;
+       i += nwg * blockDim.x) {
+    const double v = d.shift_src ? gp(d.shift_src)[i] : 0.0;
+    if (!isfinite(v)) bad = true;
+    sh[i] = v;
+  }
+  if (bad) gp(d.status)[2] = 1;
+}
+
 // Edge weights w = (kappa_p + kappa_q) / (2 h^2) of the 5-point stencil.
 // wh[c*n2 + r], c = 0..n1: edge (c-1, r)-(c, r); wv[c*(n2+1) + r], r = 0..n2:
 // edge (c, r-1)-(c, r).  Columns/rows -1 and n1/n2 are the Dirichlet ring.
@@ -114,13 +133,15 @@ int launch_maps(int n1, int n2, int b, int32_t* ck, int32_t* sc, int32_t* lc, in
 // ---------------------------------------------------------------------------
 template <typename T, int BP>
 __device__ __forceinline__ void build_D_row(T (&a)[BP], const g_t<const double>* __restrict__ wh,
-                                            const g_t<const double>* __restrict__ wv, int n2, int b,
-                                            int c0, int r, int lane) {
+                                            const g_t<const double>* __restrict__ wv,
+                                            const g_t<const double>* __restrict__ sh,
+                                            long long ss, int n2, int b, int c0, int r, int lane) {
   const bool act = lane < b;
   double d = 1.0, wl = 0.0, wr = 0.0;
   if (act) {
     const long long c = c0 + lane;
-    d = wh[c * n2 + r] + wh[(c + 1) * n2 + r] + wv[c * (n2 + 1) + r] + wv[c * (n2 + 1) + r + 1];
+    d = wh[c * n2 + r] + wh[(c + 1) * n2 + r] + wv[c * (n2 + 1) + r] + wv[c * (n2 + 1) + r + 1] +
+        sh[(c * n2 + r) * ss];
     if (lane > 0) wl = wh[c * n2 + r];
     if (lane < b - 1) wr = wh[(c + 1) * n2 + r];
   }
@@ -211,7 +232,9 @@ __global__ __launch_bounds__(NT) void k_slab_factor(const ProbDev* __restrict__ 
   for (int j = 0; j < C; ++j) g[j] = (T)0;
   // raw edge weights of row r: wh left/right of the node, wv below/above; and
   // wv below/above the nodes of this lane's columns k0 .. k0+C-1
-  double rl[D], rr[D], rd[D], ru[D], cd[D][C], cu[D][C];
+  double rl[D], rr[D], rd[D], ru[D], rs[D], cd[D][C], cu[D][C];
+  const g_t<const double>* __restrict__ sh = gp((const double*)P[it].shift);
+  const long long ss = P[it].shift_stride;
   // unconditional loads from clamped rows (a load skipped on some path makes
   // the compiler wait for every outstanding load); masked where used
   auto load = [&](int d, int t) __attribute__((always_inline)) {
@@ -221,6 +244,7 @@ __global__ __launch_bounds__(NT) void k_slab_factor(const ProbDev* __restrict__ 
     rr[d] = wh[(c + 1) * n2 + r];
     rd[d] = wv[c * (n2 + 1) + r];
     ru[d] = wv[c * (n2 + 1) + r + 1];
+    rs[d] = sh[(c * n2 + r) * ss];
 #pragma unroll
     for (int j = 0; j < C; ++j) {
       const long long ck = (long long)s * (b + 1) + min(k0 + j, b - 1);
@@ -237,7 +261,7 @@ __global__ __launch_bounds__(NT) void k_slab_factor(const ProbDev* __restrict__ 
       const int t = t0 + d;
       if (t < t_hi) {  // uniform
         const int r = dir == 0 ? t : n2 - 1 - t;
-        const double whl = rl[d], whr = rr[d], wvd = rd[d], wvu = ru[d];
+        const double whl = rl[d], whr = rr[d], wvd = rd[d], wvu = ru[d], csh = rs[d];
         // W of the coupling to the previous row step and W_r, at this lane's columns
         T wk[C], wup[C];
 #pragma unroll
@@ -247,7 +271,7 @@ __global__ __launch_bounds__(NT) void k_slab_factor(const ProbDev* __restrict__ 
           wup[j] = ak ? (T)cd[d][j] : (T)0;
         }
         load(d, t + D);
-        const T dd = act ? (T)(whl + whr + wvd + wvu) : (T)1;
+        const T dd = act ? (T)(whl + whr + wvd + wvu + csh) : (T)1;
         const T wl = (act && i > 0) ? (T)whl : (T)0;
         const T wr = (act && i < b - 1) ? (T)whr : (T)0;
         const T wc = (act && t > 0) ? (T)(dir == 0 ? wvd : wvu) : (T)0;
@@ -446,7 +470,8 @@ __global__ __launch_bounds__(256) void k_sigma(const ProbDev* __restrict__ P,
   __shared__ T pivrow[4][PPW][2][RW];
   __shared__ T wsh[4][PPW][BP];
   T a[BP];
-  build_D_row<T, BP>(a, wh, wv, n2, b, c0, rho, i);
+  build_D_row<T, BP>(a, wh, wv, gp((const double*)P[it].shift), P[it].shift_stride, n2, b, c0,
+                     rho, i);
   // top coupling W_rho Gl_{rho-1} W_rho (column weights through LDS), bottom
   // coupling W_{rho+1} Hr_{rho+1} (Hr already carries the column scaling);
   // loads from clamped rows, masked by the weights
@@ -652,7 +677,7 @@ __device__ __forceinline__ void assemble_tile(const ProbDev& pd, int j, int ti, 
     const long long cj = (long long)j * (b + 1) + b;
     const int R = min(ti * 64 + tx, n2 - 1), C = min(tj * 64 + tx, n2 - 1);
     aoo_d[tx] = wh[cj * n2 + R] + wh[(cj + 1) * n2 + R] + wv[cj * (n2 + 1) + R] +
-                wv[cj * (n2 + 1) + R + 1];
+                wv[cj * (n2 + 1) + R + 1] + gp((const double*)pd.shift)[(cj * n2 + R) * pd.shift_stride];
     aoo_s[tx] = -wv[cj * (n2 + 1) + R];
     aoo_c = -wv[cj * (n2 + 1) + C];
   }
@@ -744,8 +769,12 @@ void plan_coef_weights(Plan& plan, const std::vector<ProbDev>& probs) {
     cc.push_back((int)fill_wgs((long long)(d.n1 + 2) * (d.n2 + 2)));
     cw.push_back((int)fill_wgs((long long)(d.n1 + 1) * d.n2 + (long long)d.n1 * (d.n2 + 1)));
   }
-  long long tc, tw;
-  const size_t oc = plan.add_offsets(cc, &tc), ow = plan.add_offsets(cw, &tw);
+  std::vector<int> cs;
+  for (const ProbDev& d : probs)
+    cs.push_back((int)fill_wgs(d.shift_src ? (long long)d.n1 * d.n2 : 1));
+  long long tc, tw, ts;
+  const size_t oc = plan.add_offsets(cc, &tc), ow = plan.add_offsets(cw, &tw),
+               os = plan.add_offsets(cs, &ts);
   const int count = (int)probs.size();
   plan.step([=](const char* dev, hipStream_t st) {
     hipLaunchKernelGGL(k_status_clear, dim3((unsigned)((4 * count + 255) / 256)), dim3(256), 0,
@@ -753,6 +782,9 @@ void plan_coef_weights(Plan& plan, const std::vector<ProbDev>& probs) {
     SLAB_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_coef, dim3((unsigned)tc), dim3(256), 0, st, dev_at<ProbDev>(dev, pd),
                        dev_at<int>(dev, oc), count);
+    SLAB_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_shift, dim3((unsigned)ts), dim3(256), 0, st, dev_at<ProbDev>(dev, pd),
+                       dev_at<int>(dev, os), count);
     SLAB_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_weights, dim3((unsigned)tw), dim3(256), 0, st, dev_at<ProbDev>(dev, pd),
                        dev_at<int>(dev, ow), count);

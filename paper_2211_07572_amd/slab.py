@@ -43,7 +43,7 @@ class SlabError(RuntimeError):
 
 class slab_problem(ctypes.Structure):
     _fields_ = [("n1", ctypes.c_int32), ("n2", ctypes.c_int32), ("b", ctypes.c_int32),
-                ("h", ctypes.c_double), ("kappa", ctypes.c_void_p)]
+                ("h", ctypes.c_double), ("kappa", ctypes.c_void_p), ("shift", ctypes.c_void_p)]
 
 
 class slab_options(ctypes.Structure):
@@ -193,15 +193,22 @@ def _vec_shape(t, n2, n1):
 def slab_factor(kappa, n2: int, n1: int, b: int, h: float | None = None, precision: int = SLAB_FP64,
                 tol: float = 1e-10, max_iter: int = 10, keep_reduced: bool = False,
                 coef_log: bool = False, odd_even: bool = False, tile: int = 0,
-                stream=None) -> SlabHandle:
+                shift=None, stream=None) -> SlabHandle:
     """Alg. 3 on the device field kappa (or theta = log kappa), shape (n1+2, n2+2).
-    tile: FP32 block-product tile (0 automatic, 64 or 128)."""
+    tile: FP32 block-product tile (0 automatic, 64 or 128).  shift: optional
+    diagonal term c_p on the interior nodes, shape (n1, n2) (c = -k^2 b(x): the
+    Helmholtz term)."""
     L = load_library()
     if h is None:
         h = 1.0 / (n2 + 1)
     if tuple(kappa.shape) != (n1 + 2, n2 + 2):
         raise ValueError(f"kappa must have shape {(n1 + 2, n2 + 2)}")
-    prob = slab_problem(n1, n2, b, float(h), _dev_f64(kappa, "kappa"))
+    sh = None
+    if shift is not None:
+        if tuple(shift.shape) != (n1, n2):
+            raise ValueError(f"shift must have shape {(n1, n2)}")
+        sh = _dev_f64(shift, "shift")
+    prob = slab_problem(n1, n2, b, float(h), _dev_f64(kappa, "kappa"), sh)
     flags = ((SLAB_KEEP_REDUCED if keep_reduced else 0) | (SLAB_COEF_LOG if coef_log else 0)
              | (SLAB_ODD_EVEN if odd_even else 0))
     opts = slab_options(precision, float(tol), int(max_iter), flags, int(tile))
@@ -479,7 +486,7 @@ class SlabBatch:
 def slab_factor_batch(kappas, dims, precision: int = SLAB_FP64, tol: float = 1e-10,
                       max_iter: int = 10, odd_even: bool = True, graph: bool = False,
                       keep_reduced: bool = False, tile: int = 0, coef_log: bool = False,
-                      stream=None) -> SlabBatch:
+                      shifts=None, stream=None) -> SlabBatch:
     """Factor independent problems together.  kappas: CUDA float64 tensors of
     shape (n1+2, n2+2); dims: (n2, n1, b) or (n2, n1, b, h) per problem."""
     L = load_library()
@@ -494,7 +501,12 @@ def slab_factor_batch(kappas, dims, precision: int = SLAB_FP64, tol: float = 1e-
     for i, ((n2, n1, b, h), k) in enumerate(zip(full, kappas)):
         if tuple(k.shape) != (n1 + 2, n2 + 2):
             raise ValueError(f"kappa {i} must have shape {(n1 + 2, n2 + 2)}")
-        arr[i] = slab_problem(n1, n2, b, h, _dev_f64(k, f"kappa[{i}]"))
+        sh = None
+        if shifts is not None and shifts[i] is not None:
+            if tuple(shifts[i].shape) != (n1, n2):
+                raise ValueError(f"shift {i} must have shape {(n1, n2)}")
+            sh = _dev_f64(shifts[i], f"shift[{i}]")
+        arr[i] = slab_problem(n1, n2, b, h, _dev_f64(k, f"kappa[{i}]"), sh)
     flags = ((SLAB_ODD_EVEN if odd_even else 0) | (SLAB_GRAPH if graph else 0)
              | (SLAB_KEEP_REDUCED if keep_reduced else 0) | (SLAB_COEF_LOG if coef_log else 0))
     opts = slab_options(precision, float(tol), int(max_iter), flags, int(tile))

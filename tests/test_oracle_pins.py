@@ -586,3 +586,71 @@ def test_apply_T_equals_assembled_blocks():
             ref[j] += (s1.T_up[j] @ x[j + 1].T).T
             ref[j + 1] += (s1.T_lo[j] @ x[j].T).T
     assert np.abs(y - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+# ---------------------------------------------- Helmholtz term (eq. (var_helm))
+
+@pytest.mark.parametrize("ppw", [6.0, 12.0])
+@pytest.mark.parametrize("n2,n1,b,m", [(16, 24, 7, 3), (8, 16, 7, 2), (5, 8, 1, 4)])
+def test_helmholtz_brute_force(n2, n1, b, m, ppw):
+    """-Laplace u - k^2 u at a few points per wavelength (indefinite A): u, T
+    and the pivots of Alg. 1 against dense brute force, both orders."""
+    h = 1.0 / (n2 + 1)
+    c = G.helmholtz_shift(n2, n1, ppw, h)
+    p = O.make_problem(G.kappa_const(n2, n1), n2, n1, b, h, shift=c)
+    A = p.A.toarray()
+    ev = np.linalg.eigvalsh(A)
+    if ppw == 6.0:   # a few wavelengths across: A is indefinite
+        assert ev.min() < 0 < ev.max()
+    f = G.rhs_uniform(n2, n1, 2, 12)
+    F = f.reshape(2, -1).T
+    u_ref = np.linalg.solve(A, F).T.reshape(f.shape)
+    e, o = p.maps["perm_even"], p.maps["perm_odd"]
+    T_ref = A[np.ix_(o, o)] - A[np.ix_(o, e)] @ np.linalg.solve(A[np.ix_(e, e)], A[np.ix_(e, o)])
+    for order in ("sweep", "odd_even"):
+        fac = O.factor(p, order=order)
+        u = O.solve(fac, f)
+        assert np.abs(u - u_ref).max() <= 1e-11 * np.abs(u_ref).max(), order
+        assert np.abs(_dense_T(fac) - T_ref).max() <= 1e-12 * np.abs(T_ref).max()
+
+
+@pytest.mark.parametrize("n2,n1,b", [(31, 32, 7), (40, 30, 4)])
+def test_helmholtz_fast_solver(n2, n1, b):
+    """Constant k: the sine modes diagonalise A, eigenvalues lam_kl - k^2, so
+    the DST solve gives u for an indefinite A (k between eigenvalues)."""
+    h = 1.0 / (n2 + 1)
+    k1 = np.arange(1, n1 + 1)[:, None]
+    k2 = np.arange(1, n2 + 1)[None, :]
+    lam = (4 - 2 * np.cos(np.pi * k1 / (n1 + 1)) - 2 * np.cos(np.pi * k2 / (n2 + 1))) / h ** 2
+    c = G.helmholtz_shift(n2, n1, 8.0, h)
+    shifted = lam + c[0, 0]
+    assert shifted.min() < 0 < shifted.max() and np.abs(shifted).min() > 1e-4 * np.abs(shifted).max()
+    p = O.make_problem(G.kappa_const(n2, n1), n2, n1, b, h, shift=c)
+    f = G.rhs_uniform(n2, n1, 2, 4)
+    u_ref = np.stack([scipy.fft.idstn(scipy.fft.dstn(fi, type=1, norm="ortho") / shifted,
+                                      type=1, norm="ortho") for fi in f])
+    for order in ("sweep", "odd_even"):
+        u = O.solve(O.factor(p, order=order), f)
+        assert np.abs(u - u_ref).max() <= 1e-10 * np.abs(u_ref).max(), order
+
+
+def test_helmholtz_closed_form_T():
+    """kappa = 1, constant c: every sine mode of the interface decouples as
+    for the Laplacian with a_k shifted by c h^2 (pin P2 with a shift)."""
+    n2, n1, b = 20, 24, 3
+    h = 1.0 / (n2 + 1)
+    c = G.helmholtz_shift(n2, n1, 10.0, h)
+    p = O.make_problem(G.kappa_const(n2, n1), n2, n1, b, h, shift=c)
+    fac = O.factor(p)
+    Q = _dst_q(n2)
+    a = 4 - 2 * np.cos(np.pi * np.arange(1, n2 + 1) / (n2 + 1)) + c[0, 0] * h * h
+    ub = _cheb_u(b, a / 2)
+    ub1 = _cheb_u(b - 1, a / 2)
+    both = Q @ np.diag(a - 2 * ub1 / ub) @ Q / h ** 2
+    last = Q @ np.diag(a - ub1 / ub) @ Q / h ** 2
+    off = -Q @ np.diag(1 / ub) @ Q / h ** 2
+    scale = np.abs(both).max()
+    for j in range(p.m):
+        assert np.abs(fac.s1.T_diag[j] - (both if j < p.m - 1 else last)).max() <= 1e-12 * scale
+    for j in range(p.m - 1):
+        assert np.abs(fac.s1.T_up[j] - off).max() <= 1e-12 * scale
