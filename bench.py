@@ -208,7 +208,8 @@ def block_products(w: G.Workload, odd_even: bool, elem: int = 4):
 def kernel_source_digest(text: str | None = None) -> str:
     """Digest of the block-product GEMM's source: the k_gemm kernel and its
     launch code in k_dense.hip (from its header comment to the explicit
-    instantiations of plan_gemm), plus the shared headers it includes."""
+    instantiations of plan_gemm), common.h, and from group.h the workgroup
+    mapping (group_item, xcd_linear) and the GemmItem descriptor it reads."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_2211_07572_amd", "csrc")
     if text is None:
@@ -216,8 +217,11 @@ def kernel_source_digest(text: str | None = None) -> str:
     a = text.index("// Tiled MFMA GEMM")
     b = text.index("template void plan_gemm<double>")
     h = hashlib.sha256(text[a:b].encode())
-    for hdr in ("common.h", "group.h"):
-        h.update(open(os.path.join(csrc, hdr), "rb").read())
+    h.update(open(os.path.join(csrc, "common.h"), "rb").read())
+    grp = open(os.path.join(csrc, "group.h")).read()
+    for start, end in (("// Item owning workgroup bx", "// Refinement passes issued"),
+                       ("// One product C = beta C", "// One block-vector product")):
+        h.update(grp[grp.index(start):grp.index(end)].encode())
     return h.hexdigest()[:16]
 
 

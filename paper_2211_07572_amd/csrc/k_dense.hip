@@ -247,6 +247,9 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmItem* __restrict__ items
       }
 }
 
+#ifndef SLAB_GEMM128_TK
+#define SLAB_GEMM128_TK 16   // k per chunk of the 128-wide tiles
+#endif
 template <typename T, int TILE, int TK, bool CPRE = false>
 static void gemm_tile(bool ak, bool bn, bool vecok, unsigned grid, const GemmItem* items,
                       const int* offs, int count, T alpha, T beta, int flags, hipStream_t st) {
@@ -308,7 +311,7 @@ void plan_gemm(Plan& plan, bool ak, bool bn, const std::vector<GemmItem>& items,
       gemm_tile<T, 64, 32, true>(ak, bn, vecok, (unsigned)tot, dev_at<GemmItem>(dev, oi),
                                  dev_at<int>(dev, oo), count, alpha, beta, flags, st);
     else if (tile == 128)
-      gemm_tile<T, 128, 16>(ak, bn, vecok, (unsigned)tot, dev_at<GemmItem>(dev, oi),
+      gemm_tile<T, 128, SLAB_GEMM128_TK>(ak, bn, vecok, (unsigned)tot, dev_at<GemmItem>(dev, oi),
                             dev_at<int>(dev, oo), count, alpha, beta, flags, st);
     else
       gemm_tile<T, 64, 32>(ak, bn, vecok, (unsigned)tot, dev_at<GemmItem>(dev, oi),
