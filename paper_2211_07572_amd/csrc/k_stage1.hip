@@ -536,6 +536,9 @@ __global__ __launch_bounds__(256) void k_sigma(const ProbDev* __restrict__ P,
 //   PLR[s][r][rho] = wL_r (A_ee^-1)[(r,0),(rho,b-1)] wR_rho   (-> T_{s-1,s})
 //   PRL[s][r][rho] = wR_r (A_ee^-1)[(r,b-1),(rho,0)] wL_rho   (-> T_{s,s-1})
 // ---------------------------------------------------------------------------
+#ifndef SLAB_SCHUR_LDS
+#define SLAB_SCHUR_LDS 1
+#endif
 template <typename T, int BP>
 __global__ __launch_bounds__(256) void k_schur(const ProbDev* __restrict__ P,
                                                const int* __restrict__ offs, int count) {
@@ -574,14 +577,42 @@ __global__ __launch_bounds__(256) void k_schur(const ProbDev* __restrict__ P,
 #pragma unroll
     for (int mt = 0; mt < NM; ++mt) acc[nt][mt] = V4{0, 0, 0, 0};
 
+#if SLAB_SCHUR_LDS
+  // The four waves of a workgroup multiply by the same propagator Hr_r: it is
+  // loaded once per workgroup (each thread a quarter), one row step ahead,
+  // and parked in LDS (Hs[r & 1] holds Hr_r) instead of being fetched from
+  // L2 by every wave.
+  constexpr int HE = BP * BP / 256;   // elements per thread
+  __shared__ T Hs[2][BP * BP];
+  T hreg[HE];
+  if (rho0 + 1 < n2) {
+    const T* H = Hsw + ((size_t)s * n2 + rho0 + 1) * BP * BP;
+#pragma unroll
+    for (int e = 0; e < HE; ++e) Hs[(rho0 + 1) & 1][threadIdx.x + 256 * e] = H[threadIdx.x + 256 * e];
+  }
+  __syncthreads();
+#endif
+
   for (int r = rho0; r < n2; ++r) {
     if (r > rho0) {
-      const T* H = Hsw + ((size_t)s * n2 + r) * BP * BP;
       T afr[NM][NK];
+#if SLAB_SCHUR_LDS
+      const int rn = min(r + 1, n2 - 1);   // clamped: the last step reloads its own row
+      const T* Hn = Hsw + ((size_t)s * n2 + rn) * BP * BP;
+#pragma unroll
+      for (int e = 0; e < HE; ++e) hreg[e] = Hn[threadIdx.x + 256 * e];
+      const T* Hc = Hs[r & 1];
+#pragma unroll
+      for (int mt = 0; mt < NM; ++mt)
+#pragma unroll
+        for (int ks = 0; ks < NK; ++ks) afr[mt][ks] = Hc[(mt * NK + ks) * 64 + lane];
+#else
+      const T* H = Hsw + ((size_t)s * n2 + r) * BP * BP;
 #pragma unroll
       for (int mt = 0; mt < NM; ++mt)
 #pragma unroll
         for (int ks = 0; ks < NK; ++ks) afr[mt][ks] = H[(mt * NK + ks) * 64 + lane];
+#endif
       V4 nacc[2][NM];
 #pragma unroll
       for (int nt = 0; nt < 2; ++nt)
@@ -598,6 +629,11 @@ __global__ __launch_bounds__(256) void k_schur(const ProbDev* __restrict__ P,
       for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
         for (int mt = 0; mt < NM; ++mt) acc[nt][mt] = nacc[nt][mt];
+#if SLAB_SCHUR_LDS
+#pragma unroll
+      for (int e = 0; e < HE; ++e) Hs[(r + 1) & 1][threadIdx.x + 256 * e] = hreg[e];
+      __syncthreads();
+#endif
     }
     // start the chains of rho = r
     const int jr = r - rb;
