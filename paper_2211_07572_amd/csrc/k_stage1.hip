@@ -539,6 +539,9 @@ __global__ __launch_bounds__(256) void k_sigma(const ProbDev* __restrict__ P,
 #ifndef SLAB_SCHUR_LDS
 #define SLAB_SCHUR_LDS 1
 #endif
+#ifndef SLAB_SCHUR_ROWS
+#define SLAB_SCHUR_ROWS 1   // propagator rows per barrier (2 measured slower)
+#endif
 template <typename T, int BP>
 __global__ __launch_bounds__(256) void k_schur(const ProbDev* __restrict__ P,
                                                const int* __restrict__ offs, int count) {
@@ -579,16 +582,20 @@ __global__ __launch_bounds__(256) void k_schur(const ProbDev* __restrict__ P,
 
 #if SLAB_SCHUR_LDS
   // The four waves of a workgroup multiply by the same propagator Hr_r: it is
-  // loaded once per workgroup (each thread a quarter), one row step ahead,
-  // and parked in LDS (Hs[r & 1] holds Hr_r) instead of being fetched from
-  // L2 by every wave.
-  constexpr int HE = BP * BP / 256;   // elements per thread
-  __shared__ T Hs[2][BP * BP];
-  T hreg[HE];
-  if (rho0 + 1 < n2) {
-    const T* H = Hsw + ((size_t)s * n2 + rho0 + 1) * BP * BP;
+  // loaded once per workgroup (each thread a quarter) and parked in LDS
+  // instead of being fetched from L2 by every wave.  Rows go in groups of G
+  // (one barrier per group): while a group is multiplied, the next group's
+  // propagators are in flight in registers; a ring of 2G slots holds them
+  // (row r in slot (r - rho0 - 1) % 2G).
+  constexpr int HE = BP * BP / 256;   // elements per thread and row
+  constexpr int G = (BP == 64 && sizeof(T) == 8) ? 1 : SLAB_SCHUR_ROWS;
+  __shared__ T Hs[2 * G][BP * BP];
+  T hreg[G][HE];
 #pragma unroll
-    for (int e = 0; e < HE; ++e) Hs[(rho0 + 1) & 1][threadIdx.x + 256 * e] = H[threadIdx.x + 256 * e];
+  for (int q2 = 0; q2 < G; ++q2) {
+    const T* H = Hsw + ((size_t)s * n2 + min(rho0 + 1 + q2, n2 - 1)) * BP * BP;
+#pragma unroll
+    for (int e = 0; e < HE; ++e) Hs[q2][threadIdx.x + 256 * e] = H[threadIdx.x + 256 * e];
   }
   __syncthreads();
 #endif
@@ -597,11 +604,18 @@ __global__ __launch_bounds__(256) void k_schur(const ProbDev* __restrict__ P,
     if (r > rho0) {
       T afr[NM][NK];
 #if SLAB_SCHUR_LDS
-      const int rn = min(r + 1, n2 - 1);   // clamped: the last step reloads its own row
-      const T* Hn = Hsw + ((size_t)s * n2 + rn) * BP * BP;
+      const int ph = (r - rho0 - 1) % G;     // position in the group (uniform)
+      const int slot = (r - rho0 - 1) % (2 * G);
+      if (ph == 0) {
+        // the next group's propagators (clamped rows past the end are not used)
 #pragma unroll
-      for (int e = 0; e < HE; ++e) hreg[e] = Hn[threadIdx.x + 256 * e];
-      const T* Hc = Hs[r & 1];
+        for (int q2 = 0; q2 < G; ++q2) {
+          const T* Hn = Hsw + ((size_t)s * n2 + min(r + G + q2, n2 - 1)) * BP * BP;
+#pragma unroll
+          for (int e = 0; e < HE; ++e) hreg[q2][e] = Hn[threadIdx.x + 256 * e];
+        }
+      }
+      const T* Hc = Hs[slot];
 #pragma unroll
       for (int mt = 0; mt < NM; ++mt)
 #pragma unroll
@@ -630,9 +644,14 @@ __global__ __launch_bounds__(256) void k_schur(const ProbDev* __restrict__ P,
 #pragma unroll
         for (int mt = 0; mt < NM; ++mt) acc[nt][mt] = nacc[nt][mt];
 #if SLAB_SCHUR_LDS
+      if (ph == G - 1) {
+        const int nslot = (slot + 1) % (2 * G);   // first slot of the next group
 #pragma unroll
-      for (int e = 0; e < HE; ++e) Hs[(r + 1) & 1][threadIdx.x + 256 * e] = hreg[e];
-      __syncthreads();
+        for (int q2 = 0; q2 < G; ++q2)
+#pragma unroll
+          for (int e = 0; e < HE; ++e) Hs[(nslot + q2) % (2 * G)][threadIdx.x + 256 * e] = hreg[q2][e];
+        __syncthreads();
+      }
 #endif
     }
     // start the chains of rho = r
