@@ -35,16 +35,24 @@ namespace slab {
 // tile index over the lower triangle); GEMM_A_LOWER / GEMM_B_LOWER skip the
 // k ranges where op(A) / op(B) is known to be zero (lower-triangular factors).
 // ---------------------------------------------------------------------------
-template <typename T, int TILE, int TK, bool AK, bool BN, bool VECOK, bool CPRE = false>
-__global__ __launch_bounds__(256) void k_gemm(const GemmItem* __restrict__ items,
+#ifndef SLAB_GEMM_WAVES
+#define SLAB_GEMM_WAVES 1   // minimum waves per SIMD asked of the register allocator
+                                   // (4 fits the 128 tile in 126 registers: no faster)
+#endif
+template <typename T, int TILE, int TK, bool AK, bool BN, bool VECOK, bool CPRE = false,
+          int WNF = 1>
+__global__ __launch_bounds__(256, SLAB_GEMM_WAVES) void k_gemm(const GemmItem* __restrict__ items,
                                               const int* __restrict__ offs, int count, T alpha,
                                               T beta, int flags) {
   typedef typename acc4<T>::type V4;
-  constexpr int TM = TILE, TN = TILE;
-  constexpr int FM = TILE / 32, FN = TILE / 32;  // 16x16 MFMA tiles per wave and direction
+  // WNF = 2: TILE x 2 TILE output tiles, each wave TILE/2 x TILE (twice the
+  // MFMAs per fragment read; full-output products only)
+  constexpr int TM = TILE, TN = TILE * WNF;
+  constexpr int FM = TM / 32, FN = TN / 32;  // 16x16 MFMA tiles per wave and direction
   constexpr int VEC = 16 / sizeof(T);
-  constexpr int NV = TM * TK / 256 / VEC;  // vectors per thread per operand and chunk
-  static_assert(NV >= 1 && TM * TK == NV * VEC * 256, "tile shape");
+  constexpr int NV = TM * TK / 256 / VEC;  // vectors of op(A) per thread and chunk
+  constexpr int NVB = TN * TK / 256 / VEC;  // vectors of op(B)
+  static_assert(NV >= 1 && TM * TK == NV * VEC * 256 && NVB * VEC * 256 == TN * TK, "tile shape");
   typedef T vt __attribute__((ext_vector_type(VEC)));
   __shared__ T As[2][TK][TM + 4];
   __shared__ T Bs[2][TK][TN + 4];
@@ -89,7 +97,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmItem* __restrict__ items
   const int kmax = (flags & GEMM_A_LOWER) ? min(K, i0 + TM) : K;
   kmin = (kmin / TK) * TK;
 
-  vt ra[NV], rb[NV];
+  vt ra[NV], rb[NVB];
   auto load = [&](int k0) __attribute__((always_inline)) {
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
@@ -112,7 +120,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmItem* __restrict__ items
       }
     }
 #pragma unroll
-    for (int q = 0; q < NV; ++q) {
+    for (int q = 0; q < NVB; ++q) {
       const int v = tid + 256 * q;
       int col, kk;
       if (!BN) { kk = v / (TN / VEC); col = (v % (TN / VEC)) * VEC; }
@@ -149,6 +157,10 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmItem* __restrict__ items
         for (int e = 0; e < VEC; ++e)
           As[buf][kk][row + e] = (!VECOK || (kin && i0 + row + e < M)) ? ra[q][e] : (T)0;
       }
+    }
+#pragma unroll
+    for (int q = 0; q < NVB; ++q) {
+      const int v = tid + 256 * q;
       if (!BN) {
         const int kk = v / (TN / VEC), col = (v % (TN / VEC)) * VEC;
         const bool kin = k0 + kk < kmax;
@@ -250,17 +262,21 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmItem* __restrict__ items
 #ifndef SLAB_GEMM128_TK
 #define SLAB_GEMM128_TK 16   // k per chunk of the 128-wide tiles
 #endif
-template <typename T, int TILE, int TK, bool CPRE = false>
+#ifndef SLAB_GEMM_WIDE
+#define SLAB_GEMM_WIDE 0   // 128 x 256 tiles for full-output FP32 products (measured
+                                   // slower: 265 registers, one wave per SIMD)
+#endif
+template <typename T, int TILE, int TK, bool CPRE = false, int WNF = 1>
 static void gemm_tile(bool ak, bool bn, bool vecok, unsigned grid, const GemmItem* items,
                       const int* offs, int count, T alpha, T beta, int flags, hipStream_t st) {
 #define SLAB_GEMM_CASE(AKV, BNV)                                                                   \
   do {                                                                                             \
     if (vecok)                                                                                     \
-      hipLaunchKernelGGL((k_gemm<T, TILE, TK, AKV, BNV, true, CPRE>), dim3(grid), dim3(256), 0,   \
-                         st, items, offs, count, alpha, beta, flags);                              \
+      hipLaunchKernelGGL((k_gemm<T, TILE, TK, AKV, BNV, true, CPRE, WNF>), dim3(grid), dim3(256), \
+                         0, st, items, offs, count, alpha, beta, flags);                           \
     else                                                                                           \
-      hipLaunchKernelGGL((k_gemm<T, TILE, TK, AKV, BNV, false, CPRE>), dim3(grid), dim3(256), 0,  \
-                         st, items, offs, count, alpha, beta, flags);                              \
+      hipLaunchKernelGGL((k_gemm<T, TILE, TK, AKV, BNV, false, CPRE, WNF>), dim3(grid), dim3(256),\
+                         0, st, items, offs, count, alpha, beta, flags);                           \
   } while (0)
   if (!ak && !bn) SLAB_GEMM_CASE(false, false);
   else if (!ak && bn) SLAB_GEMM_CASE(false, true);
@@ -289,9 +305,11 @@ void plan_gemm(Plan& plan, bool ak, bool bn, const std::vector<GemmItem>& items,
   if (sizeof(T) == 4 && (force_tile == 64 || force_tile == 128)) tile = force_tile;
   if (cpre) tile = 64;
   ++plan.launches[cpre ? LK_GEMM_CPRE : (tile == 128 ? LK_GEMM128 : LK_GEMM64)];
+  // full-output products on 128-wide tiles take 128 x 256 tiles
+  const int wnf = (SLAB_GEMM_WIDE && tile == 128 && !cpre && !(flags & GEMM_LOWER_C)) ? 2 : 1;
   std::vector<int> c;
   for (const GemmItem& g : items) {
-    const long long tm = (g.M + tile - 1) / tile, tn = (g.N + tile - 1) / tile;
+    const long long tm = (g.M + tile - 1) / tile, tn = (g.N + tile * wnf - 1) / (tile * wnf);
     c.push_back((int)((flags & GEMM_LOWER_C) ? tm * (tm + 1) / 2 : tm * tn));
   }
   long long tot;
@@ -310,6 +328,10 @@ void plan_gemm(Plan& plan, bool ak, bool bn, const std::vector<GemmItem>& items,
     if (cpre)
       gemm_tile<T, 64, 32, true>(ak, bn, vecok, (unsigned)tot, dev_at<GemmItem>(dev, oi),
                                  dev_at<int>(dev, oo), count, alpha, beta, flags, st);
+    else if (tile == 128 && wnf == 2)
+      gemm_tile<T, 128, SLAB_GEMM128_TK, false, 2>(ak, bn, vecok, (unsigned)tot,
+                                                  dev_at<GemmItem>(dev, oi), dev_at<int>(dev, oo),
+                                                  count, alpha, beta, flags, st);
     else if (tile == 128)
       gemm_tile<T, 128, SLAB_GEMM128_TK>(ak, bn, vecok, (unsigned)tot, dev_at<GemmItem>(dev, oi),
                             dev_at<int>(dev, oo), count, alpha, beta, flags, st);
