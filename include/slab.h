@@ -91,10 +91,15 @@ typedef struct {
   const double* shift; /* device, n1*n2 FP64 (node (c, r) at c*n2 + r), finite, or NULL:
                           a diagonal term c_p added to A, (A u)_p += c_p u_p.  With
                           c = -k^2 b(x) it is the Helmholtz term of eq. (var_helm)
-                          (wavenumber k; the paper writes kappa for it).  The factor
-                          kernels are those of a positive definite A: a shift that
-                          makes A indefinite is reported as SLAB_E_BREAKDOWN.  Read
-                          during slab_factor (and again by slab_batch_run). */
+                          (wavenumber k; the paper writes kappa for it).  The slab
+                          interiors are factored as positive definite blocks (a shift
+                          that makes one indefinite is reported as SLAB_E_BREAKDOWN:
+                          for the Helmholtz term, k (b+1) h must stay below about pi,
+                          two slab widths per wavelength); the reduced matrix T may
+                          be indefinite: with a shift its pivot blocks are factored
+                          in signed form L J L^T (no pivoting; a zero pivot is
+                          SLAB_E_BREAKDOWN).  Read during slab_factor (and again by
+                          slab_batch_run). */
 } slab_problem;
 
 typedef struct {
@@ -276,6 +281,10 @@ int slab_export_reduced(slab_handle h, int32_t which, int32_t j, double* out, vo
 
 /* Sizes and timings of a handle: what = 0 m, 1 n1, 2 n2, 3 b, 4 precision,
    5 device bytes held, 6 the FP32 product tile in use (0: automatic),
+   7 the number of negative pivots of the signed block factorization of T
+   (problems with a shift; 0 otherwise), which is the number of negative
+   eigenvalues of T (Sylvester's law of inertia) and, with definite slab
+   interiors, of A (synchronous: copies the pivot signs to the host),
    10+p elapsed microseconds of factor phase p of the last
    factorization (0 slab factors, 1 boundary columns of the slab inverses,
    2 Schur propagation, 3 assembly of T, 4 block factorization of T, 5 the

@@ -12,6 +12,7 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -272,6 +273,7 @@ struct slab_handle_s {
   void* Linv = nullptr;
   void* Z = nullptr;
   void* Td = nullptr;  // odd-even order: U_e blocks (kept for the solve)
+  void* J = nullptr;   // pivot signs of the signed block factorization (with a shift)
   double* T64 = nullptr;
   double* O64 = nullptr;
   double* S64 = nullptr;
@@ -435,6 +437,9 @@ void persistent_layout(slab_handle h, Layout& L) {
   L.add(&h->Linv, m * nsq * e2);
   L.add(&h->Z, (m > 1 ? m - 1 : 1) * nsq * e2);
   if (h->odd_even) L.add(&h->Td, m * nsq * e2);
+  // a diagonal term can make T indefinite: its pivot blocks are factored in
+  // signed form L J L^T
+  if (h->shift_src) L.add(&h->J, m * n * e2);
   // FP64 reduced blocks: exported on request, and always kept in mixed
   // precision, where the reduced solve is refined against them
   if ((h->flags & SLAB_KEEP_REDUCED) || h->precision == SLAB_MIXED) {
@@ -534,6 +539,7 @@ void plan_chunk(Plan& p, const std::vector<slab_handle>& hs, const std::vector<P
     Stage2Prob q;
     q.n = hs[i]->n2; q.m = hs[i]->m; q.Td = t.Td; q.To = t.To; q.Linv = hs[i]->Linv;
     q.Z = hs[i]->Z; q.S64 = hs[i]->S64; q.status = hs[i]->status;
+    q.J = hs[i]->J; q.indef = hs[i]->J ? 1 : 0;
     s2.push_back(q);
   }
   // one forced product tile for the chunk when its problems agree on it
@@ -740,6 +746,7 @@ void plan_pass(Plan& p, const std::vector<SolveJob>& jobs, bool first, bool tran
     std::memset(&r, 0, sizeof(r));
     r.n = h->n2; r.m = h->m; r.nrhs = j.nrhs; r.Linv = h->Linv; r.Z = h->Z; r.Td = h->Td;
     r.ft = h->ws.ft; r.yt = h->ws.yt; r.tt = h->ws.tt; r.part = h->ws.bpart;
+    r.J = h->J;
     r.live = d.live;
     if (h->precision == SLAB_MIXED) {
       r.T64 = h->T64; r.O64 = h->O64;
@@ -829,9 +836,10 @@ int finish_jobs(std::vector<SolveJob>& jobs, const std::vector<int>& it,
       jobs[i].info->failed_block = -1;
     }
     if (!(worst[i] <= jobs[i].h->tol) && rc == SLAB_OK) {
-      set_error("refinement stopped at relative residual " + std::to_string(worst[i]) +
-                " after " + std::to_string(it[i]) + " passes (tol " +
-                std::to_string(jobs[i].h->tol) + ")" +
+      char buf[96];
+      std::snprintf(buf, sizeof buf, "%.3e after %d passes (tol %.3e)", worst[i], it[i],
+                    jobs[i].h->tol);
+      set_error(std::string("refinement stopped at relative residual ") + buf +
                 (jobs.size() > 1 ? " in problem " + std::to_string(i) : std::string()));
       rc = SLAB_E_NOCONV;
     }
@@ -1713,6 +1721,19 @@ int slab_query(slab_handle h, int32_t what, int64_t* value) {
     case 4: *value = h->precision; return SLAB_OK;
     case 5: *value = (int64_t)h->mem.bytes; return SLAB_OK;
     case 6: *value = h->tile; return SLAB_OK;
+    case 7: {  // negative pivots of the signed block factorization (0 without one)
+      *value = 0;
+      if (!h->J) return SLAB_OK;
+      SLAB_HIP_CHECK(hipSetDevice(h->device));
+      const size_t cnt = (size_t)h->m * h->n2;
+      std::vector<char> sg(cnt * h->esz2);
+      SLAB_HIP_CHECK(hipMemcpy(sg.data(), h->J, sg.size(), hipMemcpyDeviceToHost));
+      int64_t neg = 0;
+      for (size_t i = 0; i < cnt; ++i)
+        neg += h->esz2 == 8 ? (((const double*)sg.data())[i] < 0) : (((const float*)sg.data())[i] < 0);
+      *value = neg;
+      return SLAB_OK;
+    }
     default:
       if (what >= 10 && what < 16) { *value = h->phase_us[what - 10]; return SLAB_OK; }
       if (what >= 20 && what < 20 + LK_COUNT) { *value = h->launches[what - 20]; return SLAB_OK; }

@@ -93,11 +93,13 @@ struct ProbDev {
 // One pivot block of the block factorization.
 struct FactorItem {
   void* S;        // n x n, lower triangle; overwritten by L
-  void* Li;       // n x n, receives L^-1 (L L^T = S)
+  void* Li;       // n x n, receives L^-1 (L J L^T = S)
   double* S64;    // optional FP64 copy of S before the factorization
+  void* J = nullptr;  // n entries: the signs of the pivots, J = diag(+-1)
   int* status;
   int n;
   int blk;        // interface index reported on breakdown
+  int indef = 0;      // 1: negative pivots are allowed (S symmetric indefinite)
 };
 
 // One product C = beta C + alpha op(A) op(B) (row-major, leading dimensions).
@@ -107,6 +109,10 @@ struct GemmItem {
   void* C;
   int M, N, K;
   int lda, ldb, ldc;
+  // optional: op(A)(i, k) is taken times kscale[k] (the signs J of an
+  // L J L^T factorization between the two operands); all items of a launch
+  // have one or none
+  const void* kscale = nullptr;
 };
 
 // One block-vector product y = beta xin + alpha op(M) x over nrhs columns.
@@ -121,6 +127,9 @@ struct BmvItem {
   // 16*ceil(nrhs/16) columns of n), or null: the product is not split
   void* part;
   const int* live;  // refinement flag of the problem (see item_done), or null
+  // optional: x(k) is taken times xscale[k] (pivot signs J); all items of a
+  // launch have one or none
+  const void* xscale = nullptr;
 };
 
 // Most k-splits of a small block-vector launch; scratch per item in elements.
@@ -186,6 +195,7 @@ struct ReducedDev {
   void* yt;
   void* tt;         // nrhs x n temporary
   void* part;       // BMV_PART_SLOTS partial-product scratches (bmv_part_elems each)
+  const void* J;    // pivot signs (m blocks of n), or null: all +1 (L L^T)
   // refinement against the FP64 reduced matrix (null T64: none): diagonal
   // blocks T64[j], couplings O64[j] = T_{j,j+1}; FP64 right-hand side g64,
   // solution u64 and residual r64, all [j][c][r]
@@ -205,6 +215,8 @@ struct Stage2Prob {
   void* Linv;
   void* Z;        // m-1 blocks: Z_j (Alg. 1) or V_e (odd-even)
   double* S64;
+  void* J = nullptr;  // m blocks of n pivot signs
+  int indef = 0;      // signed (L J L^T) factorization of every pivot block
   int* status;
 };
 

@@ -7,12 +7,20 @@
 // block is formed as
 //   S_{j+1} = T_{j+1,j+1} - Z_j^T Z_j,   Z_j = L_j^-1 T_{j,j+1},
 // which equals T_{j+1,j+1} - T_{j+1,j} S_j^-1 T_{j,j+1} since T_{j+1,j} = T_{j,j+1}^T.
+// A Helmholtz term (eq. (var_helm)) can make T indefinite while the slab
+// interiors stay definite; the pivot blocks are then factored in signed form
+// S_j = L_j J_j L_j^T, J_j = diag(+-1) (the signs of the pivots of the
+// elimination without pivoting), S_j^-1 = L_j^-T J_j L_j^-1, and every product
+// that passes through S_j^-1 carries J_j between its two factors:
+//   S_{j+1} = T_{j+1,j+1} - Z_j^T J_j Z_j.
 // The factorization of each S_j is right-looking in 64-column panels; the
 // identity carried along as extra columns turns into L_j^-1 (forward
 // substitution with a matrix right-hand side).  All products run on
 // 16x16x4 MFMA tiles in the working precision (FP32 or FP64).
 #include "launch.h"
 
+#include <cstdio>
+#include <cstdlib>
 #include <map>
 #include <mutex>
 
@@ -39,8 +47,9 @@ namespace slab {
 #define SLAB_GEMM_WAVES 1   // minimum waves per SIMD asked of the register allocator
                                    // (4 fits the 128 tile in 126 registers: no faster)
 #endif
+// KS: op(A)(i, k) is taken times items[].kscale[k] (pivot signs J).
 template <typename T, int TILE, int TK, bool AK, bool BN, bool VECOK, bool CPRE = false,
-          int WNF = 1>
+          int WNF = 1, bool KS = false>
 __global__ __launch_bounds__(256, SLAB_GEMM_WAVES) void k_gemm(const GemmItem* __restrict__ items,
                                               const int* __restrict__ offs, int count, T alpha,
                                               T beta, int flags) {
@@ -63,6 +72,7 @@ __global__ __launch_bounds__(256, SLAB_GEMM_WAVES) void k_gemm(const GemmItem* _
   const g_t<const T>* __restrict__ A = gp((const T*)items[itm].A);
   const g_t<const T>* __restrict__ B = gp((const T*)items[itm].B);
   g_t<T>* C = gp((T*)items[itm].C);
+  const g_t<const T>* __restrict__ ksc = gp((const T*)items[itm].kscale);
   const int M = items[itm].M, N = items[itm].N, K = items[itm].K;
   const long long lda = items[itm].lda, ldb = items[itm].ldb, ldc = items[itm].ldc;
   int ti, tj;
@@ -98,6 +108,8 @@ __global__ __launch_bounds__(256, SLAB_GEMM_WAVES) void k_gemm(const GemmItem* _
   kmin = (kmin / TK) * TK;
 
   vt ra[NV], rb[NVB];
+  // KS: the scales of the k indices of ra (clamped loads, used in park())
+  T rk[KS ? NV : 1][KS && !AK ? VEC : 1];
   auto load = [&](int k0) __attribute__((always_inline)) {
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
@@ -106,6 +118,11 @@ __global__ __launch_bounds__(256, SLAB_GEMM_WAVES) void k_gemm(const GemmItem* _
       if (!AK) { row = v / (TK / VEC); kk = (v % (TK / VEC)) * VEC; }
       else { kk = v / (TM / VEC); row = (v % (TM / VEC)) * VEC; }
       const long long gi = i0 + row, gk = k0 + kk;
+      if (KS) {
+#pragma unroll
+        for (int e = 0; e < (AK ? 1 : VEC); ++e)
+          rk[KS ? q : 0][KS && !AK ? e : 0] = ksc[min(gk + e, (long long)K - 1)];
+      }
       if (VECOK) {
         // nothing here may touch the loaded value (that would wait for the
         // load): elements outside the operand are zeroed in park()
@@ -148,14 +165,18 @@ __global__ __launch_bounds__(256, SLAB_GEMM_WAVES) void k_gemm(const GemmItem* _
         const int row = v / (TK / VEC), kk = (v % (TK / VEC)) * VEC;
         const bool rin = i0 + row < M;
 #pragma unroll
-        for (int e = 0; e < VEC; ++e)
-          As[buf][kk + e][row] = (!VECOK || (rin && k0 + kk + e < kmax)) ? ra[q][e] : (T)0;
+        for (int e = 0; e < VEC; ++e) {
+          const T w = KS ? ra[q][e] * rk[KS ? q : 0][KS ? e : 0] : ra[q][e];
+          As[buf][kk + e][row] = (!VECOK || (rin && k0 + kk + e < kmax)) ? w : (T)0;
+        }
       } else {
         const int kk = v / (TM / VEC), row = (v % (TM / VEC)) * VEC;
         const bool kin = k0 + kk < kmax;
 #pragma unroll
-        for (int e = 0; e < VEC; ++e)
-          As[buf][kk][row + e] = (!VECOK || (kin && i0 + row + e < M)) ? ra[q][e] : (T)0;
+        for (int e = 0; e < VEC; ++e) {
+          const T w = KS ? ra[q][e] * rk[KS ? q : 0][0] : ra[q][e];
+          As[buf][kk][row + e] = (!VECOK || (kin && i0 + row + e < M)) ? w : (T)0;
+        }
       }
     }
 #pragma unroll
@@ -266,22 +287,28 @@ __global__ __launch_bounds__(256, SLAB_GEMM_WAVES) void k_gemm(const GemmItem* _
 #define SLAB_GEMM_WIDE 0   // 128 x 256 tiles for full-output FP32 products (measured
                                    // slower: 265 registers, one wave per SIMD)
 #endif
+// ks (scaled k of op(A)) exists for the two operand forms that use it: the
+// updates op(A) = U^T (ak, !bn) and the factorization's trailing update
+// (!ak, bn); plan_gemm checks the form.
 template <typename T, int TILE, int TK, bool CPRE = false, int WNF = 1>
-static void gemm_tile(bool ak, bool bn, bool vecok, unsigned grid, const GemmItem* items,
+static void gemm_tile(bool ak, bool bn, bool vecok, bool ks, unsigned grid, const GemmItem* items,
                       const int* offs, int count, T alpha, T beta, int flags, hipStream_t st) {
-#define SLAB_GEMM_CASE(AKV, BNV)                                                                   \
+#define SLAB_GEMM_CASE(AKV, BNV, KSV)                                                              \
   do {                                                                                             \
     if (vecok)                                                                                     \
-      hipLaunchKernelGGL((k_gemm<T, TILE, TK, AKV, BNV, true, CPRE, WNF>), dim3(grid), dim3(256), \
-                         0, st, items, offs, count, alpha, beta, flags);                           \
+      hipLaunchKernelGGL((k_gemm<T, TILE, TK, AKV, BNV, true, CPRE, WNF, KSV>), dim3(grid),       \
+                         dim3(256), 0, st, items, offs, count, alpha, beta, flags);                \
     else                                                                                           \
-      hipLaunchKernelGGL((k_gemm<T, TILE, TK, AKV, BNV, false, CPRE, WNF>), dim3(grid), dim3(256),\
-                         0, st, items, offs, count, alpha, beta, flags);                           \
+      hipLaunchKernelGGL((k_gemm<T, TILE, TK, AKV, BNV, false, CPRE, WNF, KSV>), dim3(grid),      \
+                         dim3(256), 0, st, items, offs, count, alpha, beta, flags);                \
   } while (0)
-  if (!ak && !bn) SLAB_GEMM_CASE(false, false);
-  else if (!ak && bn) SLAB_GEMM_CASE(false, true);
-  else if (ak && !bn) SLAB_GEMM_CASE(true, false);
-  else SLAB_GEMM_CASE(true, true);
+  if (ks) {
+    if (ak && !bn) SLAB_GEMM_CASE(true, false, true);
+    else SLAB_GEMM_CASE(false, true, true);
+  } else if (!ak && !bn) SLAB_GEMM_CASE(false, false, false);
+  else if (!ak && bn) SLAB_GEMM_CASE(false, true, false);
+  else if (ak && !bn) SLAB_GEMM_CASE(true, false, false);
+  else SLAB_GEMM_CASE(true, true, false);
 #undef SLAB_GEMM_CASE
 }
 
@@ -289,6 +316,20 @@ template <typename T>
 void plan_gemm(Plan& plan, bool ak, bool bn, const std::vector<GemmItem>& items, T alpha, T beta,
                int flags, int force_tile) {
   if (items.empty()) return;
+  // items with scaled k and items without go to launches of their own
+  const bool ks = items[0].kscale != nullptr;
+  for (const GemmItem& g : items)
+    if ((g.kscale != nullptr) != ks) {
+      std::vector<GemmItem> with, without;
+      for (const GemmItem& h : items) (h.kscale ? with : without).push_back(h);
+      plan_gemm<T>(plan, ak, bn, with, alpha, beta, flags, force_tile);
+      plan_gemm<T>(plan, ak, bn, without, alpha, beta, flags, force_tile);
+      return;
+    }
+  if (ks && !((ak && !bn) || (!ak && bn))) {  // a planner's mistake, not an input's
+    std::fprintf(stderr, "slab: plan_gemm: scaled k only for op(A) = A^T with B, or A with B^T\n");
+    std::abort();
+  }
   // 128-wide tiles once there are enough of them for four per compute unit,
   // unless the caller forces a width (FP32 only)
   long long area = 0;
@@ -326,17 +367,18 @@ void plan_gemm(Plan& plan, bool ak, bool bn, const std::vector<GemmItem>& items,
       SLAB_HIP_CHECK(hipEventRecord(e0, st));
     }
     if (cpre)
-      gemm_tile<T, 64, 32, true>(ak, bn, vecok, (unsigned)tot, dev_at<GemmItem>(dev, oi),
+      gemm_tile<T, 64, 32, true>(ak, bn, vecok, ks, (unsigned)tot, dev_at<GemmItem>(dev, oi),
                                  dev_at<int>(dev, oo), count, alpha, beta, flags, st);
     else if (tile == 128 && wnf == 2)
-      gemm_tile<T, 128, SLAB_GEMM128_TK, false, 2>(ak, bn, vecok, (unsigned)tot,
+      gemm_tile<T, 128, SLAB_GEMM128_TK, false, 2>(ak, bn, vecok, ks, (unsigned)tot,
                                                   dev_at<GemmItem>(dev, oi), dev_at<int>(dev, oo),
                                                   count, alpha, beta, flags, st);
     else if (tile == 128)
-      gemm_tile<T, 128, SLAB_GEMM128_TK>(ak, bn, vecok, (unsigned)tot, dev_at<GemmItem>(dev, oi),
-                            dev_at<int>(dev, oo), count, alpha, beta, flags, st);
+      gemm_tile<T, 128, SLAB_GEMM128_TK>(ak, bn, vecok, ks, (unsigned)tot,
+                                         dev_at<GemmItem>(dev, oi), dev_at<int>(dev, oo), count,
+                                         alpha, beta, flags, st);
     else
-      gemm_tile<T, 64, 32>(ak, bn, vecok, (unsigned)tot, dev_at<GemmItem>(dev, oi),
+      gemm_tile<T, 64, 32>(ak, bn, vecok, ks, (unsigned)tot, dev_at<GemmItem>(dev, oi),
                            dev_at<int>(dev, oo), count, alpha, beta, flags, st);
     SLAB_LAUNCH_CHECK();
     if (tm) SLAB_HIP_CHECK(hipEventRecord(e1, st));
@@ -355,12 +397,13 @@ template void plan_gemm<double>(Plan&, bool, bool, const std::vector<GemmItem>&,
 // 64x64 diagonal block [k0, k0+nb): Gaussian elimination without pivoting on
 // [S_kk | I], kept in one array (U on and above the diagonal, the unit lower
 // L~^-1 below it), gives S_kk = L~ U with U = D L~^T, hence
-// L_kk^-1 = D^-1/2 L~^-1.  The working matrix lives in registers (thread = row
+// L_kk^-1 = D^-1/2 L~^-1.  Signed items (indef) take L_kk^-1 = |D|^-1/2 L~^-1
+// and J_k = sign(D), so that S_kk = L_kk J_k L_kk^T.  The working matrix lives in registers (thread = row
 // x 16-column quarter); each step eliminates two pivots and exchanges only the
 // two pivot rows and columns through LDS, with one barrier per step.  L_kk^-1 overwrites the lower
 // triangle of S_kk (L_kk itself is never needed again).
 // k_panel then, on 16x16x4 MFMA tiles, either
-//   * computes 64 rows of L below the block:       L_ik = S_ik L_kk^-T, or
+//   * computes 64 rows of L below the block:       L_ik = S_ik L_kk^-T J_k, or
 //   * advances 64 columns of the carried inverse:  X_k = L_kk^-1 X_k.
 // ---------------------------------------------------------------------------
 #ifndef PANEL_DIAG_THREADS
@@ -372,7 +415,7 @@ __global__ __launch_bounds__(NT) void k_panel_diag(const FactorItem* __restrict_
   const int itm = blockIdx.x;
   g_t<T>* __restrict__ S = gp((T*)items[itm].S);
   g_t<int>* __restrict__ status = gp(items[itm].status);
-  const int n = items[itm].n, blk = items[itm].blk;
+  const int n = items[itm].n, blk = items[itm].blk, indef = items[itm].indef;
   if (k0 >= n) return;  // uniform: this item has no panel at k0
   __shared__ T rowbuf[2][2][64];  // the two pivot rows of a step
   __shared__ T colbuf[2][2][64];  // the two pivot columns of a step
@@ -461,17 +504,20 @@ __global__ __launch_bounds__(NT) void k_panel_diag(const FactorItem* __restrict_
       __syncthreads();
     }
   }
-  // diagonal of U is D; L_kk^-1 = D^-1/2 L~^-1
+  // diagonal of U is D; L_kk^-1 = |D|^-1/2 L~^-1 (a signed item keeps the
+  // signs of D in J, an unsigned one needs D > 0)
   if (q == i / CQ) {
     T d = (T)1;
 #pragma unroll
     for (int c = 0; c < CQ; ++c)
       if (c == i % CQ) d = a[c];
-    if (i < nb && (!(d > (T)0) || !isfinite((double)d))) {
+    const bool bad = indef ? !(d != (T)0) : !(d > (T)0);
+    if (i < nb && (bad || !isfinite((double)d))) {
       status[0] = 3;
       status[1] = blk;
     }
-    colbuf[0][0][i] = (T)1 / sqrt(d);
+    colbuf[0][0][i] = (T)1 / sqrt(indef ? fabs(d) : d);
+    if (indef && i < nb) gp((T*)items[itm].J)[k0 + i] = d < (T)0 ? (T)-1 : (T)1;
   }
   __syncthreads();
   if (i < nb) {
@@ -526,6 +572,13 @@ __global__ __launch_bounds__(256) void k_panel(const FactorItem* __restrict__ it
   const int wave = tid >> 6, lane = tid & 63;
   const int g = lane >> 4, nn = lane & 15;
   const int wm = wave >> 1, wn = wave & 1;
+  // signed item, rows case: L_ik = (S_ik L_kk^-T) J_k, column col times J[k0+col]
+  T js[2] = {(T)1, (T)1};
+  if (rows && items[itm].indef) {
+    const g_t<const T>* J = gp((const T*)items[itm].J);
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) js[nt] = J[k0 + min(wn * 32 + 16 * nt + nn, nb - 1)];
+  }
   V4 acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -559,7 +612,7 @@ __global__ __launch_bounds__(256) void k_panel(const FactorItem* __restrict__ it
         const int row = wm * 32 + 16 * mt + acc_row<T>(g, i);
         const int col = wn * 32 + 16 * nt + nn;
         if (rows) {
-          if (r0 + row < n && col < nb) S[(r0 + row) * n + k0 + col] = acc[mt][nt][i];
+          if (r0 + row < n && col < nb) S[(r0 + row) * n + k0 + col] = acc[mt][nt][i] * js[nt];
         } else {
           if (row < nb && c0 + col < ncols) Lv[(long long)(k0 + row) * n + c0 + col] = acc[mt][nt][i];
         }
@@ -570,7 +623,8 @@ __global__ __launch_bounds__(256) void k_panel(const FactorItem* __restrict__ it
 // The factorization advances in 128-column panels made of two 64-column
 // sub-panels.  After the first sub-panel [k0, k0+64) this kernel applies its
 // update to what the second sub-panel [k0+64, k0+128) needs:
-//   trailing  S_ij -= L_i L_j^T     (rows i >= k0+64, columns j in [k0+64, k0+128))
+//   trailing  S_ij -= L_i J_k L_j^T (rows i >= k0+64, columns j in [k0+64, k0+128);
+//                                    J_k = I for an unsigned item)
 //   carried   X_ic -= L_i X_k,c     (rows i in [k0+64, k0+128), columns c < k0+64)
 // with L_i = S[i, k0:k0+64] (just computed by the panel) and X_k the panel's
 // rows of the carried inverse.  The rest of both updates, for both sub-panels
@@ -627,6 +681,10 @@ __global__ __launch_bounds__(256) void k_rank64(const FactorItem* __restrict__ i
   // A: L rows r0.., panel columns
   // B: trailing -> L rows c0.. (B(k, j) = L[j][k]); carried -> X_k rows (B(k, c) = X[k0+k][c])
   T ta[16], tb[16];
+  // signed item, trailing tiles: A(row, k) times J[k0+k]; k = tid & 63 for
+  // every element this thread stores
+  T jk = (T)1;
+  if (trail && items[itm].indef) jk = gp((const T*)items[itm].J)[k0 + min(tid & 63, nb - 1)];
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
     const int e = tid + 256 * u, hi = e >> 6, lo = e & 63;
@@ -637,7 +695,7 @@ __global__ __launch_bounds__(256) void k_rank64(const FactorItem* __restrict__ i
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
     const int e = tid + 256 * u, hi = e >> 6, lo = e & 63;
-    As[hi][lo] = ta[u];
+    As[hi][lo] = ta[u] * jk;
     if (trail) Bs[hi][lo] = tb[u];
     else Bs[lo][hi] = tb[u];
   }
@@ -705,7 +763,8 @@ __global__ void k_sym_to_f64(const FactorItem* __restrict__ items, const int* __
 
 // Cholesky factorization with carried inverse of independent pivot blocks
 // (items, any sizes): L^-1 into item.Li, breakdown of an item reported as
-// status = {3, item.blk}.
+// status = {3, item.blk}.  Signed items (indef) factor S = L J L^T with the
+// pivot signs J into item.J; their breakdown is a zero (or non-finite) pivot.
 template <typename T>
 void plan_factor_blocks(Plan& plan, std::vector<FactorItem> items) {
   if (items.empty()) return;
@@ -801,10 +860,12 @@ void plan_factor_blocks(Plan& plan, std::vector<FactorItem> items) {
       GemmItem a;
       a.A = S + K2 * n + K0; a.B = S + K2 * n + K0; a.C = S + K2 * n + K2;
       a.M = a.N = (int)(n - K2); a.K = 128; a.lda = a.ldb = a.ldc = (int)n;
+      a.kscale = f.indef ? (const T*)f.J + K0 : nullptr;   // S_22 -= L_21 J L_21^T
       tr.push_back(a);
       GemmItem c;
       c.A = S + K2 * n + K0; c.B = X + (long long)K0 * n; c.C = X + K2 * n;
       c.M = (int)(n - K2); c.N = (int)K2; c.K = 128; c.lda = c.ldb = c.ldc = (int)n;
+      c.kscale = nullptr;
       ca.push_back(c);
     }
     plan_gemm<T>(plan, false, true, tr, (T)-1, (T)1, GEMM_LOWER_C | GEMM_C_PREFETCH);
@@ -818,25 +879,35 @@ void plan_stage2(Plan& plan, const std::vector<Stage2Prob>& probs, bool odd_even
   auto blk = [](const Stage2Prob& p, void* base, long long j) {
     return (void*)((T*)base + j * (long long)p.n * p.n);
   };
-  auto sq = [](const void* A, const void* B, void* C, int n) {
+  auto sq = [](const void* A, const void* B, void* C, int n, const void* ks = nullptr) {
     GemmItem g;
     g.A = A; g.B = B; g.C = C; g.M = g.N = g.K = n; g.lda = g.ldb = g.ldc = n;
+    g.kscale = ks;
     return g;
+  };
+  // pivot signs of block j (signed problems), or null
+  auto sg = [](const Stage2Prob& p, long long j) -> const void* {
+    return p.indef ? (const void*)((const T*)p.J + j * p.n) : nullptr;
   };
   int mmax = 0;
   for (const Stage2Prob& p : probs) mmax = std::max(mmax, p.m);
   if (!odd_even) {
     // Alg. 1 in block Cholesky form, all problems in lockstep over j:
-    // S_j = T_jj - Z_{j-1}^T Z_{j-1}, S_j = L_j L_j^T, Z_j = L_j^-1 T_{j,j+1}
+    // S_j = T_jj - Z_{j-1}^T J_{j-1} Z_{j-1}, S_j = L_j J_j L_j^T, Z_j = L_j^-1 T_{j,j+1}
+    // (J = I for an unsigned problem)
     for (int j = 0; j < mmax; ++j) {
       std::vector<GemmItem> upd, zi;
       std::vector<FactorItem> fi;
       for (const Stage2Prob& p : probs) {
         if (j >= p.m) continue;
-        if (j > 0) upd.push_back(sq(blk(p, p.Z, j - 1), blk(p, p.Z, j - 1), blk(p, p.Td, j), p.n));
+        if (j > 0)
+          upd.push_back(sq(blk(p, p.Z, j - 1), blk(p, p.Z, j - 1), blk(p, p.Td, j), p.n,
+                           sg(p, j - 1)));
         FactorItem f;
         f.S = blk(p, p.Td, j); f.Li = blk(p, p.Linv, j);
         f.S64 = p.S64 ? p.S64 + (long long)j * p.n * p.n : nullptr;
+        f.J = p.indef ? (void*)((T*)p.J + (long long)j * p.n) : nullptr;
+        f.indef = p.indef;
         f.status = p.status; f.n = p.n; f.blk = j;
         fi.push_back(f);
         if (j < p.m - 1) zi.push_back(sq(blk(p, p.Linv, j), blk(p, p.To, j), blk(p, p.Z, j), p.n));
@@ -851,9 +922,10 @@ void plan_stage2(Plan& plan, const std::vector<Stage2Prob>& probs, bool odd_even
   // are a_p = (p+1)s - 1, p < k = floor(m/s); those at even positions,
   // e_q = (2q+1)s - 1, q < E = ceil(k/2), are eliminated together.  e_q has a
   // kept neighbour l = e_q - s when q >= 1 and r = e_q + s when q < floor(k/2).
-  // With D_e = L L^T:  U_e = L^-1 C_l^T (stored over D_e), V_e = L^-1 C_e (in Z),
-  //   D_l -= U_e^T U_e,  D_r -= V_e^T V_e,  C_l = -U_e^T V_e,
-  // where C_x (in To) is the coupling of x to the next interface present.
+  // With D_e = L J L^T:  U_e = L^-1 C_l^T (stored over D_e), V_e = L^-1 C_e (in Z),
+  //   D_l -= U_e^T J U_e,  D_r -= V_e^T J V_e,  C_l = -U_e^T J V_e,
+  // where C_x (in To) is the coupling of x to the next interface present
+  // (J = I for an unsigned problem).
   for (long long s = 1; s <= mmax; s *= 2) {
     std::vector<FactorItem> fi;
     std::vector<GemmItem> gu, gv, gdl, gdr, gc;
@@ -866,26 +938,28 @@ void plan_stage2(Plan& plan, const std::vector<Stage2Prob>& probs, bool odd_even
         FactorItem f;
         f.S = blk(p, p.Td, e); f.Li = blk(p, p.Linv, e);
         f.S64 = p.S64 ? p.S64 + e * p.n * p.n : nullptr;
+        f.J = p.indef ? (void*)((T*)p.J + e * p.n) : nullptr;
+        f.indef = p.indef;
         f.status = p.status; f.n = p.n; f.blk = (int)e;
         fi.push_back(f);
         if (q >= 1) {
           gu.push_back(sq(blk(p, p.Linv, e), blk(p, p.To, e - s), blk(p, p.Td, e), p.n));
-          gdl.push_back(sq(blk(p, p.Td, e), blk(p, p.Td, e), blk(p, p.Td, e - s), p.n));
+          gdl.push_back(sq(blk(p, p.Td, e), blk(p, p.Td, e), blk(p, p.Td, e - s), p.n, sg(p, e)));
         }
         if (q < NR) {
           gv.push_back(sq(blk(p, p.Linv, e), blk(p, p.To, e), blk(p, p.Z, e), p.n));
-          gdr.push_back(sq(blk(p, p.Z, e), blk(p, p.Z, e), blk(p, p.Td, e + s), p.n));
+          gdr.push_back(sq(blk(p, p.Z, e), blk(p, p.Z, e), blk(p, p.Td, e + s), p.n, sg(p, e)));
         }
         if (q >= 1 && q < NR)
-          gc.push_back(sq(blk(p, p.Td, e), blk(p, p.Z, e), blk(p, p.To, e - s), p.n));
+          gc.push_back(sq(blk(p, p.Td, e), blk(p, p.Z, e), blk(p, p.To, e - s), p.n, sg(p, e)));
       }
     }
     plan_factor_blocks<T>(plan, fi);
     plan_gemm<T>(plan, false, true, gu, (T)1, (T)0, GEMM_A_LOWER, tile);    // U_e = L^-1 C_l^T
     plan_gemm<T>(plan, false, false, gv, (T)1, (T)0, GEMM_A_LOWER, tile);   // V_e = L^-1 C_e
-    plan_gemm<T>(plan, true, false, gdl, (T)-1, (T)1, GEMM_LOWER_C, tile);  // D_l -= U^T U
-    plan_gemm<T>(plan, true, false, gdr, (T)-1, (T)1, GEMM_LOWER_C, tile);  // D_r -= V^T V
-    plan_gemm<T>(plan, true, false, gc, (T)-1, (T)0, 0, tile);              // C_l = -U^T V
+    plan_gemm<T>(plan, true, false, gdl, (T)-1, (T)1, GEMM_LOWER_C, tile);  // D_l -= U^T J U
+    plan_gemm<T>(plan, true, false, gdr, (T)-1, (T)1, GEMM_LOWER_C, tile);  // D_r -= V^T J V
+    plan_gemm<T>(plan, true, false, gc, (T)-1, (T)0, 0, tile);              // C_l = -U^T J V
   }
 }
 template void plan_stage2<float>(Plan&, const std::vector<Stage2Prob>&, bool, int);
@@ -907,8 +981,10 @@ template void plan_stage2<double>(Plan&, const std::vector<Stage2Prob>&, bool, i
 // (64 rows x TK) is fetched with 16-byte loads along the block's contiguous
 // dimension (k for M, i for M^T: 256-byte runs), parked in LDS, and consumed
 // by 16x16x4 MFMA tiles (one per wave) while the next chunk is in flight.
+// XS: x(k) is taken times items[].xscale[k] (pivot signs J of a signed
+// factorization), loaded with the x chunk.
 // ---------------------------------------------------------------------------
-template <typename T, bool TR, bool LOWER, bool VECOK>
+template <typename T, bool TR, bool LOWER, bool VECOK, bool XS = false>
 __global__ __launch_bounds__(256) void k_bmv(const BmvItem* __restrict__ items,
                                             const int* __restrict__ offs, int count, T alpha,
                                             T beta, int nsplit) {
@@ -937,6 +1013,7 @@ __global__ __launch_bounds__(256) void k_bmv(const BmvItem* __restrict__ items,
   const int rp = bx % nrw, cg = (bx / nrw) % ncg, sk = bx / (nrw * ncg);
   const g_t<const T>* __restrict__ M = gp((const T*)items[itm].M);
   const g_t<const T>* __restrict__ x = gp((const T*)items[itm].x) + (long long)cg * 16 * n;
+  const g_t<const T>* __restrict__ xsc = gp((const T*)items[itm].xscale);
   const g_t<const T>* xin = gp((const T*)items[itm].xin);
   if (xin) xin += (long long)cg * 16 * n;
   g_t<T>* y = gp((T*)items[itm].y) + (long long)cg * 16 * n;
@@ -971,7 +1048,7 @@ __global__ __launch_bounds__(256) void k_bmv(const BmvItem* __restrict__ items,
   // (triangular operands: many row tiles walk only a few chunks, so the ring
   // is shallower; measured faster)
   constexpr int D = VECOK ? (LOWER ? 2 : 3) : 1;
-  vt ra[D][NVA], rb[D];
+  vt ra[D][NVA], rb[D], rs[XS ? D : 1];
   auto load = [&](int d, int k0) __attribute__((always_inline)) {
 #pragma unroll
     for (int q = 0; q < NVA; ++q) {
@@ -996,11 +1073,14 @@ __global__ __launch_bounds__(256) void k_bmv(const BmvItem* __restrict__ items,
       const int c = tid / (TK / VEC), kk = (tid % (TK / VEC)) * VEC;
       if (VECOK) {
         rb[d] = *(const g_t<const vt>*)(x + (long long)min(c, nc - 1) * n + min(k0 + kk, n - VEC));
+        if (XS) rs[XS ? d : 0] = *(const g_t<const vt>*)(xsc + min(k0 + kk, n - VEC));
       } else {
         const long long gk = k0 + kk;
 #pragma unroll
-        for (int e = 0; e < VEC; ++e)
+        for (int e = 0; e < VEC; ++e) {
           rb[d][e] = (c < nc && gk + e < khi) ? x[(long long)c * n + gk + e] : (T)0;
+          if (XS) rs[XS ? d : 0][e] = xsc[min(gk + e, (long long)n - 1)];
+        }
       }
     }
   };
@@ -1026,8 +1106,10 @@ __global__ __launch_bounds__(256) void k_bmv(const BmvItem* __restrict__ items,
     }
     const int c = tid / (TK / VEC), kk = (tid % (TK / VEC)) * VEC;
 #pragma unroll
-    for (int e = 0; e < VEC; ++e)
-      Bs[buf][kk + e][c] = VECOK ? keep_if(c < nc && k0 + kk + e < khi, rb[d][e]) : rb[d][e];
+    for (int e = 0; e < VEC; ++e) {
+      const T xv = XS ? rb[d][e] * rs[XS ? d : 0][e] : rb[d][e];
+      Bs[buf][kk + e][c] = VECOK ? keep_if(c < nc && k0 + kk + e < khi, xv) : xv;
+    }
   };
   // two accumulators: the chunk's MFMAs form two interleaved dependency chains
   V4 acc2[2] = {V4{0, 0, 0, 0}, V4{0, 0, 0, 0}};
@@ -1103,6 +1185,20 @@ template <typename T>
 void plan_gemv(Plan& plan, bool tr, bool lower, const std::vector<BmvItem>& items, T alpha,
                T beta) {
   if (items.empty()) return;
+  // items with scaled x and items without go to launches of their own
+  const bool xs = items[0].xscale != nullptr;
+  for (const BmvItem& b : items)
+    if ((b.xscale != nullptr) != xs) {
+      std::vector<BmvItem> with, without;
+      for (const BmvItem& c : items) (c.xscale ? with : without).push_back(c);
+      plan_gemv<T>(plan, tr, lower, with, alpha, beta);
+      plan_gemv<T>(plan, tr, lower, without, alpha, beta);
+      return;
+    }
+  if (xs && !tr) {  // a planner's mistake, not an input's
+    std::fprintf(stderr, "slab: plan_gemv: scaled x only for products with M^T\n");
+    std::abort();
+  }
   bool vecok = true, can_split = true;
   const uintptr_t al = 16;
   long long base = 0;
@@ -1111,7 +1207,7 @@ void plan_gemv(Plan& plan, bool tr, bool lower, const std::vector<BmvItem>& item
   for (const BmvItem& b : items) {
     base += row_wgs(b.n) * ((b.nrhs + 15) / 16);
     vecok = vecok && b.n % (int)(16 / sizeof(T)) == 0 && ((uintptr_t)b.M % al) == 0 &&
-            ((uintptr_t)b.x % al) == 0;
+            ((uintptr_t)b.x % al) == 0 && ((uintptr_t)b.xscale % al) == 0;
     can_split = can_split && b.part != nullptr && b.n >= 512;
   }
   // a launch of few workgroups is bound by one workgroup's walk over k: split
@@ -1136,19 +1232,22 @@ void plan_gemv(Plan& plan, bool tr, bool lower, const std::vector<BmvItem>& item
   plan.step([=](const char* dev, hipStream_t st) {
     const BmvItem* it = dev_at<BmvItem>(dev, oi);
     const int* of = dev_at<int>(dev, oo);
-#define SLAB_BMV_CASE(TRV, LOV)                                                                 \
+#define SLAB_BMV_CASE(TRV, LOV, XSV)                                                            \
   do {                                                                                          \
     if (vecok)                                                                                  \
-      hipLaunchKernelGGL((k_bmv<T, TRV, LOV, true>), dim3((unsigned)tot), dim3(256), 0, st, it, \
-                         of, count, alpha, beta, nsplit);                                       \
+      hipLaunchKernelGGL((k_bmv<T, TRV, LOV, true, XSV>), dim3((unsigned)tot), dim3(256), 0,    \
+                         st, it, of, count, alpha, beta, nsplit);                               \
     else                                                                                        \
-      hipLaunchKernelGGL((k_bmv<T, TRV, LOV, false>), dim3((unsigned)tot), dim3(256), 0, st,    \
-                         it, of, count, alpha, beta, nsplit);                                   \
+      hipLaunchKernelGGL((k_bmv<T, TRV, LOV, false, XSV>), dim3((unsigned)tot), dim3(256), 0,   \
+                         st, it, of, count, alpha, beta, nsplit);                               \
   } while (0)
-    if (!tr && !lower) SLAB_BMV_CASE(false, false);
-    else if (!tr && lower) SLAB_BMV_CASE(false, true);
-    else if (tr && !lower) SLAB_BMV_CASE(true, false);
-    else SLAB_BMV_CASE(true, true);
+    if (xs) {
+      if (lower) SLAB_BMV_CASE(true, true, true);
+      else SLAB_BMV_CASE(true, false, true);
+    } else if (!tr && !lower) SLAB_BMV_CASE(false, false, false);
+    else if (!tr && lower) SLAB_BMV_CASE(false, true, false);
+    else if (tr && !lower) SLAB_BMV_CASE(true, false, false);
+    else SLAB_BMV_CASE(true, true, false);
 #undef SLAB_BMV_CASE
     SLAB_LAUNCH_CHECK();
     if (nsplit > 1) {

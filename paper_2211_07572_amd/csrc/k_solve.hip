@@ -328,11 +328,16 @@ static void plan_reduced(Plan& plan, const std::vector<ReducedDev>& R, bool odd_
   // every product of a problem carries its refinement flag
   const int* live_flag = nullptr;
   auto item = [&live_flag](const void* M, const void* x, const void* xin, void* y, int n,
-                           int nrhs, void* part = nullptr) {
+                           int nrhs, void* part = nullptr, const void* xs = nullptr) {
     BmvItem b;
     b.M = M; b.x = x; b.xin = xin; b.y = y; b.n = n; b.nrhs = nrhs; b.part = part;
     b.live = live_flag;
+    b.xscale = xs;
     return b;
+  };
+  // pivot signs J_j of a signed factorization, or null
+  auto sg = [](const ReducedDev& r, long long j) -> const void* {
+    return r.J ? (const void*)((const TR*)r.J + j * r.n) : nullptr;
   };
   // scratch slot s of a problem for a product split over k (see plan_gemv)
   auto part = [](const ReducedDev& r, int s) -> void* {
@@ -342,8 +347,9 @@ static void plan_reduced(Plan& plan, const std::vector<ReducedDev>& R, bool odd_
   int mmax = 0;
   for (const ReducedDev& r : R) mmax = std::max(mmax, r.m);
   if (!odd_even) {
-    // T = R R^T with R_jj = L_j, R_{j+1,j} = Z_j^T: forward y_j = L_j^-1 (f~_j - Z_{j-1}^T y_{j-1}),
-    // backward x_j = L_j^-T (y_j - Z_j x_{j+1}), x overwriting f~
+    // T = R J R^T with R_jj = L_j, R_{j+1,j} = Z_j^T J_j (J = I unless signed):
+    // forward y_j = L_j^-1 (f~_j - Z_{j-1}^T J_{j-1} y_{j-1}),
+    // backward x_j = L_j^-T J_j (y_j - Z_j x_{j+1}), x overwriting f~
     for (int j = 0; j < mmax; ++j) {
       std::vector<BmvItem> a, bb;
       for (const ReducedDev& r : R) {
@@ -353,7 +359,7 @@ static void plan_reduced(Plan& plan, const std::vector<ReducedDev>& R, bool odd_
         const void* src = at(r.ft, j, vs);
         if (j > 0) {
           a.push_back(item(at(r.Z, j - 1, nsq), at(r.yt, j - 1, vs), at(r.ft, j, vs), r.tt, r.n,
-                           r.nrhs, part(r, 0)));
+                           r.nrhs, part(r, 0), sg(r, j - 1)));
           src = r.tt;
         }
         bb.push_back(item(at(r.Linv, j, nsq), src, nullptr, at(r.yt, j, vs), r.n, r.nrhs,
@@ -375,7 +381,7 @@ static void plan_reduced(Plan& plan, const std::vector<ReducedDev>& R, bool odd_
           src = r.tt;
         }
         bb.push_back(item(at(r.Linv, j, nsq), src, nullptr, at(r.ft, j, vs), r.n, r.nrhs,
-                          part(r, 1)));
+                          part(r, 1), sg(r, j)));
       }
       plan_gemv<TR>(plan, false, false, a, (TR)-1, (TR)1);
       plan_gemv<TR>(plan, true, true, bb, (TR)1, (TR)0);
@@ -383,9 +389,9 @@ static void plan_reduced(Plan& plan, const std::vector<ReducedDev>& R, bool odd_
     return;
   }
   // odd-even order (levels as in the factorization): reduce the right-hand
-  // side level by level, y_e = L_e^-1 g_e, g_l -= U_e^T y_e, g_r -= V_e^T y_e;
-  // then from the top level down x_e = L_e^-T (y_e - U_e x_l - V_e x_r),
-  // x_e overwriting g_e.
+  // side level by level, y_e = L_e^-1 g_e, g_l -= U_e^T J_e y_e, g_r -= V_e^T J_e y_e;
+  // then from the top level down x_e = L_e^-T J_e (y_e - U_e x_l - V_e x_r),
+  // x_e overwriting g_e (J_e = I unless signed).
   std::vector<long long> strides;
   for (long long s = 1; s <= mmax; s *= 2) strides.push_back(s);
   for (int pass = 0; pass < 2; ++pass) {
@@ -405,10 +411,10 @@ static void plan_reduced(Plan& plan, const std::vector<ReducedDev>& R, bool odd_
                              r.nrhs, part(r, q)));
             if (q < NR)
               bb.push_back(item(at(r.Z, e, nsq), at(r.yt, e, vs), at(r.ft, e + s, vs),
-                                at(r.ft, e + s, vs), r.n, r.nrhs, part(r, q)));
+                                at(r.ft, e + s, vs), r.n, r.nrhs, part(r, q), sg(r, e)));
             if (q >= 1)
               cc.push_back(item(at(r.Td, e, nsq), at(r.yt, e, vs), at(r.ft, e - s, vs),
-                                at(r.ft, e - s, vs), r.n, r.nrhs, part(r, q - 1)));
+                                at(r.ft, e - s, vs), r.n, r.nrhs, part(r, q - 1), sg(r, e)));
           } else {
             if (q < NR)
               a.push_back(item(at(r.Z, e, nsq), at(r.ft, e + s, vs), at(r.yt, e, vs),
@@ -417,18 +423,18 @@ static void plan_reduced(Plan& plan, const std::vector<ReducedDev>& R, bool odd_
               bb.push_back(item(at(r.Td, e, nsq), at(r.ft, e - s, vs), at(r.yt, e, vs),
                                 at(r.yt, e, vs), r.n, r.nrhs, part(r, q - 1)));
             cc.push_back(item(at(r.Linv, e, nsq), at(r.yt, e, vs), nullptr, at(r.ft, e, vs), r.n,
-                              r.nrhs, part(r, q)));
+                              r.nrhs, part(r, q), sg(r, e)));
           }
         }
       }
       if (pass == 0) {
         plan_gemv<TR>(plan, false, true, a, (TR)1, (TR)0);    // y_e = L^-1 g_e
-        plan_gemv<TR>(plan, true, false, bb, (TR)-1, (TR)1);  // g_r -= V^T y_e
-        plan_gemv<TR>(plan, true, false, cc, (TR)-1, (TR)1);  // g_l -= U^T y_e
+        plan_gemv<TR>(plan, true, false, bb, (TR)-1, (TR)1);  // g_r -= V^T J y_e
+        plan_gemv<TR>(plan, true, false, cc, (TR)-1, (TR)1);  // g_l -= U^T J y_e
       } else {
         plan_gemv<TR>(plan, false, false, a, (TR)-1, (TR)1);  // y_e -= V x_r
         plan_gemv<TR>(plan, false, false, bb, (TR)-1, (TR)1); // y_e -= U x_l
-        plan_gemv<TR>(plan, true, true, cc, (TR)1, (TR)0);    // x_e = L^-T y_e
+        plan_gemv<TR>(plan, true, true, cc, (TR)1, (TR)0);    // x_e = L^-T J y_e
       }
     }
   }

@@ -175,6 +175,12 @@ class SlabHandle:
                  "block_products"]
         return {n: self.query(10 + i) for i, n in enumerate(names)}
 
+    def negative_pivots(self) -> int:
+        """Negative pivots of the signed block factorization of T (factored
+        with a diagonal term; 0 otherwise): the number of negative eigenvalues
+        of T."""
+        return self.query(7)
+
     LAUNCH_KINDS = ("gemm128", "gemm64", "gemm_cprefetch", "bmv_split", "bmv")
 
     def launches(self) -> dict:

@@ -1,12 +1,16 @@
 """The diagonal term c_p of the operator (the Helmholtz term of eq.
 (var_helm), c = -k^2 b(x)), on the GPU against the oracle.
 
-The factor kernels are those of a positive definite A, so the cases that must
-match the oracle are the definite ones: a nonnegative c (screened diffusion on
-a lognormal coefficient) and a Helmholtz term -k^2 below the lowest
-eigenvalue of the Laplacian.  A Helmholtz term a few wavelengths across the
-grid makes A indefinite, and the factorization must say so
-(SLAB_E_BREAKDOWN) rather than return a wrong answer.
+Definite cases: a nonnegative c (screened diffusion on a lognormal
+coefficient) and a Helmholtz term -k^2 below the lowest eigenvalue of the
+Laplacian.  Indefinite cases: a Helmholtz term several wavelengths across the
+grid with slabs narrower than half a wavelength, so that the slab interiors
+stay definite and only T is indefinite; its pivot blocks are factored in
+signed form L J L^T.  There the number of negative pivots must equal the
+number of Laplacian eigenvalues below k^2 (closed form, inertia of Schur
+complements) and the solution must match the oracle within cond(A) times the
+two residuals.  Slabs wider than that are indefinite themselves, and the
+factorization must say so (SLAB_E_BREAKDOWN) rather than return a wrong answer.
 """
 import numpy as np
 import pytest
@@ -120,11 +124,110 @@ def test_shift_in_batch_and_graph_run():
     bt.free()
 
 
-def test_indefinite_helmholtz_is_reported():
-    """Six points per wavelength on a 64 x 64 grid: A is indefinite (and so are
-    the slab blocks, eight columns wide); the factorization reports it."""
+def test_indefinite_slabs_are_reported():
+    """Six points per wavelength on a 64 x 64 grid: A is indefinite, and so are
+    the slab blocks, eight columns wide (more than half a wavelength); the
+    factorization reports it."""
     n2, n1, b = 64, 64, 7
     c = G.helmholtz_shift(n2, n1, 6.0)
     with pytest.raises(S.SlabError) as ei:
         S.slab_factor(_dev(G.kappa_const(n2, n1)), n2, n1, b, odd_even=True, shift=_dev(c))
     assert ei.value.status == S.SLAB_E_BREAKDOWN
+
+
+# ------------------------------------------------- indefinite T (signed pivots)
+
+def _laplace_eigs(n2, n1, h):
+    k1 = np.arange(1, n1 + 1)[:, None]
+    k2 = np.arange(1, n2 + 1)[None, :]
+    return (4 - 2 * np.cos(np.pi * k1 / (n1 + 1)) - 2 * np.cos(np.pi * k2 / (n2 + 1))) / h ** 2
+
+
+# (name, n2, n1, b, points per wavelength): n2 = 200 spans three full 64-column
+# panels and a ragged one; 139 and 35 negative eigenvalues; cond(A) 4.6e4, 3.6e4
+INDEF = [("ppw20_b7", 200, 96, 7, 20.0), ("ppw40_b15", 130, 160, 15, 40.0)]
+
+
+def _indef_setup(n2, n1, b, ppw):
+    h = 1.0 / (n2 + 1)
+    c = G.helmholtz_shift(n2, n1, ppw, h)
+    k2 = -c[0, 0]
+    lam = _laplace_eigs(n2, n1, h)
+    gap = np.abs(lam - k2)
+    slab_min = (4 - 2 * np.cos(np.pi / (b + 1)) - 2 * np.cos(np.pi / (n2 + 1))) / h ** 2
+    assert slab_min > k2  # definite slab interiors
+    neg = int((lam < k2).sum())
+    assert neg > 0
+    cond = gap.max() / gap.min()   # A = -Laplace - k^2 is symmetric: exact cond_2
+    return c, neg, cond
+
+
+@pytest.mark.parametrize("order", ORDERS)
+@pytest.mark.parametrize("case", INDEF, ids=[c[0] for c in INDEF])
+def test_indefinite_T_fp64(case, order):
+    name, n2, n1, b, ppw = case
+    c, neg, cond = _indef_setup(n2, n1, b, ppw)
+    kap = G.kappa_const(n2, n1)
+    prob = O.make_problem(kap, n2, n1, b, shift=c)
+    fac = O.factor(prob, order=order)
+    h = S.slab_factor(_dev(kap), n2, n1, b, keep_reduced=True, odd_even=order == "odd_even",
+                      shift=_dev(c))
+    assert h.negative_pivots() == neg
+    for j in range(prob.m):   # stage one does not depend on the signs
+        assert _rel_fro(S.slab_export_reduced(h, 0, j).cpu().numpy(), fac.s1.T_diag[j]) <= 1e-12
+    f = G.rhs_uniform(n2, n1, 3, 5)
+    u = S.slab_solve(h, _dev(f)).cpu().numpy()
+    rr = O.relres(prob, u, f)
+    assert rr.max() <= 1e-10
+    u_ref = O.solve(fac, f)
+    rr_ref = O.relres(prob, u_ref, f)
+    # ||u - u*|| / ||u*|| <= cond(A) ||A u - f|| / ||f|| for both solutions
+    assert np.all(_col_rel(u, u_ref) <= cond * (rr + rr_ref) * 1.01 + 1e-15)
+    h.free()
+
+
+@pytest.mark.parametrize("precision", [S.SLAB_MIXED, S.SLAB_FP32_REFINE])
+@pytest.mark.parametrize("order", ORDERS)
+def test_indefinite_T_refined_forms(order, precision):
+    name, n2, n1, b, ppw = INDEF[0]
+    c, neg, cond = _indef_setup(n2, n1, b, ppw)
+    assert cond * 6e-8 < 0.01   # FP32 pivots keep the signs of the exact ones
+    kap = G.kappa_const(n2, n1)
+    prob = O.make_problem(kap, n2, n1, b, shift=c)
+    # each pass shrinks the error by about cond(A) eps_32 times the growth of
+    # the elimination (measured 0.1-0.2 per pass with FP32 slab sweeps in
+    # odd-even order here: 1e-10 after about 12 passes; the mixed form needs 5)
+    h = S.slab_factor(_dev(kap), n2, n1, b, precision=precision, tol=1e-10, max_iter=20,
+                      odd_even=order == "odd_even", shift=_dev(c))
+    assert h.negative_pivots() == neg
+    f = G.rhs_uniform(n2, n1, 2, 8)
+    u = S.slab_solve(h, _dev(f)).cpu().numpy()
+    assert O.relres(prob, u, f).max() <= 1e-10
+    h.free()
+
+
+def test_indefinite_in_batch_and_graph_run():
+    """Signed and unsigned problems in one batch (their block products go to
+    launches of their own), eager and as one graph."""
+    name, n2, n1, b, ppw = INDEF[1]
+    c, neg, cond = _indef_setup(n2, n1, b, ppw)
+    dims = [(n2, n1, b), (70, 96, 15), (96, 64, 7)]
+    kaps = [G.kappa_const(n2, n1), G.kappa_lognormal(70, 96, 61), G.kappa_const(96, 64)]
+    c3, neg3, cond3 = _indef_setup(96, 64, 7, 24.0)
+    shifts = [c, None, c3]
+    fs = [G.rhs_uniform(d[0], d[1], 2, 70 + i) for i, d in enumerate(dims)]
+    kd = [_dev(k) for k in kaps]
+    sd = [None if x is None else _dev(x) for x in shifts]
+    fd = [_dev(f) for f in fs]
+    for order in (False, True):
+        bt = S.slab_factor_batch(kd, dims, precision=S.SLAB_MIXED, shifts=sd, odd_even=order)
+        assert bt.handle(0).negative_pivots() == neg
+        assert bt.handle(1).negative_pivots() == 0
+        assert bt.handle(2).negative_pivots() == neg3
+        us = S.slab_solve_batch(bt, fd)
+        us2 = S.slab_batch_run(bt, kd, fd)
+        for i, (a2, a1, ab) in enumerate(dims):
+            prob = O.make_problem(kaps[i], a2, a1, ab, shift=shifts[i])
+            assert O.relres(prob, us[i].cpu().numpy(), fs[i]).max() <= 1e-10, (order, i)
+            assert np.array_equal(us2[i].cpu().numpy(), us[i].cpu().numpy()), (order, i)
+        bt.free()

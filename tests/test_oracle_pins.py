@@ -654,3 +654,32 @@ def test_helmholtz_closed_form_T():
         assert np.abs(fac.s1.T_diag[j] - (both if j < p.m - 1 else last)).max() <= 1e-12 * scale
     for j in range(p.m - 1):
         assert np.abs(fac.s1.T_up[j] - off).max() <= 1e-12 * scale
+
+
+def _laplace_eigs(n2, n1, h):
+    """Eigenvalues of the 5-point Laplacian (kappa = 1) on the n1 x n2 grid."""
+    k1 = np.arange(1, n1 + 1)[:, None]
+    k2 = np.arange(1, n2 + 1)[None, :]
+    return (4 - 2 * np.cos(np.pi * k1 / (n1 + 1)) - 2 * np.cos(np.pi * k2 / (n2 + 1))) / h ** 2
+
+
+@pytest.mark.parametrize("n2,n1,b,ppw", [(48, 64, 7, 20.0), (37, 40, 3, 10.0)])
+def test_helmholtz_pivot_inertia(n2, n1, b, ppw):
+    """Slab interiors definite (their lowest eigenvalue, from b columns, above
+    k^2), A indefinite: by the inertia additivity of Schur complements the
+    negative eigenvalues of all pivot blocks of either order add up to those
+    of A, which the sine modes give in closed form (lam_kl < k^2)."""
+    h = 1.0 / (n2 + 1)
+    c = G.helmholtz_shift(n2, n1, ppw, h)
+    k2 = -c[0, 0]
+    slab_min = (4 - 2 * np.cos(np.pi / (b + 1)) - 2 * np.cos(np.pi / (n2 + 1))) / h ** 2
+    assert slab_min > k2
+    lam = _laplace_eigs(n2, n1, h)
+    neg_ref = int((lam < k2).sum())
+    assert neg_ref >= 5 and np.abs(lam - k2).min() > 1e-6 * k2
+    p = O.make_problem(G.kappa_const(n2, n1), n2, n1, b, h, shift=c)
+    for order in ("sweep", "odd_even"):
+        fac = O.factor(p, order=order)
+        piv = [fac.s2.pivot(j) if order == "odd_even" else fac.s2.S[j] for j in range(p.m)]
+        neg = sum(int((np.linalg.eigvalsh(0.5 * (S + S.T)) < 0).sum()) for S in piv)
+        assert neg == neg_ref, order
