@@ -257,11 +257,12 @@ def copy_calibration():
                       "copies": 3}))
 
 
-def run_gpu(w: G.Workload, precision: int, steps: int, warmup: int, kappa, f, odd_even: bool):
+def run_gpu(w: G.Workload, precision: int, steps: int, warmup: int, kappa, f, odd_even: bool,
+            shift=None):
     """W untimed steps, then K timed ones.  Returns the mean time per step over
     the K steps (one interval, synchronized on both sides), the per-step times
     (each synchronized), the last solution, and per-step solve infos and phase
-    times."""
+    times.  shift: optional device diagonal term (Helmholtz)."""
     import torch
     from paper_2211_07572_amd import slab as S
     torch.cuda.synchronize()
@@ -270,7 +271,7 @@ def run_gpu(w: G.Workload, precision: int, steps: int, warmup: int, kappa, f, od
 
     def one():
         h = S.slab_factor(kappa, w.n2, w.n1, w.b, w.h, precision=precision, tol=1e-10, max_iter=10,
-                          odd_even=odd_even)
+                          odd_even=odd_even, shift=shift)
         u = S.slab_solve(h, f)
         infos.append((h.last_info.iterations, h.last_info.max_relres))
         phases.append(h.phase_us())
@@ -437,7 +438,47 @@ def extra_workloads(warmup: int, steps: int) -> dict:
                 "max_relres": max(r for _, r in info), "refine_passes": max(i for i, _ in info)}
     out[f"{G.ADJOINT_512.name}_batch16_fp64_factor_solve_adjoint_grad"] = differentiation_batch(
         warmup, steps)
+    out.update(helmholtz_workload(warmup, steps))
     return out
+
+
+def helmholtz_workload(warmup: int, steps: int) -> dict:
+    """Indefinite Helmholtz on 1024 x 1024 (b = 15, 40 points per wavelength),
+    factor + solve per step in FP64 (odd-even order, signed block
+    factorization).  The negative pivots are reported beside the number
+    of Laplacian eigenvalues below k^2 (sine modes, closed form), which they
+    must equal, and cond(A) from the same eigenvalues."""
+    import torch
+    from paper_2211_07572_amd import slab as S
+    w = G.HELMHOLTZ_1024
+    c = w.shift()
+    k2 = -float(c[0, 0])
+    p1 = np.arange(1, w.n1 + 1)[:, None]
+    p2 = np.arange(1, w.n2 + 1)[None, :]
+    lam = (4 - 2 * np.cos(np.pi * p1 / (w.n1 + 1)) - 2 * np.cos(np.pi * p2 / (w.n2 + 1))) / w.h ** 2
+    gap = np.abs(lam - k2)
+    kap = torch.as_tensor(w.kappa(), device="cuda")
+    cd = torch.as_tensor(c, device="cuda")
+    f = torch.as_tensor(w.rhs(1), device="cuda").contiguous()
+    _, per, _, info, _ = run_gpu(w, S.SLAB_FP64, steps, warmup, kap, f, True, shift=cd)
+    h = S.slab_factor(kap, w.n2, w.n1, w.b, w.h, precision=S.SLAB_FP64, odd_even=True, shift=cd)
+    neg = h.negative_pivots()
+    h.free()
+    med = float(np.median(per))
+    res = {"ms_per_step": med * 1e3, "dof_per_s": w.N / med,
+           "max_relres": max(r for _, r in info), "refine_passes": max(i for i, _ in info),
+           "negative_pivots": neg, "laplace_eigs_below_k2": int((lam < k2).sum()),
+           "cond_A": float(gap.max() / gap.min())}
+    # the FP32 reduced factorization (mixed form) converges only while cond(T)
+    # times its growth times the FP32 rounding stays below one: its outcome
+    # here (one untimed solve, not checked)
+    h = S.slab_factor(kap, w.n2, w.n1, w.b, w.h, precision=S.SLAB_MIXED, odd_even=True,
+                      shift=cd, max_iter=10)
+    S.slab_solve(h, f, check=False)
+    res["mixed_form"] = {"refine_passes": h.last_info.iterations,
+                         "max_relres": h.last_info.max_relres}
+    h.free()
+    return {f"{w.name}_fp64": res}
 
 
 def sketch_workload(w: G.Workload, kappa, warmup: int, steps: int) -> dict:

@@ -120,6 +120,12 @@ class Workload:
             return rhs_normal(self.n2, self.n1, k, self.rhs_seed)
         return rhs_uniform(self.n2, self.n1, k, self.rhs_seed)
 
+    def shift(self) -> np.ndarray | None:
+        """Helmholtz diagonal term for workloads with extra["ppw"], else None."""
+        if "ppw" not in self.extra:
+            return None
+        return helmholtz_shift(self.n2, self.n1, self.extra["ppw"], self.h)
+
 
 # The five synthetic workloads: Poisson 64x64 (b=7, 8 slabs); lognormal
 # diffusion 1024x1024 (b=31); lognormal diffusion 2048 rows x 4096 columns
@@ -129,6 +135,11 @@ POISSON_64 = Workload("poisson_64x64_b7", 64, 64, 7, 1, "const", "uniform")
 DIFFUSION_1024 = Workload("diffusion_1024x1024_b31", 1024, 1024, 31, 1, "lognormal", "uniform")
 DIFFUSION_2048x4096 = Workload("diffusion_2048x4096_b31", 2048, 4096, 31, 16, "lognormal", "normal")
 ADJOINT_512 = Workload("adjoint_512x512_b15", 512, 512, 15, 1, "lognormal", "uniform")
+# Helmholtz -Laplace u - k^2 u at 40 points per wavelength on 1024 x 1024 (25.6
+# wavelengths across, 2018 eigenvalues below k^2): slabs of 16 columns are
+# under half a wavelength, so only the reduced matrix is indefinite
+HELMHOLTZ_1024 = Workload("helmholtz_1024x1024_b15_ppw40", 1024, 1024, 15, 1, "const", "uniform",
+                          extra={"ppw": 40.0})
 
 
 # The differentiation workload: 16 coefficient fields theta_i = log kappa_i on
