@@ -165,6 +165,21 @@ def helmholtz_shift(n2: int, n1: int, ppw: float, h: float | None = None) -> np.
     return np.full((n1, n2), -k * k)
 
 
+def bessel_field(n2: int, n1: int, k: float, h: float | None = None,
+                 source=(-0.1, 0.5)) -> np.ndarray:
+    """J0(k |x - source|) on the grid with its ring, in the layout of kappa:
+    shape (n1+2, n2+2), entry [i, j] at x = (i h, j h) (column i, row j; the
+    interior nodes are 1..n1 and 1..n2).  The exact solution of the
+    constant-coefficient Helmholtz benchmark -Laplace u - k^2 u = 0 with
+    Dirichlet data u = J0 on the boundary of the unit square."""
+    from scipy.special import j0
+    if h is None:
+        h = default_h(n2)
+    x1 = np.arange(n1 + 2)[:, None] * h
+    x2 = np.arange(n2 + 2)[None, :] * h
+    return j0(k * np.hypot(x1 - source[0], x2 - source[1]))
+
+
 def gaussian_test_vectors(m: int, ncols: int, n2: int, seed: int = SEED_SKETCH) -> np.ndarray:
     """ncols standard normal interface vectors, shape (m, ncols, n2): block j
     of column k is interface j's part (the test vectors of a sketch of T)."""

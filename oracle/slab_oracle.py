@@ -202,6 +202,22 @@ def apply_A(prob: Problem, u: np.ndarray) -> np.ndarray:
     return out.reshape(u.shape)
 
 
+def dirichlet_load(prob: Problem, g: np.ndarray) -> np.ndarray:
+    """Load of Dirichlet data (eq. (bvp): u = g on the boundary) on the
+    right-hand side of eq. (Au=f): an edge e from interior node p to a ring
+    node q carries w_e (u_p - g_q), so w_e g_q moves to f_p.  g has the layout
+    of kappa, shape (n1+2, n2+2) or (nrhs, n1+2, n2+2); only its ring is read.
+    Returns the load alone, shape (nrhs, n1, n2) (or (n1, n2))."""
+    n1, n2 = prob.n1, prob.n2
+    g3 = np.asarray(g, dtype=np.float64).reshape(-1, n1 + 2, n2 + 2)
+    f = np.zeros((g3.shape[0], n1, n2))
+    f[:, 0, :] += prob.wh[0, :] * g3[:, 0, 1:n2 + 1]              # left ring column
+    f[:, n1 - 1, :] += prob.wh[n1, :] * g3[:, n1 + 1, 1:n2 + 1]   # right ring column
+    f[:, :, 0] += prob.wv[:, 0] * g3[:, 1:n1 + 1, 0]              # ring row below
+    f[:, :, n2 - 1] += prob.wv[:, n2] * g3[:, 1:n1 + 1, n2 + 1]   # ring row above
+    return f if np.ndim(g) == 3 else f[0]
+
+
 def relres(prob: Problem, u: np.ndarray, f: np.ndarray) -> np.ndarray:
     """relerr_res = ||A u - f||_2 / ||f||_2 per right-hand side (Sec. 5.1)."""
     r = apply_A(prob, u) - f

@@ -683,3 +683,71 @@ def test_helmholtz_pivot_inertia(n2, n1, b, ppw):
         piv = [fac.s2.pivot(j) if order == "odd_even" else fac.s2.S[j] for j in range(p.m)]
         neg = sum(int((np.linalg.eigvalsh(0.5 * (S + S.T)) < 0).sum()) for S in piv)
         assert neg == neg_ref, order
+
+
+# ------------------------------------ Dirichlet data (eq. (bvp) -> eq. (Au=f))
+
+@pytest.mark.parametrize("n2,n1,b", [(7, 8, 3), (1, 4, 1), (12, 6, 2)])
+def test_dirichlet_load_harmonic_exact(n2, n1, b):
+    """kappa = 1: the 5-point Laplacian is exact on the harmonic quadratic
+    u = 1 + 2x + 3y + x^2 - y^2, so A u = (load of u's ring values) with no
+    source, to rounding."""
+    h = 1.0 / (n2 + 1)
+    p = O.make_problem(G.kappa_const(n2, n1), n2, n1, b, h)
+    x = np.arange(n1 + 2)[:, None] * h
+    y = np.arange(n2 + 2)[None, :] * h
+    u = 1 + 2 * x + 3 * y + x * x - y * y
+    lhs = O.apply_A(p, u[1:-1, 1:-1])
+    rhs = O.dirichlet_load(p, u)
+    scale = np.abs(u).max() * 8 / h ** 2
+    assert np.abs(lhs - rhs).max() <= 1e-13 * scale
+    # two right-hand sides at once: the same load per column
+    both = O.dirichlet_load(p, np.stack([u, 2 * u]))
+    assert both.shape == (2, n1, n2) and np.array_equal(both[0], rhs)
+
+
+def test_dirichlet_load_brute_force():
+    """Lognormal kappa, random ring data: the interior of the full-grid system
+    (ring rows u = g, interior rows from the edge weights, assembled node by
+    node) equals A^-1 (load of g)."""
+    n2, n1, b = 9, 12, 3
+    h = 1.0 / (n2 + 1)
+    kap = G.kappa_lognormal(n2, n1, 17)
+    p = O.make_problem(kap, n2, n1, b, h)
+    g = np.random.default_rng(5).standard_normal((n1 + 2, n2 + 2))
+    ny = n2 + 2
+    M = np.zeros(((n1 + 2) * ny, (n1 + 2) * ny))
+    rhs = np.zeros((n1 + 2) * ny)
+    for i in range(n1 + 2):
+        for j in range(ny):
+            k = i * ny + j
+            if i in (0, n1 + 1) or j in (0, n2 + 1):
+                M[k, k] = 1.0
+                rhs[k] = g[i, j]
+                continue
+            for di, dj in ((-1, 0), (1, 0), (0, -1), (0, 1)):
+                w = 0.5 * (kap[i, j] + kap[i + di, j + dj]) / h ** 2
+                M[k, k] += w
+                M[k, (i + di) * ny + j + dj] -= w
+    full = np.linalg.solve(M, rhs).reshape(n1 + 2, ny)
+    u = O.direct_solve(p, O.dirichlet_load(p, g))
+    assert np.abs(u - full[1:-1, 1:-1]).max() <= 1e-12 * np.abs(full).max()
+
+
+def test_helmholtz_bessel_second_order():
+    """The paper's FD Helmholtz benchmark (eq. (constant_coeff_helm)): with
+    Dirichlet data from u_true = J0(k |x - (-0.1, 0.5)|) and no source, the
+    discrete solution converges to u_true at second order in h (k fixed):
+    relerr_true falls by about 4 per halving of h."""
+    k = 8.0
+    errs, hs = [], []
+    for n in (64, 128, 256):   # unit square, n x n interior nodes, h = 1/(n+1)
+        h = 1.0 / (n + 1)
+        ut = G.bessel_field(n, n, k, h)
+        p = O.make_problem(G.kappa_const(n, n), n, n, 7, h, shift=np.full((n, n), -k * k))
+        u = O.direct_solve(p, O.dirichlet_load(p, ut))
+        errs.append(np.linalg.norm(u - ut[1:-1, 1:-1]) / np.linalg.norm(ut[1:-1, 1:-1]))
+        hs.append(h)
+    for i in range(2):
+        ratio = errs[i] / errs[i + 1]
+        assert 0.9 <= ratio / (hs[i] / hs[i + 1]) ** 2 <= 1.1, (errs, ratio)
