@@ -255,6 +255,17 @@ int slab_index_maps(int32_t n1, int32_t n2, int32_t b, int32_t* col_kind, int32_
 int slab_kappa_grad(slab_handle h, const double* u, const double* lam, int32_t nrhs, int64_t ld,
                     int32_t mode, double* grad, void* hip_stream);
 
+/* Load of Dirichlet boundary data (eq. (bvp): u = g on the boundary) moved to
+   the right-hand side of eq. (Au=f): for every edge e between an interior node
+   p and a ring node q, f_p += w_e g_q, with the edge weights of the factored
+   handle (those of its kappa and h).  g: device FP64, nrhs fields of
+   (n1+2)*(n2+2) in the layout of kappa (node (i, j) at i*(n2+2) + j; only the
+   ring, i = 0 or n1+1 or j = 0 or n2+1, is read).  f: device FP64, nrhs
+   columns of n1*n2 at stride ld >= n1*n2, updated in place (holding a source
+   term, or zero).  Asynchronous on hip_stream; g and f owned by the caller. */
+int slab_dirichlet_load(slab_handle h, const double* g, double* f, int32_t nrhs, int64_t ld,
+                        void* hip_stream);
+
 /* Per-column relative residual ||f - A u||_2/||f||_2 in FP64 (relerr_res of
    Sec. 5.1); relres is a HOST array of nrhs doubles. */
 int slab_residual(slab_handle h, const double* f, const double* u, int32_t nrhs, int64_t ld,

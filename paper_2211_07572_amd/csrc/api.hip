@@ -1643,6 +1643,18 @@ int slab_kappa_grad(slab_handle h, const double* u, const double* lam, int32_t n
   return SLAB_OK;
 }
 
+int slab_dirichlet_load(slab_handle h, const double* g, double* f, int32_t nrhs, int64_t ld,
+                        void* hip_stream) {
+  if (!h || !g || !f || nrhs <= 0 || ld < (long long)h->n1 * h->n2) {
+    set_error("bad arguments to slab_dirichlet_load");
+    return SLAB_E_INVALID;
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  SLAB_HIP_CHECK(hipSetDevice(h->device));
+  SLAB_TRY(launch_dirichlet(h->n1, h->n2, nrhs, ld, h->wh, h->wv, g, f, st));
+  return SLAB_OK;
+}
+
 int slab_residual(slab_handle h, const double* f, const double* u, int32_t nrhs, int64_t ld,
                   double* relres, void* hip_stream) {
   if (!relres) { set_error("null relres"); return SLAB_E_INVALID; }

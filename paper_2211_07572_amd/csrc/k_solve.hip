@@ -887,4 +887,55 @@ int launch_kappa_grad(int n1, int n2, int nrhs, long long ld, double h, const do
   return SLAB_OK;
 }
 
+// Load of Dirichlet data g on the ring (eq. (bvp)) into the right-hand side of
+// eq. (Au=f): f_p += sum over the edges from p to a ring node q of w_e g_q.
+// One thread per interior node next to the ring, each node once: the n2 nodes
+// of the first and of the last column, then the nodes of the bottom and top
+// rows of the columns between them.  The terms are added left, right, below,
+// above, then to f.
+__global__ void k_dirichlet(int n1, int n2, int nrhs, long long ld, const double* __restrict__ wh,
+                            const double* __restrict__ wv, const double* __restrict__ g,
+                            double* __restrict__ f) {
+  const int nc = min(n1, 2), nr = min(n2, 2);
+  const long long per = (long long)nc * n2 + (long long)max(n1 - 2, 0) * nr;
+  const long long gs = (long long)(n1 + 2) * (n2 + 2);
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < per * nrhs;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long k = e / per, q = e % per;
+    int c, r;
+    if (q < (long long)nc * n2) {
+      c = q < n2 ? 0 : n1 - 1;
+      r = (int)(q % n2);
+    } else {
+      const long long q2 = q - (long long)nc * n2;
+      c = 1 + (int)(q2 / nr);
+      r = (q2 % nr == 0) ? 0 : n2 - 1;
+    }
+    const double* gk = g + k * gs;
+    // every product and sum rounded on its own (no fused multiply-add), so the
+    // load is the same to the bit whatever the compiler contracts
+    double add = 0.0;
+    if (c == 0) add = __dadd_rn(add, __dmul_rn(wh[r], gk[r + 1]));
+    if (c == n1 - 1)
+      add = __dadd_rn(add, __dmul_rn(wh[(long long)n1 * n2 + r],
+                                     gk[(long long)(n1 + 1) * (n2 + 2) + r + 1]));
+    if (r == 0)
+      add = __dadd_rn(add, __dmul_rn(wv[(long long)c * (n2 + 1)], gk[(long long)(c + 1) * (n2 + 2)]));
+    if (r == n2 - 1)
+      add = __dadd_rn(add, __dmul_rn(wv[(long long)c * (n2 + 1) + n2],
+                                     gk[(long long)(c + 1) * (n2 + 2) + n2 + 1]));
+    double* fp = f + k * ld + (long long)c * n2 + r;
+    *fp = __dadd_rn(*fp, add);
+  }
+}
+
+int launch_dirichlet(int n1, int n2, int nrhs, long long ld, const double* wh, const double* wv,
+                     const double* g, double* f, hipStream_t st) {
+  const long long per = (long long)std::min(n1, 2) * n2 + (long long)std::max(n1 - 2, 0) * std::min(n2, 2);
+  const unsigned grid = (unsigned)std::min<long long>((per * nrhs + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_dirichlet, dim3(grid), dim3(256), 0, st, n1, n2, nrhs, ld, wh, wv, g, f);
+  SLAB_LAUNCH_CHECK();
+  return SLAB_OK;
+}
+
 }  // namespace slab

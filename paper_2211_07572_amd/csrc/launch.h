@@ -91,6 +91,10 @@ void plan_converge(Plan& plan, const std::vector<ConvDev>& conv, bool first);
 int launch_kappa_grad(int n1, int n2, int nrhs, long long ld, double h, const double* kappa,
                       const double* u, const double* lam, int mode, double* grad, hipStream_t st);
 
+// f += load of the Dirichlet data g on the ring (nrhs fields of (n1+2)(n2+2)).
+int launch_dirichlet(int n1, int n2, int nrhs, long long ld, const double* wh, const double* wv,
+                     const double* g, double* f, hipStream_t st);
+
 // FP64 copy of a float or double array.
 int launch_cast_f64(const void* src, int src_is_float, double* dst, long long count,
                     hipStream_t st);

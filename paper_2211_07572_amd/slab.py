@@ -87,6 +87,7 @@ def load_library(path: str = LIB_PATH):
     L.slab_index_maps.argtypes = [i32, i32, i32, vp, vp, vp, vp, vp, vp]
     L.slab_kappa_grad.argtypes = [vp, vp, vp, i32, i64, i32, vp, vp]
     L.slab_residual.argtypes = [vp, vp, vp, i32, i64, ctypes.POINTER(dp), vp]
+    L.slab_dirichlet_load.argtypes = [vp, vp, vp, i32, i64, vp]
     L.slab_export_reduced.argtypes = [vp, i32, i32, vp, vp]
     L.slab_apply_reduced.argtypes = [vp, vp, vp, i32, vp]
     L.slab_query.argtypes = [vp, i32, ctypes.POINTER(i64)]
@@ -294,6 +295,28 @@ def slab_kappa_grad(handle: SlabHandle, u, lam, mode: int = 1, stream=None):
                                           u3.shape[0], handle.n1 * handle.n2, mode,
                                           _dev_f64(grad, "grad"), _stream_ptr(stream)))
     return grad
+
+
+def slab_dirichlet_load(handle: SlabHandle, g, f=None, stream=None):
+    """f += load of the Dirichlet data g (ring values of (n1+2, n2+2) fields,
+    shape (nrhs, n1+2, n2+2) or (n1+2, n2+2), CUDA float64) on the right-hand
+    side of A u = f; f (nrhs, n1, n2) is updated in place, or a new zero one is
+    made.  Returns f."""
+    import torch
+    g3 = g.unsqueeze(0) if g.dim() == 2 else g
+    if g3.dim() != 3 or tuple(g3.shape[1:]) != (handle.n1 + 2, handle.n2 + 2):
+        raise ValueError(f"g must have shape (nrhs, {handle.n1 + 2}, {handle.n2 + 2})")
+    g3 = g3.contiguous()
+    if f is None:
+        f = torch.zeros((g3.shape[0], handle.n1, handle.n2), dtype=torch.float64,
+                        device=g3.device)
+    f3 = _vec_shape(f, handle.n2, handle.n1)
+    if not f3.is_contiguous() or f3.shape[0] != g3.shape[0]:
+        raise ValueError("f must be contiguous with one column per field of g")
+    _check(load_library().slab_dirichlet_load(handle.ptr, _dev_f64(g3, "g"), _dev_f64(f3, "f"),
+                                              g3.shape[0], handle.n1 * handle.n2,
+                                              _stream_ptr(stream)))
+    return f
 
 
 def slab_residual(handle: SlabHandle, f, u, stream=None) -> list[float]:
