@@ -419,8 +419,9 @@ def cpu_oracle_whole(w: G.Workload, workers: int, one_core: bool = False) -> dic
 
 def extra_workloads(warmup: int, steps: int) -> dict:
     """The 1024x1024 (FP64, 1 and 64 right-hand sides; mixed, 1 RHS) and
-    512x512 (FP64 factor + solve + adjoint + gradient) workloads on the GPU,
-    median step times."""
+    512x512 (FP64 factor + solve + adjoint + gradient) workloads, the
+    indefinite Helmholtz workloads (40 points per wavelength, and the paper's
+    J0 benchmark at 1M and 4M unknowns) on the GPU, median step times."""
     import torch
     from paper_2211_07572_amd import slab as S
     out = {}
@@ -439,6 +440,67 @@ def extra_workloads(warmup: int, steps: int) -> dict:
     out[f"{G.ADJOINT_512.name}_batch16_fp64_factor_solve_adjoint_grad"] = differentiation_batch(
         warmup, steps)
     out.update(helmholtz_workload(warmup, steps))
+    out.update(helmholtz_fd_paper(warmup, steps))
+    return out
+
+
+# The paper's FD Helmholtz runs at 250 points per wavelength (Sec. 5.2, the
+# figure of constant points-per-wavelength runs): N, b, kappa, relerr_res,
+# relerr_true and T_solve (one RHS, on its CPU) of its first two rows.
+PAPER_FD_ROWS = [
+    {"N": 1.0e6, "b": 50, "kappa": 27.1, "relerr_res": 1.1e-11, "relerr_true": 1.8e-3,
+     "T_solve_s": 0.9},
+    {"N": 4.0e6, "b": 100, "kappa": 52.3, "relerr_res": 1.8e-11, "relerr_true": 2.6e-3,
+     "T_solve_s": 2.9},
+]
+
+
+def helmholtz_fd_paper(warmup: int, steps: int) -> dict:
+    """The paper's FD Helmholtz benchmark (-Laplace u - kappa^2 u = 0 on the
+    unit square, Dirichlet data from u_true = J0(kappa |x - (-0.1, 0.5)|)) at
+    its first two sizes: n = 1000 and 2000 per side (h = 1/(n+1)), b = 49 (the
+    largest width whose period divides n; the paper's b is 50 and 100), FP64,
+    odd-even order.  One step: factor, load of the boundary data, solve.
+    relerr_res and relerr_true are reported beside the paper's printed ones
+    (its T_solve is on its CPU: context only)."""
+    import torch
+    from paper_2211_07572_amd import slab as S
+    out = {}
+    log("extra workload: the paper's FD Helmholtz benchmark (J0 data), 1M and 4M unknowns")
+    for row in PAPER_FD_ROWS:
+        n = int(round(np.sqrt(row["N"])))
+        k = row["kappa"]
+        h = 1.0 / (n + 1)
+        ut = G.bessel_field(n, n, k, h)
+        kap = torch.as_tensor(G.kappa_const(n, n), device="cuda")
+        cd = torch.full((n, n), -k * k, dtype=torch.float64, device="cuda")
+        g = torch.as_tensor(ut, device="cuda")
+        times, solve_times = [], []
+        for it in range(warmup + steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            hd = S.slab_factor(kap, n, n, 49, h, odd_even=True, shift=cd)
+            f = S.slab_dirichlet_load(hd, g)
+            t1 = time.perf_counter()
+            u = S.slab_solve(hd, f)   # returns after its work has finished
+            t2 = time.perf_counter()
+            if it >= warmup:
+                times.append(t2 - t0)
+                solve_times.append(t2 - t1)
+            if it < warmup + steps - 1:
+                hd.free()
+        rr = S.slab_residual(hd, f, u)[0]
+        passes = hd.last_info.iterations
+        neg = hd.negative_pivots()
+        hd.free()
+        e = float(np.linalg.norm(u.cpu().numpy()[0] - ut[1:-1, 1:-1]) /
+                  np.linalg.norm(ut[1:-1, 1:-1]))
+        med = float(np.median(times))
+        out[f"helmholtz_fd_j0_{n}x{n}_b49_kappa{k}_fp64"] = {
+            "ms_per_step": med * 1e3, "dof_per_s": n * n / med,
+            "solve_ms": float(np.median(solve_times)) * 1e3, "relerr_res": rr,
+            "relerr_true": e, "refine_passes": passes, "negative_pivots": neg,
+            "paper": row, "steps": steps, "warmup": warmup}
     return out
 
 
@@ -450,6 +512,7 @@ def helmholtz_workload(warmup: int, steps: int) -> dict:
     must equal, and cond(A) from the same eigenvalues."""
     import torch
     from paper_2211_07572_amd import slab as S
+    log("extra workload: indefinite Helmholtz 1024x1024, 40 points per wavelength")
     w = G.HELMHOLTZ_1024
     c = w.shift()
     k2 = -float(c[0, 0])
