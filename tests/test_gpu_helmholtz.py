@@ -317,3 +317,36 @@ def test_paper_fd_helmholtz_1m():
     assert rr <= PAPER_FD_1M["relerr_res"]
     assert PAPER_FD_1M["relerr_true"] / 1.5 <= e <= PAPER_FD_1M["relerr_true"] * 1.5
     hd.free()
+
+
+@pytest.mark.parametrize("precision", [S.SLAB_FP64, S.SLAB_MIXED])
+def test_indefinite_T_512(precision):
+    """512 x 512, b = 15, 36 points per wavelength (612 negative eigenvalues,
+    cond(A) 5.4e4): pivot blocks of eight 64-column panels, so the signed
+    trailing updates run at several panel offsets; the block-vector products
+    split over k (n >= 512) with their pivot signs; the mixed form on forced
+    128-wide FP32 tiles with scaled k.  Negative pivots against the closed
+    form, u against the oracle's SuperLU solve within cond(A) times the
+    residuals."""
+    n, b, ppw = 512, 15, 36.0
+    c, neg, cond = _indef_setup(n, n, b, ppw)
+    kap = G.kappa_const(n, n)
+    prob = O.make_problem(kap, n, n, b, shift=c)
+    f = G.rhs_uniform(n, n, 2, 12)
+    u_ref = O.direct_solve(prob, f)
+    rr_ref = O.relres(prob, u_ref, f)
+    print(f"case: indefinite 512x512 b=15 ppw=36 precision={precision}", flush=True)
+    h = S.slab_factor(_dev(kap), n, n, b, precision=precision, tol=1e-10, max_iter=20,
+                      odd_even=True, shift=_dev(c), tile=128 if precision == S.SLAB_MIXED else 0)
+    assert h.negative_pivots() == neg
+    u = S.slab_solve(h, _dev(f)).cpu().numpy()
+    rr = O.relres(prob, u, f)
+    lc = h.launches()
+    print(f"  relres {rr.max():.2e} after {h.last_info.iterations} passes, "
+          f"u vs oracle {_col_rel(u, u_ref).max():.2e}, launches {lc}", flush=True)
+    assert rr.max() <= 1e-10
+    assert np.all(_col_rel(u, u_ref) <= cond * (rr + rr_ref) * 1.01 + 1e-15)
+    assert lc["bmv_split"] > 0
+    if precision == S.SLAB_MIXED:
+        assert lc["gemm128"] > 0
+    h.free()
