@@ -283,6 +283,21 @@ __global__ __launch_bounds__(256, SLAB_GEMM_WAVES) void k_gemm(const GemmItem* _
 #ifndef SLAB_GEMM128_TK
 #define SLAB_GEMM128_TK 16   // k per chunk of the 128-wide tiles
 #endif
+#ifndef SLAB_GEMM_F64_TILE
+#define SLAB_GEMM_F64_TILE 64   // FP64 block-product tile (64 or 128)
+#endif
+#ifndef SLAB_GEMM_F64_TK
+#define SLAB_GEMM_F64_TK 16     // k per chunk of the 64-wide FP64 tiles (32 and 8: slower)
+#endif
+#ifndef SLAB_GEMM_CPRE_F64_TK
+#define SLAB_GEMM_CPRE_F64_TK 16  // k per chunk of the FP64 factorization updates (32: slower)
+#endif
+#ifndef SLAB_GEMM_F32_TK
+#define SLAB_GEMM_F32_TK 32       // k per chunk of the 64-wide FP32 tiles
+#endif
+#ifndef SLAB_GEMM_CPRE_F32_TK
+#define SLAB_GEMM_CPRE_F32_TK 32  // k per chunk of the FP32 factorization updates
+#endif
 #ifndef SLAB_GEMM_WIDE
 #define SLAB_GEMM_WIDE 0   // 128 x 256 tiles for full-output FP32 products (measured
                                    // slower: 265 registers, one wave per SIMD)
@@ -344,6 +359,7 @@ void plan_gemm(Plan& plan, bool ak, bool bn, const std::vector<GemmItem>& items,
   int tile = (sizeof(T) == 4 && area >= 1024LL * 128 * 128) ? 128 : 64;
   const bool cpre = (flags & GEMM_C_PREFETCH) != 0;
   if (sizeof(T) == 4 && (force_tile == 64 || force_tile == 128)) tile = force_tile;
+  if (sizeof(T) == 8) tile = SLAB_GEMM_F64_TILE;
   if (cpre) tile = 64;
   ++plan.launches[cpre ? LK_GEMM_CPRE : (tile == 128 ? LK_GEMM128 : LK_GEMM64)];
   // full-output products on 128-wide tiles take 128 x 256 tiles
@@ -367,8 +383,9 @@ void plan_gemm(Plan& plan, bool ak, bool bn, const std::vector<GemmItem>& items,
       SLAB_HIP_CHECK(hipEventRecord(e0, st));
     }
     if (cpre)
-      gemm_tile<T, 64, 32, true>(ak, bn, vecok, ks, (unsigned)tot, dev_at<GemmItem>(dev, oi),
-                                 dev_at<int>(dev, oo), count, alpha, beta, flags, st);
+      gemm_tile<T, 64, (sizeof(T) == 8 ? SLAB_GEMM_CPRE_F64_TK : SLAB_GEMM_CPRE_F32_TK), true>(
+          ak, bn, vecok, ks, (unsigned)tot, dev_at<GemmItem>(dev, oi), dev_at<int>(dev, oo), count,
+          alpha, beta, flags, st);
     else if (tile == 128 && wnf == 2)
       gemm_tile<T, 128, SLAB_GEMM128_TK, false, 2>(ak, bn, vecok, ks, (unsigned)tot,
                                                   dev_at<GemmItem>(dev, oi), dev_at<int>(dev, oo),
@@ -378,8 +395,9 @@ void plan_gemm(Plan& plan, bool ak, bool bn, const std::vector<GemmItem>& items,
                                          dev_at<GemmItem>(dev, oi), dev_at<int>(dev, oo), count,
                                          alpha, beta, flags, st);
     else
-      gemm_tile<T, 64, 32>(ak, bn, vecok, ks, (unsigned)tot, dev_at<GemmItem>(dev, oi),
-                           dev_at<int>(dev, oo), count, alpha, beta, flags, st);
+      gemm_tile<T, 64, (sizeof(T) == 8 ? SLAB_GEMM_F64_TK : SLAB_GEMM_F32_TK)>(
+          ak, bn, vecok, ks, (unsigned)tot, dev_at<GemmItem>(dev, oi), dev_at<int>(dev, oo), count,
+          alpha, beta, flags, st);
     SLAB_LAUNCH_CHECK();
     if (tm) SLAB_HIP_CHECK(hipEventRecord(e1, st));
     return SLAB_OK;
