@@ -91,15 +91,14 @@ typedef struct {
   const double* shift; /* device, n1*n2 FP64 (node (c, r) at c*n2 + r), finite, or NULL:
                           a diagonal term c_p added to A, (A u)_p += c_p u_p.  With
                           c = -k^2 b(x) it is the Helmholtz term of eq. (var_helm)
-                          (wavenumber k; the paper writes kappa for it).  The slab
-                          interiors are factored as positive definite blocks (a shift
-                          that makes one indefinite is reported as SLAB_E_BREAKDOWN:
-                          for the Helmholtz term, k (b+1) h must stay below about pi,
-                          two slab widths per wavelength); the reduced matrix T may
-                          be indefinite: with a shift its pivot blocks are factored
-                          in signed form L J L^T (no pivoting; a zero pivot is
-                          SLAB_E_BREAKDOWN).  Read during slab_factor (and again by
-                          slab_batch_run). */
+                          (wavenumber k; the paper writes kappa for it).  A shift
+                          may make A indefinite: with one, both stages eliminate
+                          with pivots of either sign and no pivoting (the slab
+                          blocks by 2 x 2 pivot blocks, the pivot blocks of the
+                          reduced matrix T in signed form L J L^T).  A zero pivot
+                          is SLAB_E_BREAKDOWN; growth from small ones shows as a
+                          refinement that does not converge (SLAB_E_NOCONV).  Read
+                          during slab_factor (and again by slab_batch_run). */
 } slab_problem;
 
 typedef struct {
@@ -294,8 +293,8 @@ int slab_export_reduced(slab_handle h, int32_t which, int32_t j, double* out, vo
    5 device bytes held, 6 the FP32 product tile in use (0: automatic),
    7 the number of negative pivots of the signed block factorization of T
    (problems with a shift; 0 otherwise), which is the number of negative
-   eigenvalues of T (Sylvester's law of inertia) and, with definite slab
-   interiors, of A (synchronous: copies the pivot signs to the host),
+   eigenvalues of T (Sylvester's law of inertia): those of A less those of the
+   slab interiors (synchronous: copies the pivot signs to the host),
    10+p elapsed microseconds of factor phase p of the last
    factorization (0 slab factors, 1 boundary columns of the slab inverses,
    2 Schur propagation, 3 assembly of T, 4 block factorization of T, 5 the

@@ -235,6 +235,9 @@ __global__ __launch_bounds__(NT) void k_slab_factor(const ProbDev* __restrict__ 
   double rl[D], rr[D], rd[D], ru[D], rs[D], cd[D][C], cu[D][C];
   const g_t<const double>* __restrict__ sh = gp((const double*)P[it].shift);
   const long long ss = P[it].shift_stride;
+  // with a diagonal term the slab blocks may be indefinite: nonzero pivots
+  // of either sign are taken (no pivoting), else they must be positive
+  const bool signed_piv = ss != 0;
   // unconditional loads from clamped rows (a load skipped on some path makes
   // the compiler wait for every outstanding load); masked where used
   auto load = [&](int d, int t) __attribute__((always_inline)) {
@@ -307,7 +310,8 @@ __global__ __launch_bounds__(NT) void k_slab_factor(const ProbDev* __restrict__ 
           if constexpr (PB == 2) {
             const T h00 = h[0][0], h01 = h[0][1], h11 = h[1][1];
             const T det = fma(h00, h11, -(h01 * h01));
-            ok = ok && (h00 > (T)0) && (det > (T)0) && isfinite((double)det);
+            ok = ok && (signed_piv ? det != (T)0 : (h00 > (T)0) && (det > (T)0)) &&
+                 isfinite((double)det);
             const T ninv = -fast_recip(det);
             h[0][0] = h11 * ninv;
             h[1][1] = h00 * ninv;
@@ -316,7 +320,7 @@ __global__ __launch_bounds__(NT) void k_slab_factor(const ProbDev* __restrict__ 
 #pragma unroll
           for (int pp = 0; pp < PB; ++pp) {
             const T dp = h[pp][pp];
-            ok = ok && (dp > (T)0) && isfinite((double)dp);
+            ok = ok && (signed_piv ? dp != (T)0 : dp > (T)0) && isfinite((double)dp);
             const T inv = fast_recip(dp);
 #pragma unroll
             for (int u = 0; u < PB; ++u) {
@@ -486,6 +490,7 @@ __global__ __launch_bounds__(256) void k_sigma(const ProbDev* __restrict__ P,
     for (int k = 0; k < BP; ++k) a[k] -= wt * G[k] * wsh[wave][h][k] + wb * H[swz_index<T>(i, k, BP)];
   }
   T rl = (i == 0) ? (T)1 : (T)0, rr = (i == b - 1) ? (T)1 : (T)0;
+  const bool signed_piv = P[it].shift_stride != 0;   // as in k_slab_factor
   bool ok = true;
 #pragma unroll
   for (int p = 0; p < BP; ++p) {
@@ -498,7 +503,7 @@ __global__ __launch_bounds__(256) void k_sigma(const ProbDev* __restrict__ P,
     }
     wave_lds_sync();
     const T d = pr[p];
-    ok = ok && (d > (T)0) && isfinite((double)d);
+    ok = ok && (signed_piv ? d != (T)0 : d > (T)0) && isfinite((double)d);
     const T inv = fast_recip(d);
     const bool piv = i == p;
     // other rows: x -= f x_p with f = a[p] / d; the pivot row is scaled (no

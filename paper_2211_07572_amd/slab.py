@@ -179,7 +179,7 @@ class SlabHandle:
     def negative_pivots(self) -> int:
         """Negative pivots of the signed block factorization of T (factored
         with a diagonal term; 0 otherwise): the number of negative eigenvalues
-        of T."""
+        of T, i.e. those of A less those of the slab interiors."""
         return self.query(7)
 
     LAUNCH_KINDS = ("gemm128", "gemm64", "gemm_cprefetch", "bmv_split", "bmv")

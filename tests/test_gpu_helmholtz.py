@@ -4,13 +4,14 @@
 Definite cases: a nonnegative c (screened diffusion on a lognormal
 coefficient) and a Helmholtz term -k^2 below the lowest eigenvalue of the
 Laplacian.  Indefinite cases: a Helmholtz term several wavelengths across the
-grid with slabs narrower than half a wavelength, so that the slab interiors
-stay definite and only T is indefinite; its pivot blocks are factored in
-signed form L J L^T.  There the number of negative pivots must equal the
-number of Laplacian eigenvalues below k^2 (closed form, inertia of Schur
-complements) and the solution must match the oracle within cond(A) times the
-two residuals.  Slabs wider than that are indefinite themselves, and the
-factorization must say so (SLAB_E_BREAKDOWN) rather than return a wrong answer.
+grid, with slabs narrower than half a wavelength (only T indefinite) or wider
+(indefinite slab interiors too); both stages then eliminate with pivots of
+either sign and no pivoting, the pivot blocks of T in signed form L J L^T.
+The number of negative pivots of T must equal the closed-form count from the
+sine modes (negative eigenvalues of A minus those of the m slab interiors,
+by the inertia additivity of Schur complements) and the solution must match
+the oracle within cond(A) times the two residuals.  An exactly zero pivot must
+be reported (SLAB_E_BREAKDOWN) rather than return a wrong answer.
 """
 import numpy as np
 import pytest
@@ -124,14 +125,16 @@ def test_shift_in_batch_and_graph_run():
     bt.free()
 
 
-def test_indefinite_slabs_are_reported():
-    """Six points per wavelength on a 64 x 64 grid: A is indefinite, and so are
-    the slab blocks, eight columns wide (more than half a wavelength); the
-    factorization reports it."""
-    n2, n1, b = 64, 64, 7
-    c = G.helmholtz_shift(n2, n1, 6.0)
+def test_zero_slab_pivot_is_reported():
+    """A diagonal term that makes the first pivot of every slab exactly zero
+    (b = 1, h = 1/32 so that c = -4/h^2 cancels the diagonal 4/h^2 exactly):
+    the signed elimination without pivoting cannot go on, and the
+    factorization says so instead of returning a wrong answer."""
+    n2, n1, b = 31, 32, 1
+    h = 1.0 / 32
+    c = np.full((n1, n2), -4.0 / h ** 2)
     with pytest.raises(S.SlabError) as ei:
-        S.slab_factor(_dev(G.kappa_const(n2, n1)), n2, n1, b, odd_even=True, shift=_dev(c))
+        S.slab_factor(_dev(G.kappa_const(n2, n1)), n2, n1, b, h, odd_even=True, shift=_dev(c))
     assert ei.value.status == S.SLAB_E_BREAKDOWN
 
 
@@ -148,15 +151,15 @@ def _laplace_eigs(n2, n1, h):
 INDEF = [("ppw20_b7", 200, 96, 7, 20.0), ("ppw40_b15", 130, 160, 15, 40.0)]
 
 
-def _indef_setup(n2, n1, b, ppw):
+def _indef_setup(n2, n1, b, ppw, slabs_definite=True):
     h = 1.0 / (n2 + 1)
     c = G.helmholtz_shift(n2, n1, ppw, h)
     k2 = -c[0, 0]
     lam = _laplace_eigs(n2, n1, h)
     gap = np.abs(lam - k2)
-    slab_min = (4 - 2 * np.cos(np.pi / (b + 1)) - 2 * np.cos(np.pi / (n2 + 1))) / h ** 2
-    assert slab_min > k2  # definite slab interiors
-    neg = int((lam < k2).sum())
+    slab_neg = int((_laplace_eigs(n2, b, h) < k2).sum())   # one slab interior
+    assert (slab_neg == 0) == slabs_definite
+    neg = int((lam < k2).sum()) - (n1 // (b + 1)) * slab_neg   # negative eigenvalues of T
     assert neg > 0
     cond = gap.max() / gap.min()   # A = -Laplace - k^2 is symmetric: exact cond_2
     return c, neg, cond
@@ -349,4 +352,45 @@ def test_indefinite_T_512(precision):
     assert lc["bmv_split"] > 0
     if precision == S.SLAB_MIXED:
         assert lc["gemm128"] > 0
+    h.free()
+
+
+# indefinite slab interiors too: 8, 8 and 32 columns against 6, 10 and 12 points
+# per wavelength (35, 47 and 160 negative eigenvalues per slab)
+INDEF_SLABS = [("ppw6_b7", 64, 64, 7, 6.0), ("ppw10_b7", 200, 96, 7, 10.0),
+               ("ppw12_b31", 256, 256, 31, 12.0)]
+
+
+@pytest.mark.parametrize("order", ORDERS)
+@pytest.mark.parametrize("case", INDEF_SLABS, ids=[c[0] for c in INDEF_SLABS])
+def test_indefinite_slabs_fp64(case, order):
+    name, n2, n1, b, ppw = case
+    c, neg, cond = _indef_setup(n2, n1, b, ppw, slabs_definite=False)
+    kap = G.kappa_const(n2, n1)
+    prob = O.make_problem(kap, n2, n1, b, shift=c)
+    f = G.rhs_uniform(n2, n1, 2, 5)
+    u_ref = O.direct_solve(prob, f)
+    rr_ref = O.relres(prob, u_ref, f)
+    h = S.slab_factor(_dev(kap), n2, n1, b, odd_even=order == "odd_even", shift=_dev(c))
+    assert h.negative_pivots() == neg
+    u = S.slab_solve(h, _dev(f)).cpu().numpy()
+    rr = O.relres(prob, u, f)
+    assert rr.max() <= 1e-10
+    assert np.all(_col_rel(u, u_ref) <= cond * (rr + rr_ref) * 1.01 + 1e-15)
+    h.free()
+
+
+@pytest.mark.parametrize("order", ORDERS)
+def test_indefinite_slabs_mixed(order):
+    """Mixed form, 130 x 160 with 16-column slabs at 20 points per wavelength."""
+    n2, n1, b, ppw = 130, 160, 15, 20.0
+    c, neg, cond = _indef_setup(n2, n1, b, ppw, slabs_definite=False)
+    kap = G.kappa_const(n2, n1)
+    prob = O.make_problem(kap, n2, n1, b, shift=c)
+    h = S.slab_factor(_dev(kap), n2, n1, b, precision=S.SLAB_MIXED, tol=1e-10, max_iter=20,
+                      odd_even=order == "odd_even", shift=_dev(c))
+    assert h.negative_pivots() == neg
+    f = G.rhs_uniform(n2, n1, 2, 8)
+    u = S.slab_solve(h, _dev(f)).cpu().numpy()
+    assert O.relres(prob, u, f).max() <= 1e-10
     h.free()

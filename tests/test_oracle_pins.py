@@ -663,19 +663,22 @@ def _laplace_eigs(n2, n1, h):
     return (4 - 2 * np.cos(np.pi * k1 / (n1 + 1)) - 2 * np.cos(np.pi * k2 / (n2 + 1))) / h ** 2
 
 
-@pytest.mark.parametrize("n2,n1,b,ppw", [(48, 64, 7, 20.0), (37, 40, 3, 10.0)])
+@pytest.mark.parametrize("n2,n1,b,ppw", [(48, 64, 7, 20.0), (37, 40, 3, 10.0), (40, 48, 7, 8.0),
+                                         (33, 40, 9, 10.0)])
 def test_helmholtz_pivot_inertia(n2, n1, b, ppw):
-    """Slab interiors definite (their lowest eigenvalue, from b columns, above
-    k^2), A indefinite: by the inertia additivity of Schur complements the
-    negative eigenvalues of all pivot blocks of either order add up to those
-    of A, which the sine modes give in closed form (lam_kl < k^2)."""
+    """By the inertia additivity of Schur complements, the negative
+    eigenvalues of all pivot blocks of either order add up to those of A
+    minus those of the m slab interiors; both come from sine modes in closed
+    form (lam_kl < k^2 on the n1 x n2 grid, and on the b x n2 grid of one
+    slab with its interfaces as boundary).  The first two cases have definite
+    slabs, the last two indefinite ones."""
     h = 1.0 / (n2 + 1)
     c = G.helmholtz_shift(n2, n1, ppw, h)
     k2 = -c[0, 0]
-    slab_min = (4 - 2 * np.cos(np.pi / (b + 1)) - 2 * np.cos(np.pi / (n2 + 1))) / h ** 2
-    assert slab_min > k2
     lam = _laplace_eigs(n2, n1, h)
-    neg_ref = int((lam < k2).sum())
+    lam_slab = _laplace_eigs(n2, b, h)
+    m = n1 // (b + 1)
+    neg_ref = int((lam < k2).sum()) - m * int((lam_slab < k2).sum())
     assert neg_ref >= 5 and np.abs(lam - k2).min() > 1e-6 * k2
     p = O.make_problem(G.kappa_const(n2, n1), n2, n1, b, h, shift=c)
     for order in ("sweep", "odd_even"):
