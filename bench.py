@@ -29,6 +29,17 @@ from gen import inputs as G  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 
 
+def finite_json(obj):
+    """obj with every non-finite float replaced by None (strict JSON)."""
+    if isinstance(obj, dict):
+        return {k: finite_json(v) for k, v in obj.items()}
+    if isinstance(obj, (list, tuple)):
+        return [finite_json(v) for v in obj]
+    if isinstance(obj, float) and not np.isfinite(obj):
+        return None
+    return obj
+
+
 def log(msg: str) -> None:
     """Progress line on stderr (stdout carries only the JSON line)."""
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -507,43 +518,56 @@ def helmholtz_fd_paper(warmup: int, steps: int) -> dict:
 
 
 def helmholtz_workload(warmup: int, steps: int) -> dict:
-    """Indefinite Helmholtz on 1024 x 1024 (b = 15, 40 points per wavelength),
-    factor + solve per step in FP64 (odd-even order, signed block
-    factorization).  The negative pivots are reported beside the number
-    of Laplacian eigenvalues below k^2 (sine modes, closed form), which they
-    must equal, and cond(A) from the same eigenvalues."""
+    """Indefinite Helmholtz, -Laplace u - k^2 u, factor + solve per step in FP64
+    (odd-even order, signed elimination): 1024 x 1024, b = 15, 40 points per
+    wavelength (definite slabs, indefinite T) and 2048 x 2048, b = 31, 20 points
+    per wavelength (indefinite slabs too).  The negative pivots of T are
+    reported beside their closed-form count (the sine modes: eigenvalues of A
+    below k^2 less m times those of one slab interior), with cond(A) from the
+    same eigenvalues, and the outcome of the mixed form (one untimed solve)."""
     import torch
     from paper_2211_07572_amd import slab as S
-    log("extra workload: indefinite Helmholtz 1024x1024, 40 points per wavelength")
-    w = G.HELMHOLTZ_1024
-    c = w.shift()
-    k2 = -float(c[0, 0])
-    p1 = np.arange(1, w.n1 + 1)[:, None]
-    p2 = np.arange(1, w.n2 + 1)[None, :]
-    lam = (4 - 2 * np.cos(np.pi * p1 / (w.n1 + 1)) - 2 * np.cos(np.pi * p2 / (w.n2 + 1))) / w.h ** 2
-    gap = np.abs(lam - k2)
-    kap = torch.as_tensor(w.kappa(), device="cuda")
-    cd = torch.as_tensor(c, device="cuda")
-    f = torch.as_tensor(w.rhs(1), device="cuda").contiguous()
-    _, per, _, info, _ = run_gpu(w, S.SLAB_FP64, steps, warmup, kap, f, True, shift=cd)
-    h = S.slab_factor(kap, w.n2, w.n1, w.b, w.h, precision=S.SLAB_FP64, odd_even=True, shift=cd)
-    neg = h.negative_pivots()
-    h.free()
-    med = float(np.median(per))
-    res = {"ms_per_step": med * 1e3, "dof_per_s": w.N / med,
-           "max_relres": max(r for _, r in info), "refine_passes": max(i for i, _ in info),
-           "negative_pivots": neg, "laplace_eigs_below_k2": int((lam < k2).sum()),
-           "cond_A": float(gap.max() / gap.min())}
-    # the FP32 reduced factorization (mixed form) converges only while cond(T)
-    # times its growth times the FP32 rounding stays below one: its outcome
-    # here (one untimed solve, not checked)
-    h = S.slab_factor(kap, w.n2, w.n1, w.b, w.h, precision=S.SLAB_MIXED, odd_even=True,
-                      shift=cd, max_iter=10)
-    S.slab_solve(h, f, check=False)
-    res["mixed_form"] = {"refine_passes": h.last_info.iterations,
-                         "max_relres": h.last_info.max_relres}
-    h.free()
-    return {f"{w.name}_fp64": res}
+    log("extra workload: indefinite Helmholtz 1024x1024 (40 points per wavelength) and "
+        "2048x2048 (20)")
+
+    def laplace_eigs(n2, n1, h):
+        p1 = np.arange(1, n1 + 1)[:, None]
+        p2 = np.arange(1, n2 + 1)[None, :]
+        return (4 - 2 * np.cos(np.pi * p1 / (n1 + 1)) - 2 * np.cos(np.pi * p2 / (n2 + 1))) / h ** 2
+
+    out = {}
+    for w in (G.HELMHOLTZ_1024, G.HELMHOLTZ_2048):
+        c = w.shift()
+        k2 = -float(c[0, 0])
+        lam = laplace_eigs(w.n2, w.n1, w.h)
+        gap = np.abs(lam - k2)
+        neg_closed = int((lam < k2).sum()) - w.m * int((laplace_eigs(w.n2, w.b, w.h) < k2).sum())
+        kap = torch.as_tensor(w.kappa(), device="cuda")
+        cd = torch.as_tensor(c, device="cuda")
+        f = torch.as_tensor(w.rhs(1), device="cuda").contiguous()
+        _, per, _, info, _ = run_gpu(w, S.SLAB_FP64, steps, warmup, kap, f, True, shift=cd)
+        h = S.slab_factor(kap, w.n2, w.n1, w.b, w.h, precision=S.SLAB_FP64, odd_even=True,
+                          shift=cd)
+        neg = h.negative_pivots()
+        h.free()
+        med = float(np.median(per))
+        res = {"ms_per_step": med * 1e3, "dof_per_s": w.N / med,
+               "max_relres": max(r for _, r in info), "refine_passes": max(i for i, _ in info),
+               "negative_pivots": neg, "negative_pivots_closed_form": neg_closed,
+               "cond_A": float(gap.max() / gap.min()), "steps": steps, "warmup": warmup}
+        # the FP32 reduced factorization (mixed form) converges only while cond(T)
+        # times its growth times the FP32 rounding stays below one: its outcome
+        # here (one untimed solve, not checked)
+        h = S.slab_factor(kap, w.n2, w.n1, w.b, w.h, precision=S.SLAB_MIXED, odd_even=True,
+                          shift=cd, max_iter=10)
+        S.slab_solve(h, f, check=False)
+        rr = h.last_info.max_relres
+        res["mixed_form"] = {"refine_passes": h.last_info.iterations,
+                             "max_relres": rr if np.isfinite(rr) else None,
+                             "converged": bool(rr <= 1e-10)}
+        h.free()
+        out[f"{w.name}_fp64"] = res
+    return out
 
 
 def sketch_workload(w: G.Workload, kappa, warmup: int, steps: int) -> dict:
@@ -613,7 +637,7 @@ def main():
     from paper_2211_07572_amd import slab as S
     S.load_library()
     if args.workload == "batch256":
-        print(json.dumps(run_batch_line(args)))
+        print(json.dumps(finite_json(run_batch_line(args)), allow_nan=False))
         return
     w = workload(args.workload)
     kappa_np = w.kappa()
@@ -730,7 +754,7 @@ def main():
             f"poisson_64x64_b7_{workers}workers": cpu_oracle_whole(G.POISSON_64, workers),
             f"diffusion_1024x1024_b31_{workers}workers": cpu_oracle_whole(G.DIFFUSION_1024, workers),
         }
-    print(json.dumps(result))
+    print(json.dumps(finite_json(result), allow_nan=False))
 
 
 if __name__ == "__main__":

@@ -140,6 +140,10 @@ ADJOINT_512 = Workload("adjoint_512x512_b15", 512, 512, 15, 1, "lognormal", "uni
 # under half a wavelength, so only the reduced matrix is indefinite
 HELMHOLTZ_1024 = Workload("helmholtz_1024x1024_b15_ppw40", 1024, 1024, 15, 1, "const", "uniform",
                           extra={"ppw": 40.0})
+# 2048 x 2048 at 20 points per wavelength (102 wavelengths across): slabs of 32
+# columns span 1.6 wavelengths, so the slab interiors are indefinite as well
+HELMHOLTZ_2048 = Workload("helmholtz_2048x2048_b31_ppw20", 2048, 2048, 31, 1, "const", "uniform",
+                          extra={"ppw": 20.0})
 
 
 # The differentiation workload: 16 coefficient fields theta_i = log kappa_i on

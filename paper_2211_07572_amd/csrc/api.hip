@@ -873,8 +873,12 @@ int solve_group(std::vector<SolveJob>& jobs, int precision, bool trans, hipStrea
     for (size_t k = 0; k < live.size(); ++k) {
       const size_t i = idx[k];
       ++it[i];
+      const double prev = worst[i];
       worst[i] = worst_of(rr[k]);
-      const bool done = !(worst[i] > jobs[i].h->tol) || it[i] >= jobs[i].h->max_iter;
+      // a residual above the right-hand side that grew since the last pass:
+      // the refinement diverges (the device-side test stops it the same way)
+      const bool diverged = it[i] >= 2 && worst[i] > 1.0 && worst[i] > prev;
+      const bool done = !(worst[i] > jobs[i].h->tol) || it[i] >= jobs[i].h->max_iter || diverged;
       if (!done) {
         next.push_back(live[k]);
         nidx.push_back(i);

@@ -794,8 +794,8 @@ void plan_residual(Plan& plan, const std::vector<SolveDev>& probs) {
 // synchronization in between: after the residual norms of a pass, the pass
 // count and the max-over-columns relative residual of every live problem are
 // updated, and the problem stays live while relres > tol and passes remain
-// (a non-finite residual stops it, like the host test).  One thread per
-// problem.
+// (a non-finite residual, or one above 1 that grew, stops it, like the host
+// test).  One thread per problem.
 // ---------------------------------------------------------------------------
 __global__ void k_converge(const ConvDev* __restrict__ C, int count, int first) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -818,9 +818,12 @@ __global__ void k_converge(const ConvDev* __restrict__ C, int count, int first) 
   }
   if (!finite) worst = NAN;
   const int it = *c.iters + 1;
+  // a residual above the right-hand side that grew since the last pass: the
+  // refinement diverges (stopped, like the host test)
+  const bool diverged = it >= 2 && worst > 1.0 && worst > *c.relres;
   *c.iters = it;
   *c.relres = worst;
-  *c.live = (worst > c.tol && it < c.max_iter) ? 1 : 0;
+  *c.live = (worst > c.tol && it < c.max_iter && !diverged) ? 1 : 0;
 }
 
 void plan_converge(Plan& plan, const std::vector<ConvDev>& conv, bool first) {

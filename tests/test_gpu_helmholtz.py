@@ -394,3 +394,21 @@ def test_indefinite_slabs_mixed(order):
     u = S.slab_solve(h, _dev(f)).cpu().numpy()
     assert O.relres(prob, u, f).max() <= 1e-10
     h.free()
+
+
+def test_diverging_refinement_stops_early():
+    """The mixed form on 1024 x 1024 at 40 points per wavelength (cond(A) 3e5):
+    the FP32 reduced factorization is too inexact for the refinement to
+    contract, the residual grows past the right-hand side, and the solve stops
+    there with SLAB_E_NOCONV instead of running every allowed pass."""
+    w = G.HELMHOLTZ_1024
+    print("case: mixed form, Helmholtz 1024x1024 b=15 ppw=40", flush=True)
+    h = S.slab_factor(_dev(w.kappa()), w.n2, w.n1, w.b, w.h, precision=S.SLAB_MIXED,
+                      odd_even=True, shift=_dev(w.shift()), max_iter=10)
+    with pytest.raises(S.SlabError) as ei:
+        S.slab_solve(h, _dev(w.rhs(1)))
+    assert ei.value.status == S.SLAB_E_NOCONV
+    it, rr = h.last_info.iterations, h.last_info.max_relres
+    print(f"  stopped after {it} passes at relres {rr:.2e}", flush=True)
+    assert 2 <= it < 10 and not (rr <= 1.0)
+    h.free()

@@ -77,3 +77,19 @@ def test_noalloc_refuses_oversize_request():
     f1 = _dev(G.rhs_uniform(n2, n1, 1, G.SEED_RHS))
     S.slab_solve(h, f1)
     h.free()
+
+
+def test_noalloc_signed_factorization():
+    """A Helmholtz term with indefinite slabs and T (pivots of either sign,
+    pivot signs kept by the handle): the allocation-free solve matches
+    slab_solve on the same handle."""
+    n2, n1, b = 96, 96, 7
+    print("noalloc case: Helmholtz 96x96 b=7, 10 points per wavelength", flush=True)
+    c = G.helmholtz_shift(n2, n1, 10.0)
+    h = S.slab_factor(_dev(G.kappa_const(n2, n1)), n2, n1, b, odd_even=True, shift=_dev(c))
+    assert h.negative_pivots() > 0
+    f = _dev(G.rhs_uniform(n2, n1, 2, 21))
+    r = S.slab_solve(h, f).cpu().numpy()
+    a = S.slab_solve_noalloc(h, f, out=torch.full_like(f, float("nan"))).cpu().numpy()
+    assert _col_rel(a, r).max() <= 1e-12
+    h.free()
