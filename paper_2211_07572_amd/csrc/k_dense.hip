@@ -292,6 +292,9 @@ __global__ __launch_bounds__(256, SLAB_GEMM_WAVES) void k_gemm(const GemmItem* _
 #ifndef SLAB_GEMM_CPRE_F64_TK
 #define SLAB_GEMM_CPRE_F64_TK 16  // k per chunk of the FP64 factorization updates (32: slower)
 #endif
+#ifndef SLAB_GEMM_CPRE_TILE
+#define SLAB_GEMM_CPRE_TILE 64    // tile of the factorization updates (C prefetched)
+#endif
 #ifndef SLAB_GEMM_F32_TK
 #define SLAB_GEMM_F32_TK 32       // k per chunk of the 64-wide FP32 tiles
 #endif
@@ -360,7 +363,7 @@ void plan_gemm(Plan& plan, bool ak, bool bn, const std::vector<GemmItem>& items,
   const bool cpre = (flags & GEMM_C_PREFETCH) != 0;
   if (sizeof(T) == 4 && (force_tile == 64 || force_tile == 128)) tile = force_tile;
   if (sizeof(T) == 8) tile = SLAB_GEMM_F64_TILE;
-  if (cpre) tile = 64;
+  if (cpre) tile = sizeof(T) == 4 ? SLAB_GEMM_CPRE_TILE : 64;
   ++plan.launches[cpre ? LK_GEMM_CPRE : (tile == 128 ? LK_GEMM128 : LK_GEMM64)];
   // full-output products on 128-wide tiles take 128 x 256 tiles
   const int wnf = (SLAB_GEMM_WIDE && tile == 128 && !cpre && !(flags & GEMM_LOWER_C)) ? 2 : 1;
@@ -382,7 +385,11 @@ void plan_gemm(Plan& plan, bool ak, bool bn, const std::vector<GemmItem>& items,
       tm->ev.push_back(e1);
       SLAB_HIP_CHECK(hipEventRecord(e0, st));
     }
-    if (cpre)
+    if (cpre && tile == 128)
+      gemm_tile<T, 128, SLAB_GEMM128_TK, true>(ak, bn, vecok, ks, (unsigned)tot,
+                                               dev_at<GemmItem>(dev, oi), dev_at<int>(dev, oo),
+                                               count, alpha, beta, flags, st);
+    else if (cpre)
       gemm_tile<T, 64, (sizeof(T) == 8 ? SLAB_GEMM_CPRE_F64_TK : SLAB_GEMM_CPRE_F32_TK), true>(
           ak, bn, vecok, ks, (unsigned)tot, dev_at<GemmItem>(dev, oi), dev_at<int>(dev, oo), count,
           alpha, beta, flags, st);
