@@ -17,8 +17,8 @@ namespace slab {
 // MODE 1 (interior): y = f_e + wL u_o(s-1) + wR u_o(s) (the coupling terms
 //   precomputed by k_coupling into xb); writes (or adds) x into the
 //   natural-order output (the interface values go through k_interface_out).
-// One workgroup per (problem, slab, group of 256/BP columns); thread = (row i,
-// column).
+// One workgroup per (problem, slab, group of SLAB_SWEEP_THREADS/BP columns);
+// thread = (row i, column).
 // Software pipeline: while row step r is computed, the block inverses and
 // edge weights of the next D steps are in flight in a register ring and
 // parked in the other half of double-buffered LDS when their step comes (one
@@ -29,12 +29,20 @@ namespace slab {
 // thread that owns each entry, so a step reads only the block inverse and
 // that vector from LDS.
 // ---------------------------------------------------------------------------
+#ifndef SLAB_SWEEP_THREADS
+#define SLAB_SWEEP_THREADS 256   // threads per sweep workgroup (64, 128 or 256)
+#endif
 template <typename T, typename TU, int BP, bool TRANS, int MODE>
-__global__ __launch_bounds__(256) void k_sweep(const SolveDev* __restrict__ P,
-                                               const int* __restrict__ offs, int count) {
-  constexpr int NC = 256 / BP;            // columns per workgroup
-  constexpr int GPT = BP * BP / 256;      // block-inverse elements loaded per thread
-  constexpr int D = BP == 64 ? (sizeof(T) == 8 ? 2 : 4) : 8;  // prefetch depth (row steps)
+__global__ __launch_bounds__(SLAB_SWEEP_THREADS) void k_sweep(const SolveDev* __restrict__ P,
+                                                              const int* __restrict__ offs,
+                                                              int count) {
+  constexpr int NT = SLAB_SWEEP_THREADS;
+  constexpr int NC = NT / BP;             // columns per workgroup
+  constexpr int GPT = BP * BP / NT;       // block-inverse elements loaded per thread
+  static_assert(NC >= 1 && GPT * NT == BP * BP, "sweep workgroup shape");
+  // prefetch depth (row steps), scaled with the elements each thread loads
+  constexpr int D0 = BP == 64 ? (sizeof(T) == 8 ? 2 : 4) : 8;
+  constexpr int D = D0 * NT / 256 > 0 ? D0 * NT / 256 : 1;
   __shared__ T Gs[2][BP][BP + 1];
   __shared__ T Vs[2][NC][BP + 1];
   const int itm = group_item(offs, count, blockIdx.x);
@@ -85,7 +93,7 @@ __global__ __launch_bounds__(256) void k_sweep(const SolveDev* __restrict__ P,
     if (gr >= 0) {
       const g_t<const T>* G = Gl + (size_t)gr * BP * BP;
 #pragma unroll
-      for (int e = 0; e < GPT; ++e) rg[d][e] = G[tid + 256 * e];
+      for (int e = 0; e < GPT; ++e) rg[d][e] = G[tid + NT * e];
     }
     rw[d] = load_w(r);
   };
@@ -100,7 +108,7 @@ __global__ __launch_bounds__(256) void k_sweep(const SolveDev* __restrict__ P,
   auto load_bwd = [&](int d, int r) __attribute__((always_inline)) {
     const g_t<const T>* G = Gl + (size_t)r * BP * BP;
 #pragma unroll
-    for (int e = 0; e < GPT; ++e) rg[d][e] = G[tid + 256 * e];
+    for (int e = 0; e < GPT; ++e) rg[d][e] = G[tid + NT * e];
     rw[d] = load_w(r + 1);
     rz[d] = valid ? zbuf[((size_t)c * n2 + r) * BP + i] : (T)0;
     ru[d] = (MODE == 1 && valid && acc_out && act) ? out_g[(long long)c * ldo + ci * n2 + r] : 0.0;
@@ -112,7 +120,7 @@ __global__ __launch_bounds__(256) void k_sweep(const SolveDev* __restrict__ P,
   auto parkG = [&](int d, int buf) __attribute__((always_inline)) {
 #pragma unroll
     for (int e = 0; e < GPT; ++e) {
-      const int idx = tid + 256 * e;
+      const int idx = tid + NT * e;
       Gs[buf][idx / BP][idx % BP] = rg[d][e];
     }
   };
@@ -443,7 +451,7 @@ static void plan_reduced(Plan& plan, const std::vector<ReducedDev>& R, bool odd_
 template <typename T, typename TR, int BP>
 static void plan_sweep(Plan& plan, const std::vector<SolveDev>& probs, size_t pd, bool trans,
                        int mode) {
-  constexpr int NC = 256 / BP;
+  constexpr int NC = SLAB_SWEEP_THREADS / BP;
   std::vector<int> c;
   for (const SolveDev& d : probs) c.push_back(d.m * ((d.nrhs + NC - 1) / NC));
   long long tot;
@@ -453,11 +461,11 @@ static void plan_sweep(Plan& plan, const std::vector<SolveDev>& probs, size_t pd
     const SolveDev* P = dev_at<SolveDev>(dev, pd);
     const int* of = dev_at<int>(dev, oo);
     if (mode == 0) {
-      if (trans) hipLaunchKernelGGL((k_sweep<T, TR, BP, true, 0>), dim3((unsigned)tot), dim3(256), 0, st, P, of, count);
-      else hipLaunchKernelGGL((k_sweep<T, TR, BP, false, 0>), dim3((unsigned)tot), dim3(256), 0, st, P, of, count);
+      if (trans) hipLaunchKernelGGL((k_sweep<T, TR, BP, true, 0>), dim3((unsigned)tot), dim3(SLAB_SWEEP_THREADS), 0, st, P, of, count);
+      else hipLaunchKernelGGL((k_sweep<T, TR, BP, false, 0>), dim3((unsigned)tot), dim3(SLAB_SWEEP_THREADS), 0, st, P, of, count);
     } else {
-      if (trans) hipLaunchKernelGGL((k_sweep<T, TR, BP, true, 1>), dim3((unsigned)tot), dim3(256), 0, st, P, of, count);
-      else hipLaunchKernelGGL((k_sweep<T, TR, BP, false, 1>), dim3((unsigned)tot), dim3(256), 0, st, P, of, count);
+      if (trans) hipLaunchKernelGGL((k_sweep<T, TR, BP, true, 1>), dim3((unsigned)tot), dim3(SLAB_SWEEP_THREADS), 0, st, P, of, count);
+      else hipLaunchKernelGGL((k_sweep<T, TR, BP, false, 1>), dim3((unsigned)tot), dim3(SLAB_SWEEP_THREADS), 0, st, P, of, count);
     }
     SLAB_LAUNCH_CHECK();
     return SLAB_OK;
