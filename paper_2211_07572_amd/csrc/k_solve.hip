@@ -29,9 +29,31 @@ namespace slab {
 // thread that owns each entry, so a step reads only the block inverse and
 // that vector from LDS.
 // ---------------------------------------------------------------------------
+#ifndef SLAB_SWEEP_VEC
+#define SLAB_SWEEP_VEC 1   // 16-byte LDS reads in the sweep products (0: 8-byte, measured slower)
+#endif
 #ifndef SLAB_SWEEP_THREADS
 #define SLAB_SWEEP_THREADS 256   // threads per sweep workgroup (64, 128 or 256)
 #endif
+// t[k mod 4] += g[k] v[k] over k < BP; VEC: 16-byte LDS reads (g and v
+// 16-byte aligned)
+template <typename T, int BP, bool VEC>
+__device__ __forceinline__ void dot_row(const T* g, const T* v, T (&t)[4]) {
+  if constexpr (VEC) {
+    constexpr int W = 16 / sizeof(T);
+    typedef T vt __attribute__((ext_vector_type(W)));
+#pragma unroll
+    for (int k = 0; k < BP; k += W) {
+      const vt gg = *(const vt*)(g + k), vv = *(const vt*)(v + k);
+#pragma unroll
+      for (int e = 0; e < W; ++e) t[(k + e) & 3] += gg[e] * vv[e];
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < BP; ++k) t[k & 3] += g[k] * v[k];
+  }
+}
+
 template <typename T, typename TU, int BP, bool TRANS, int MODE>
 __global__ __launch_bounds__(SLAB_SWEEP_THREADS) void k_sweep(const SolveDev* __restrict__ P,
                                                               const int* __restrict__ offs,
@@ -43,8 +65,11 @@ __global__ __launch_bounds__(SLAB_SWEEP_THREADS) void k_sweep(const SolveDev* __
   // prefetch depth (row steps), scaled with the elements each thread loads
   constexpr int D0 = BP == 64 ? (sizeof(T) == 8 ? 2 : 4) : 8;
   constexpr int D = D0 * NT / 256 > 0 ? D0 * NT / 256 : 1;
-  __shared__ T Gs[2][BP][BP + 1];
-  __shared__ T Vs[2][NC][BP + 1];
+  // SLAB_SWEEP_VEC: rows padded to 16 bytes and read as 16-byte vectors in the
+  // products with Gl (not transposed)
+  constexpr int GPAD = SLAB_SWEEP_VEC ? 16 / (int)sizeof(T) : 1;
+  __shared__ __attribute__((aligned(16))) T Gs[2][BP][BP + GPAD];
+  __shared__ __attribute__((aligned(16))) T Vs[2][NC][BP + GPAD];
   const int itm = group_item(offs, count, blockIdx.x);
   if (item_done(P[itm].live)) return;
   const int bx = blockIdx.x - offs[itm];
@@ -167,10 +192,7 @@ __global__ __launch_bounds__(SLAB_SWEEP_THREADS) void k_sweep(const SolveDev* __
       T out, vn;
       if (!TRANS) {
         T t[4] = {(T)0, (T)0, (T)0, (T)0};
-        if (r > 0) {
-#pragma unroll
-          for (int k = 0; k < BP; ++k) t[k & 3] += Gs[cur][i][k] * Vs[cur][cl][k];
-        }
+        if (r > 0) dot_row<T, BP, SLAB_SWEEP_VEC>(&Gs[cur][i][0], &Vs[cur][cl][0], t);
         out = y + w * ((t[0] + t[1]) + (t[2] + t[3]));
         vn = out;
       } else {
@@ -221,8 +243,7 @@ __global__ __launch_bounds__(SLAB_SWEEP_THREADS) void k_sweep(const SolveDev* __
       const int dn = (d + 1) % D;  // ring slot of the next step (row r - 1)
       if (!TRANS) {
         T t[4] = {(T)0, (T)0, (T)0, (T)0};
-#pragma unroll
-        for (int k = 0; k < BP; ++k) t[k & 3] += Gs[cur][i][k] * Vs[cur][cl][k];
+        dot_row<T, BP, SLAB_SWEEP_VEC>(&Gs[cur][i][0], &Vs[cur][cl][0], t);
         x = (t[0] + t[1]) + (t[2] + t[3]);
         Vs[cur ^ 1][cl][i] = rz[dn] + (T)rw[dn] * x;
       } else {
