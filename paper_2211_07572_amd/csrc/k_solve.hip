@@ -142,11 +142,13 @@ __global__ __launch_bounds__(SLAB_SWEEP_THREADS) void k_sweep(const SolveDev* __
       rbr[d] = (valid && i == b - 1) ? wh[(c0 + b) * n2 + r] : 0.0;
     }
   };
+  // (A^T x: the block is parked transposed, so that every product reads a row)
   auto parkG = [&](int d, int buf) __attribute__((always_inline)) {
 #pragma unroll
     for (int e = 0; e < GPT; ++e) {
       const int idx = tid + NT * e;
-      Gs[buf][idx / BP][idx % BP] = rg[d][e];
+      if (TRANS) Gs[buf][idx % BP][idx / BP] = rg[d][e];
+      else Gs[buf][idx / BP][idx % BP] = rg[d][e];
     }
   };
   // right-hand side of ring slot d (forward steps)
@@ -197,8 +199,7 @@ __global__ __launch_bounds__(SLAB_SWEEP_THREADS) void k_sweep(const SolveDev* __
         vn = out;
       } else {
         T t[4] = {(T)0, (T)0, (T)0, (T)0};
-#pragma unroll
-        for (int k = 0; k < BP; ++k) t[k & 3] += Gs[cur][k][i] * Vs[cur][cl][k];
+        dot_row<T, BP, SLAB_SWEEP_VEC>(&Gs[cur][i][0], &Vs[cur][cl][0], t);
         out = (t[0] + t[1]) + (t[2] + t[3]);
         const int dn = (d + 1) % D;  // ring slot of the next step
         // (the next pass's first right-hand side is still in the batch buffer)
@@ -248,8 +249,7 @@ __global__ __launch_bounds__(SLAB_SWEEP_THREADS) void k_sweep(const SolveDev* __
         Vs[cur ^ 1][cl][i] = rz[dn] + (T)rw[dn] * x;
       } else {
         T t[4] = {(T)0, (T)0, (T)0, (T)0};
-#pragma unroll
-        for (int k = 0; k < BP; ++k) t[k & 3] += Gs[cur][k][i] * Vs[cur][cl][k];
+        dot_row<T, BP, SLAB_SWEEP_VEC>(&Gs[cur][i][0], &Vs[cur][cl][0], t);
         x = z + ((t[0] + t[1]) + (t[2] + t[3]));
         Vs[cur ^ 1][cl][i] = (T)rw[dn] * x;
       }
