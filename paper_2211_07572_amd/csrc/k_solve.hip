@@ -63,7 +63,12 @@ __global__ __launch_bounds__(SLAB_SWEEP_THREADS) void k_sweep(const SolveDev* __
   constexpr int GPT = BP * BP / NT;       // block-inverse elements loaded per thread
   static_assert(NC >= 1 && GPT * NT == BP * BP, "sweep workgroup shape");
   // prefetch depth (row steps), scaled with the elements each thread loads
-  constexpr int D0 = BP == 64 ? (sizeof(T) == 8 ? 2 : 4) : 8;
+#ifdef SLAB_SWEEP_D0
+  constexpr int D0 = SLAB_SWEEP_D0;
+#else
+  // (16 for 16- and 32-row blocks: measured faster than 8 and 4; 32 spills)
+  constexpr int D0 = BP == 64 ? (sizeof(T) == 8 ? 2 : 4) : 16;
+#endif
   constexpr int D = D0 * NT / 256 > 0 ? D0 * NT / 256 : 1;
   // SLAB_SWEEP_VEC: rows padded to 16 bytes and read as 16-byte vectors in the
   // products with Gl (not transposed)
