@@ -400,10 +400,11 @@ struct FactorTemps {
 };
 
 // Segments of the slab recursion's chains (k_slab_factor): chains of n2 row
-// steps are cut into segments of about `seg` = 512 steps once there are at
-// least two (at 2048 x 4096, b = 31: 9.7 ms unsegmented, 8.1 ms with 512,
-// 10.2 ms with 256, 14.5 ms with 128: the redundant warm-up work, not the
-// chain, bounds the shorter segments),
+// steps are cut into round(n2 / 680) equal segments (the last takes the
+// remainder) once there are at least two.  At 2048 x 4096, b = 31: 9.7 ms
+// unsegmented, 7.2 ms with three segments of 682 steps, 8.7 with four of 512,
+// 10.2 with 256, 14.5 with 128: the redundant warm-up work, not the chain,
+// bounds the shorter segments;
 // each segment after the first warming up over `warm` = 7 (b+1) steps (the
 // influence of the start shrinks by about exp(-2 pi/(b+1)) per step, so by
 // ~1e-19 over the warm-up).  The environment variables SLAB_FACTOR_SEG
@@ -412,10 +413,15 @@ struct FactorTemps {
 void slab_segments(int n2, int b, int* nseg, int* seg, int* warm) {
   const char* es = getenv("SLAB_FACTOR_SEG");
   const char* ew = getenv("SLAB_FACTOR_WARM");
-  const int seg_len = es ? atoi(es) : 512;
   *warm = ew ? std::max(1, atoi(ew)) : 7 * (b + 1);
-  *seg = seg_len > 0 ? seg_len : n2;
-  *nseg = seg_len > 0 ? std::max(1, n2 / seg_len) : 1;
+  if (es) {
+    const int seg_len = atoi(es);
+    *seg = seg_len > 0 ? seg_len : n2;
+    *nseg = seg_len > 0 ? std::max(1, n2 / seg_len) : 1;
+  } else {
+    *nseg = std::max(1, (int)std::lround(n2 / 680.0));
+    *seg = n2 / *nseg;
+  }
   if (*nseg < 2) {
     *nseg = 1;
     *seg = n2;
