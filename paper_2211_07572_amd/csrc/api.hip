@@ -400,11 +400,12 @@ struct FactorTemps {
 };
 
 // Segments of the slab recursion's chains (k_slab_factor): chains of n2 row
-// steps are cut into round(n2 / 680) equal segments (the last takes the
-// remainder) once there are at least two.  At 2048 x 4096, b = 31: 9.7 ms
-// unsegmented, 7.2 ms with three segments of 682 steps, 8.7 with four of 512,
-// 10.2 with 256, 14.5 with 128: the redundant warm-up work, not the chain,
-// bounds the shorter segments;
+// steps are cut into round(n2 / L) equal segments, L = 512 + 5 (b - 31) (at
+// least 384), the last taking the remainder, once there are at least two.  At 2048 x 4096, b = 31, with
+// two-wave workgroups: 6.2 ms with four segments, 6.5 with three, 8.5 with
+// two, 8.6 with five (four-wave workgroups: 9.7 ms unsegmented, 7.2 with
+// three, 8.7 with four, 10.2 with segments of 256, 14.5 with 128): the
+// redundant warm-up work, not the chain, bounds the shorter segments;
 // each segment after the first warming up over `warm` = 7 (b+1) steps (the
 // influence of the start shrinks by about exp(-2 pi/(b+1)) per step, so by
 // ~1e-19 over the warm-up).  The environment variables SLAB_FACTOR_SEG
@@ -419,7 +420,11 @@ void slab_segments(int n2, int b, int* nseg, int* seg, int* warm) {
     *seg = seg_len > 0 ? seg_len : n2;
     *nseg = seg_len > 0 ? std::max(1, n2 / seg_len) : 1;
   } else {
-    *nseg = std::max(1, (int)std::lround(n2 / 680.0));
+    // (longer segments for wider slabs, whose warm-up is longer: at b = 49,
+    // three of 667 measured faster than four of 500 at n2 = 2000, and two of
+    // 500 faster than none at n2 = 1000)
+    const double target = std::max(384.0, 512.0 + 5.0 * (b - 31));
+    *nseg = std::max(1, (int)std::lround(n2 / target));
     *seg = n2 / *nseg;
   }
   if (*nseg < 2) {

@@ -183,9 +183,13 @@ __device__ __forceinline__ void build_D_row(T (&a)[BP], const g_t<const double>*
 // there is recomputed in one piece by the redo launch (redo = 1: one
 // workgroup per chain, only for marked chains).
 // ---------------------------------------------------------------------------
-#ifndef SLAB_FACTOR_THREADS
+// Threads per slab-recursion workgroup: 256 by default; 128 (two waves) for
+// blocks of up to 32 rows when a launch has at least four workgroups per
+// compute unit to interleave (measured faster there: 6.2 against 7.1 ms at
+// 2048 x 4096, b = 31, and slower with fewer workgroups); 64-row blocks keep
+// 256 (fewer would spill).
 #define SLAB_FACTOR_THREADS 256
-#endif
+constexpr int SLAB_FACTOR_MANY = 1024;   // workgroups of a launch that take 128 threads
 #ifndef SLAB_FACTOR_PB
 #define SLAB_FACTOR_PB 2
 #endif
@@ -880,9 +884,15 @@ static void plan_stage1_bp(Plan& plan, const std::vector<ProbDev>& probs, int ph
     const long long t_redo = tot;
     // a converged warm-up differs from the full chain by rounding only
     const double tol = sizeof(T) == 8 ? 1e-13 : 1e-5;
+    const bool narrow = BP <= 32 && t_seg >= SLAB_FACTOR_MANY;
     plan.step([=](const char* dev, hipStream_t st) {
-      hipLaunchKernelGGL((k_slab_factor<T, BP>), dim3((unsigned)t_seg), dim3(SLAB_FACTOR_THREADS), 0, st,
-                         dev_at<ProbDev>(dev, pd), dev_at<int>(dev, o_seg), count, 0);
+      if (narrow)
+        hipLaunchKernelGGL((k_slab_factor<T, BP, (BP <= 32 ? 128 : SLAB_FACTOR_THREADS)>),
+                           dim3((unsigned)t_seg), dim3(BP <= 32 ? 128 : SLAB_FACTOR_THREADS), 0,
+                           st, dev_at<ProbDev>(dev, pd), dev_at<int>(dev, o_seg), count, 0);
+      else
+        hipLaunchKernelGGL((k_slab_factor<T, BP>), dim3((unsigned)t_seg), dim3(SLAB_FACTOR_THREADS),
+                           0, st, dev_at<ProbDev>(dev, pd), dev_at<int>(dev, o_seg), count, 0);
       SLAB_LAUNCH_CHECK();
       if (t_chk > 0) {
         hipLaunchKernelGGL((k_factor_check<T, BP>), dim3((unsigned)t_chk), dim3(256), 0, st,
