@@ -406,15 +406,16 @@ struct FactorTemps {
 // two, 8.6 with five (four-wave workgroups: 9.7 ms unsegmented, 7.2 with
 // three, 8.7 with four, 10.2 with segments of 256, 14.5 with 128): the
 // redundant warm-up work, not the chain, bounds the shorter segments;
-// each segment after the first warming up over `warm` = 7 (b+1) steps (the
+// each segment after the first warming up over `warm` = 6 (b+1) steps (the
 // influence of the start shrinks by about exp(-2 pi/(b+1)) per step, so by
-// ~1e-19 over the warm-up).  The environment variables SLAB_FACTOR_SEG
+// ~4e-17 over the warm-up, far below the check's 1e-13; 7 (b+1): 6.25 ms,
+// 6 (b+1): 6.0 ms at 2048 x 4096).  The environment variables SLAB_FACTOR_SEG
 // (segment length, 0: no segments) and SLAB_FACTOR_WARM (warm-up steps)
 // override both, for measurements and tests.
 void slab_segments(int n2, int b, int* nseg, int* seg, int* warm) {
   const char* es = getenv("SLAB_FACTOR_SEG");
   const char* ew = getenv("SLAB_FACTOR_WARM");
-  *warm = ew ? std::max(1, atoi(ew)) : 7 * (b + 1);
+  *warm = ew ? std::max(1, atoi(ew)) : 6 * (b + 1);
   if (es) {
     const int seg_len = atoi(es);
     *seg = seg_len > 0 ? seg_len : n2;

@@ -415,7 +415,7 @@ SEG_CASES = [(130, 128, 7), (300, 48, 15), (200, 96, 31), (97, 64, 3)]
 @pytest.mark.parametrize("n2,n1,b", SEG_CASES)
 def test_segmented_slab_factor(monkeypatch, n2, n1, b, warm):
     """The slab recursion cut into segments of 32 row steps that start early
-    from a zero inverse (warm-up of 7 (b+1) steps): T, the pivot blocks and u
+    from a zero inverse (warm-up of 6 (b+1) steps): T, the pivot blocks and u
     equal the oracle's to 1e-12.  With a one-step warm-up the segments cannot
     agree with their predecessors, so every segmented chain must be caught by
     the check and recomputed in one piece; the results are still exact."""
