@@ -295,6 +295,12 @@ int slab_export_reduced(slab_handle h, int32_t which, int32_t j, double* out, vo
    (problems with a shift; 0 otherwise), which is the number of negative
    eigenvalues of T (Sylvester's law of inertia): those of A less those of the
    slab interiors (synchronous: copies the pivot signs to the host),
+   8 the device address of the stored block inverses Gl_r of the slab
+   factor (Alg. 3, first loop) that every slab sweep reads: m*n2 blocks of
+   BP x BP row-major elements, BP = b rounded up to 16, 32 or 64, block (s, r)
+   of slab s and row r at element (s*n2 + r)*BP*BP, FP64 (FP32 in
+   SLAB_FP32_REFINE); owned by the handle, for inspection (a caller that
+   writes them changes every later solve of the handle),
    10+p elapsed microseconds of factor phase p of the last
    factorization (0 slab factors, 1 boundary columns of the slab inverses,
    2 Schur propagation, 3 assembly of T, 4 block factorization of T, 5 the

@@ -1762,6 +1762,7 @@ int slab_query(slab_handle h, int32_t what, int64_t* value) {
       *value = neg;
       return SLAB_OK;
     }
+    case 8: *value = (int64_t)(intptr_t)h->Gl; return SLAB_OK;
     default:
       if (what >= 10 && what < 16) { *value = h->phase_us[what - 10]; return SLAB_OK; }
       if (what >= 20 && what < 20 + LK_COUNT) { *value = h->launches[what - 20]; return SLAB_OK; }

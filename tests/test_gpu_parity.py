@@ -5,6 +5,8 @@ oracle on the same seeded inputs.  Tolerances: FP64 results within 1e-12
 relative (per block / per column); mixed precision is judged by the
 relative residual 1e-10 recomputed on the host with the oracle's A.
 """
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -145,6 +147,74 @@ def test_adjoint_matches_oracle(n2, n1, b, order):
     f = G.rhs_uniform(n2, n1, 2, 10)
     uf = S.slab_solve(h, _dev(f)).cpu().numpy()
     assert abs(np.sum(uf * g) - np.sum(f * lam)) <= 1e-11 * abs(np.sum(uf * g))
+    h.free()
+
+
+def _write_block_inverses(h, values):
+    """Overwrite the handle's stored block inverses Gl_r (slab_query 8) with
+    values (a device tensor of the stored element type and count)."""
+    L = S.load_library()
+    L.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    L.hipMemcpy.restype = ctypes.c_int
+    L.hipDeviceSynchronize.restype = ctypes.c_int
+    torch.cuda.synchronize()
+    nbytes = values.numel() * values.element_size()
+    # hipMemcpyDefault (4): the direction follows from the addresses
+    assert L.hipMemcpy(ctypes.c_void_p(h.query(8)), ctypes.c_void_p(values.data_ptr()), nbytes, 4) == 0
+    assert L.hipDeviceSynchronize() == 0
+
+
+def _read_block_inverses(h, count, dtype):
+    L = S.load_library()
+    L.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    L.hipMemcpy.restype = ctypes.c_int
+    out = torch.empty(count, dtype=dtype, device=DEV)
+    torch.cuda.synchronize()
+    assert L.hipMemcpy(ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(h.query(8)),
+                       out.numel() * out.element_size(), 4) == 0
+    torch.cuda.synchronize()
+    return out
+
+
+# The operator is symmetric, so its slab block inverses are too and a slip
+# between Gl_r and its transpose in the transposed sweeps would not change any
+# adjoint result.  Here the stored Gl_r are replaced by non-symmetric ones:
+# one solve pass is then a fixed linear map M of the right-hand side, and the
+# adjoint solve must apply exactly M^T.  Both maps are formed column by column
+# on every grid node (identity right-hand sides).
+@pytest.mark.parametrize("order", ORDERS)
+@pytest.mark.parametrize("precision,tol", [(S.SLAB_FP64, 1e-12), (S.SLAB_MIXED, 1e-5),
+                                           (S.SLAB_FP32_REFINE, 1e-5)])
+@pytest.mark.parametrize("n2,n1,b", [(40, 32, 7), (40, 32, 15), (36, 64, 31), (20, 96, 47)])
+def test_adjoint_is_transpose_with_nonsymmetric_block_inverses(n2, n1, b, precision, tol, order):
+    kap = G.kappa_lognormal(n2, n1, 21)
+    # one pass per solve: u = M f, lambda = M^T g, whatever the residual
+    h = S.slab_factor(_dev(kap), n2, n1, b, precision=precision, tol=1e300, max_iter=1,
+                      odd_even=order == "odd_even")
+    m, BP = n1 // (b + 1), (16 if b <= 16 else (32 if b <= 32 else 64))
+    dt = torch.float32 if precision == S.SLAB_FP32_REFINE else torch.float64
+    count = m * n2 * BP * BP
+    gl = _read_block_inverses(h, count, dt).view(m, n2, BP, BP)
+    rng = np.random.default_rng(31)
+    scale = float(gl[:, :, :b, :b].abs().amax())
+    pert = torch.as_tensor(rng.standard_normal((m, n2, b, b)), dtype=dt, device=DEV)
+    # (entries of 0.05 max|Gl| / sqrt(b): the perturbation's norm stays near a
+    # tenth of the blocks', so the row recursions of the sweeps do not grow
+    # beyond the FP32 range over n2 rows)
+    gl[:, :, :b, :b] += 0.05 / np.sqrt(b) * scale * pert
+    _write_block_inverses(h, gl.reshape(-1))
+    N = n1 * n2
+    E = torch.eye(N, dtype=torch.float64, device=DEV).view(N, n1, n2)
+    Mf = S.slab_solve(h, E).reshape(N, N).cpu().numpy()           # row k = (M e_k)^T
+    Ma = S.slab_solve_adjoint(h, E).reshape(N, N).cpu().numpy()   # row k = (M^T e_k)^T
+    assert np.isfinite(Mf).all() and np.isfinite(Ma).all()
+    norm = np.abs(Mf).max()
+    err = np.abs(Ma - Mf.T).max() / norm
+    asym = np.abs(Mf - Mf.T).max() / norm
+    print(f"\n  case: n2={n2} n1={n1} b={b} precision={precision} {order}: "
+          f"|M_adj - M^T| {err:.2e}, |M - M^T| {asym:.2e} (relative to max |M|)")
+    assert asym >= 100 * tol, asym    # the perturbation is seen by the check
+    assert err <= tol, err
     h.free()
 
 
