@@ -176,6 +176,28 @@ def _read_block_inverses(h, count, dtype):
     return out
 
 
+def _perturb_block_inverses(h, n2, n1, b, precision, seed=31):
+    """Add seeded non-symmetric noise to every stored Gl_r of handle h
+    (entries of 0.05 max|Gl| / sqrt(b): the perturbation's norm stays near a
+    tenth of the blocks', so the row recursions of the sweeps do not grow
+    beyond the FP32 range over n2 rows)."""
+    m, BP = n1 // (b + 1), (16 if b <= 16 else (32 if b <= 32 else 64))
+    dt = torch.float32 if precision == S.SLAB_FP32_REFINE else torch.float64
+    gl = _read_block_inverses(h, m * n2 * BP * BP, dt).view(m, n2, BP, BP)
+    rng = np.random.default_rng(seed)
+    scale = float(gl[:, :, :b, :b].abs().amax())
+    pert = torch.as_tensor(rng.standard_normal((m, n2, b, b)), dtype=dt, device=DEV)
+    gl[:, :, :b, :b] += 0.05 / np.sqrt(b) * scale * pert
+    _write_block_inverses(h, gl.reshape(-1))
+
+
+def _transpose_errors(Mf, Ma):
+    """(|M_adj - M^T|, |M - M^T|) relative to max |M|."""
+    assert np.isfinite(Mf).all() and np.isfinite(Ma).all()
+    norm = np.abs(Mf).max()
+    return np.abs(Ma - Mf.T).max() / norm, np.abs(Mf - Mf.T).max() / norm
+
+
 # The operator is symmetric, so its slab block inverses are too and a slip
 # between Gl_r and its transpose in the transposed sweeps would not change any
 # adjoint result.  Here the stored Gl_r are replaced by non-symmetric ones:
@@ -191,31 +213,40 @@ def test_adjoint_is_transpose_with_nonsymmetric_block_inverses(n2, n1, b, precis
     # one pass per solve: u = M f, lambda = M^T g, whatever the residual
     h = S.slab_factor(_dev(kap), n2, n1, b, precision=precision, tol=1e300, max_iter=1,
                       odd_even=order == "odd_even")
-    m, BP = n1 // (b + 1), (16 if b <= 16 else (32 if b <= 32 else 64))
-    dt = torch.float32 if precision == S.SLAB_FP32_REFINE else torch.float64
-    count = m * n2 * BP * BP
-    gl = _read_block_inverses(h, count, dt).view(m, n2, BP, BP)
-    rng = np.random.default_rng(31)
-    scale = float(gl[:, :, :b, :b].abs().amax())
-    pert = torch.as_tensor(rng.standard_normal((m, n2, b, b)), dtype=dt, device=DEV)
-    # (entries of 0.05 max|Gl| / sqrt(b): the perturbation's norm stays near a
-    # tenth of the blocks', so the row recursions of the sweeps do not grow
-    # beyond the FP32 range over n2 rows)
-    gl[:, :, :b, :b] += 0.05 / np.sqrt(b) * scale * pert
-    _write_block_inverses(h, gl.reshape(-1))
+    _perturb_block_inverses(h, n2, n1, b, precision)
     N = n1 * n2
     E = torch.eye(N, dtype=torch.float64, device=DEV).view(N, n1, n2)
     Mf = S.slab_solve(h, E).reshape(N, N).cpu().numpy()           # row k = (M e_k)^T
     Ma = S.slab_solve_adjoint(h, E).reshape(N, N).cpu().numpy()   # row k = (M^T e_k)^T
-    assert np.isfinite(Mf).all() and np.isfinite(Ma).all()
-    norm = np.abs(Mf).max()
-    err = np.abs(Ma - Mf.T).max() / norm
-    asym = np.abs(Mf - Mf.T).max() / norm
+    err, asym = _transpose_errors(Mf, Ma)
     print(f"\n  case: n2={n2} n1={n1} b={b} precision={precision} {order}: "
           f"|M_adj - M^T| {err:.2e}, |M - M^T| {asym:.2e} (relative to max |M|)")
     assert asym >= 100 * tol, asym    # the perturbation is seen by the check
     assert err <= tol, err
     h.free()
+
+
+# The same through the batched entry points: three problems of the three
+# padded block orders in the grouped launches of one batch.
+@pytest.mark.parametrize("precision,tol", [(S.SLAB_FP64, 1e-12), (S.SLAB_FP32_REFINE, 1e-5)])
+def test_batch_adjoint_is_transpose_with_nonsymmetric_block_inverses(precision, tol):
+    dims = [(40, 32, 7), (36, 64, 31), (20, 96, 47)]
+    kaps = [_dev(G.kappa_lognormal(n2, n1, 22 + i)) for i, (n2, n1, _) in enumerate(dims)]
+    bt = S.slab_factor_batch(kaps, dims, precision=precision, tol=1e300, max_iter=1)
+    for i, (n2, n1, b) in enumerate(dims):
+        _perturb_block_inverses(bt.handle(i), n2, n1, b, precision, seed=40 + i)
+    Es = [torch.eye(n1 * n2, dtype=torch.float64, device=DEV).view(n1 * n2, n1, n2)
+          for n2, n1, _ in dims]
+    Mfs = S.slab_solve_batch(bt, Es)
+    Mas = S.slab_solve_adjoint_batch(bt, Es)
+    for (n2, n1, b), Mf, Ma in zip(dims, Mfs, Mas):
+        N = n1 * n2
+        err, asym = _transpose_errors(Mf.reshape(N, N).cpu().numpy(), Ma.reshape(N, N).cpu().numpy())
+        print(f"\n  case: batch n2={n2} n1={n1} b={b} precision={precision}: "
+              f"|M_adj - M^T| {err:.2e}, |M - M^T| {asym:.2e} (relative to max |M|)")
+        assert asym >= 100 * tol, asym
+        assert err <= tol, err
+    bt.free()
 
 
 def test_gradient_kernel_matches_oracle():
